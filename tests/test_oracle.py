@@ -1,0 +1,308 @@
+"""Pins of the CPU oracle (CPU only).
+
+Each oracle function is checked against something other than itself: dense
+matrix-vector products and LU solves (LAPACK), exact rational sums
+(fractions.Fraction), exact small-integer arithmetic, a closed-form plane-wave
+response of the unjittered Kuhn stencil, SciPy's independent BiCGStab, torch's
+dense complex autograd, and central finite differences.
+"""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from synth import helmholtz as H
+from synth import configs
+
+
+def tiny_problem(nc=3, jitter=0.2, seed=3, kappa2=complex(40.0, 0.4)):
+    m = H.make_mesh(nc, nc, nc, 1.0 / nc, jitter=jitter, rng=np.random.default_rng(seed))
+    p = H.build_problem(m)
+    return p, H.helmholtz_values(p, kappa2)
+
+
+def dense(p, val):
+    A = np.zeros((p.n, p.n), dtype=np.complex128)
+    rows = np.repeat(np.arange(p.n), np.diff(p.rowptr))
+    A[rows, p.col] = val
+    return A
+
+
+def crandn(rng, n):
+    return rng.standard_normal(n) + 1j * rng.standard_normal(n)
+
+
+# ------------------------------------------------------------------ SpMV
+
+@pytest.mark.parametrize("nc", [2, 3, 4])
+def test_spmv_matches_dense(oracle, nc):
+    p, val = tiny_problem(nc)
+    x = crandn(np.random.default_rng(nc), p.n)
+    A = dense(p, val)
+    y = oracle.spmv(p.rowptr, p.col, val, x)
+    ref = A @ x
+    bound = 1e-15 * 16 * (np.abs(A) @ np.abs(x))
+    assert np.all(np.abs(y - ref) <= bound)
+
+
+def test_spmv_plane_wave_closed_form(oracle):
+    """Interior rows of A = K - kappa2 M on the unjittered mesh applied to
+    x_j = exp(i theta . j) give x_i [h(6 - 2 sum cos) - kappa2 h^3 (0.4 +
+    0.1 sum cos th_d + 1/15 sum_{d<e} cos(th_d + th_e) + 0.1 cos(th1+th2+th3))]."""
+    nc = 8
+    h = 1.0 / nc
+    m = H.make_mesh(nc, nc, nc, h)
+    p = H.build_problem(m)
+    kappa2 = complex(250.0, 2.5)
+    val = H.helmholtz_values(p, kappa2)
+    th = np.array([0.3, -0.7, 1.1])
+    i, j, k = m.ijk()
+    x = np.exp(1j * (th[0] * i + th[1] * j + th[2] * k))
+    y = oracle.spmv(p.rowptr, p.col, val, x)
+    cs = np.cos(th)
+    sym = (0.4 + 0.1 * cs.sum() + (np.cos(th[0] + th[1]) + np.cos(th[0] + th[2]) + np.cos(th[1] + th[2])) / 15.0
+           + 0.1 * np.cos(th.sum()))
+    lam = h * (6 - 2 * cs.sum()) - kappa2 * h ** 3 * sym
+    inner = (i > 0) & (i < nc) & (j > 0) & (j < nc) & (k > 1) & (k < nc)
+    assert np.max(np.abs(y[inner] - lam * x[inner])) < 1e-14
+
+
+# -------------------------------------------------------------- BLAS-1
+
+def _frac(z):
+    return Fraction(z.real), Fraction(z.imag)
+
+
+def _exact_dot(x, y, conj):
+    sr, si = Fraction(0), Fraction(0)
+    for a, b in zip(x, y):
+        ar, ai = _frac(a)
+        br, bi = _frac(b)
+        if conj:
+            ai = -ai
+        sr += ar * br - ai * bi
+        si += ar * bi + ai * br
+    return sr, si
+
+
+@pytest.mark.parametrize("conj", [True, False])
+def test_dots_exact_on_dyadic_inputs(oracle, conj):
+    rng = np.random.default_rng(11)
+    n = 64
+    x = (rng.integers(-1000, 1000, n) + 1j * rng.integers(-1000, 1000, n)) / 1024.0
+    y = (rng.integers(-1000, 1000, n) + 1j * rng.integers(-1000, 1000, n)) / 512.0
+    d = oracle.zdotc(x, y) if conj else oracle.zdotu(x, y)
+    sr, si = _exact_dot(x, y, conj)
+    assert Fraction(d.real) == sr and Fraction(d.imag) == si
+
+
+@pytest.mark.parametrize("conj", [True, False])
+def test_dots_within_rounding_of_exact(oracle, conj):
+    rng = np.random.default_rng(12)
+    n = 61
+    x, y = crandn(rng, n), crandn(rng, n)
+    d = oracle.zdotc(x, y) if conj else oracle.zdotu(x, y)
+    sr, si = _exact_dot(x, y, conj)
+    bound = 2 * n * 2.0 ** -53 * float(np.sum(np.abs(x) * np.abs(y)))
+    assert abs(d.real - float(sr)) <= bound and abs(d.imag - float(si)) <= bound
+
+
+def test_norm_and_dot_identities(oracle):
+    rng = np.random.default_rng(13)
+    x = crandn(rng, 50)
+    nrm = oracle.dznrm2(x)
+    exact = math.sqrt(float(sum(Fraction(v.real) ** 2 + Fraction(v.imag) ** 2 for v in x)))
+    assert abs(nrm - exact) <= 1e-15 * exact * 4
+    dxx = oracle.zdotc(x, x)
+    assert dxx.imag == 0.0 and abs(dxx.real - nrm ** 2) <= 1e-13 * nrm ** 2
+    dxi = oracle.zdotc(x, 1j * x)
+    assert dxi.real == 0.0 and dxi.imag == dxx.real
+    assert oracle.zdotu(np.ones(37), np.ones(37)) == 37
+
+
+def test_axpy_scal_axmy_exact_on_integers(oracle):
+    rng = np.random.default_rng(14)
+    n = 40
+    x = rng.integers(-50, 50, n) + 1j * rng.integers(-50, 50, n)
+    y = rng.integers(-50, 50, n) + 1j * rng.integers(-50, 50, n)
+    a = complex(3, -2)
+    ex_axpy = [complex(a * complex(int(u.real), int(u.imag)) + complex(int(v.real), int(v.imag)))
+               for u, v in zip(x, y)]
+    assert np.array_equal(oracle.zaxpy(a, x, y), np.array(ex_axpy))
+    assert np.array_equal(oracle.zscal(a, x), np.array([a * complex(u) for u in x]))
+    assert np.array_equal(oracle.zaxmy(x, y), np.array([complex(u) * complex(v) for u, v in zip(x, y)]))
+
+
+# ------------------------------------------------------------- BiCGStab
+
+@pytest.mark.parametrize("nc,seed", [(3, 3), (4, 5)])
+def test_bicgstab_matches_dense_lu(oracle, nc, seed):
+    p, val = tiny_problem(nc, seed=seed)
+    b = crandn(np.random.default_rng(seed), p.n)
+    b[p.dirichlet] = 0
+    x, info = oracle.bicgstab(p.rowptr, p.col, val, b, tol=1e-13)
+    assert info["status"] == 0 and info["relres_true"] <= 2e-13
+    xs = np.linalg.solve(dense(p, val), b)
+    assert np.linalg.norm(x - xs) <= 1e-10 * np.linalg.norm(xs)
+
+
+def test_bicgstab_diagonal_converges_in_one_iteration(oracle):
+    n = 20
+    rng = np.random.default_rng(2)
+    d = crandn(rng, n) + 3.0
+    rowptr = np.arange(n + 1, dtype=np.int32)
+    col = np.arange(n, dtype=np.int32)
+    b = crandn(rng, n)
+    x, info = oracle.bicgstab(rowptr, col, d, b, tol=1e-12)
+    assert info["status"] == 0 and info["iters"] == 1
+    assert np.allclose(x, b / d, rtol=1e-14, atol=0)
+
+
+def test_bicgstab_config1_true_residual_and_scipy(oracle):
+    c1 = configs.config1()
+    x8, i8 = oracle.bicgstab(c1["rowptr"], c1["col"], c1["val"], c1["g"], tol=1e-8)
+    assert i8["status"] == 0 and i8["relres_true"] <= 1.05e-8
+    x10, i10 = oracle.bicgstab(c1["rowptr"], c1["col"], c1["val"], c1["g"], tol=1e-10)
+    assert i10["status"] == 0 and i10["relres_true"] <= 1.05e-10
+    n = int(c1["n"])
+    A = sp.csr_matrix((c1["val"], c1["col"], c1["rowptr"]), shape=(n, n))
+    dinv = 1.0 / A.diagonal()
+    M = spla.LinearOperator((n, n), matvec=lambda v: dinv * v, dtype=np.complex128)
+    xs, flag = spla.bicgstab(A, c1["g"], rtol=1e-11, atol=0.0, maxiter=20000, M=M)
+    assert flag == 0
+    assert np.linalg.norm(x10 - xs) <= 1e-7 * np.linalg.norm(xs)
+
+
+def test_bicgstab_sigma_breakdown(oracle):
+    # D = I and g^H A g = 1*(-1.5) + 2*0.75 = 0 exactly at the first step
+    rowptr = np.array([0, 2, 4], dtype=np.int32)
+    col = np.array([0, 1, 0, 1], dtype=np.int32)
+    val = np.array([1.0, -1.25, -1.25, 1.0], dtype=np.complex128)
+    x, info = oracle.bicgstab(rowptr, col, val, np.array([1.0, 2.0]), tol=1e-12)
+    assert info["status"] == oracle.BREAKDOWN and info["breakdown"] == oracle.BD_SIGMA
+    assert info["iters"] == 0 and np.all(x == 0)
+
+
+def test_bicgstab_omega_breakdown(oracle):
+    """b = e1 and a11 = 1 give alpha = 1 and s = -(0, a21, a31) = -(0, 1, 1);
+    with a22 + a23 + a32 + a33 = 0 the first omega = t^H s / t^H t is exactly 0."""
+    A = np.array([[1, 1, 0], [1, 1, -1], [1, -1, 1]], dtype=np.complex128)
+    rowptr = np.array([0, 3, 6, 9], dtype=np.int32)
+    col = np.tile(np.arange(3, dtype=np.int32), 3)
+    for pre in (False, True):  # diag(A) = I, so Jacobi changes nothing
+        x, info = oracle.bicgstab(rowptr, col, A.ravel(), np.array([1.0, 0, 0]), tol=1e-14,
+                                  precond=pre)
+        assert info["status"] == oracle.BREAKDOWN and info["breakdown"] == oracle.BD_OMEGA
+        assert info["iters"] == 1 and np.array_equal(x, np.array([1.0, 0, 0]))
+
+
+def test_bicgstab_error_paths(oracle):
+    c1 = configs.config1()
+    g = c1["g"].copy()
+    g[5] = np.nan
+    _, info = oracle.bicgstab(c1["rowptr"], c1["col"], c1["val"], g)
+    assert info["status"] == oracle.NONFINITE
+    rowptr = np.array([0, 1, 2], dtype=np.int32)
+    col = np.array([1, 0], dtype=np.int32)
+    _, info = oracle.bicgstab(rowptr, col, np.array([1.0, 1.0], dtype=complex), np.array([1.0, 1.0]))
+    assert info["status"] == oracle.EINVAL
+    x, info = oracle.bicgstab(c1["rowptr"], c1["col"], c1["val"], c1["g"], maxit=1)
+    assert info["status"] == oracle.NOT_CONVERGED and info["iters"] == 1
+    assert 0 < info["relres_true"] < 1 and np.any(x != 0)
+
+
+def test_mixed_refinement_config1(oracle):
+    c1 = configs.config1()
+    u, info = oracle.mixed_refine(c1["rowptr"], c1["col"], c1["val"], c1["g"])
+    assert info["status"] == 0 and info["relres_true"] <= 1e-10
+    x, _ = oracle.bicgstab(c1["rowptr"], c1["col"], c1["val"], c1["g"], tol=1e-12)
+    assert np.linalg.norm(u - x) <= 1e-8 * np.linalg.norm(x)
+
+
+# ------------------------------------------------------------- adjoint
+
+def _block_problem(nc=4, bs=2, seed=1):
+    m = H.make_mesh(nc, nc, nc, 1.0 / nc, jitter=0.2, rng=np.random.default_rng(seed))
+    nb = (nc // bs) ** 3
+    c = np.random.default_rng(seed + 10).uniform(300, 400, nb)
+    (_, nby, nbz), blk = H.cell_blocks(m, bs)
+    p = H.build_problem(m)
+    tn, tb, tv, tp = H.tets_by_block(m, bs)
+    omega = 2 * math.pi * c.min() / (10 * m.h)
+    return m, p, c, tn, tb, omega, blk
+
+
+def test_oracle_assembly_matches_generator(oracle):
+    m, p, c, tn, tb, omega, blk = _block_problem(6, 3, 2)
+    pw = H.build_problem(m, cell_weight=lambda I, J, K: 1.0 / c[blk(I, J, K)] ** 2)
+    ref = H.helmholtz_values(pw, complex(omega ** 2, 0.01 * omega ** 2))
+    val = oracle.assemble_helmholtz(p.rowptr, p.col, p.K, p.dirichlet, tn, tb, m.coords, c, omega)
+    assert np.max(np.abs(val - ref)) <= 1e-13 * np.max(np.abs(ref))
+
+
+def test_adjoint_matches_torch_dense_autograd(oracle):
+    torch = pytest.importorskip("torch")
+    m, p, c, tn, tb, omega, blk = _block_problem(4, 2, 1)
+    val = oracle.assemble_helmholtz(p.rowptr, p.col, p.K, p.dirichlet, tn, tb, m.coords, c, omega)
+    g = crandn(np.random.default_rng(3), p.n)
+    g[p.dirichlet] = 0
+    S = np.flatnonzero(~p.dirichlet)[::5]
+    L, gg, gc, u, _ = oracle.adjoint_gradients(p.rowptr, p.col, val, g, S, tn, tb, m.coords,
+                                               p.dirichlet, c, omega, tol=1e-14)
+    # torch: dense A(c) = K - omega^2 (1+0.01i) sum_b c_b^-2 M_b with M_b from one-hot speeds
+    nb = c.shape[0]
+    Mb = []
+    for b in range(nb):
+        cb = np.full(nb, np.inf)
+        cb[b] = 1.0
+        vb = oracle.assemble_helmholtz(p.rowptr, p.col, np.zeros_like(p.K), p.dirichlet, tn, tb,
+                                       m.coords, cb, 1.0, damp=0.0)
+        Mb.append(-dense(p, vb).real)
+    Kd = torch.tensor(dense(p, p.K.astype(complex)).real)
+    Mb = torch.tensor(np.stack(Mb))
+    ct = torch.tensor(c, requires_grad=True)
+    gt = torch.tensor(g, requires_grad=True)
+    kap = omega ** 2 * (1 + 0.01j)
+    A = Kd.to(torch.complex128) - kap * torch.einsum("b,bij->ij", ct ** -2, Mb).to(torch.complex128)
+    ut = torch.linalg.solve(A, gt)
+    Lt = (ut[torch.tensor(S)].abs() ** 2).sum()
+    Lt.backward()
+    assert abs(L - Lt.item()) <= 1e-10 * L
+    assert np.linalg.norm(gg - gt.grad.numpy()) <= 1e-8 * np.linalg.norm(gg)
+    assert np.linalg.norm(gc - ct.grad.numpy()) <= 1e-8 * np.linalg.norm(gc)
+
+
+def test_adjoint_matches_central_differences(oracle):
+    m, p, c, tn, tb, omega, blk = _block_problem(6, 3, 4)
+    asm = lambda cc: oracle.assemble_helmholtz(p.rowptr, p.col, p.K, p.dirichlet, tn, tb, m.coords,
+                                               cc, omega)
+    val = asm(c)
+    g = crandn(np.random.default_rng(8), p.n)
+    g[p.dirichlet] = 0
+    S = np.flatnonzero(~p.dirichlet)[::7]
+
+    def loss(v, gg):
+        u, info = oracle.bicgstab(p.rowptr, p.col, v, gg, tol=1e-14)
+        return float(np.sum(np.abs(u[S]) ** 2))
+
+    L, grad_g, grad_c, u, _ = oracle.adjoint_gradients(p.rowptr, p.col, val, g, S, tn, tb, m.coords,
+                                                       p.dirichlet, c, omega, tol=1e-14)
+    rng = np.random.default_rng(9)
+    for b in rng.choice(c.shape[0], 3, replace=False):
+        hstep = 1e-6 * c[b]
+        cp, cm = c.copy(), c.copy()
+        cp[b] += hstep
+        cm[b] -= hstep
+        fd = (loss(asm(cp), g) - loss(asm(cm), g)) / (2 * hstep)
+        assert abs(fd - grad_c[b]) <= 1e-5 * max(abs(fd), 1e-3 * np.abs(grad_c).max())
+    for _ in range(2):
+        d = crandn(rng, p.n)
+        d[p.dirichlet] = 0
+        d /= np.linalg.norm(d)
+        hstep = 1e-6 * np.linalg.norm(g)
+        fd = (loss(val, g + hstep * d) - loss(val, g - hstep * d)) / (2 * hstep)
+        # dL = Re(conj(grad_g) . dg) for the dL/dRe + i dL/dIm convention
+        assert abs(fd - np.real(np.vdot(grad_g, d))) <= 1e-6 * np.linalg.norm(grad_g)
