@@ -1,0 +1,184 @@
+#!/usr/bin/env python3
+"""Benchmark of the complex Helmholtz Krylov path on one MI355X.
+
+Workload: the 2:1:1 box of 192x96x96 Kuhn-split cubes (P1 tetrahedra,
+jittered nodes, 3,456 speed blocks, 1% damping): 1,815,937 rows, 26,606,015
+nonzeros, complex128 CSR, Jacobi BiCGStab to a relative residual of 1e-8.
+
+One step = one pass over the hot path on that system: R back-to-back CSR
+products (timed with HIP events on the launch stream), a zdotc and a
+dznrm2, then one full Jacobi-BiCGStab solve to 1e-8 from x = 0.
+`value` is the CSR product's achieved algorithmic bandwidth (GB/s):
+20 B per nonzero (int32 col + complex128 value) + 36 B per row (int32
+rowptr + complex128 x and y) divided by the mean kernel time.
+After the timed steps (untimed for ms_per_step): the mixed-precision
+refinement on the same matrix (complex64 inner to 1e-4, complex128 outer to
+1e-10) and, unless --no-cpu, the CPU oracle's CSR product on the same matrix
+on the host cores (a bounded sample).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "z-CSR SpMV GB/s (%HBM peak) + BiCGStab time-to-1e-8, plain FP64 vs mixed/batched"
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def spmv_bytes(n, nnz):
+    return 4 * (n + 1) + 20 * nnz + 32 * n
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--spmv-reps", type=int, default=20)
+    ap.add_argument("--workload", default="config2", choices=["config1", "config2"])
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-solve", action="store_true", help="CSR products only (profiling runs)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the row-slab design for several GPUs is described, not built).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2112_11880_amd as hk
+    from synth import configs
+
+    t0 = time.time()
+    c = configs.config2() if args.workload == "config2" else configs.config1()
+    n, nnz = int(c["n"]), int(c["col"].shape[0])
+    log(f"inputs {args.workload}: n={n} nnz={nnz} ({time.time() - t0:.1f}s)")
+    assert torch.cuda.is_available(), "no HIP device"
+    dev = "cuda:0"
+    hk.load()
+    rowptr = torch.from_numpy(c["rowptr"]).to(dev)
+    col = torch.from_numpy(c["col"]).to(dev)
+    val = torch.from_numpy(c["val"]).to(dev)
+    g = torch.from_numpy(c["g"]).to(dev)
+    rng = np.random.default_rng(123)
+    x = torch.from_numpy(rng.standard_normal(n) + 1j * rng.standard_normal(n)).to(dev)
+    y = torch.empty_like(x)
+    A = hk.CSR(rowptr, col, val, autotune=True)
+    plan = A.plan()
+    log("plan", plan)
+    stream = torch.cuda.current_stream()
+    nbytes = spmv_bytes(n, nnz)
+
+    def step(timed_spmv):
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(args.spmv_reps):
+            A.spmv(x, y)
+        ev1.record(stream)
+        hk.zdotc(x, y)
+        hk.dznrm2(y)
+        info = None
+        if not args.no_solve:
+            _, info = hk.krylov_solve(A, g, tol=1e-8)
+        torch.cuda.synchronize()
+        timed_spmv.append(ev0.elapsed_time(ev1) / args.spmv_reps)
+        return info
+
+    # practical streaming ceiling: complex128 copy of 64 Mi elements (2 GiB moved)
+    ncp = 1 << 26
+    src = torch.zeros(ncp, dtype=torch.complex128, device=dev)
+    dst = torch.empty_like(src)
+    hk.zcopy(src, dst)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(10):
+        hk.zcopy(src, dst)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = 32 * ncp / (e0.elapsed_time(e1) / 10 * 1e-3) / 1e9
+    log(f"copy ceiling {copy_gbs:.0f} GB/s")
+    del src, dst
+
+    spmv_ms = []
+    for _ in range(args.warmup):
+        step([])
+        log("warmup step done")
+    torch.cuda.synchronize()
+    infos, solve_s = [], []
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        ts = time.perf_counter()
+        infos.append(step(spmv_ms))
+        torch.cuda.synchronize()
+        solve_s.append(time.perf_counter() - ts)
+        log(f"step {k}: spmv {spmv_ms[-1] * 1e3:.1f} us, step {solve_s[-1]:.3f} s, solve {infos[-1]}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    ms_spmv = float(np.mean(spmv_ms))
+    gbs = nbytes / (ms_spmv * 1e-3) / 1e9
+    out = {
+        "metric": METRIC, "value": round(gbs, 1), "unit": "GB/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(elapsed / max(args.steps, 1) * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": ("helmholtz-p1-192x96x96-jittered (1,815,937 rows, 26,606,015 nnz, "
+                                "complex128 CSR, Jacobi BiCGStab to 1e-8)") if args.workload == "config2"
+                   else "helmholtz-p1-16^3 (4,913 rows, 63,183 nnz)",
+                   "n": n, "nnz": nnz, "spmv_plan": plan, "spmv_reps_per_step": args.spmv_reps},
+        "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_spmv (complex128 CSR product)",
+                     "algorithmic_bytes_per_launch": nbytes, "mean_kernel_us": round(ms_spmv * 1e3, 2),
+                     "gflops": round(8 * nnz / (ms_spmv * 1e-3) / 1e9, 1),
+                     "copy_kernel_gbs": round(copy_gbs, 1)},
+    }
+    if infos and infos[0] is not None:
+        st = infos[-1]
+        out["solve_plain"] = {"tol": 1e-8, "iters": st["iters"], "status": st["status"],
+                              "relres_true": st["relres_true"],
+                              "time_s_mean": round(float(np.mean(solve_s)) - args.spmv_reps * ms_spmv * 1e-3, 4),
+                              "us_per_iter": round((float(np.mean(solve_s)) - args.spmv_reps * ms_spmv * 1e-3)
+                                                   / max(st["iters"], 1) * 1e6, 2)}
+    if not args.no_mixed and not args.no_solve:
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        xm, im = hk.krylov_solve_mixed(A, g, inner_tol=1e-4, outer_tol=1e-10)
+        torch.cuda.synchronize()
+        tm = time.perf_counter() - ts
+        log("mixed", im, f"{tm:.3f}s")
+        out["solve_mixed"] = {"inner_tol": 1e-4, "outer_tol": 1e-10, "outer": im["iters"],
+                              "inner_iters": im["inner_iters"], "status": im["status"],
+                              "relres_true": im["relres_true"], "time_s": round(tm, 4)}
+    if not args.no_cpu:
+        from oracle import oracle
+        xh = x.cpu().numpy()
+        oracle.spmv(c["rowptr"], c["col"], c["val"], xh)
+        reps, tc = 0, 0.0
+        while tc < 10.0 and reps < 200:
+            ts = time.perf_counter()
+            oracle.spmv(c["rowptr"], c["col"], c["val"], xh)
+            tc += time.perf_counter() - ts
+            reps += 1
+        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        out["cpu_baseline"] = {"value": round(nbytes / (tc / reps) / 1e9, 2), "unit": "GB/s",
+                               "cores": cores, "kind": "oracle",
+                               "sample": f"{reps} oracle CSR products (plain C, OpenMP over rows) "
+                                         f"on the same matrix, {tc:.1f} s"}
+        log("cpu", out["cpu_baseline"])
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,248 @@
+/*
+ * hk.h -- C ABI of libhk: complex Krylov solvers for finite-element Helmholtz
+ * systems on AMD Instinct MI355X (gfx950).
+ *
+ * Problem (the paper, arXiv 2112.11880, Introduction and Section 2): the
+ * finite-element discretisation of -lap(u) - k^2 u = g with Dirichlet
+ * conditions on part of the boundary gives a large sparse complex system
+ * A u = g, stored in compressed sparse row (CSR) form.  Section 3 defines the
+ * complex double BLAS-1 operations (scale, axpy, element-wise product, dot,
+ * L2 norm) and the CSR product; Section 4 composes them into a
+ * preconditioned BiCGStab started from zero with a residual tolerance and an
+ * iteration cap.
+ *
+ * Conventions for every entry point:
+ *   - Complex vectors are interleaved (re, im) pairs: complex128 = two
+ *     doubles (16 bytes), complex64 = two floats (8 bytes).
+ *   - Pointers named d_* are device pointers (HIP device memory of the
+ *     current device); all other pointers are host pointers.
+ *   - The caller owns every buffer passed in.  The library never frees
+ *     caller memory; a matrix handle owns only its launch plan and workspace.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Calls enqueue work
+ *     on it and return without waiting, except where stated.
+ *   - Return value: HK_OK (0); a negative code for a usage or runtime error,
+ *     raised before any work is enqueued where possible (the text is
+ *     available from hk_last_error()); a positive code for a numerical
+ *     outcome of a solve.
+ *   - Indices are int32 (rowptr has n+1 entries, col has nnz entries, column
+ *     indices ascending within a row, 0 <= col < n).
+ */
+#ifndef HK_H_
+#define HK_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum hk_status {
+  HK_OK = 0,
+  HK_EINVAL = -1,          /* invalid argument (null pointer, bad size, bad matrix) */
+  HK_EHIP = -2,            /* a HIP runtime call failed */
+  HK_ENOMEM = -3,          /* device allocation failed */
+  HK_NOT_CONVERGED = 1,    /* iteration cap reached; x holds the last iterate */
+  HK_BREAKDOWN = 2,        /* a BiCGStab scalar vanished; x holds the last iterate */
+  HK_NONFINITE = 3         /* Inf/NaN in the input or in an iteration scalar */
+};
+
+enum hk_dtype { HK_C128 = 0, HK_C64 = 1 };
+
+enum hk_csr_flags {
+  HK_VALIDATE = 1,   /* structure check at creation (always done) */
+  HK_AUTOTUNE = 2    /* time the SpMV launch shapes on this matrix and keep the fastest */
+};
+
+enum hk_breakdown { HK_BD_NONE = 0, HK_BD_RHO = 1, HK_BD_SIGMA = 2, HK_BD_TAU = 3, HK_BD_OMEGA = 4 };
+
+typedef struct hk_csr_s* hk_csr;
+
+/* Text of the last error raised on the calling thread ("" if none). */
+const char* hk_last_error(void);
+
+/* ------------------------------------------------------------ matrices */
+
+/*
+ * Wrap a CSR matrix that lives in caller-owned device memory (Section 2:
+ * FE matrices in CSR).  d_val holds nnz complex values of type dtype.  The
+ * buffers must stay valid and unchanged in layout while the handle lives;
+ * values may be updated between calls.  The structure is always checked on
+ * the device (rowptr non-decreasing from 0 to nnz, every col in [0, n) and
+ * strictly ascending within its row; HK_EINVAL otherwise), which also finds
+ * the longest row; this synchronises `stream` once.  HK_VALIDATE is
+ * accepted and implied.  HK_AUTOTUNE times the candidate launch shapes on
+ * this matrix (values are not modified) and keeps the fastest.
+ */
+int hk_csr_create(hk_csr* out, int64_t n, int64_t nnz, const int32_t* d_rowptr,
+                  const int32_t* d_col, const void* d_val, int dtype, int flags, void* stream);
+
+/* Release the handle and its workspace (not the caller's buffers). NULL is a no-op. */
+int hk_csr_destroy(hk_csr A);
+
+/* Launch shape chosen for the matrix: lanes per row, rows per lane group,
+ * workgroups per launch, and whether it was chosen by timing. */
+int hk_csr_plan(hk_csr A, int32_t* lanes_per_row, int32_t* rows_per_group, int32_t* grid,
+                int32_t* tuned);
+
+/* Override the launch shape (lanes_per_row in {4,8,16,32}, rows_per_group in
+ * {1,2,4}, grid > 0 or 0 for one workgroup per tile). */
+int hk_csr_set_plan(hk_csr A, int32_t lanes_per_row, int32_t rows_per_group, int32_t grid);
+
+/*
+ * y = alpha * A x + beta * y (Section 3, Table 8: CSR SpMV).  alpha and
+ * beta are host complex scalars {re, im} of A's precision (double[2] for
+ * complex128, float[2] for complex64); beta == 0 does not read y.  x and y
+ * have n entries and must not overlap.
+ */
+int hk_spmv(hk_csr A, const void* alpha, const void* d_x, const void* beta, void* d_y,
+            void* stream);
+
+/* r = b - A x (the residual of the refinement loop; complex128 or complex64). */
+int hk_residual(hk_csr A, const void* d_b, const void* d_x, void* d_r, void* stream);
+
+/* ------------------------------------------------ BLAS-1, complex128 */
+
+/* *d_res = x^H y = sum conj(x_i) y_i (Section 3, ZDOT: element-wise product,
+ * then a two-stage sum: per-workgroup partials, then their sum).  d_res is
+ * one complex128 in device memory.  Deterministic: the same bits on every
+ * call for the same n and data. */
+int hk_zdotc(int64_t n, const void* d_x, const void* d_y, void* d_res, void* stream);
+
+/* *d_res = x^T y = sum x_i y_i (unconjugated form of the same reduction). */
+int hk_zdotu(int64_t n, const void* d_x, const void* d_y, void* d_res, void* stream);
+
+/* *d_res = ||x||_2 = sqrt(sum re^2 + im^2) (Section 3, ZNORM); one double in device memory. */
+int hk_dznrm2(int64_t n, const void* d_x, double* d_res, void* stream);
+
+/* y = alpha x + y (Section 3, ZAXPY listing); alpha is a host double[2]. */
+int hk_zaxpy(int64_t n, const double* alpha, const void* d_x, void* d_y, void* stream);
+
+/* x = alpha x (Section 3, ZSCAL listing); alpha is a host double[2]. */
+int hk_zscal(int64_t n, const double* alpha, void* d_x, void* stream);
+
+/* y = x .* y (Section 3, element-wise product listing, ZAXMY). */
+int hk_zaxmy(int64_t n, const void* d_x, void* d_y, void* stream);
+
+/* y = x (Section 3, ZASSIGN). */
+int hk_zcopy(int64_t n, const void* d_x, void* d_y, void* stream);
+
+/* y = conj(x) (x == y allowed); used to form adjoint right-hand sides. */
+int hk_zconj(int64_t n, const void* d_x, void* d_y, void* stream);
+
+/* ------------------------------------------------------------- solvers */
+
+typedef struct {
+  double tol;            /* stop when ||b - A x||_2 <= tol * ||b||_2 (recursive residual) */
+  int64_t max_iter;      /* iteration cap (the paper uses 1000; larger FE systems need more) */
+  int32_t precond;       /* 0: none, 1: Jacobi (diagonal), applied on the right */
+  int32_t check_every;   /* iterations enqueued between host status reads (0: automatic) */
+  int32_t use_x0;        /* 0: start from x = 0 (the paper's choice), 1: from d_x */
+  int32_t reserved;
+  double* d_history;     /* optional device buffer of max_iter+1 doubles: ||r_k||/||b|| */
+} hk_solve_opts;
+
+typedef struct {
+  int64_t iters;         /* completed iterations (a half-step exit counts as one) */
+  double relres_rec;     /* recursive ||r|| / ||b|| at exit */
+  double relres_true;    /* ||b - A x|| / ||b|| recomputed at exit */
+  int32_t status;        /* HK_OK / HK_NOT_CONVERGED / HK_BREAKDOWN / HK_NONFINITE */
+  int32_t breakdown;     /* hk_breakdown: which scalar vanished */
+  int64_t inner_iters;   /* mixed precision: total inner iterations; else 0 */
+} hk_solve_info;
+
+/*
+ * Preconditioned BiCGStab on A x = b (Section 4: P-BiCGSTAB, zero initial
+ * guess, residual tolerance, iteration cap; Jacobi preconditioner on the
+ * right).  A must be complex128.  Scalars stay in device memory; the host
+ * reads a status word every check_every iterations and synchronises the
+ * stream once at the end to fill *info.  A zero diagonal entry with
+ * precond = 1 gives HK_EINVAL.  Returns info->status (>= 0) or an error.
+ * x always holds the last iterate.
+ */
+int hk_krylov_solve(hk_csr A, const void* d_b, void* d_x, const hk_solve_opts* opts,
+                    hk_solve_info* info, void* stream);
+
+/*
+ * Mixed-precision iterative refinement (not in the paper): r = b - A u, its
+ * norm, the stopping test ||r|| <= outer_tol ||b|| and the update u += d run
+ * in complex128; d solves A d = r with Jacobi BiCGStab in complex64 (values
+ * of A rounded to nearest per component, float accumulation) to inner_tol
+ * relative to ||r||.  At most max_outer cycles; a cycle that does not lower
+ * ||r|| ends the loop (HK_NOT_CONVERGED).  opts->max_iter caps each inner
+ * solve.  The complex64 copy of A is kept in the handle.
+ */
+int hk_krylov_solve_mixed(hk_csr A, const void* d_b, void* d_x, double inner_tol,
+                          double outer_tol, int32_t max_outer, const hk_solve_opts* opts,
+                          hk_solve_info* info, void* stream);
+
+/* ------------------------------------------------------ batched solves */
+
+/*
+ * Frequency sweep in one persistent launch (not in the paper; it batches the
+ * paper's P-BiCGSTAB over systems that share a sparsity pattern): for
+ * j < nsys (nsys <= 64), solve (K - kappa_j M) x_j = b_j with Jacobi
+ * BiCGStab, K and M real (double) CSR values on one pattern (d_rowptr,
+ * d_col, nnz entries), kappa a host array of nsys complex values
+ * {re, im}.  d_B and d_X are n x 64 complex128, interleaved system-fastest
+ * (entry (i, j) at index i*64 + j; columns j >= nsys are ignored).  x starts
+ * at 0.  opts->tol, max_iter apply to every system; infos receives nsys
+ * records.  Synchronises `stream`.  Returns the largest per-system status.
+ */
+int hk_sweep_solve(int64_t n, int64_t nnz, const int32_t* d_rowptr, const int32_t* d_col,
+                   const double* d_K, const double* d_M, int32_t nsys, const double* kappa,
+                   const void* d_B, void* d_X, const hk_solve_opts* opts, hk_solve_info* infos,
+                   void* stream);
+
+/*
+ * Uneven batch in one persistent launch: A (complex128) is block-diagonal
+ * with nsys <= 64 diagonal blocks; system k owns rows and columns
+ * [row_off[k], row_off[k+1]) (host array, row_off[0] = 0, row_off[nsys] =
+ * n).  Each system is solved with Jacobi BiCGStab from x = 0 to its own
+ * relative tolerance; systems that finish drop out of the work list.
+ * d_b, d_x: n complex128 (systems concatenated).  A column outside its
+ * row's system gives HK_EINVAL.  Synchronises `stream`.
+ */
+int hk_blockdiag_solve(hk_csr A, int32_t nsys, const int64_t* row_off, const void* d_b, void* d_x,
+                       const hk_solve_opts* opts, hk_solve_info* infos, void* stream);
+
+/* --------------------------------------------- operator and adjoint */
+
+/*
+ * Helmholtz matrix values for a piecewise-constant sound speed (the paper's
+ * operator -lap(u) - k^2 u with a speed that varies in space, Introduction):
+ *   val[p] = K[p] - omega^2 (1 + i damp) * sum_q bm_val[q] / c[bm_blk[q]]^2,
+ * q over [bm_ptr[p], bm_ptr[p+1]): the mass of entry p split by speed block
+ * (element masses of the elements of each block, Dirichlet entries
+ * removed).  d_K, d_bm_val, d_c: double; d_bm_ptr: nnz+1 int32 offsets into
+ * the nlist-long lists d_bm_blk (int32 block ids < nblocks) and d_bm_val;
+ * d_val: nnz complex128 (output).  Malformed lists give HK_EINVAL.
+ * Synchronises `stream` (error check).
+ */
+int hk_assemble_helmholtz(int64_t nnz, const double* d_K, const int32_t* d_bm_ptr,
+                          const int32_t* d_bm_blk, const double* d_bm_val, int64_t nlist,
+                          int32_t nblocks, const double* d_c, double omega, double damp,
+                          void* d_val, void* stream);
+
+/*
+ * Adjoint sensitivities of a real loss to the block speeds (not in the
+ * paper; differentiation of the operator above): with u = A(c)^-1 g and
+ * lambda solving A lambda = conj(dL/du) (A is complex symmetric, so this is
+ * the forward solver on the same matrix),
+ *   grad_c[b] = -Re( 2 omega^2 (1 + i damp) c_b^-3 sum_{e in b} lambda_e^T M_e u_e ),
+ * M_e the P1 element mass matrix vol_e/20 (1 + delta_ab) with Dirichlet
+ * nodes masked.  Elements of block b are d_tet_nodes[4*e .. 4*e+3] for e in
+ * [d_tet_ptr[b], d_tet_ptr[b+1]); d_tet_vol their volumes; d_dirichlet one
+ * byte per node (nonzero: Dirichlet).  d_lambda, d_u: n complex128;
+ * d_grad_c: nblocks doubles (output).  One workgroup per block, fixed
+ * summation order.  Synchronises `stream` (error checks).
+ */
+int hk_elem_sens(int64_t n, int64_t ntet, int32_t nblocks, const int32_t* d_tet_nodes,
+                 const int32_t* d_tet_ptr, const double* d_tet_vol, const uint8_t* d_dirichlet,
+                 const void* d_lambda, const void* d_u, const double* d_c, double omega,
+                 double damp, double* d_grad_c, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HK_H_ */

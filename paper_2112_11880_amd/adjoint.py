@@ -1,0 +1,102 @@
+"""torch.autograd.Function for u = A(c)^-1 g with the hand-written adjoint.
+
+A(c) = K - omega^2 (1 + i damp) sum_b c_b^-2 M_b is assembled by the library
+(hk_assemble_helmholtz), the forward solve is the library's Jacobi
+BiCGStab, and the backward pass solves A lambda = conj(grad_u) with the same
+solver on the same matrix (A is complex symmetric), returns
+grad_g = conj(lambda) and grad_c from hk_elem_sens.  grad_u and the returned
+gradients follow torch's convention for complex tensors
+(dL/dRe + i dL/dIm).  This module only marshals arguments.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import torch
+
+from . import hk as _hk
+
+
+def _declare():
+    return _hk.load()
+
+
+@dataclass
+class HelmholtzProblem:
+    """Device-resident description of the speed-dependent FE operator."""
+    rowptr: torch.Tensor      # int32 (n+1)
+    col: torch.Tensor         # int32 (nnz)
+    K: torch.Tensor           # float64 (nnz), Dirichlet rows carry 1 on the diagonal
+    bm_ptr: torch.Tensor      # int32 (nnz+1): per-entry lists of (block, mass)
+    bm_blk: torch.Tensor      # int32
+    bm_val: torch.Tensor      # float64
+    tet_nodes: torch.Tensor   # int32 (T, 4), grouped by block
+    tet_ptr: torch.Tensor     # int32 (nblocks+1)
+    tet_vol: torch.Tensor     # float64 (T)
+    dirichlet: torch.Tensor   # uint8 (n)
+    omega: float
+    damp: float = 0.01
+
+    @property
+    def n(self):
+        return self.rowptr.numel() - 1
+
+    @property
+    def nblocks(self):
+        return self.tet_ptr.numel() - 1
+
+
+def assemble(prob: HelmholtzProblem, c: torch.Tensor, out=None):
+    """Complex128 CSR values of A(c) (library kernel)."""
+    lib = _declare()
+    val = torch.empty(prob.col.numel(), dtype=torch.complex128, device=prob.col.device) if out is None else out
+    c = c.detach().contiguous()
+    _hk._check(lib.hk_assemble_helmholtz(prob.col.numel(), _hk._ptr(prob.K), _hk._ptr(prob.bm_ptr),
+                                         _hk._ptr(prob.bm_blk), _hk._ptr(prob.bm_val),
+                                         prob.bm_blk.numel(), prob.nblocks, _hk._ptr(c),
+                                         float(prob.omega), float(prob.damp), _hk._ptr(val),
+                                         _hk._stream()))
+    return val
+
+
+def elem_sens(prob: HelmholtzProblem, lam, u, c):
+    """dL/dc_b from the adjoint state (library kernel)."""
+    lib = _declare()
+    c = c.detach().contiguous()
+    out = torch.empty(prob.nblocks, dtype=torch.float64, device=c.device)
+    _hk._check(lib.hk_elem_sens(prob.n, prob.tet_nodes.shape[0], prob.nblocks, _hk._ptr(prob.tet_nodes),
+                                _hk._ptr(prob.tet_ptr), _hk._ptr(prob.tet_vol), _hk._ptr(prob.dirichlet),
+                                _hk._ptr(lam), _hk._ptr(u), _hk._ptr(c), float(prob.omega),
+                                float(prob.damp), _hk._ptr(out), _hk._stream()))
+    return out
+
+
+class HelmholtzSolve(torch.autograd.Function):
+    """u = A(c)^-1 g (Jacobi BiCGStab) with the adjoint backward pass."""
+
+    @staticmethod
+    def forward(ctx, g, c, prob: HelmholtzProblem, tol: float, max_iter: int):
+        val = assemble(prob, c)
+        A = _hk.CSR(prob.rowptr, prob.col, val)
+        u, info = _hk.krylov_solve(A, g.detach().contiguous(), tol=tol, max_iter=max_iter)
+        if info["status"] != _hk.HK_OK:
+            raise _hk.HKError(info["status"], f"forward solve did not converge: {info}")
+        ctx.A, ctx.prob, ctx.tol, ctx.max_iter = A, prob, tol, max_iter
+        ctx.info_forward = info
+        ctx.save_for_backward(c, u)
+        return u
+
+    @staticmethod
+    def backward(ctx, grad_u):
+        c, u = ctx.saved_tensors
+        rhs = _hk.zconj(grad_u.contiguous())
+        lam, info = _hk.krylov_solve(ctx.A, rhs, tol=ctx.tol, max_iter=ctx.max_iter)
+        if info["status"] != _hk.HK_OK:
+            raise _hk.HKError(info["status"], f"adjoint solve did not converge: {info}")
+        grad_g = _hk.zconj(lam) if ctx.needs_input_grad[0] else None
+        grad_c = elem_sens(ctx.prob, lam, u, c) if ctx.needs_input_grad[1] else None
+        return grad_g, grad_c, None, None, None
+
+
+def helmholtz_solve(g, c, prob: HelmholtzProblem, tol=1e-8, max_iter=400000):
+    return HelmholtzSolve.apply(g, c, prob, tol, max_iter)

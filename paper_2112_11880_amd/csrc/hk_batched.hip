@@ -1,0 +1,938 @@
+// hk_batched.hip -- batched Jacobi-BiCGStab in one persistent launch (gfx950).
+//
+// Two batch shapes, both solved by a single cooperative kernel that runs
+// every iteration of every system, with grid barriers between phases:
+//
+// (a) Frequency sweep: nsys <= 64 systems A_j = K - kappa_j M sharing one
+//     sparsity pattern, with K and M real.  Vectors are interleaved
+//     system-fastest (x[node][64]); lane j of every wave works on system j,
+//     so a gather of x[col] is one contiguous 1 KB access, the matrix row
+//     (col, K, M) is read once per wave for all systems, and each system's
+//     reduction terms stay in their own lane.  A_j is formed on the fly.
+// (b) Uneven systems: a block-diagonal CSR (systems concatenated, global
+//     indices) with per-system row ranges.  Rows are grouped in tiles that
+//     never straddle systems; phases walk the list of tiles of the systems
+//     still iterating, which is compacted whenever a system finishes.
+//
+// Jacobi is applied on the right through hatted vectors: phat = D^-1 p and
+// shat = D^-1 s are stored, s = D shat and D^-1 v are formed on the fly, and
+// x += alpha phat + omega shat.  Per-system scalars, statuses and iteration
+// counts live in device memory; the workgroup arriving last at a barrier
+// finishes the reductions (fixed order) and updates them.
+#include <algorithm>
+#include <vector>
+
+#include "hk_grid.hpp"
+#include "hk_internal.hpp"
+#include "hk_spmv.hpp"
+
+namespace hk {
+
+constexpr int kSys = 64;          // systems per launch (lanes of a wave)
+constexpr int kPB = 1024;         // threads per workgroup of the persistent kernels
+constexpr int kPW = kPB / kWave;  // waves per workgroup
+
+enum : int { B_RUN = 100, B_HALF = 101, B_TAUBD = 102 };
+
+struct BatchState {
+  double2 rho[kSys], rho_old[kSys], alpha[kSys], omega[kSys], beta[kSys];
+  double rr[kSys], ss[kSys], bb[kSys], theta2[kSys], rr_true[kSys];
+  int status[kSys], bd[kSys];
+  long long iters[kSys];
+  long long iter, maxit;
+  int running;
+  int changed;       // a system stopped in the last iteration (tile list to rebuild)
+  int ntiles_active;
+  int pad;
+};
+
+// ------------------------------------------------------------ shared helpers
+
+// v (this lane's NV partial sums, lane = system) summed over the waves of
+// the workgroup and stored at partials[(k*G + block)*64 + lane].
+template <int NV>
+__device__ __forceinline__ void store_partials64(const double (&v)[NV], double* partials, double* lds) {
+  const int w = threadIdx.x >> 6, j = threadIdx.x & 63, G = gridDim.x;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NV; ++k) lds[(k * kPW + w) * kSys + j] = v[k];
+  __syncthreads();
+  if (w == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      double s = 0;
+      for (int u = 0; u < kPW; ++u) s += lds[(k * kPW + u) * kSys + j];
+      partials[((size_t)k * G + blockIdx.x) * kSys + j] = s;
+    }
+  }
+}
+
+// Second stage: out[k] (valid in threads 0..63, thread j = system j) = sum
+// over workgroups in a fixed order.
+template <int NV>
+__device__ __forceinline__ void final_partials64(const double* partials, double (&out)[NV], double* lds) {
+  const int j = threadIdx.x & 63, g = threadIdx.x >> 6, G = gridDim.x;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double s = 0;
+    for (int b = g; b < G; b += kPW) s += partials[((size_t)k * G + b) * kSys + j];
+    lds[(k * kPW + g) * kSys + j] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < kSys) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      double s = 0;
+      for (int u = 0; u < kPW; ++u) s += lds[(k * kPW + u) * kSys + j];
+      out[k] = s;
+    }
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ double2 crecip(double2 d) { return cdiv(make_double2(1.0, 0.0), d); }
+
+// Scalar updates shared by both batch shapes (thread j = system j).
+__device__ __forceinline__ void upd_sigma(BatchState* st, int j, double2 sigma) {
+  if (st->status[j] != B_RUN) return;
+  if (!cfinite(sigma)) {
+    st->status[j] = HK_NONFINITE; st->iters[j] = st->iter - 1; st->changed = 1;
+  } else if (sigma.x == 0 && sigma.y == 0) {
+    st->status[j] = HK_BREAKDOWN; st->bd[j] = HK_BD_SIGMA; st->iters[j] = st->iter - 1; st->changed = 1;
+  } else {
+    st->alpha[j] = cdiv(st->rho[j], sigma);
+  }
+}
+__device__ __forceinline__ void upd_s(BatchState* st, int j, double ss) {
+  if (st->status[j] != B_RUN) return;
+  st->ss[j] = ss;
+  if (!isfinite(ss)) { st->status[j] = HK_NONFINITE; st->iters[j] = st->iter - 1; st->changed = 1; }
+  else if (ss <= st->theta2[j]) st->status[j] = B_HALF;
+}
+__device__ __forceinline__ void upd_omega(BatchState* st, int j, double tau, double2 ts) {
+  if (st->status[j] != B_RUN) return;
+  if (!isfinite(tau) || !cfinite(ts)) { st->status[j] = HK_NONFINITE; st->iters[j] = st->iter - 1; st->changed = 1; }
+  else if (tau == 0) st->status[j] = B_TAUBD;
+  else st->omega[j] = make_double2(ts.x / tau, ts.y / tau);
+}
+// end of an iteration; returns 1 if system j is still running afterwards
+__device__ __forceinline__ int upd_xr(BatchState* st, int j, double rr, double2 rho) {
+  const int s = st->status[j];
+  const long long it = st->iter;
+  if (s == B_HALF) {
+    st->status[j] = HK_OK; st->rr[j] = st->ss[j]; st->iters[j] = it; st->changed = 1; return 0;
+  }
+  if (s == B_TAUBD) {
+    st->status[j] = HK_BREAKDOWN; st->bd[j] = HK_BD_TAU; st->rr[j] = st->ss[j]; st->iters[j] = it;
+    st->changed = 1; return 0;
+  }
+  if (s != B_RUN) return 0;
+  st->rr[j] = rr;
+  st->rho_old[j] = st->rho[j];
+  st->rho[j] = rho;
+  st->iters[j] = it;
+  const double2 om = st->omega[j];
+  int next = B_RUN;
+  if (!isfinite(rr) || !cfinite(rho)) next = HK_NONFINITE;
+  else if (rr <= st->theta2[j]) next = HK_OK;
+  else if (om.x == 0 && om.y == 0) { next = HK_BREAKDOWN; st->bd[j] = HK_BD_OMEGA; }
+  else if (rho.x == 0 && rho.y == 0) { next = HK_BREAKDOWN; st->bd[j] = HK_BD_RHO; }
+  else if (it >= st->maxit) next = HK_NOT_CONVERGED;
+  if (next != B_RUN) { st->status[j] = next; st->changed = 1; return 0; }
+  st->beta[j] = cmul(cdiv(rho, st->rho_old[j]), cdiv(st->alpha[j], om));
+  return 1;
+}
+__device__ __forceinline__ void init_sys(BatchState* st, int j, double bb, double tol, long long maxit) {
+  st->bb[j] = bb; st->rr[j] = bb; st->theta2[j] = tol * tol * bb;
+  st->rho[j] = make_double2(bb, 0); st->rho_old[j] = make_double2(1, 0);
+  st->alpha[j] = make_double2(1, 0); st->omega[j] = make_double2(1, 0);
+  st->beta[j] = make_double2(0, 0); st->iters[j] = 0; st->bd[j] = HK_BD_NONE; st->rr_true[j] = 0;
+  if (!isfinite(bb)) st->status[j] = HK_NONFINITE;
+  else if (bb == 0 || bb <= st->theta2[j]) st->status[j] = HK_OK;
+  else if (maxit <= 0) st->status[j] = HK_NOT_CONVERGED;
+  else st->status[j] = B_RUN;
+}
+
+// =============================================================== (a) sweep
+
+struct SweepArgs {
+  int n, nsys;
+  const int* rowptr;
+  const int* col;
+  const double* K;
+  const double* M;
+  const double* kd;   // diag(K)
+  const double* md;   // diag(M)
+  const double2* kap; // kappa_j (nsys entries)
+  const double2* B;   // n x 64, interleaved
+  double2* X;
+  double2 *R, *RH, *PH, *V, *SH, *T;
+  double* partials;
+  BatchState* st;
+  GridBar* bar;
+  double tol;
+  long long maxit;
+};
+
+__device__ __forceinline__ double2 sweep_diag(const SweepArgs& a, int i, double2 kap) {
+  const double k = a.kd[i], m = a.md[i];
+  return make_double2(k - kap.x * m, -kap.y * m);
+}
+
+// y[row][j] = sum_q (K_q - kap_j M_q) src[col_q][j] for this wave's rows;
+// EPI 1: part += conj(RH) y ; EPI 2: part += |y|^2, conj(y) (d .* SH) ;
+// EPI 3: y = B - A src, part += |y|^2 (true residual).
+template <int EPI, int NV>
+__device__ __forceinline__ void sweep_spmv(const SweepArgs& a, int r0, int r1, const double2* src,
+                                           double2* dst, bool act, double2 kap, double (&part)[NV]) {
+  const int j = threadIdx.x & 63;
+  for (int row = r0; row < r1; ++row) {
+    const int s = a.rowptr[row], e = a.rowptr[row + 1];
+    double2 acc = make_double2(0, 0);
+    int q = s;
+    for (; q + 4 <= e; q += 4) {
+      int c[4];
+      double kv[4], mv[4];
+      double2 xv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) { c[u] = a.col[q + u]; kv[u] = a.K[q + u]; mv[u] = a.M[q + u]; }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) xv[u] = act ? src[(size_t)c[u] * kSys + j] : make_double2(0, 0);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc = cfma(make_double2(kv[u] - kap.x * mv[u], -kap.y * mv[u]), xv[u], acc);
+    }
+    for (; q < e; ++q) {
+      const int c = a.col[q];
+      const double2 xv = act ? src[(size_t)c * kSys + j] : make_double2(0, 0);
+      acc = cfma(make_double2(a.K[q] - kap.x * a.M[q], -kap.y * a.M[q]), xv, acc);
+    }
+    if (!act) continue;
+    const size_t o = (size_t)row * kSys + j;
+    if (EPI == 3) {
+      const double2 rt = csub(a.B[o], acc);
+      part[0] += cabs2(rt);
+      continue;
+    }
+    dst[o] = acc;
+    if (EPI == 1) {
+      const double2 h = a.RH[o];
+      part[0] = fma(h.x, acc.x, fma(h.y, acc.y, part[0]));
+      part[1] = fma(h.x, acc.y, fma(-h.y, acc.x, part[1]));
+    } else if (EPI == 2) {
+      const double2 sv = cmul(sweep_diag(a, row, kap), a.SH[o]);
+      part[0] = fma(acc.x, acc.x, fma(acc.y, acc.y, part[0]));
+      part[1] = fma(acc.x, sv.x, fma(acc.y, sv.y, part[1]));
+      part[2] = fma(acc.x, sv.y, fma(-acc.y, sv.x, part[2]));
+    }
+  }
+}
+
+__global__ __launch_bounds__(kPB) void k_sweep(SweepArgs a) {
+  __shared__ double lds[4 * kPW * kSys];
+  BatchState* st = a.st;
+  const int j = threadIdx.x & 63;
+  const int G = gridDim.x;
+  const int wid = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, G) * kPW + (threadIdx.x >> 6));
+  const int W = G * kPW;
+  const int r0 = (int)(((long long)wid * a.n) / W), r1 = (int)(((long long)(wid + 1) * a.n) / W);
+  const bool lane_ok = j < a.nsys;
+  const double2 kap = lane_ok ? a.kap[j] : make_double2(0, 0);
+
+  // ---- start: r = rhat = b, phat = D^-1 b, x = 0
+  {
+    double part[1] = {0};
+    for (int row = r0; row < r1; ++row) {
+      const size_t o = (size_t)row * kSys + j;
+      if (!lane_ok) continue;
+      const double2 b = a.B[o];
+      a.R[o] = b; a.RH[o] = b;
+      a.PH[o] = cmul(crecip(sweep_diag(a, row, kap)), b);
+      a.X[o] = make_double2(0, 0);
+      part[0] += cabs2(b);
+    }
+    store_partials64<1>(part, a.partials, lds);
+    if (barrier_last(a.bar, [&] {
+          double tot[1];
+          final_partials64<1>(a.partials, tot, lds);
+          if (threadIdx.x < kSys) {
+            if (threadIdx.x < a.nsys) init_sys(st, threadIdx.x, tot[0], a.tol, a.maxit);
+            else st->status[threadIdx.x] = HK_OK;
+          }
+          if (threadIdx.x == 0) { st->iter = 1; st->maxit = a.maxit; st->changed = 0; }
+          __syncthreads();
+          if (threadIdx.x == 0) {
+            int run = 0;
+            for (int u = 0; u < a.nsys; ++u) run += st->status[u] == B_RUN;
+            st->running = run;
+          }
+        }))
+      return;
+  }
+
+  while (st->running > 0) {
+    const long long it = st->iter;
+    bool act = lane_ok && st->status[j] == B_RUN;
+    // ---- phat = D^-1 (r - beta omega v) + beta phat
+    if (it > 1) {
+      const double2 beta = st->beta[j], bo = cmul(st->beta[j], st->omega[j]);
+      for (int row = r0; row < r1 && act; ++row) {
+        const size_t o = (size_t)row * kSys + j;
+        const double2 w = csub(a.R[o], cmul(bo, a.V[o]));
+        a.PH[o] = cfma(beta, a.PH[o], cmul(crecip(sweep_diag(a, row, kap)), w));
+      }
+      if (barrier_last(a.bar, [] {})) return;
+    }
+    // ---- v = A phat ; sigma = rhat^H v
+    {
+      double part[2] = {0, 0};
+      sweep_spmv<1, 2>(a, r0, r1, a.PH, a.V, act, kap, part);
+      store_partials64<2>(part, a.partials, lds);
+      if (barrier_last(a.bar, [&] {
+            double tot[2];
+            final_partials64<2>(a.partials, tot, lds);
+            if (threadIdx.x < a.nsys) upd_sigma(st, threadIdx.x, make_double2(tot[0], tot[1]));
+          }))
+        return;
+    }
+    act = lane_ok && st->status[j] == B_RUN;
+    // ---- s = r - alpha v ; shat = D^-1 s ; ||s||^2
+    {
+      double part[1] = {0};
+      const double2 alpha = st->alpha[j];
+      for (int row = r0; row < r1 && act; ++row) {
+        const size_t o = (size_t)row * kSys + j;
+        const double2 s = csub(a.R[o], cmul(alpha, a.V[o]));
+        a.SH[o] = cmul(crecip(sweep_diag(a, row, kap)), s);
+        part[0] += cabs2(s);
+      }
+      store_partials64<1>(part, a.partials, lds);
+      if (barrier_last(a.bar, [&] {
+            double tot[1];
+            final_partials64<1>(a.partials, tot, lds);
+            if (threadIdx.x < a.nsys) upd_s(st, threadIdx.x, tot[0]);
+          }))
+        return;
+    }
+    act = lane_ok && st->status[j] == B_RUN;
+    // ---- t = A shat ; tau = t^H t ; t^H s
+    {
+      double part[3] = {0, 0, 0};
+      sweep_spmv<2, 3>(a, r0, r1, a.SH, a.T, act, kap, part);
+      store_partials64<3>(part, a.partials, lds);
+      if (barrier_last(a.bar, [&] {
+            double tot[3];
+            final_partials64<3>(a.partials, tot, lds);
+            if (threadIdx.x < a.nsys) upd_omega(st, threadIdx.x, tot[0], make_double2(tot[1], tot[2]));
+          }))
+        return;
+    }
+    // ---- x += alpha phat + omega shat ; r = s - omega t ; ||r||^2 ; rhat^H r
+    {
+      const int sj = lane_ok ? st->status[j] : HK_OK;
+      double part[3] = {0, 0, 0};
+      const double2 alpha = st->alpha[j], omega = st->omega[j];
+      if (sj == B_RUN) {
+        for (int row = r0; row < r1; ++row) {
+          const size_t o = (size_t)row * kSys + j;
+          const double2 sh = a.SH[o];
+          a.X[o] = cfma(omega, sh, cfma(alpha, a.PH[o], a.X[o]));
+          const double2 r = csub(cmul(sweep_diag(a, row, kap), sh), cmul(omega, a.T[o]));
+          a.R[o] = r;
+          part[0] += cabs2(r);
+          const double2 h = a.RH[o];
+          part[1] = fma(h.x, r.x, fma(h.y, r.y, part[1]));
+          part[2] = fma(h.x, r.y, fma(-h.y, r.x, part[2]));
+        }
+      } else if (sj == B_HALF || sj == B_TAUBD) {
+        for (int row = r0; row < r1; ++row) {
+          const size_t o = (size_t)row * kSys + j;
+          a.X[o] = cfma(alpha, a.PH[o], a.X[o]);
+        }
+      }
+      store_partials64<3>(part, a.partials, lds);
+      if (barrier_last(a.bar, [&] {
+            double tot[3];
+            final_partials64<3>(a.partials, tot, lds);
+            __shared__ int s_run[kSys];
+            if (threadIdx.x < kSys)
+              s_run[threadIdx.x] = threadIdx.x < a.nsys
+                                       ? upd_xr(st, threadIdx.x, tot[0], make_double2(tot[1], tot[2]))
+                                       : 0;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+              int run = 0;
+              for (int u = 0; u < kSys; ++u) run += s_run[u];
+              st->running = run;
+              st->iter = st->iter + 1;
+            }
+          }))
+        return;
+    }
+  }
+  // ---- true residual ||b - A x||^2 per system
+  {
+    double part[1] = {0};
+    sweep_spmv<3, 1>(a, r0, r1, a.X, nullptr, lane_ok, kap, part);
+    store_partials64<1>(part, a.partials, lds);
+    barrier_last(a.bar, [&] {
+      double tot[1];
+      final_partials64<1>(a.partials, tot, lds);
+      if (threadIdx.x < a.nsys) st->rr_true[threadIdx.x] = tot[0];
+    });
+  }
+}
+
+// ======================================================= (b) block-diagonal
+
+struct BdArgs {
+  int n, nsys, L;
+  const int* rowptr;
+  const int* col;
+  const double2* val;
+  const double2* d;      // diag(A)
+  const double2* dinv;   // 1 / diag(A)
+  const double2* B;
+  double2* X;
+  double2 *R, *RH, *PH, *V, *SH, *T;
+  const int* tsys;       // static tile -> system
+  const int* trow;       // static tile -> first row
+  const int* sys_end;    // system -> one past its last row
+  const int* sys_tile0;  // system -> first static tile (nsys+1 entries)
+  int* active;           // active tile list (static tile ids)
+  double* partials;
+  BatchState* st;
+  GridBar* bar;
+  double tol;
+  long long maxit;
+  int tile_rows;
+};
+
+// Flush the workgroup's running sums of the current system into the LDS
+// per-system accumulators (thread 0 adds; uniform call).
+template <int NV>
+__device__ __forceinline__ void bd_flush(double (&acc)[NV], int sys, double* red, double* sysacc) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) acc[k] = wave_sum(acc[k]);
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) red[k * kPW + w] = acc[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && sys >= 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      double s = 0;
+      for (int u = 0; u < kPW; ++u) s += red[k * kPW + u];
+      sysacc[k * kSys + sys] += s;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NV; ++k) acc[k] = 0;
+}
+
+// Walk this workgroup's share of the active tiles.  For each tile, f(row,
+// lane_in_group, group, sys, acc) handles rows of the tile; per-system sums
+// end in partials[(k*G + block)*64 + sys].
+template <int NV, class F>
+__device__ __forceinline__ void bd_phase(const BdArgs& a, double* lds, F&& f) {
+  double* red = lds;                    // NV * kPW
+  double* sysacc = lds + 4 * kPW;       // NV * 64
+  const int G = gridDim.x;
+  const int lb = xcd_block(blockIdx.x, G);
+  const int na = a.st->ntiles_active;
+  const int t0 = (int)(((long long)lb * na) / G), t1 = (int)(((long long)(lb + 1) * na) / G);
+  for (int k = threadIdx.x; k < NV * kSys; k += kPB) sysacc[k] = 0;
+  double acc[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) acc[k] = 0;
+  int cur = -1;
+  for (int t = t0; t < t1; ++t) {
+    const int tile = a.active[t];
+    const int sys = a.tsys[tile];
+    if (sys != cur) {
+      if (cur >= 0) bd_flush<NV>(acc, cur, red, sysacc);
+      cur = sys;
+    }
+    f(tile, sys, acc);
+  }
+  bd_flush<NV>(acc, cur, red, sysacc);
+  __syncthreads();
+  for (int k = threadIdx.x; k < NV * kSys; k += kPB) {
+    const int kk = k / kSys, s = k % kSys;
+    a.partials[((size_t)kk * G + blockIdx.x) * kSys + s] = sysacc[k];
+  }
+}
+
+// Row sums of the kPB rows of a tile, kPB / L rows at a time (one L-lane
+// group per row); each sum goes to callback g(row, acc) on the group's
+// first lane.
+template <int L, class G2>
+__device__ __forceinline__ void bd_tile_spmv(const BdArgs& a, int tile, const double2* src, G2&& g) {
+  const int grp = threadIdx.x / L, lane = threadIdx.x & (L - 1);
+  const int end = a.sys_end[a.tsys[tile]];
+  const int base = a.trow[tile];
+  for (int sub = 0; sub < L; ++sub) {
+    const int row = base + sub * (kPB / L) + grp;
+    if (base + sub * (kPB / L) >= end) break;
+    double2 acc[1];
+    csr_rows<L, 1, double2>(row, end, a.rowptr, a.col, a.val, src, acc);
+    if (lane == 0 && row < end) g(row, acc[0]);
+  }
+}
+
+template <int L>
+__global__ __launch_bounds__(kPB) void k_blockdiag(BdArgs a) {
+  __shared__ double lds[4 * kPW + 4 * kSys + 4 * kPW * kSys];
+  double* fin = lds + 4 * kPW + 4 * kSys;
+  BatchState* st = a.st;
+  const int TR = kPB;  // rows per tile: one per thread in the element-wise phases
+
+  // rebuild the active tile list from the statuses (last workgroup only)
+  auto rebuild = [&] {
+    __shared__ int s_off[kSys + 1];
+    if (threadIdx.x == 0) {
+      int off = 0;
+      for (int s = 0; s < a.nsys; ++s) {
+        s_off[s] = off;
+        if (st->status[s] == B_RUN) off += a.sys_tile0[s + 1] - a.sys_tile0[s];
+      }
+      s_off[a.nsys] = off;
+      st->ntiles_active = off;
+      st->changed = 0;
+    }
+    __syncthreads();
+    for (int s = 0; s < a.nsys; ++s) {
+      if (st->status[s] != B_RUN) continue;
+      const int base = s_off[s], t0 = a.sys_tile0[s], cnt = a.sys_tile0[s + 1] - t0;
+      for (int k = threadIdx.x; k < cnt; k += kPB) a.active[base + k] = t0 + k;
+    }
+  };
+
+  // ---- start: r = rhat = b, phat = D^-1 b, x = 0 (all tiles are active)
+  bd_phase<1>(a, lds, [&](int tile, int sys, double(&acc)[1]) {
+    const int row = a.trow[tile] + threadIdx.x;
+    if (threadIdx.x < TR && row < a.sys_end[sys]) {
+      const double2 b = a.B[row];
+      a.R[row] = b; a.RH[row] = b; a.PH[row] = cmul(a.dinv[row], b); a.X[row] = make_double2(0, 0);
+      acc[0] += cabs2(b);
+    }
+  });
+  if (barrier_last(a.bar, [&] {
+        double tot[1];
+        final_partials64<1>(a.partials, tot, fin);
+        if (threadIdx.x < a.nsys) init_sys(st, threadIdx.x, tot[0], a.tol, a.maxit);
+        if (threadIdx.x == 0) { st->iter = 1; st->maxit = a.maxit; }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+          int run = 0;
+          for (int u = 0; u < a.nsys; ++u) run += st->status[u] == B_RUN;
+          st->running = run;
+        }
+        __syncthreads();
+        rebuild();
+      }))
+    return;
+
+  while (st->running > 0) {
+    const long long it = st->iter;
+    if (it > 1) {
+      bd_phase<1>(a, lds, [&](int tile, int sys, double(&)[1]) {
+        const int row = a.trow[tile] + threadIdx.x;
+        if (threadIdx.x < TR && row < a.sys_end[sys]) {
+          const double2 beta = st->beta[sys], bo = cmul(beta, st->omega[sys]);
+          const double2 w = csub(a.R[row], cmul(bo, a.V[row]));
+          a.PH[row] = cfma(beta, a.PH[row], cmul(a.dinv[row], w));
+        }
+      });
+      if (barrier_last(a.bar, [] {})) return;
+    }
+    // v = A phat ; sigma
+    bd_phase<2>(a, lds, [&](int tile, int sys, double(&acc)[2]) {
+      bd_tile_spmv<L>(a, tile, a.PH, [&](int row, double2 v) {
+        a.V[row] = v;
+        const double2 h = a.RH[row];
+        acc[0] = fma(h.x, v.x, fma(h.y, v.y, acc[0]));
+        acc[1] = fma(h.x, v.y, fma(-h.y, v.x, acc[1]));
+      });
+    });
+    if (barrier_last(a.bar, [&] {
+          double tot[2];
+          final_partials64<2>(a.partials, tot, fin);
+          if (threadIdx.x < a.nsys) upd_sigma(st, threadIdx.x, make_double2(tot[0], tot[1]));
+        }))
+      return;
+    // s = r - alpha v ; shat ; ||s||^2
+    bd_phase<1>(a, lds, [&](int tile, int sys, double(&acc)[1]) {
+      const int row = a.trow[tile] + threadIdx.x;
+      if (threadIdx.x < TR && row < a.sys_end[sys] && st->status[sys] == B_RUN) {
+        const double2 s = csub(a.R[row], cmul(st->alpha[sys], a.V[row]));
+        a.SH[row] = cmul(a.dinv[row], s);
+        acc[0] += cabs2(s);
+      }
+    });
+    if (barrier_last(a.bar, [&] {
+          double tot[1];
+          final_partials64<1>(a.partials, tot, fin);
+          if (threadIdx.x < a.nsys) upd_s(st, threadIdx.x, tot[0]);
+        }))
+      return;
+    // t = A shat ; tau ; t^H s
+    bd_phase<3>(a, lds, [&](int tile, int sys, double(&acc)[3]) {
+      if (st->status[sys] != B_RUN) return;
+      bd_tile_spmv<L>(a, tile, a.SH, [&](int row, double2 t) {
+        a.T[row] = t;
+        const double2 s = cmul(a.d[row], a.SH[row]);
+        acc[0] = fma(t.x, t.x, fma(t.y, t.y, acc[0]));
+        acc[1] = fma(t.x, s.x, fma(t.y, s.y, acc[1]));
+        acc[2] = fma(t.x, s.y, fma(-t.y, s.x, acc[2]));
+      });
+    });
+    if (barrier_last(a.bar, [&] {
+          double tot[3];
+          final_partials64<3>(a.partials, tot, fin);
+          if (threadIdx.x < a.nsys) upd_omega(st, threadIdx.x, tot[0], make_double2(tot[1], tot[2]));
+        }))
+      return;
+    // x, r updates ; ||r||^2 ; rhat^H r
+    bd_phase<3>(a, lds, [&](int tile, int sys, double(&acc)[3]) {
+      const int row = a.trow[tile] + threadIdx.x;
+      if (threadIdx.x >= TR || row >= a.sys_end[sys]) return;
+      const int ss = st->status[sys];
+      const double2 alpha = st->alpha[sys], omega = st->omega[sys];
+      if (ss == B_RUN) {
+        const double2 sh = a.SH[row];
+        a.X[row] = cfma(omega, sh, cfma(alpha, a.PH[row], a.X[row]));
+        const double2 r = csub(cmul(a.d[row], sh), cmul(omega, a.T[row]));
+        a.R[row] = r;
+        acc[0] += cabs2(r);
+        const double2 h = a.RH[row];
+        acc[1] = fma(h.x, r.x, fma(h.y, r.y, acc[1]));
+        acc[2] = fma(h.x, r.y, fma(-h.y, r.x, acc[2]));
+      } else if (ss == B_HALF || ss == B_TAUBD) {
+        a.X[row] = cfma(alpha, a.PH[row], a.X[row]);
+      }
+    });
+    if (barrier_last(a.bar, [&] {
+          double tot[3];
+          final_partials64<3>(a.partials, tot, fin);
+          __shared__ int s_run[kSys];
+          if (threadIdx.x < kSys)
+            s_run[threadIdx.x] = threadIdx.x < a.nsys
+                                     ? upd_xr(st, threadIdx.x, tot[0], make_double2(tot[1], tot[2]))
+                                     : 0;
+          __syncthreads();
+          if (threadIdx.x == 0) {
+            int run = 0;
+            for (int u = 0; u < kSys; ++u) run += s_run[u];
+            st->running = run;
+            st->iter = st->iter + 1;
+          }
+          __syncthreads();
+          if (st->changed) rebuild();
+        }))
+      return;
+  }
+  // true residual: all tiles
+  if (barrier_last(a.bar, [&] {
+        if (threadIdx.x == 0) st->ntiles_active = a.sys_tile0[a.nsys];
+        __syncthreads();
+        for (int k = threadIdx.x; k < a.sys_tile0[a.nsys]; k += kPB) a.active[k] = k;
+      }))
+    return;
+  bd_phase<1>(a, lds, [&](int tile, int sys, double(&acc)[1]) {
+    bd_tile_spmv<L>(a, tile, a.X, [&](int row, double2 ax) {
+      acc[0] += cabs2(csub(a.B[row], ax));
+    });
+  });
+  barrier_last(a.bar, [&] {
+    double tot[1];
+    final_partials64<1>(a.partials, tot, fin);
+    if (threadIdx.x < a.nsys) st->rr_true[threadIdx.x] = tot[0];
+  });
+}
+
+// ------------------------------------------------------------- set-up kernels
+
+__global__ void k_real_diag(int n, const int* __restrict__ rowptr, const int* __restrict__ col,
+                            const double* __restrict__ K, const double* __restrict__ M,
+                            double* kd, double* md) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  double k = 0, m = 0;
+  for (int p = rowptr[i]; p < rowptr[i + 1]; ++p)
+    if (col[p] == i) { k += K[p]; m += M[p]; }
+  kd[i] = k;
+  md[i] = m;
+}
+
+// zero diagonal for some lane -> flag
+__global__ void k_sweep_diag_check(int n, int nsys, const double* kd, const double* md,
+                                   const double2* kap, int* flag) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  for (int j = 0; j < nsys; ++j) {
+    const double re = kd[i] - kap[j].x * md[i], im = -kap[j].y * md[i];
+    if (re == 0 && im == 0) { atomicOr(flag, 1); return; }
+  }
+}
+
+// d, dinv of a complex CSR; flag[0] |= 1 on a zero diagonal; flag[0] |= 2 if
+// a row has a column outside its system's row range.
+__global__ void k_bd_diag(int n, const int* __restrict__ rowptr, const int* __restrict__ col,
+                          const double2* __restrict__ val, const int* __restrict__ sys_of_row,
+                          const int* __restrict__ sys_begin, const int* __restrict__ sys_end,
+                          double2* d, double2* dinv, int* flag) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const int s = sys_of_row[i];
+  const int lo = sys_begin[s], hi = sys_end[s];
+  double2 dd = make_double2(0, 0);
+  for (int p = rowptr[i]; p < rowptr[i + 1]; ++p) {
+    const int c = col[p];
+    if (c < lo || c >= hi) atomicOr(flag, 2);
+    if (c == i) dd = cadd(dd, val[p]);
+  }
+  if (dd.x == 0 && dd.y == 0) { atomicOr(flag, 1); dinv[i] = make_double2(0, 0); }
+  else dinv[i] = cdiv(make_double2(1, 0), dd);
+  d[i] = dd;
+}
+
+// ----------------------------------------------------------------- host side
+
+static size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Arena {
+  char* base = nullptr;
+  size_t off = 0;
+  template <class T> T* take(size_t count) {
+    T* p = (T*)(base + off);
+    off += a256(sizeof(T) * (count > 0 ? count : 1));
+    return p;
+  }
+};
+
+static int coop_grid(const void* kernel, int* grid) {
+  int dev = 0, cus = 0, per = 0, coop = 0;
+  HK_HIP(hipGetDevice(&dev));
+  HK_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  HK_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+  if (!coop) HK_FAIL(HK_EHIP, "device does not support cooperative launches");
+  HK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, kPB, 0));
+  if (per < 1) HK_FAIL(HK_EHIP, "persistent kernel does not fit on a CU");
+  *grid = cus * std::min(per, 2);
+  return HK_OK;
+}
+
+static void fill_infos(const BatchState& hs, int nsys, hk_solve_info* infos) {
+  for (int j = 0; j < nsys; ++j) {
+    hk_solve_info& in = infos[j];
+    const int s = hs.status[j];
+    in.status = s >= B_RUN ? HK_NOT_CONVERGED : s;
+    in.breakdown = hs.bd[j];
+    in.iters = hs.iters[j];
+    const double bb = hs.bb[j];
+    in.relres_rec = bb > 0 ? std::sqrt(hs.rr[j] / bb) : std::sqrt(hs.rr[j]);
+    in.relres_true = bb > 0 ? std::sqrt(hs.rr_true[j] / bb) : std::sqrt(hs.rr_true[j]);
+    in.inner_iters = 0;
+  }
+}
+
+static int worst_status(const hk_solve_info* infos, int nsys) {
+  int w = HK_OK;
+  for (int j = 0; j < nsys; ++j) w = std::max(w, infos[j].status);
+  return w;
+}
+
+}  // namespace hk
+
+using namespace hk;
+
+extern "C" int hk_sweep_solve(int64_t n, int64_t nnz, const int32_t* d_rowptr, const int32_t* d_col,
+                              const double* d_K, const double* d_M, int32_t nsys,
+                              const double* kappa, const void* d_B, void* d_X,
+                              const hk_solve_opts* opts, hk_solve_info* infos, void* stream) {
+  if (!d_rowptr || !d_col || !d_K || !d_M || !kappa || !d_B || !d_X || !opts || !infos)
+    HK_FAIL(HK_EINVAL, "hk_sweep_solve: null argument");
+  if (nsys < 1 || nsys > kSys) HK_FAIL(HK_EINVAL, "hk_sweep_solve: nsys must be in [1, 64]");
+  if (!(opts->tol >= 0) || opts->max_iter < 0) HK_FAIL(HK_EINVAL, "hk_sweep_solve: bad options");
+  hipStream_t s = as_stream(stream);
+  // structure check through a temporary handle (real values are not read)
+  hk_csr A = nullptr;
+  int rc = hk_csr_create(&A, n, nnz, d_rowptr, d_col, d_K, HK_C128, 0, stream);
+  if (rc != HK_OK) return rc;
+  (void)hk_csr_destroy(A);
+  int grid = 0;
+  rc = coop_grid((const void*)k_sweep, &grid);
+  if (rc != HK_OK) return rc;
+  const size_t vec = (size_t)n * kSys;
+  Arena ar;
+  const size_t bytes = 6 * a256(16 * vec) + 2 * a256(8 * n) + a256(16 * kSys) +
+                       a256(8 * 4 * (size_t)grid * kSys) + a256(sizeof(BatchState)) + a256(sizeof(GridBar)) +
+                       a256(64);
+  if (hipMalloc((void**)&ar.base, bytes) != hipSuccess) HK_FAIL(HK_ENOMEM, "hk_sweep_solve: hipMalloc(%zu)", bytes);
+  SweepArgs a{};
+  a.n = (int)n; a.nsys = nsys; a.rowptr = d_rowptr; a.col = d_col; a.K = d_K; a.M = d_M;
+  a.R = ar.take<double2>(vec); a.RH = ar.take<double2>(vec); a.PH = ar.take<double2>(vec);
+  a.V = ar.take<double2>(vec); a.SH = ar.take<double2>(vec); a.T = ar.take<double2>(vec);
+  double* kd = ar.take<double>(n);
+  double* md = ar.take<double>(n);
+  double2* kap = ar.take<double2>(kSys);
+  a.partials = ar.take<double>(4 * (size_t)grid * kSys);
+  a.st = ar.take<BatchState>(1);
+  a.bar = ar.take<GridBar>(1);
+  int* flag = ar.take<int>(16);
+  a.kd = kd; a.md = md; a.kap = kap;
+  a.B = (const double2*)d_B; a.X = (double2*)d_X;
+  a.tol = opts->tol; a.maxit = opts->max_iter;
+  std::vector<double2> hk(kSys, make_double2(0, 0));
+  for (int j = 0; j < nsys; ++j) hk[j] = make_double2(kappa[2 * j], kappa[2 * j + 1]);
+  int hflag = 0;
+  hipError_t e = hipMemcpyAsync(kap, hk.data(), 16 * kSys, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemsetAsync(a.bar, 0, sizeof(GridBar), s);
+  if (e == hipSuccess) e = hipMemsetAsync(flag, 0, 64, s);
+  if (e == hipSuccess) e = hipMemsetAsync(a.st, 0, sizeof(BatchState), s);
+  const dim3 ew((unsigned)((n + kBlock - 1) / kBlock));
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_real_diag, ew, dim3(kBlock), 0, s, (int)n, d_rowptr, d_col, d_K, d_M, kd, md);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_sweep_diag_check, ew, dim3(kBlock), 0, s, (int)n, nsys, kd, md, kap, flag);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess && hflag) {
+    (void)hipFree(ar.base);
+    HK_FAIL(HK_EINVAL, "hk_sweep_solve: zero diagonal entry for some system (Jacobi undefined)");
+  }
+  if (e == hipSuccess) {
+    void* args[] = {&a};
+    e = hipLaunchCooperativeKernel((const void*)k_sweep, dim3(grid), dim3(kPB), args, 0, s);
+  }
+  BatchState hs{};
+  GridBar hb{};
+  if (e == hipSuccess) e = hipMemcpyAsync(&hs, a.st, sizeof(hs), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(&hb, a.bar, sizeof(hb), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(ar.base);
+  if (e != hipSuccess) HK_FAIL(HK_EHIP, "hk_sweep_solve: %s", hipGetErrorString(e));
+  if (hb.abort) HK_FAIL(HK_EHIP, "hk_sweep_solve: grid barrier timed out");
+  fill_infos(hs, nsys, infos);
+  return worst_status(infos, nsys);
+}
+
+extern "C" int hk_blockdiag_solve(hk_csr A, int32_t nsys, const int64_t* row_off, const void* d_b,
+                                  void* d_x, const hk_solve_opts* opts, hk_solve_info* infos,
+                                  void* stream) {
+  if (!A || !row_off || !d_b || !d_x || !opts || !infos) HK_FAIL(HK_EINVAL, "hk_blockdiag_solve: null argument");
+  if (A->dtype != HK_C128) HK_FAIL(HK_EINVAL, "hk_blockdiag_solve: matrix must be complex128");
+  if (nsys < 1 || nsys > kSys) HK_FAIL(HK_EINVAL, "hk_blockdiag_solve: nsys must be in [1, 64]");
+  if (!(opts->tol >= 0) || opts->max_iter < 0) HK_FAIL(HK_EINVAL, "hk_blockdiag_solve: bad options");
+  if (row_off[0] != 0 || row_off[nsys] != A->n) HK_FAIL(HK_EINVAL, "hk_blockdiag_solve: row offsets must span [0, n]");
+  for (int k = 0; k < nsys; ++k)
+    if (row_off[k + 1] <= row_off[k]) HK_FAIL(HK_EINVAL, "hk_blockdiag_solve: empty or decreasing system %d", k);
+  hipStream_t s = as_stream(stream);
+  const int L = A->plan.L;
+  const int TR = kPB;
+  // static tiles
+  std::vector<int> tsys, trow, sys_end(kSys, 0), sys_begin(kSys, 0), tile0(kSys + 1, 0);
+  std::vector<int> sys_of_row((size_t)A->n);
+  for (int k = 0; k < nsys; ++k) {
+    tile0[k] = (int)tsys.size();
+    sys_begin[k] = (int)row_off[k];
+    sys_end[k] = (int)row_off[k + 1];
+    for (int64_t r = row_off[k]; r < row_off[k + 1]; r += TR) {
+      tsys.push_back(k);
+      trow.push_back((int)r);
+    }
+    for (int64_t r = row_off[k]; r < row_off[k + 1]; ++r) sys_of_row[r] = k;
+  }
+  tile0[nsys] = (int)tsys.size();
+  for (int k = nsys + 1; k <= kSys; ++k) tile0[k] = tile0[nsys];
+  const int nt = (int)tsys.size();
+  const void* kern = nullptr;
+  if (L == 4) kern = (const void*)k_blockdiag<4>;
+  else if (L == 8) kern = (const void*)k_blockdiag<8>;
+  else if (L == 16) kern = (const void*)k_blockdiag<16>;
+  else kern = (const void*)k_blockdiag<32>;
+  int grid = 0;
+  int rc = coop_grid(kern, &grid);
+  if (rc != HK_OK) return rc;
+  const int64_t n = A->n;
+  Arena ar;
+  const size_t bytes = 8 * a256(16 * (size_t)n) + 2 * a256(4 * (size_t)nt) + a256(4 * (size_t)nt) +
+                       a256(4 * (size_t)n) + 4 * a256(4 * (kSys + 1)) + a256(8 * 4 * (size_t)grid * kSys) +
+                       a256(sizeof(BatchState)) + a256(sizeof(GridBar)) + a256(64);
+  if (hipMalloc((void**)&ar.base, bytes) != hipSuccess) HK_FAIL(HK_ENOMEM, "hk_blockdiag_solve: hipMalloc(%zu)", bytes);
+  BdArgs a{};
+  a.n = (int)n; a.nsys = nsys; a.L = L; a.rowptr = A->rowptr; a.col = A->col;
+  a.val = (const double2*)A->val;
+  a.R = ar.take<double2>(n); a.RH = ar.take<double2>(n); a.PH = ar.take<double2>(n);
+  a.V = ar.take<double2>(n); a.SH = ar.take<double2>(n); a.T = ar.take<double2>(n);
+  double2* d = ar.take<double2>(n);
+  double2* dinv = ar.take<double2>(n);
+  int* d_tsys = ar.take<int>(nt);
+  int* d_trow = ar.take<int>(nt);
+  a.active = ar.take<int>(nt);
+  int* d_sor = ar.take<int>(n);
+  int* d_send = ar.take<int>(kSys + 1);
+  int* d_sbeg = ar.take<int>(kSys + 1);
+  int* d_t0 = ar.take<int>(kSys + 1);
+  (void)ar.take<int>(kSys + 1);
+  a.partials = ar.take<double>(4 * (size_t)grid * kSys);
+  a.st = ar.take<BatchState>(1);
+  a.bar = ar.take<GridBar>(1);
+  int* flag = ar.take<int>(16);
+  a.d = d; a.dinv = dinv; a.tsys = d_tsys; a.trow = d_trow; a.sys_end = d_send; a.sys_tile0 = d_t0;
+  a.B = (const double2*)d_b; a.X = (double2*)d_x; a.tol = opts->tol; a.maxit = opts->max_iter;
+  a.tile_rows = TR;
+  int hflag = 0;
+  hipError_t e = hipMemcpyAsync(d_tsys, tsys.data(), 4 * (size_t)nt, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_trow, trow.data(), 4 * (size_t)nt, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_sor, sys_of_row.data(), 4 * (size_t)n, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_send, sys_end.data(), 4 * kSys, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_sbeg, sys_begin.data(), 4 * kSys, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_t0, tile0.data(), 4 * (kSys + 1), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemsetAsync(a.bar, 0, sizeof(GridBar), s);
+  if (e == hipSuccess) e = hipMemsetAsync(flag, 0, 64, s);
+  if (e == hipSuccess) e = hipMemsetAsync(a.st, 0, sizeof(BatchState), s);
+  if (e == hipSuccess) {
+    // the start phase walks every tile
+    std::vector<int> all(nt);
+    for (int k = 0; k < nt; ++k) all[k] = k;
+    BatchState init{};
+    init.ntiles_active = nt;
+    e = hipMemcpyAsync(a.active, all.data(), 4 * (size_t)nt, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(a.st, &init, sizeof(init), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);  // host vectors above go out of scope
+  }
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_bd_diag, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, (int)n,
+                       A->rowptr, A->col, (const double2*)A->val, d_sor, d_sbeg, d_send, d, dinv, flag);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess && hflag) {
+    (void)hipFree(ar.base);
+    if (hflag & 2) HK_FAIL(HK_EINVAL, "hk_blockdiag_solve: matrix is not block-diagonal for the given offsets");
+    HK_FAIL(HK_EINVAL, "hk_blockdiag_solve: zero diagonal entry (Jacobi undefined)");
+  }
+  if (e == hipSuccess) {
+    void* args[] = {&a};
+    e = hipLaunchCooperativeKernel(kern, dim3(grid), dim3(kPB), args, 0, s);
+  }
+  BatchState hs{};
+  GridBar hb{};
+  if (e == hipSuccess) e = hipMemcpyAsync(&hs, a.st, sizeof(hs), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(&hb, a.bar, sizeof(hb), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(ar.base);
+  if (e != hipSuccess) HK_FAIL(HK_EHIP, "hk_blockdiag_solve: %s", hipGetErrorString(e));
+  if (hb.abort) HK_FAIL(HK_EHIP, "hk_blockdiag_solve: grid barrier timed out");
+  fill_infos(hs, nsys, infos);
+  return worst_status(infos, nsys);
+}

@@ -1,0 +1,162 @@
+// hk_blas1.hip -- complex128 BLAS-1 of the paper's Section 3 on gfx950.
+//
+// Element-wise kernels (scal, axpy, element-wise product, assign) move one
+// 16-byte complex per lane per vector.  Dots and the norm follow the
+// paper's two-task scheme (element-wise product, then sum): each workgroup
+// reduces a contiguous chunk (wave butterfly, then across its 4 waves) into
+// one partial, and the last workgroup to finish sums the partials in a
+// fixed order and writes the result to device memory, so no host copy is
+// needed and the result is bitwise reproducible.
+#include "hk_common.hpp"
+#include "hk_internal.hpp"
+
+namespace hk {
+
+constexpr int kRedMaxBlocks = 1024;
+
+static int reduce_blocks(int64_t n) {
+  int64_t b = (n + kBlock * 4 - 1) / (kBlock * 4);
+  if (b < 1) b = 1;
+  return (int)(b > kRedMaxBlocks ? kRedMaxBlocks : b);
+}
+
+// KIND 0: x^H y, 1: x^T y, 2: ||x||^2 (then sqrt)
+template <int KIND>
+__global__ __launch_bounds__(kBlock) void k_reduce(int64_t n, const double2* __restrict__ x,
+                                                   const double2* __restrict__ y,
+                                                   double* partials, unsigned* ticket,
+                                                   double* __restrict__ out) {
+  __shared__ double lds[2 * (kBlock / kWave)];
+  const int nb = gridDim.x;
+  const int lb = xcd_block(blockIdx.x, nb);
+  const int64_t chunk = (n + nb - 1) / nb;
+  const int64_t i0 = (int64_t)lb * chunk;
+  const int64_t i1 = i0 + chunk < n ? i0 + chunk : n;
+  double2 acc = make_double2(0.0, 0.0);
+  int64_t i = i0 + threadIdx.x;
+  for (; i + 3 * kBlock < i1; i += 4 * kBlock) {
+    double2 a[4], b[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      a[u] = x[i + u * kBlock];
+      if (KIND != 2) b[u] = y[i + u * kBlock];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (KIND == 0) acc = cfmac(a[u], b[u], acc);
+      else if (KIND == 1) acc = cfma(a[u], b[u], acc);
+      else acc.x = fma(a[u].x, a[u].x, fma(a[u].y, a[u].y, acc.x));
+    }
+  }
+  for (; i < i1; i += kBlock) {
+    const double2 a = x[i];
+    if (KIND == 0) acc = cfmac(a, y[i], acc);
+    else if (KIND == 1) acc = cfma(a, y[i], acc);
+    else acc.x = fma(a.x, a.x, fma(a.y, a.y, acc.x));
+  }
+  constexpr int NV = KIND == 2 ? 1 : 2;
+  double v[NV];
+  v[0] = acc.x;
+  if (NV == 2) v[NV - 1] = acc.y;
+  block_sum<NV>(v, lds);
+  double tot[NV];
+  if (last_block_reduce<NV>(v, partials, ticket, tot, lds)) {
+    if (threadIdx.x == 0) {
+      if (KIND == 2) out[0] = sqrt(tot[0]);
+      else { out[0] = tot[0]; out[NV - 1] = tot[NV - 1]; }
+    }
+  }
+}
+
+__global__ void k_axpy(int64_t n, double2 a, const double2* __restrict__ x, double2* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) y[i] = cfma(a, x[i], y[i]);
+}
+__global__ void k_scal(int64_t n, double2 a, double2* __restrict__ x) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) x[i] = cmul(a, x[i]);
+}
+__global__ void k_axmy(int64_t n, const double2* __restrict__ x, double2* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) y[i] = cmul(x[i], y[i]);
+}
+__global__ void k_copy(int64_t n, const double2* __restrict__ x, double2* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) y[i] = x[i];
+}
+__global__ void k_conj(int64_t n, const double2* x, double2* y) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) y[i] = cconj(x[i]);
+}
+
+static dim3 ew_grid(int64_t n) { return dim3((unsigned)((n + kBlock - 1) / kBlock)); }
+
+template <int KIND>
+static int reduce(int64_t n, const void* x, const void* y, void* res, void* stream, const char* who) {
+  if (n <= 0 || !x || !res || (KIND != 2 && !y)) HK_FAIL(HK_EINVAL, "%s: bad argument (n=%lld)", who, (long long)n);
+  if (n > (int64_t)kRedMaxBlocks * (int64_t)(1ll << 40)) HK_FAIL(HK_EINVAL, "%s: n too large", who);
+  hipStream_t s = as_stream(stream);
+  const int nb = reduce_blocks(n);
+  ReduceScratch* rs = nullptr;
+  int rc = reduce_scratch(s, sizeof(double) * 2 * nb, &rs);
+  if (rc != HK_OK) return rc;
+  hipLaunchKernelGGL(k_reduce<KIND>, dim3(nb), dim3(kBlock), 0, s, n, (const double2*)x,
+                     (const double2*)y, (double*)rs->partials, rs->ticket, (double*)res);
+  HK_CHECK_LAUNCH();
+  return HK_OK;
+}
+
+}  // namespace hk
+
+using namespace hk;
+
+extern "C" int hk_zdotc(int64_t n, const void* x, const void* y, void* res, void* stream) {
+  return reduce<0>(n, x, y, res, stream, "hk_zdotc");
+}
+extern "C" int hk_zdotu(int64_t n, const void* x, const void* y, void* res, void* stream) {
+  return reduce<1>(n, x, y, res, stream, "hk_zdotu");
+}
+extern "C" int hk_dznrm2(int64_t n, const void* x, double* res, void* stream) {
+  return reduce<2>(n, x, nullptr, res, stream, "hk_dznrm2");
+}
+
+extern "C" int hk_zaxpy(int64_t n, const double* alpha, const void* x, void* y, void* stream) {
+  if (n < 0 || !alpha || (n > 0 && (!x || !y))) HK_FAIL(HK_EINVAL, "hk_zaxpy: bad argument");
+  if (n == 0) return HK_OK;
+  hipLaunchKernelGGL(k_axpy, ew_grid(n), dim3(kBlock), 0, as_stream(stream), n,
+                     make_double2(alpha[0], alpha[1]), (const double2*)x, (double2*)y);
+  HK_CHECK_LAUNCH();
+  return HK_OK;
+}
+extern "C" int hk_zscal(int64_t n, const double* alpha, void* x, void* stream) {
+  if (n < 0 || !alpha || (n > 0 && !x)) HK_FAIL(HK_EINVAL, "hk_zscal: bad argument");
+  if (n == 0) return HK_OK;
+  hipLaunchKernelGGL(k_scal, ew_grid(n), dim3(kBlock), 0, as_stream(stream), n,
+                     make_double2(alpha[0], alpha[1]), (double2*)x);
+  HK_CHECK_LAUNCH();
+  return HK_OK;
+}
+extern "C" int hk_zaxmy(int64_t n, const void* x, void* y, void* stream) {
+  if (n < 0 || (n > 0 && (!x || !y))) HK_FAIL(HK_EINVAL, "hk_zaxmy: bad argument");
+  if (n == 0) return HK_OK;
+  hipLaunchKernelGGL(k_axmy, ew_grid(n), dim3(kBlock), 0, as_stream(stream), n, (const double2*)x,
+                     (double2*)y);
+  HK_CHECK_LAUNCH();
+  return HK_OK;
+}
+extern "C" int hk_zcopy(int64_t n, const void* x, void* y, void* stream) {
+  if (n < 0 || (n > 0 && (!x || !y))) HK_FAIL(HK_EINVAL, "hk_zcopy: bad argument");
+  if (n == 0) return HK_OK;
+  hipLaunchKernelGGL(k_copy, ew_grid(n), dim3(kBlock), 0, as_stream(stream), n, (const double2*)x,
+                     (double2*)y);
+  HK_CHECK_LAUNCH();
+  return HK_OK;
+}
+extern "C" int hk_zconj(int64_t n, const void* x, void* y, void* stream) {
+  if (n < 0 || (n > 0 && (!x || !y))) HK_FAIL(HK_EINVAL, "hk_zconj: bad argument");
+  if (n == 0) return HK_OK;
+  hipLaunchKernelGGL(k_conj, ew_grid(n), dim3(kBlock), 0, as_stream(stream), n, (const double2*)x,
+                     (double2*)y);
+  HK_CHECK_LAUNCH();
+  return HK_OK;
+}

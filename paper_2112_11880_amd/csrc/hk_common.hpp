@@ -1,0 +1,146 @@
+// hk_common.hpp -- device helpers shared by the HIP kernels of libhk (gfx950).
+//
+// Complex values are stored interleaved (re, im) as double2 / float2, the
+// layout of the paper's complex<T> structure (Section 3: a pair of reals with
+// the usual complex operations).  Reductions are deterministic: every sum is
+// taken in an order fixed by the launch shape, never by atomics on values.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hk {
+
+constexpr int kWave = 64;      // CDNA wavefront
+constexpr int kBlock = 256;    // threads per workgroup (4 waves)
+constexpr int kXcds = 8;       // MI355X: 8 XCDs, workgroup b runs on XCD b % 8
+
+// ------------------------------------------------------------ complex ops
+template <class R> struct cvec;
+template <> struct cvec<double> { using type = double2; };
+template <> struct cvec<float> { using type = float2; };
+template <class R> using cplx = typename cvec<R>::type;
+
+template <class V> __device__ __forceinline__ V cmake(decltype(V::x) re, decltype(V::x) im) {
+  V v; v.x = re; v.y = im; return v;
+}
+template <class V> __device__ __forceinline__ V czero() { return cmake<V>(0, 0); }
+template <class V> __device__ __forceinline__ V cadd(V a, V b) { return cmake<V>(a.x + b.x, a.y + b.y); }
+template <class V> __device__ __forceinline__ V csub(V a, V b) { return cmake<V>(a.x - b.x, a.y - b.y); }
+template <class V> __device__ __forceinline__ V cmul(V a, V b) {
+  return cmake<V>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// acc + a * b
+template <class V> __device__ __forceinline__ V cfma(V a, V b, V acc) {
+  acc.x = fma(a.x, b.x, acc.x); acc.x = fma(-a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y); acc.y = fma(a.y, b.x, acc.y);
+  return acc;
+}
+// acc + conj(a) * b
+template <class V> __device__ __forceinline__ V cfmac(V a, V b, V acc) {
+  acc.x = fma(a.x, b.x, acc.x); acc.x = fma(a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y); acc.y = fma(-a.y, b.x, acc.y);
+  return acc;
+}
+template <class V> __device__ __forceinline__ V cconj(V a) { return cmake<V>(a.x, -a.y); }
+template <class V> __device__ __forceinline__ decltype(V::x) cabs2(V a) { return a.x * a.x + a.y * a.y; }
+// a / b by Smith's method (R. L. Smith, CACM 5(8), 1962): divide through by
+// the larger component of b so |b|^2 is never formed.  Forming |b|^2
+// underflows in float once |b| < 1e-19, which the BiCGStab scalars reach.
+template <class V> __device__ __forceinline__ V cdiv(V a, V b) {
+  if (fabs(b.x) >= fabs(b.y)) {
+    const auto r = b.y / b.x;
+    const auto d = b.x + b.y * r;
+    return cmake<V>((a.x + a.y * r) / d, (a.y - a.x * r) / d);
+  }
+  const auto r = b.x / b.y;
+  const auto d = b.x * r + b.y;
+  return cmake<V>((a.x * r + a.y) / d, (a.y * r - a.x) / d);
+}
+template <class V> __device__ __forceinline__ bool cfinite(V a) {
+  return isfinite(a.x) && isfinite(a.y);
+}
+
+__device__ __forceinline__ double2 to_c128(float2 a) { return make_double2(a.x, a.y); }
+__device__ __forceinline__ float2 to_c64(double2 a) { return make_float2((float)a.x, (float)a.y); }
+
+// ------------------------------------------------------- launch geometry
+// Logical block id such that each XCD gets one contiguous range of ids, so
+// neighbouring rows (which share x gathers) meet in the same L2.
+__device__ __forceinline__ int xcd_block(int b, int nblocks) {
+  int x = b % kXcds, i = b / kXcds;
+  int q = nblocks / kXcds, r = nblocks % kXcds;
+  return x * q + (x < r ? x : r) + i;
+}
+
+// ------------------------------------------------------------ reductions
+template <class T> __device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int m = kWave / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m, kWave);
+  return v;
+}
+// Sum over aligned groups of L lanes; every lane of the group gets the sum.
+template <int L, class T> __device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+  for (int m = L / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m, kWave);
+  return v;
+}
+
+// Block-wide sum of NV values per thread (blockDim.x == kBlock); the result
+// is valid in thread 0.  Order: butterfly within each wave, then waves 0..3.
+template <int NV, class T> __device__ __forceinline__ void block_sum(T (&v)[NV], T* lds /*[NV*4]*/) {
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) lds[k * (kBlock / kWave) + w] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      T s = lds[k * (kBlock / kWave)];
+      for (int j = 1; j < kBlock / kWave; ++j) s += lds[k * (kBlock / kWave) + j];
+      v[k] = s;
+    }
+  }
+}
+
+// Two-stage reduction, second stage by the last block to arrive.
+// Each block stores its NV partials at partials[k * nblocks + block]; the
+// block that takes the last ticket sums them in block order with a fixed
+// tree and returns true (in every thread of that block) with the totals in
+// out[] (valid in thread 0).  The ticket counter is reset for the next use.
+template <int NV, class T>
+__device__ __forceinline__ bool last_block_reduce(const T (&mine)[NV], T* partials, unsigned* ticket,
+                                                  T (&out)[NV], T* lds) {
+  __shared__ bool is_last;
+  const int nb = gridDim.x;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) partials[k * nb + blockIdx.x] = mine[k];
+    __threadfence();
+    unsigned t = atomicAdd(ticket, 1u);
+    is_last = (t == (unsigned)nb - 1);
+  }
+  __syncthreads();
+  if (!is_last) return false;
+  __threadfence();
+  T v[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    T s = 0;
+    for (int j = threadIdx.x; j < nb; j += kBlock) s += partials[k * nb + j];
+    v[k] = s;
+  }
+  block_sum<NV>(v, lds);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) out[k] = v[k];
+    atomicExch(ticket, 0u);
+  }
+  return true;
+}
+
+}  // namespace hk

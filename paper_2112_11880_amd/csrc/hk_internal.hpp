@@ -1,0 +1,81 @@
+// hk_internal.hpp -- host-side plumbing shared by the libhk translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+
+#include "../../include/hk.h"
+
+namespace hk {
+
+// Thread-local text of the last failure, returned by hk_last_error().
+void set_error_text(const char* fmt, ...);
+const char* error_text();
+
+#define HK_FAIL(code, ...)              \
+  do {                                  \
+    ::hk::set_error_text(__VA_ARGS__);  \
+    return (code);                      \
+  } while (0)
+
+#define HK_HIP(call)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      HK_FAIL(HK_EHIP, "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, \
+              __LINE__);                                                              \
+  } while (0)
+
+#define HK_CHECK_LAUNCH() HK_HIP(hipGetLastError())
+
+inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Per-(device, stream) scratch for the two-stage reductions of the BLAS-1
+// entry points: partial sums plus a zeroed ticket counter.  Grows on demand;
+// lives until the process ends.
+struct ReduceScratch {
+  void* partials = nullptr;
+  size_t bytes = 0;
+  unsigned* ticket = nullptr;
+};
+int reduce_scratch(hipStream_t s, size_t bytes, ReduceScratch** out);
+
+// Launch shape of a CSR product: lanes per row, rows per lane group, grid.
+struct SpmvPlan {
+  int L = 16;
+  int U = 2;
+  int grid = 0;     // workgroups per launch (0: one per tile)
+  int tuned = 0;    // 1 if chosen by timing on the device
+};
+
+}  // namespace hk
+
+// The opaque matrix handle.
+struct hk_csr_s {
+  int64_t n = 0, nnz = 0;
+  const int32_t* rowptr = nullptr;
+  const int32_t* col = nullptr;
+  const void* val = nullptr;
+  int dtype = HK_C128;
+  int device = 0;
+  int max_row = 0;         // longest row (host copy, from the validation pass)
+  hk::SpmvPlan plan;
+  // solver workspace (device), allocated on first solve, freed by destroy
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  // complex64 copy of the values for the mixed-precision solve
+  void* val32 = nullptr;
+  void* ws32 = nullptr;
+  size_t ws32_bytes = 0;
+  // pinned host words the solver reads its status through
+  int* pinned = nullptr;
+};
+
+namespace hk {
+int spmv_tiles(const hk_csr_s* A, int L, int U);
+int default_grid(int ntiles);
+}

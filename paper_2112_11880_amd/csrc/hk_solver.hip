@@ -1,0 +1,730 @@
+// hk_solver.hip -- Jacobi right-preconditioned BiCGStab on gfx950, with
+// device-resident scalars, and the complex64/complex128 refinement loop.
+//
+// The paper's P-BiCGSTAB (Section 4) copies every dot product and norm back
+// to the host.  Here each reduction ends in the last workgroup of the kernel
+// that produced its terms, which also updates the scalars (rho, alpha,
+// omega, beta), tests convergence / breakdown and writes a status word, all
+// in device memory.  The host enqueues iterations in chunks and reads the
+// status word once per chunk; kernels enqueued after the solve has ended
+// return at once.
+//
+// Jacobi is applied on the right by scaling the columns once per solve:
+// Ahat = A D^-1 (a workspace copy of the values), and the iteration runs the
+// unpreconditioned recurrences on Ahat y = b with x = D^-1 y at the end.
+// Mathematically this is the preconditioned method with phat = D^-1 p and
+// shat = D^-1 s; it saves one vector pass per preconditioner application.
+//
+// One iteration is five kernels:
+//   K_p   : p = r + beta (p - omega v)                      (iteration > 1)
+//   K_v   : v = Ahat p,  sigma = rhat^H v  -> alpha = rho / sigma
+//   K_s   : s = r - alpha v, ||s||^2       -> half-step convergence test
+//   K_t   : t = Ahat s,  tau = t^H t, t^H s -> omega
+//   K_xr  : y += alpha p + omega s, r = s - omega t, ||r||^2, rhat^H r
+//           -> rho, beta, convergence / breakdown / cap tests
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "hk_internal.hpp"
+#include "hk_spmv.hpp"
+
+namespace hk {
+
+int spmv_dispatch(const hk_csr_s* A, const void* x, void* y, const void* b, const void* alpha,
+                  const void* beta, int mode, hipStream_t s);
+
+enum : int { S_RUN = 100, S_HALF = 101, S_TAUBD = 102 };
+
+template <class R> struct SolveState {
+  cplx<R> rho, rho_old, alpha, omega, beta;
+  R rr, ss, bb, theta2, rr_true;
+  int status, bd;
+  long long iter, maxit, iters_done;
+  double* history;
+};
+
+constexpr int kMaxGrid = 2048;   // workgroups of the fused SpMV launches
+constexpr int kEw = 4;           // elements per thread in the element-wise solver kernels
+
+// workgroups of an element-wise solver kernel over n elements
+static inline int ew_blocks(int64_t n) {
+  const int64_t b = (n + kBlock * kEw - 1) / (kBlock * kEw);
+  return (int)(b < 1 ? 1 : b);
+}
+// partial-sum slots needed by any solver reduction
+static inline int64_t partial_slots(int64_t n) {
+  const int64_t e = ew_blocks(n);
+  return e > kMaxGrid ? e : kMaxGrid;
+}
+
+template <class V> __device__ __forceinline__ V cscale(decltype(V::x) a, V v) { return cmake<V>(a * v.x, a * v.y); }
+
+// ------------------------------------------------------------ set-up kernels
+
+// dinv_i = 1 / a_ii (flag[0] = 1 if a row has no nonzero diagonal); with
+// precond == 0, dinv = 1.
+template <class V>
+__global__ void k_diag_inv(int n, const int* __restrict__ rowptr, const int* __restrict__ col,
+                           const V* __restrict__ val, V* __restrict__ dinv, int precond, int* flag) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  if (!precond) { dinv[i] = cmake<V>(1, 0); return; }
+  V d = czero<V>();
+  for (int p = rowptr[i]; p < rowptr[i + 1]; ++p)
+    if (col[p] == i) d = cadd(d, val[p]);
+  if (d.x == 0 && d.y == 0) { atomicOr(flag, 1); dinv[i] = cmake<V>(0, 0); return; }
+  dinv[i] = cdiv(cmake<V>(1, 0), d);
+}
+
+// ahat_p = a_p * dinv_col(p)  (one thread per row, so the row's columns stay in cache)
+template <class V>
+__global__ void k_scale_cols(int n, const int* __restrict__ rowptr, const int* __restrict__ col,
+                             const V* __restrict__ val, const V* __restrict__ dinv, V* __restrict__ ahat) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  for (int p = rowptr[i]; p < rowptr[i + 1]; ++p) ahat[p] = cmul(val[p], dinv[col[p]]);
+}
+
+// Start of the iteration: r = b - A x0 (already in r when use_x0) or r = b,
+// rhat = p = r, y = x0 / dinv or 0; ||b||^2 and ||r||^2 -> state.
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_init(int n, int use_x0, const cplx<R>* __restrict__ b,
+                                                 const cplx<R>* __restrict__ x0,
+                                                 const cplx<R>* __restrict__ dinv,
+                                                 cplx<R>* __restrict__ r, cplx<R>* __restrict__ rh,
+                                                 cplx<R>* __restrict__ p, cplx<R>* __restrict__ y,
+                                                 R tol, long long maxit, SolveState<R>* st,
+                                                 R* partials, unsigned* ticket) {
+  using V = cplx<R>;
+  __shared__ R lds[2 * (kBlock / kWave)];
+  R acc[2] = {0, 0};
+  const int base = blockIdx.x * (kBlock * kEw) + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < kEw; ++k) {
+    const int i = base + k * kBlock;
+    if (i >= n) break;
+    const V bi = b[i];
+    V ri = bi;
+    V yi = czero<V>();
+    if (use_x0) {
+      ri = r[i];
+      yi = cdiv(x0[i], dinv[i]);
+    } else {
+      r[i] = bi;
+    }
+    rh[i] = ri;
+    p[i] = ri;
+    y[i] = yi;
+    acc[0] += cabs2(bi);
+    acc[1] += cabs2(ri);
+  }
+  block_sum<2>(acc, lds);
+  R tot[2];
+  if (last_block_reduce<2>(acc, partials, ticket, tot, lds) && threadIdx.x == 0) {
+    st->bb = tot[0];
+    st->rr = tot[1];
+    st->theta2 = tol * tol * tot[0];
+    st->rho = cmake<V>(tot[1], 0);
+    st->rho_old = cmake<V>(1, 0);
+    st->alpha = cmake<V>(1, 0);
+    st->omega = cmake<V>(1, 0);
+    st->beta = czero<V>();
+    st->iter = 1;
+    st->maxit = maxit;
+    st->iters_done = 0;
+    st->bd = HK_BD_NONE;
+    if (!isfinite(tot[0]) || !isfinite(tot[1])) st->status = HK_NONFINITE;
+    else if (tot[1] <= st->theta2) st->status = HK_OK;
+    else if (maxit <= 0) st->status = HK_NOT_CONVERGED;
+    else st->status = S_RUN;
+    if (st->history) st->history[0] = tot[0] > 0 ? sqrt((double)tot[1] / (double)tot[0]) : 0.0;
+  }
+}
+
+// ----------------------------------------------------------- iteration kernels
+
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_p(int n, const SolveState<R>* __restrict__ st,
+                                              const cplx<R>* __restrict__ r, cplx<R>* __restrict__ p,
+                                              const cplx<R>* __restrict__ v) {
+  using V = cplx<R>;
+  if (st->status != S_RUN || st->iter == 1) return;
+  const V beta = st->beta, omega = st->omega;
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  // p = r + beta (p - omega v)
+  V q = csub(p[i], cmul(omega, v[i]));
+  p[i] = cfma(beta, q, r[i]);
+}
+
+// v = Ahat p and sigma = rhat^H v  (DOT == 1), or
+// t = Ahat s, tau = t^H t and t^H s (DOT == 2).
+template <int L, int U, class R, int DOT>
+__global__ __launch_bounds__(kBlock) void k_spmv_dot(int n, int ntiles, const int* __restrict__ rowptr,
+                                                     const int* __restrict__ col,
+                                                     const cplx<R>* __restrict__ val,
+                                                     const cplx<R>* __restrict__ x,
+                                                     cplx<R>* __restrict__ y,
+                                                     const cplx<R>* __restrict__ w,
+                                                     SolveState<R>* st, R* partials, unsigned* ticket) {
+  using V = cplx<R>;
+  constexpr int NV = DOT == 1 ? 2 : 3;
+  __shared__ R lds[NV * (kBlock / kWave)];
+  if (st->status != S_RUN) return;
+  constexpr int RT = (kBlock / L) * U;
+  const int g = threadIdx.x / L, lane = threadIdx.x & (L - 1);
+  int t0, t1;
+  tile_range(ntiles, t0, t1);
+  R part[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) part[k] = 0;
+  for (int t = t0; t < t1; ++t) {
+    const int r0 = t * RT + g * U;
+    V acc[U];
+    csr_rows<L, U, V>(r0, n, rowptr, col, val, x, acc);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int r = r0 + u;
+      if (lane == u && r < n) {
+        y[r] = acc[u];
+        const V wr = w[r];
+        if (DOT == 1) {
+          // conj(rhat_r) * v_r
+          part[0] = fma(wr.x, acc[u].x, fma(wr.y, acc[u].y, part[0]));
+          part[1] = fma(wr.x, acc[u].y, fma(-wr.y, acc[u].x, part[1]));
+        } else {
+          part[0] = fma(acc[u].x, acc[u].x, fma(acc[u].y, acc[u].y, part[0]));
+          // conj(t_r) * s_r
+          part[1] = fma(acc[u].x, wr.x, fma(acc[u].y, wr.y, part[1]));
+          part[2] = fma(acc[u].x, wr.y, fma(-acc[u].y, wr.x, part[2]));
+        }
+      }
+    }
+  }
+  block_sum<NV>(part, lds);
+  R tot[NV];
+  if (last_block_reduce<NV>(part, partials, ticket, tot, lds) && threadIdx.x == 0) {
+    if (DOT == 1) {
+      const V sigma = cmake<V>(tot[0], tot[1]);
+      if (!cfinite(sigma)) {
+        st->status = HK_NONFINITE;
+        st->iters_done = st->iter - 1;
+      } else if (sigma.x == 0 && sigma.y == 0) {
+        st->status = HK_BREAKDOWN;
+        st->bd = HK_BD_SIGMA;
+        st->iters_done = st->iter - 1;
+      } else {
+        st->alpha = cdiv(st->rho, sigma);
+      }
+    } else {
+      const R tau = tot[0];
+      const V ts = cmake<V>(tot[1], tot[2]);
+      if (!isfinite(tau) || !cfinite(ts)) {
+        st->status = HK_NONFINITE;
+        st->iters_done = st->iter - 1;
+      } else if (tau == 0) {
+        st->status = S_TAUBD;
+      } else {
+        st->omega = cscale<V>(R(1) / tau, ts);
+      }
+    }
+  }
+}
+
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_s(int n, SolveState<R>* st, const cplx<R>* __restrict__ r,
+                                              const cplx<R>* __restrict__ v, cplx<R>* __restrict__ s,
+                                              R* partials, unsigned* ticket) {
+  using V = cplx<R>;
+  __shared__ R lds[kBlock / kWave];
+  if (st->status != S_RUN) return;
+  const V alpha = st->alpha;
+  R acc[1] = {0};
+  const int base = blockIdx.x * (kBlock * kEw) + threadIdx.x;
+  if (base + (kEw - 1) * kBlock < n) {
+    V rv[kEw], vv[kEw];
+#pragma unroll
+    for (int k = 0; k < kEw; ++k) { rv[k] = r[base + k * kBlock]; vv[k] = v[base + k * kBlock]; }
+#pragma unroll
+    for (int k = 0; k < kEw; ++k) {
+      // s = r - alpha v
+      const V si = csub(rv[k], cmul(alpha, vv[k]));
+      s[base + k * kBlock] = si;
+      acc[0] += cabs2(si);
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < kEw; ++k) {
+      const int i = base + k * kBlock;
+      if (i >= n) break;
+      const V si = csub(r[i], cmul(alpha, v[i]));
+      s[i] = si;
+      acc[0] += cabs2(si);
+    }
+  }
+  block_sum<1>(acc, lds);
+  R tot[1];
+  if (last_block_reduce<1>(acc, partials, ticket, tot, lds) && threadIdx.x == 0) {
+    st->ss = tot[0];
+    if (!isfinite(tot[0])) {
+      st->status = HK_NONFINITE;
+      st->iters_done = st->iter - 1;
+    } else if (tot[0] <= st->theta2) {
+      st->status = S_HALF;
+    }
+  }
+}
+
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_xr(int n, SolveState<R>* st, const cplx<R>* __restrict__ rh,
+                                               cplx<R>* __restrict__ r, const cplx<R>* __restrict__ p,
+                                               const cplx<R>* __restrict__ s,
+                                               const cplx<R>* __restrict__ t, cplx<R>* __restrict__ y,
+                                               R* partials, unsigned* ticket) {
+  using V = cplx<R>;
+  __shared__ R lds[3 * (kBlock / kWave)];
+  const int status = st->status;
+  if (status != S_RUN && status != S_HALF && status != S_TAUBD) return;
+  const V alpha = st->alpha, omega = st->omega;
+  R acc[3] = {0, 0, 0};
+  const int base = blockIdx.x * (kBlock * kEw) + threadIdx.x;
+  if (status == S_RUN) {
+    // y += alpha p + omega s ; r = s - omega t ; ||r||^2 ; rhat^H r
+    auto upd = [&](int i, V si, V pi, V ti, V yi, V hi) {
+      y[i] = cfma(omega, si, cfma(alpha, pi, yi));
+      const V ri = csub(si, cmul(omega, ti));
+      r[i] = ri;
+      acc[0] += cabs2(ri);
+      acc[1] = fma(hi.x, ri.x, fma(hi.y, ri.y, acc[1]));
+      acc[2] = fma(hi.x, ri.y, fma(-hi.y, ri.x, acc[2]));
+    };
+    if (base + (kEw - 1) * kBlock < n) {
+      V sv[kEw], pv[kEw], tv[kEw], yv[kEw], hv[kEw];
+#pragma unroll
+      for (int k = 0; k < kEw; ++k) {
+        const int i = base + k * kBlock;
+        sv[k] = s[i]; pv[k] = p[i]; tv[k] = t[i]; yv[k] = y[i]; hv[k] = rh[i];
+      }
+#pragma unroll
+      for (int k = 0; k < kEw; ++k) upd(base + k * kBlock, sv[k], pv[k], tv[k], yv[k], hv[k]);
+    } else {
+#pragma unroll
+      for (int k = 0; k < kEw; ++k) {
+        const int i = base + k * kBlock;
+        if (i >= n) break;
+        upd(i, s[i], p[i], t[i], y[i], rh[i]);
+      }
+    }
+  } else {
+    // half-step exit (converged on s) or tau breakdown: y += alpha p
+#pragma unroll
+    for (int k = 0; k < kEw; ++k) {
+      const int i = base + k * kBlock;
+      if (i < n) y[i] = cfma(alpha, p[i], y[i]);
+    }
+  }
+  block_sum<3>(acc, lds);
+  R tot[3];
+  if (last_block_reduce<3>(acc, partials, ticket, tot, lds) && threadIdx.x == 0) {
+    const long long it = st->iter;
+    if (status == S_HALF) {
+      st->status = HK_OK;
+      st->rr = st->ss;
+      st->iters_done = it;
+      if (st->history) st->history[it] = st->bb > 0 ? sqrt((double)st->ss / (double)st->bb) : 0.0;
+      return;
+    }
+    if (status == S_TAUBD) {
+      st->status = HK_BREAKDOWN;
+      st->bd = HK_BD_TAU;
+      st->rr = st->ss;
+      st->iters_done = it;
+      return;
+    }
+    const R rr = tot[0];
+    const V rho = cmake<V>(tot[1], tot[2]);
+    st->rr = rr;
+    st->rho_old = st->rho;
+    st->rho = rho;
+    st->iters_done = it;
+    if (st->history) st->history[it] = st->bb > 0 ? sqrt((double)rr / (double)st->bb) : 0.0;
+    if (!isfinite(rr) || !cfinite(rho)) {
+      st->status = HK_NONFINITE;
+    } else if (rr <= st->theta2) {
+      st->status = HK_OK;
+    } else if (omega.x == 0 && omega.y == 0) {
+      st->status = HK_BREAKDOWN;
+      st->bd = HK_BD_OMEGA;
+    } else if (rho.x == 0 && rho.y == 0) {
+      st->status = HK_BREAKDOWN;
+      st->bd = HK_BD_RHO;
+    } else if (it >= st->maxit) {
+      st->status = HK_NOT_CONVERGED;
+    } else {
+      // beta = (rho / rho_old) (alpha / omega)
+      st->beta = cmul(cdiv(rho, st->rho_old), cdiv(alpha, omega));
+      st->iter = it + 1;
+    }
+  }
+}
+
+// x = dinv .* y
+template <class V>
+__global__ void k_unscale(int n, const V* __restrict__ dinv, const V* __restrict__ y, V* __restrict__ x) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) x[i] = cmul(dinv[i], y[i]);
+}
+
+// ||w||^2 -> st->rr_true
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_true_norm(int n, const cplx<R>* __restrict__ w, SolveState<R>* st,
+                                                      R* partials, unsigned* ticket) {
+  __shared__ R lds[kBlock / kWave];
+  R acc[1] = {0};
+  const int base = blockIdx.x * (kBlock * kEw) + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < kEw; ++k) {
+    const int i = base + k * kBlock;
+    if (i < n) acc[0] += cabs2(w[i]);
+  }
+  block_sum<1>(acc, lds);
+  R tot[1];
+  if (last_block_reduce<1>(acc, partials, ticket, tot, lds) && threadIdx.x == 0) st->rr_true = tot[0];
+}
+
+// --------------------------------------------------------- mixed-precision helpers
+
+// b = round_to_c64(scale * a); scale is a power of two, so the scaling is exact
+__global__ void k_round_c64(int64_t m, const double2* __restrict__ a, float2* __restrict__ b, double scale) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < m) {
+    const double2 v = a[i];
+    b[i] = make_float2((float)(scale * v.x), (float)(scale * v.y));
+  }
+}
+// u += scale * d (complex128 accumulation; scale a power of two)
+__global__ void k_add_c64(int n, const float2* __restrict__ d, double2* __restrict__ u, double scale) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) {
+    const double2 a = u[i];
+    const float2 e = d[i];
+    u[i] = make_double2(a.x + scale * (double)e.x, a.y + scale * (double)e.y);
+  }
+}
+
+// ------------------------------------------------------------------- driver
+
+template <class R> struct Work {
+  using V = cplx<R>;
+  V *y, *r, *rh, *p, *v, *s, *t, *dinv, *ahat;
+  R* partials;
+  unsigned* ticket;
+  SolveState<R>* st;
+  int* flag;
+};
+
+static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+template <class R> static size_t work_bytes(int64_t n, int64_t nnz) {
+  using V = cplx<R>;
+  return 8 * align_up(sizeof(V) * n) + align_up(sizeof(V) * (nnz > 0 ? nnz : 1)) +
+         align_up(sizeof(R) * 4 * partial_slots(n)) + align_up(64) + align_up(sizeof(SolveState<R>)) +
+         align_up(64);
+}
+
+template <class R> static Work<R> carve(void* base, int64_t n, int64_t nnz) {
+  using V = cplx<R>;
+  char* q = static_cast<char*>(base);
+  auto take = [&](size_t bytes) { char* r = q; q += align_up(bytes); return r; };
+  Work<R> w;
+  w.y = (V*)take(sizeof(V) * n);
+  w.r = (V*)take(sizeof(V) * n);
+  w.rh = (V*)take(sizeof(V) * n);
+  w.p = (V*)take(sizeof(V) * n);
+  w.v = (V*)take(sizeof(V) * n);
+  w.s = (V*)take(sizeof(V) * n);
+  w.t = (V*)take(sizeof(V) * n);
+  w.dinv = (V*)take(sizeof(V) * n);
+  w.ahat = (V*)take(sizeof(V) * (nnz > 0 ? nnz : 1));
+  w.partials = (R*)take(sizeof(R) * 4 * partial_slots(n));
+  w.ticket = (unsigned*)take(64);
+  w.st = (SolveState<R>*)take(sizeof(SolveState<R>));
+  w.flag = (int*)take(64);
+  return w;
+}
+
+static int ensure_ws(void** ws, size_t* have, size_t need, hipStream_t s) {
+  if (*have >= need) return HK_OK;
+  if (*ws) {
+    HK_HIP(hipStreamSynchronize(s));
+    HK_HIP(hipFree(*ws));
+    *ws = nullptr;
+    *have = 0;
+  }
+  if (hipMalloc(ws, need) != hipSuccess) HK_FAIL(HK_ENOMEM, "solver workspace: hipMalloc(%zu) failed", need);
+  *have = need;
+  // tickets must start at zero; every reduction leaves them at zero
+  HK_HIP(hipMemsetAsync(*ws, 0, need, s));
+  return HK_OK;
+}
+
+template <class R>
+static hipError_t launch_spmv_dot(const hk_csr_s* A, int L, int U, int grid, int dot, const cplx<R>* val,
+                                  const cplx<R>* x, cplx<R>* y, const cplx<R>* w, const Work<R>& wk,
+                                  hipStream_t s) {
+  const int ntiles = spmv_tiles(A, L, U);
+  const int n = (int)A->n;
+#define HK_SD_CASE(LL, UU)                                                                          \
+  if (L == LL && U == UU) {                                                                         \
+    if (dot == 1)                                                                                   \
+      hipLaunchKernelGGL((k_spmv_dot<LL, UU, R, 1>), dim3(grid), dim3(kBlock), 0, s, n, ntiles,     \
+                         A->rowptr, A->col, val, x, y, w, wk.st, wk.partials, wk.ticket);           \
+    else                                                                                            \
+      hipLaunchKernelGGL((k_spmv_dot<LL, UU, R, 2>), dim3(grid), dim3(kBlock), 0, s, n, ntiles,     \
+                         A->rowptr, A->col, val, x, y, w, wk.st, wk.partials, wk.ticket);           \
+    return hipGetLastError();                                                                       \
+  }
+  HK_SD_CASE(4, 1) HK_SD_CASE(4, 2) HK_SD_CASE(4, 4)
+  HK_SD_CASE(8, 1) HK_SD_CASE(8, 2) HK_SD_CASE(8, 4)
+  HK_SD_CASE(16, 1) HK_SD_CASE(16, 2) HK_SD_CASE(16, 4)
+  HK_SD_CASE(32, 1) HK_SD_CASE(32, 2) HK_SD_CASE(32, 4)
+#undef HK_SD_CASE
+  return hipErrorInvalidValue;
+}
+
+// Runs the whole solve for precision R on values `val` (A's pattern), right
+// side b, solution x (input when use_x0).  Fills info (host), synchronises.
+template <class R>
+static int bicgstab(const hk_csr_s* A, const cplx<R>* val, const cplx<R>* b, cplx<R>* x,
+                    const hk_solve_opts& o, void* wsbase, hk_solve_info* info, hipStream_t s) {
+  using V = cplx<R>;
+  const int n = (int)A->n;
+  const Work<R> wk = carve<R>(wsbase, A->n, A->nnz);
+  const dim3 ew((unsigned)((n + kBlock - 1) / kBlock));
+  const int gv = ew_blocks(n);
+  const int ntiles = spmv_tiles(A, A->plan.L, A->plan.U);
+  int gs = A->plan.grid > 0 ? A->plan.grid : kMaxGrid;
+  gs = std::max(1, std::min(gs, std::min(ntiles, kMaxGrid)));
+
+  // set-up: D^-1, Ahat = A D^-1, initial residual
+  HK_HIP(hipMemsetAsync(wk.flag, 0, sizeof(int), s));
+  hipLaunchKernelGGL(k_diag_inv<V>, ew, dim3(kBlock), 0, s, n, A->rowptr, A->col, val, wk.dinv,
+                     o.precond ? 1 : 0, wk.flag);
+  HK_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_scale_cols<V>, ew, dim3(kBlock), 0, s, n, A->rowptr, A->col, val, wk.dinv,
+                     wk.ahat);
+  HK_CHECK_LAUNCH();
+  if (o.use_x0) {
+    hk_csr_s tmp = *A;
+    tmp.val = val;
+    int rc = spmv_dispatch(&tmp, x, wk.r, b, nullptr, nullptr, 1, s);
+    if (rc != HK_OK) return rc;
+  }
+  SolveState<R> init{};
+  init.history = o.d_history;
+  HK_HIP(hipMemcpyAsync(wk.st, &init, sizeof(init), hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_init<R>, dim3(gv), dim3(kBlock), 0, s, n, o.use_x0 ? 1 : 0, b, x, wk.dinv,
+                     wk.r, wk.rh, wk.p, wk.y, (R)o.tol, (long long)o.max_iter, wk.st, wk.partials,
+                     wk.ticket);
+  HK_CHECK_LAUNCH();
+  int hflag = 0;
+  HK_HIP(hipMemcpyAsync(&hflag, wk.flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  HK_HIP(hipStreamSynchronize(s));
+  if (hflag) HK_FAIL(HK_EINVAL, "krylov solve: zero diagonal entry (Jacobi undefined)");
+
+  // iterations, in chunks; the status word is read one chunk behind
+  int m = o.check_every > 0 ? o.check_every : (n < 200000 ? 64 : 16);
+  int* pin = A->pinned;
+  hipEvent_t ev[2];
+  HK_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+  HK_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+  int rc = HK_OK;
+  long long enq = 0;
+  int k = 0;
+  const size_t status_off = offsetof(SolveState<R>, status);
+  for (;;) {
+    for (int j = 0; j < m && rc == HK_OK; ++j) {
+      hipLaunchKernelGGL(k_p<R>, ew, dim3(kBlock), 0, s, n, wk.st, wk.r, wk.p, wk.v);
+      hipError_t e = hipGetLastError();
+      if (e == hipSuccess)
+        e = launch_spmv_dot<R>(A, A->plan.L, A->plan.U, gs, 1, wk.ahat, wk.p, wk.v, wk.rh, wk, s);
+      if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_s<R>, dim3(gv), dim3(kBlock), 0, s, n, wk.st, wk.r, wk.v, wk.s,
+                           wk.partials, wk.ticket);
+        e = hipGetLastError();
+      }
+      if (e == hipSuccess)
+        e = launch_spmv_dot<R>(A, A->plan.L, A->plan.U, gs, 2, wk.ahat, wk.s, wk.t, wk.s, wk, s);
+      if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_xr<R>, dim3(gv), dim3(kBlock), 0, s, n, wk.st, wk.rh, wk.r, wk.p, wk.s,
+                           wk.t, wk.y, wk.partials, wk.ticket);
+        e = hipGetLastError();
+      }
+      if (e != hipSuccess) {
+        set_error_text("krylov solve: launch failed: %s", hipGetErrorString(e));
+        rc = HK_EHIP;
+      }
+    }
+    if (rc != HK_OK) break;
+    enq += m;
+    hipError_t e = hipMemcpyAsync(&pin[k & 1], (char*)wk.st + status_off, sizeof(int),
+                                  hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipEventRecord(ev[k & 1], s);
+    if (e == hipSuccess && k > 0) e = hipEventSynchronize(ev[(k - 1) & 1]);
+    if (e != hipSuccess) {
+      set_error_text("krylov solve: %s", hipGetErrorString(e));
+      rc = HK_EHIP;
+      break;
+    }
+    if (k > 0 && pin[(k - 1) & 1] < S_RUN) break;
+    if (enq >= o.max_iter) break;
+    ++k;
+  }
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
+  if (rc != HK_OK) return rc;
+
+  // x = D^-1 y; true residual with the original values
+  hipLaunchKernelGGL(k_unscale<V>, ew, dim3(kBlock), 0, s, n, wk.dinv, wk.y, x);
+  HK_CHECK_LAUNCH();
+  {
+    hk_csr_s tmp = *A;
+    tmp.val = val;
+    int rc2 = spmv_dispatch(&tmp, x, wk.t, b, nullptr, nullptr, 1, s);
+    if (rc2 != HK_OK) return rc2;
+  }
+  hipLaunchKernelGGL(k_true_norm<R>, dim3(gv), dim3(kBlock), 0, s, n, wk.t, wk.st, wk.partials,
+                     wk.ticket);
+  HK_CHECK_LAUNCH();
+  SolveState<R> hs;
+  HK_HIP(hipMemcpyAsync(&hs, wk.st, sizeof(hs), hipMemcpyDeviceToHost, s));
+  HK_HIP(hipStreamSynchronize(s));
+  info->status = hs.status >= S_RUN ? HK_NOT_CONVERGED : hs.status;
+  info->breakdown = hs.bd;
+  info->iters = hs.status >= S_RUN ? hs.iter : hs.iters_done;
+  const double bb = (double)hs.bb;
+  info->relres_rec = bb > 0 ? std::sqrt((double)hs.rr / bb) : std::sqrt((double)hs.rr);
+  info->relres_true = bb > 0 ? std::sqrt((double)hs.rr_true / bb) : std::sqrt((double)hs.rr_true);
+  info->inner_iters = 0;
+  return HK_OK;
+}
+
+static int ensure_pinned(hk_csr_s* A) {
+  if (A->pinned) return HK_OK;
+  HK_HIP(hipHostMalloc((void**)&A->pinned, 64, hipHostMallocDefault));
+  return HK_OK;
+}
+
+static int check_opts(const hk_solve_opts* o, const char* who) {
+  if (!o) HK_FAIL(HK_EINVAL, "%s: opts is NULL", who);
+  if (!(o->tol >= 0) || o->max_iter < 0 || o->check_every < 0)
+    HK_FAIL(HK_EINVAL, "%s: bad options (tol=%g max_iter=%lld)", who, o->tol, (long long)o->max_iter);
+  return HK_OK;
+}
+
+}  // namespace hk
+
+using namespace hk;
+
+extern "C" int hk_krylov_solve(hk_csr A, const void* d_b, void* d_x, const hk_solve_opts* opts,
+                               hk_solve_info* info, void* stream) {
+  if (!A || !d_b || !d_x || !info) HK_FAIL(HK_EINVAL, "hk_krylov_solve: null argument");
+  if (A->dtype != HK_C128) HK_FAIL(HK_EINVAL, "hk_krylov_solve: matrix must be complex128");
+  int rc = check_opts(opts, "hk_krylov_solve");
+  if (rc != HK_OK) return rc;
+  hipStream_t s = as_stream(stream);
+  rc = ensure_pinned(A);
+  if (rc != HK_OK) return rc;
+  rc = ensure_ws(&A->ws, &A->ws_bytes, work_bytes<double>(A->n, A->nnz), s);
+  if (rc != HK_OK) return rc;
+  rc = bicgstab<double>(A, (const double2*)A->val, (const double2*)d_b, (double2*)d_x, *opts, A->ws,
+                        info, s);
+  if (rc != HK_OK) return rc;
+  return info->status;
+}
+
+extern "C" int hk_krylov_solve_mixed(hk_csr A, const void* d_b, void* d_x, double inner_tol,
+                                     double outer_tol, int32_t max_outer, const hk_solve_opts* opts,
+                                     hk_solve_info* info, void* stream) {
+  if (!A || !d_b || !d_x || !info) HK_FAIL(HK_EINVAL, "hk_krylov_solve_mixed: null argument");
+  if (A->dtype != HK_C128) HK_FAIL(HK_EINVAL, "hk_krylov_solve_mixed: matrix must be complex128");
+  int rc = check_opts(opts, "hk_krylov_solve_mixed");
+  if (rc != HK_OK) return rc;
+  if (!(inner_tol > 0) || !(outer_tol >= 0) || max_outer < 0)
+    HK_FAIL(HK_EINVAL, "hk_krylov_solve_mixed: bad tolerances");
+  hipStream_t s = as_stream(stream);
+  const int64_t n = A->n;
+  // complex64 workspace + r (c128) + r32, d32 (c64) + norm scratch
+  const size_t extra = align_up(16 * n) + 2 * align_up(8 * n) + align_up(64);
+  rc = ensure_pinned(A);
+  if (rc != HK_OK) return rc;
+  rc = ensure_ws(&A->ws32, &A->ws32_bytes, work_bytes<float>(A->n, A->nnz) + extra, s);
+  if (rc != HK_OK) return rc;
+  if (!A->val32) {
+    if (hipMalloc(&A->val32, 8 * (size_t)(A->nnz > 0 ? A->nnz : 1)) != hipSuccess)
+      HK_FAIL(HK_ENOMEM, "hk_krylov_solve_mixed: hipMalloc failed");
+  }
+  char* tail = (char*)A->ws32 + work_bytes<float>(A->n, A->nnz);
+  double2* r = (double2*)tail;
+  float2* r32 = (float2*)(tail + align_up(16 * n));
+  float2* d32 = (float2*)(tail + align_up(16 * n) + align_up(8 * n));
+  double* dnorm = (double*)(tail + align_up(16 * n) + 2 * align_up(8 * n));
+  const dim3 ew((unsigned)((n + kBlock - 1) / kBlock));
+  // A32 = round-to-nearest of each component of A
+  if (A->nnz > 0) {
+    hipLaunchKernelGGL(k_round_c64, dim3((unsigned)((A->nnz + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                       s, (int64_t)A->nnz, (const double2*)A->val, (float2*)A->val32, 1.0);
+    HK_CHECK_LAUNCH();
+  }
+  if (!opts->use_x0) HK_HIP(hipMemsetAsync(d_x, 0, 16 * n, s));
+  rc = hk_dznrm2(n, d_b, dnorm, stream);
+  if (rc != HK_OK) return rc;
+  double bn = 0;
+  HK_HIP(hipMemcpyAsync(&bn, dnorm, sizeof(double), hipMemcpyDeviceToHost, s));
+  HK_HIP(hipStreamSynchronize(s));
+  hk_solve_opts io = *opts;
+  io.tol = inner_tol;
+  io.use_x0 = 0;
+  io.d_history = nullptr;
+  int64_t inner_total = 0;
+  double prev = INFINITY, rel = 0;
+  int status = HK_NOT_CONVERGED, k = 0;
+  hk_csr_s A32 = *A;
+  A32.val = A->val32;
+  A32.dtype = HK_C64;
+  for (k = 0; k <= max_outer; ++k) {
+    rc = spmv_dispatch(A, d_x, r, d_b, nullptr, nullptr, 1, s);   // r = b - A u (complex128)
+    if (rc != HK_OK) return rc;
+    rc = hk_dznrm2(n, r, dnorm, stream);
+    if (rc != HK_OK) return rc;
+    double rn = 0;
+    HK_HIP(hipMemcpyAsync(&rn, dnorm, sizeof(double), hipMemcpyDeviceToHost, s));
+    HK_HIP(hipStreamSynchronize(s));
+    rel = bn > 0 ? rn / bn : rn;
+    if (!std::isfinite(rn)) { status = HK_NONFINITE; break; }
+    if (rel <= outer_tol) { status = HK_OK; break; }
+    if (rn >= prev || k == max_outer) { status = HK_NOT_CONVERGED; break; }
+    prev = rn;
+    // the inner right-hand side is r scaled by a power of two to unit size, so
+    // the complex64 iteration runs far from its under/overflow range
+    const double scale = std::ldexp(1.0, -std::ilogb(rn));
+    hipLaunchKernelGGL(k_round_c64, ew, dim3(kBlock), 0, s, n, (const double2*)r, r32, scale);
+    HK_CHECK_LAUNCH();
+    hk_solve_info ii{};
+    rc = bicgstab<float>(&A32, (const float2*)A->val32, r32, d32, io, A->ws32, &ii, s);
+    if (rc != HK_OK) return rc;
+    inner_total += ii.iters;
+    if (ii.status == HK_NONFINITE) { status = HK_NONFINITE; break; }
+    hipLaunchKernelGGL(k_add_c64, ew, dim3(kBlock), 0, s, (int)n, (const float2*)d32, (double2*)d_x,
+                       1.0 / scale);
+    HK_CHECK_LAUNCH();
+  }
+  info->status = status;
+  info->breakdown = HK_BD_NONE;
+  info->iters = k;
+  info->relres_rec = rel;
+  info->relres_true = rel;
+  info->inner_iters = inner_total;
+  return status;
+}

@@ -1,0 +1,104 @@
+// hk_spmv.hpp -- CSR row kernels for gfx950 (complex128 / complex64).
+//
+// The paper calls the CSR sparse matrix-vector product the most time
+// consuming operation of a Krylov iteration and organises threads on the
+// grid per matrix (Section 3, Table 8).  Here a row is owned by a group of
+// L lanes of a 64-wide wave (L in {4, 8, 16, 32}); each lane streams
+// (col, val) pairs of its row -- one 16-byte value load per lane, so a
+// 16-lane group reads a row's values as one contiguous run -- gathers x, and
+// the group reduces with cross-lane shuffles.  A group handles U consecutive
+// rows with all loads issued before the multiply-adds, to keep enough bytes
+// in flight per wave.  Matrix streams use non-temporal loads so they do not
+// evict the x window from L2.  A workgroup of 256 threads covers
+// (256/L)*U consecutive rows ("tile"); a launch of G workgroups walks the
+// tiles in contiguous ranges, one range per workgroup, XCD-major.
+#pragma once
+
+#include "hk_common.hpp"
+
+namespace hk {
+
+typedef double nd2 __attribute__((ext_vector_type(2)));
+typedef float nf2 __attribute__((ext_vector_type(2)));
+
+template <class V> struct native;
+template <> struct native<double2> { using type = nd2; };
+template <> struct native<float2> { using type = nf2; };
+
+template <class V> __device__ __forceinline__ V ldnt(const V* p) {
+  using N = typename native<V>::type;
+  N v = __builtin_nontemporal_load(reinterpret_cast<const N*>(p));
+  return cmake<V>(v.x, v.y);
+}
+__device__ __forceinline__ int ldnt(const int* p) { return __builtin_nontemporal_load(p); }
+
+// Row sums of rows r0 .. r0+U-1 (rows >= n give 0).  Every lane of the
+// L-lane group returns the full sums.  Within a row, lane j accumulates
+// entries j, j+L, j+2L, ...; the group total is a fixed butterfly.
+// All loads are issued unconditionally from in-bounds indices (a lane past
+// the end of its row re-reads the row's last entry and contributes zero),
+// so the compiler keeps the U rows' loads in flight together instead of
+// branching around each one.
+template <int L, int U, class V>
+__device__ __forceinline__ void csr_rows(int r0, int n, const int* __restrict__ rowptr,
+                                         const int* __restrict__ col, const V* __restrict__ val,
+                                         const V* __restrict__ x, V (&acc)[U]) {
+  const int lane = threadIdx.x & (L - 1);
+  int s[U], e[U];
+  int len = 0;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int r = r0 + u;
+    const int rc = r < n ? r : n - 1;
+    const int a = rowptr[rc], b = rowptr[rc + 1];
+    s[u] = r < n ? a : 0;
+    e[u] = r < n ? b : 0;
+    len = max(len, e[u] - s[u]);
+    acc[u] = czero<V>();
+  }
+  for (int k = 0; k < len; k += L) {
+    int c[U];
+    V a[U];
+    bool ok[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int p = s[u] + k + lane;
+      ok[u] = p < e[u];
+      // len > 0 here, so the matrix has entries and index 0 is valid
+      const int pc = ok[u] ? p : (e[u] > 0 ? e[u] - 1 : 0);
+      c[u] = ldnt(col + pc);
+      a[u] = ldnt(val + pc);
+    }
+    V xv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) xv[u] = x[c[u]];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const V av = ok[u] ? a[u] : czero<V>();
+      acc[u] = cfma(av, xv[u], acc[u]);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    acc[u].x = group_sum<L>(acc[u].x);
+    acc[u].y = group_sum<L>(acc[u].y);
+  }
+}
+
+// Tile range [t0, t1) of the calling workgroup for a launch of gridDim.x
+// workgroups over ntiles tiles (contiguous per workgroup, XCD-major).
+__device__ __forceinline__ void tile_range(int ntiles, int& t0, int& t1) {
+  const int nb = gridDim.x;
+  const int lb = xcd_block(blockIdx.x, nb);
+  t0 = (int)(((long long)lb * ntiles) / nb);
+  t1 = (int)(((long long)(lb + 1) * ntiles) / nb);
+}
+
+// Shape of one SpMV variant.
+struct SpmvShape {
+  int L;        // lanes per row
+  int U;        // rows per lane group
+  int rows_per_tile() const { return (kBlock / L) * U; }
+};
+
+}  // namespace hk

@@ -1,0 +1,190 @@
+"""GPU parity of the batched persistent solvers against per-system oracle solves.
+
+Small batches are compared solution by solution (tol 1e-10, within 1e-7 of
+the oracle's solution, iteration counts within 10%).  The full-size
+workloads (64-frequency sweep on the 48^3 mesh; 32 uneven cubes) are checked
+through the oracle's recomputed true residual of every system (<= 1.05e-8
+at tol 1e-8), which holds at any size.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from synth import helmholtz as H
+from synth import configs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def hk():
+    if not torch.cuda.is_available():
+        pytest.fail("no HIP device visible")
+    import paper_2112_11880_amd as hk
+    hk.load()
+    return hk
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def crandn(rng, n):
+    return rng.standard_normal(n) + 1j * rng.standard_normal(n)
+
+
+def sweep_inputs(nc, nsys, seed=1):
+    m = H.make_mesh(nc, nc, nc, 1.0 / nc, jitter=0.2, rng=np.random.default_rng(seed))
+    p = H.build_problem(m)
+    k0 = 2 * math.pi / (10 * m.h)
+    ks = np.linspace(0.5 * k0, 1.5 * k0, nsys)
+    kap = [complex(k * k, 0.01 * k * k) for k in ks]
+    rng = np.random.default_rng(seed + 1)
+    B = np.zeros((p.n, 64), dtype=np.complex128)
+    for j in range(nsys):
+        b = crandn(rng, p.n)
+        b[p.dirichlet] = 0
+        B[:, j] = b
+    return p, kap, B
+
+
+@pytest.mark.parametrize("nc,nsys", [(6, 64), (7, 5)])
+def test_sweep_small_matches_oracle(hk, oracle, nc, nsys):
+    p, kap, B = sweep_inputs(nc, nsys)
+    say("sweep", nc, nsys)
+    X, infos = hk.sweep_solve(dev(p.rowptr), dev(p.col), dev(p.K), dev(p.M), kap, dev(B), tol=1e-10)
+    Xh = host(X)
+    for j in range(nsys):
+        val = H.helmholtz_values(p, kap[j])
+        xo, oi = oracle.bicgstab(p.rowptr, p.col, val, B[:, j], tol=1e-10)
+        assert infos[j]["status"] == 0, (j, infos[j])
+        assert np.linalg.norm(Xh[:, j] - xo) <= 1e-7 * np.linalg.norm(xo), j
+        assert abs(infos[j]["iters"] - oi["iters"]) <= max(2, 0.1 * oi["iters"]), (j, infos[j], oi)
+        r = oracle.residual(p.rowptr, p.col, val, B[:, j], Xh[:, j])
+        assert abs(np.linalg.norm(r) / np.linalg.norm(B[:, j]) - infos[j]["relres_true"]) <= 1e-12
+    assert np.all(Xh[:, nsys:] == 0)
+
+
+def test_sweep_iteration_cap_and_zero_rhs(hk, oracle):
+    p, kap, B = sweep_inputs(5, 3)
+    B[:, 1] = 0
+    say("sweep cap")
+    X, infos = hk.sweep_solve(dev(p.rowptr), dev(p.col), dev(p.K), dev(p.M), kap, dev(B), tol=1e-14,
+                              max_iter=4)
+    assert infos[1]["status"] == 0 and infos[1]["iters"] == 0
+    for j in (0, 2):
+        assert infos[j]["status"] == hk.HK_NOT_CONVERGED and infos[j]["iters"] == 4
+        val = H.helmholtz_values(p, kap[j])
+        xo, _ = oracle.bicgstab(p.rowptr, p.col, val, B[:, j], tol=1e-14, maxit=4)
+        assert np.linalg.norm(host(X)[:, j] - xo) <= 1e-12 * np.linalg.norm(xo)
+
+
+def blockdiag_inputs(sizes, seed=2):
+    rng = np.random.default_rng(seed)
+    rows, cols, vals, bs, offs = [], [], [], [], [0]
+    for ns in sizes:
+        m = H.make_mesh(ns, ns, ns, 1.0 / ns)
+        p = H.build_problem(m)
+        k = 2 * math.pi * ns / 10
+        v = H.helmholtz_values(p, complex(k * k, 0.01 * k * k))
+        b = crandn(rng, p.n)
+        b[p.dirichlet] = 0
+        rows.append(p.rowptr[:-1] + sum(c.shape[0] for c in cols))
+        cols.append(p.col + offs[-1])
+        vals.append(v)
+        bs.append(b)
+        offs.append(offs[-1] + p.n)
+    nnz = sum(c.shape[0] for c in cols)
+    rowptr = np.concatenate(rows + [np.array([nnz])]).astype(np.int32)
+    return (rowptr, np.concatenate(cols).astype(np.int32), np.concatenate(vals), np.concatenate(bs),
+            np.array(offs, dtype=np.int64))
+
+
+def test_blockdiag_small_matches_oracle(hk, oracle):
+    sizes = [5, 3, 8, 4, 6, 2, 7]
+    rowptr, col, val, b, offs = blockdiag_inputs(sizes)
+    A = hk.CSR(dev(rowptr), dev(col), dev(val))
+    say("blockdiag small", sizes)
+    x, infos = hk.blockdiag_solve(A, offs, dev(b), tol=1e-10)
+    xh = host(x)
+    for k in range(len(sizes)):
+        lo, hi = offs[k], offs[k + 1]
+        rp = rowptr[lo:hi + 1] - rowptr[lo]
+        cc = col[rowptr[lo]:rowptr[hi]] - lo
+        vv = val[rowptr[lo]:rowptr[hi]]
+        xo, oi = oracle.bicgstab(rp, cc, vv, b[lo:hi], tol=1e-10)
+        assert infos[k]["status"] == 0, (k, infos[k])
+        assert np.linalg.norm(xh[lo:hi] - xo) <= 1e-7 * np.linalg.norm(xo), k
+        assert abs(infos[k]["iters"] - oi["iters"]) <= max(2, 0.1 * oi["iters"]), (k, infos[k], oi)
+
+
+def test_blockdiag_rejects_coupled_systems(hk):
+    rowptr, col, val, b, offs = blockdiag_inputs([3, 3])
+    A = hk.CSR(dev(rowptr), dev(col), dev(val))
+    say("blockdiag bad offsets")
+    with pytest.raises(hk.HKError):
+        hk.blockdiag_solve(A, [0, 30, int(offs[-1])], dev(b))
+
+
+def test_sweep_config4a_full(hk, oracle):
+    """64 frequencies on the 48^3 jittered mesh (117,649 nodes), tol 1e-8."""
+    c = configs.config4a()
+    n = int(c["n"])
+    kap = [complex(a, b) for a, b in c["kappa2"]]
+    B = np.repeat(c["g"][:, None], 64, axis=1)
+    say("sweep config4a")
+    X, infos = hk.sweep_solve(dev(c["rowptr"]), dev(c["col"]), dev(c["K"]), dev(c["M"]), kap, dev(B),
+                              tol=1e-8)
+    Xh = host(X)
+    say("iters", [i["iters"] for i in infos])
+    for j in range(64):
+        assert infos[j]["status"] == 0, (j, infos[j])
+        val = np.empty(c["K"].shape[0], dtype=np.complex128)
+        val.real = c["K"] - kap[j].real * c["M"]
+        val.imag = -kap[j].imag * c["M"]
+        r = oracle.residual(c["rowptr"], c["col"], val, c["g"], Xh[:, j])
+        assert np.linalg.norm(r) / np.linalg.norm(c["g"]) <= 1.05e-8, j
+    assert n == 117649
+
+
+def test_blockdiag_config4b_full(hk, oracle):
+    """32 unjittered cubes with 8..48 cells per side (1,073,278 rows), tol 1e-8."""
+    systems = configs.config4b_systems()
+    offs = [0]
+    rows, cols, vals, bs = [], [], [], []
+    for s in systems:
+        rows.append(s["rowptr"][:-1] + sum(c.shape[0] for c in cols))
+        cols.append(s["col"] + offs[-1])
+        vals.append(s["val"])
+        bs.append(s["g"])
+        offs.append(offs[-1] + int(s["n"]))
+    nnz = sum(c.shape[0] for c in cols)
+    rowptr = np.concatenate(rows + [np.array([nnz])]).astype(np.int32)
+    col = np.concatenate(cols).astype(np.int32)
+    val = np.concatenate(vals)
+    b = np.concatenate(bs)
+    A = hk.CSR(dev(rowptr), dev(col), dev(val), autotune=True)
+    say("blockdiag config4b", offs[-1])
+    x, infos = hk.blockdiag_solve(A, offs, dev(b), tol=1e-8)
+    xh = host(x)
+    say("iters", [i["iters"] for i in infos])
+    for k, s in enumerate(systems):
+        lo, hi = offs[k], offs[k + 1]
+        assert infos[k]["status"] == 0, (k, infos[k])
+        r = oracle.residual(s["rowptr"], s["col"], s["val"], s["g"], xh[lo:hi])
+        assert np.linalg.norm(r) / np.linalg.norm(s["g"]) <= 1.05e-8, k
+    assert offs[-1] == 1073278
