@@ -37,6 +37,89 @@ def spmv_bytes(n, nnz):
     return 4 * (n + 1) + 20 * nnz + 32 * n
 
 
+def bench_batched(hk, torch, np, dev, log):
+    """Batched persistent solves vs the plain solver on the same systems.
+
+    Frequency sweep: 64 wavenumbers on the 48^3 jittered mesh (117,649 nodes),
+    one launch; the plain-solver reference runs every 8th frequency and is
+    scaled by 8 (marked extrapolated).  Uneven batch: 32 cubes of 8..48 cells
+    per side (1,073,278 rows) in one launch vs 32 plain solves.
+    """
+    from synth import configs
+    res = {}
+    c = configs.config4a()
+    kap = [complex(a, b) for a, b in c["kappa2"]]
+    B = torch.from_numpy(np.repeat(c["g"][:, None], 64, axis=1)).to(dev)
+    rp, cl = torch.from_numpy(c["rowptr"]).to(dev), torch.from_numpy(c["col"]).to(dev)
+    Kd, Md = torch.from_numpy(c["K"]).to(dev), torch.from_numpy(c["M"]).to(dev)
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    X, infos = hk.sweep_solve(rp, cl, Kd, Md, kap, B, tol=1e-8)
+    torch.cuda.synchronize()
+    t_sweep = time.perf_counter() - ts
+    its = [i["iters"] for i in infos]
+    log(f"sweep 64 systems: {t_sweep:.3f} s, iters {min(its)}..{max(its)}, "
+        f"worst relres {max(i['relres_true'] for i in infos):.2e}")
+    g = torch.from_numpy(c["g"]).to(dev)
+    t_plain, it_plain = 0.0, []
+    for j in range(0, 64, 8):
+        v = np.empty(c["K"].shape[0], dtype=np.complex128)
+        v.real = c["K"] - kap[j].real * c["M"]
+        v.imag = -kap[j].imag * c["M"]
+        A = hk.CSR(rp, cl, torch.from_numpy(v).to(dev), autotune=True)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        _, inf = hk.krylov_solve(A, g, tol=1e-8)
+        torch.cuda.synchronize()
+        t_plain += time.perf_counter() - ts
+        it_plain.append(inf["iters"])
+    log(f"plain every 8th frequency: {t_plain:.3f} s x 8 (iters {it_plain})")
+    res["solve_sweep"] = {"systems": 64, "n": int(c["n"]), "time_s": round(t_sweep, 4),
+                          "iters_min": min(its), "iters_max": max(its),
+                          "status_all_ok": all(i["status"] == 0 for i in infos),
+                          "relres_true_max": max(i["relres_true"] for i in infos),
+                          "plain_time_s_extrapolated": round(8 * t_plain, 4),
+                          "speedup_vs_plain": round(8 * t_plain / t_sweep, 3)}
+    systems = configs.config4b_systems()
+    offs, rows, cols, vals, bs = [0], [], [], [], []
+    for sy in systems:
+        rows.append(sy["rowptr"][:-1] + sum(x.shape[0] for x in cols))
+        cols.append(sy["col"] + offs[-1])
+        vals.append(sy["val"])
+        bs.append(sy["g"])
+        offs.append(offs[-1] + int(sy["n"]))
+    nnz = sum(x.shape[0] for x in cols)
+    rowptr = np.concatenate(rows + [np.array([nnz])]).astype(np.int32)
+    A = hk.CSR(torch.from_numpy(rowptr).to(dev), torch.from_numpy(np.concatenate(cols).astype(np.int32)).to(dev),
+               torch.from_numpy(np.concatenate(vals)).to(dev), autotune=True)
+    b = torch.from_numpy(np.concatenate(bs)).to(dev)
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    _, infos = hk.blockdiag_solve(A, offs, b, tol=1e-8)
+    torch.cuda.synchronize()
+    t_bd = time.perf_counter() - ts
+    its = [i["iters"] for i in infos]
+    log(f"uneven batch 32 systems: {t_bd:.3f} s, iters {min(its)}..{max(its)}")
+    t_seq = 0.0
+    for sy in systems:
+        As = hk.CSR(torch.from_numpy(sy["rowptr"]).to(dev), torch.from_numpy(sy["col"]).to(dev),
+                    torch.from_numpy(sy["val"]).to(dev), autotune=True)
+        gs = torch.from_numpy(sy["g"]).to(dev)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        hk.krylov_solve(As, gs, tol=1e-8)
+        torch.cuda.synchronize()
+        t_seq += time.perf_counter() - ts
+    log(f"32 plain solves: {t_seq:.3f} s")
+    res["solve_uneven"] = {"systems": 32, "rows": offs[-1], "time_s": round(t_bd, 4),
+                           "iters_min": min(its), "iters_max": max(its),
+                           "status_all_ok": all(i["status"] == 0 for i in infos),
+                           "relres_true_max": max(i["relres_true"] for i in infos),
+                           "plain_sequential_time_s": round(t_seq, 4),
+                           "speedup_vs_plain": round(t_seq / t_bd, 3)}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -47,6 +130,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-solve", action="store_true", help="CSR products only (profiling runs)")
+    ap.add_argument("--plan", default="", help="force the CSR launch shape 'L,U,grid' instead of tuning")
+    ap.add_argument("--no-batched", dest="batched", action="store_false",
+                    help="skip the batched sweep / uneven-batch extras")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -73,7 +159,9 @@ def main():
     rng = np.random.default_rng(123)
     x = torch.from_numpy(rng.standard_normal(n) + 1j * rng.standard_normal(n)).to(dev)
     y = torch.empty_like(x)
-    A = hk.CSR(rowptr, col, val, autotune=True)
+    A = hk.CSR(rowptr, col, val, autotune=not args.plan)
+    if args.plan:
+        A.set_plan(*[int(v) for v in args.plan.split(",")])
     plan = A.plan()
     log("plan", plan)
     stream = torch.cuda.current_stream()
@@ -161,6 +249,20 @@ def main():
         out["solve_mixed"] = {"inner_tol": 1e-4, "outer_tol": 1e-10, "outer": im["iters"],
                               "inner_iters": im["inner_iters"], "status": im["status"],
                               "relres_true": im["relres_true"], "time_s": round(tm, 4)}
+        # same accuracy as the plain solve (1e-8), for the like-for-like comparison
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        xm8, im8 = hk.krylov_solve_mixed(A, g, inner_tol=1e-4, outer_tol=1e-8)
+        torch.cuda.synchronize()
+        tm8 = time.perf_counter() - ts
+        log("mixed to 1e-8", im8, f"{tm8:.3f}s")
+        out["solve_mixed_1e-8"] = {"inner_tol": 1e-4, "outer_tol": 1e-8, "outer": im8["iters"],
+                                   "inner_iters": im8["inner_iters"], "status": im8["status"],
+                                   "relres_true": im8["relres_true"], "time_s": round(tm8, 4)}
+        if "solve_plain" in out:
+            out["solve_mixed_1e-8"]["speedup_vs_plain"] = round(out["solve_plain"]["time_s_mean"] / tm8, 3)
+    if args.batched and not args.no_solve:
+        out.update(bench_batched(hk, torch, np, dev, log))
     if not args.no_cpu:
         from oracle import oracle
         xh = x.cpu().numpy()

@@ -85,7 +85,8 @@ int hk_csr_plan(hk_csr A, int32_t* lanes_per_row, int32_t* rows_per_group, int32
                 int32_t* tuned);
 
 /* Override the launch shape (lanes_per_row in {4,8,16,32}, rows_per_group in
- * {1,2,4}, grid > 0 or 0 for one workgroup per tile). */
+ * {1,2,4,8} and not above lanes_per_row, grid > 0 or 0 for one workgroup per
+ * tile); anything else gives HK_EINVAL. */
 int hk_csr_set_plan(hk_csr A, int32_t lanes_per_row, int32_t rows_per_group, int32_t grid);
 
 /*

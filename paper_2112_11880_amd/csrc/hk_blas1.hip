@@ -4,28 +4,29 @@
 // 16-byte complex per lane per vector.  Dots and the norm follow the
 // paper's two-task scheme (element-wise product, then sum): each workgroup
 // reduces a contiguous chunk (wave butterfly, then across its 4 waves) into
-// one partial, and the last workgroup to finish sums the partials in a
-// fixed order and writes the result to device memory, so no host copy is
-// needed and the result is bitwise reproducible.
+// one partial, and a one-workgroup kernel sums the partials in a fixed order
+// and writes the result to device memory, so no host copy is needed and the
+// result is bitwise reproducible.
 #include "hk_common.hpp"
 #include "hk_internal.hpp"
 
 namespace hk {
 
-constexpr int kRedMaxBlocks = 1024;
+constexpr int kRedMaxBlocks = 4096;
 
+// workgroups of a reduction over n elements: at least 8 elements per thread,
+// at most kRedMaxBlocks workgroups (each then walks a longer chunk)
 static int reduce_blocks(int64_t n) {
-  int64_t b = (n + kBlock * 4 - 1) / (kBlock * 4);
+  int64_t b = (n + kBlock * 8 - 1) / (kBlock * 8);
   if (b < 1) b = 1;
   return (int)(b > kRedMaxBlocks ? kRedMaxBlocks : b);
 }
 
-// KIND 0: x^H y, 1: x^T y, 2: ||x||^2 (then sqrt)
+// First stage. KIND 0: x^H y, 1: x^T y, 2: ||x||^2.  Each workgroup reduces
+// a contiguous chunk, 4 independent loads per vector in flight per thread.
 template <int KIND>
 __global__ __launch_bounds__(kBlock) void k_reduce(int64_t n, const double2* __restrict__ x,
-                                                   const double2* __restrict__ y,
-                                                   double* partials, unsigned* ticket,
-                                                   double* __restrict__ out) {
+                                                   const double2* __restrict__ y, double* partials) {
   __shared__ double lds[2 * (kBlock / kWave)];
   const int nb = gridDim.x;
   const int lb = xcd_block(blockIdx.x, nb);
@@ -59,12 +60,19 @@ __global__ __launch_bounds__(kBlock) void k_reduce(int64_t n, const double2* __r
   v[0] = acc.x;
   if (NV == 2) v[NV - 1] = acc.y;
   block_sum<NV>(v, lds);
+  store_block_partials<NV>(v, partials);
+}
+
+// Second stage (one workgroup): the result, written to device memory.
+template <int KIND>
+__global__ __launch_bounds__(kFinBlock) void k_reduce_fin(const double* partials, int nb, double* out) {
+  constexpr int NV = KIND == 2 ? 1 : 2;
+  __shared__ double lds[NV * (kFinBlock / kWave)];
   double tot[NV];
-  if (last_block_reduce<NV>(v, partials, ticket, tot, lds)) {
-    if (threadIdx.x == 0) {
-      if (KIND == 2) out[0] = sqrt(tot[0]);
-      else { out[0] = tot[0]; out[NV - 1] = tot[NV - 1]; }
-    }
+  final_sum<NV>(partials, nb, tot, lds);
+  if (threadIdx.x == 0) {
+    if (KIND == 2) out[0] = sqrt(tot[0]);
+    else { out[0] = tot[0]; out[NV - 1] = tot[NV - 1]; }
   }
 }
 
@@ -94,14 +102,16 @@ static dim3 ew_grid(int64_t n) { return dim3((unsigned)((n + kBlock - 1) / kBloc
 template <int KIND>
 static int reduce(int64_t n, const void* x, const void* y, void* res, void* stream, const char* who) {
   if (n <= 0 || !x || !res || (KIND != 2 && !y)) HK_FAIL(HK_EINVAL, "%s: bad argument (n=%lld)", who, (long long)n);
-  if (n > (int64_t)kRedMaxBlocks * (int64_t)(1ll << 40)) HK_FAIL(HK_EINVAL, "%s: n too large", who);
   hipStream_t s = as_stream(stream);
   const int nb = reduce_blocks(n);
   ReduceScratch* rs = nullptr;
   int rc = reduce_scratch(s, sizeof(double) * 2 * nb, &rs);
   if (rc != HK_OK) return rc;
   hipLaunchKernelGGL(k_reduce<KIND>, dim3(nb), dim3(kBlock), 0, s, n, (const double2*)x,
-                     (const double2*)y, (double*)rs->partials, rs->ticket, (double*)res);
+                     (const double2*)y, (double*)rs->partials);
+  HK_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_reduce_fin<KIND>, dim3(1), dim3(kFinBlock), 0, s, (const double*)rs->partials, nb,
+                     (double*)res);
   HK_CHECK_LAUNCH();
   return HK_OK;
 }

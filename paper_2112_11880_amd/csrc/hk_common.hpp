@@ -107,40 +107,44 @@ template <int NV, class T> __device__ __forceinline__ void block_sum(T (&v)[NV],
   }
 }
 
-// Two-stage reduction, second stage by the last block to arrive.
-// Each block stores its NV partials at partials[k * nblocks + block]; the
-// block that takes the last ticket sums them in block order with a fixed
-// tree and returns true (in every thread of that block) with the totals in
-// out[] (valid in thread 0).  The ticket counter is reset for the next use.
+// First stage of a two-stage reduction: thread 0 stores the block's NV
+// totals at partials[k * gridDim.x + blockIdx.x].  No fence or atomic: the
+// second stage runs in a later kernel on the same stream, and the kernel
+// boundary makes these stores visible.  (A per-workgroup release fence here
+// costs an L2 write-back on gfx950 and made reduction kernels 4-6x slower.)
 template <int NV, class T>
-__device__ __forceinline__ bool last_block_reduce(const T (&mine)[NV], T* partials, unsigned* ticket,
-                                                  T (&out)[NV], T* lds) {
-  __shared__ bool is_last;
-  const int nb = gridDim.x;
+__device__ __forceinline__ void store_block_partials(const T (&v)[NV], T* partials) {
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int k = 0; k < NV; ++k) partials[k * nb + blockIdx.x] = mine[k];
-    __threadfence();
-    unsigned t = atomicAdd(ticket, 1u);
-    is_last = (t == (unsigned)nb - 1);
+    for (int k = 0; k < NV; ++k) partials[k * gridDim.x + blockIdx.x] = v[k];
   }
-  __syncthreads();
-  if (!is_last) return false;
-  __threadfence();
-  T v[NV];
+}
+
+constexpr int kFinBlock = 1024;  // threads of a second-stage (finalize) kernel
+
+// Second stage, run by one workgroup of kFinBlock threads: out[k] (valid in
+// thread 0) = sum over nb partials, each thread summing a strided subset in
+// index order, then a fixed tree over the waves.
+template <int NV, class T>
+__device__ __forceinline__ void final_sum(const T* partials, int nb, T (&out)[NV], T* lds /*[NV*16]*/) {
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  constexpr int W = kFinBlock / kWave;
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
     T s = 0;
-    for (int j = threadIdx.x; j < nb; j += kBlock) s += partials[k * nb + j];
-    v[k] = s;
+    for (int j = threadIdx.x; j < nb; j += kFinBlock) s += partials[k * nb + j];
+    s = wave_sum(s);
+    if (lane == 0) lds[k * W + w] = s;
   }
-  block_sum<NV>(v, lds);
+  __syncthreads();
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int k = 0; k < NV; ++k) out[k] = v[k];
-    atomicExch(ticket, 0u);
+    for (int k = 0; k < NV; ++k) {
+      T s = lds[k * W];
+      for (int j = 1; j < W; ++j) s += lds[k * W + j];
+      out[k] = s;
+    }
   }
-  return true;
 }
 
 }  // namespace hk

@@ -34,13 +34,11 @@ const char* error_text();
 
 inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
-// Per-(device, stream) scratch for the two-stage reductions of the BLAS-1
-// entry points: partial sums plus a zeroed ticket counter.  Grows on demand;
-// lives until the process ends.
+// Per-(device, stream) scratch for the partial sums of the BLAS-1
+// reductions.  Grows on demand; lives until the process ends.
 struct ReduceScratch {
   void* partials = nullptr;
   size_t bytes = 0;
-  unsigned* ticket = nullptr;
 };
 int reduce_scratch(hipStream_t s, size_t bytes, ReduceScratch** out);
 

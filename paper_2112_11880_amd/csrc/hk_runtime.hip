@@ -27,11 +27,6 @@ int reduce_scratch(hipStream_t s, size_t bytes, ReduceScratch** out) {
   HK_HIP(hipGetDevice(&dev));
   std::lock_guard<std::mutex> lock(mu);
   ReduceScratch& r = pool[{dev, s}];
-  if (r.ticket == nullptr) {
-    // the counter must start at zero; every reduction leaves it at zero
-    HK_HIP(hipMalloc(&r.ticket, 64));
-    HK_HIP(hipMemset(r.ticket, 0, 64));
-  }
   if (r.bytes < bytes) {
     if (r.partials) {
       HK_HIP(hipStreamSynchronize(s));

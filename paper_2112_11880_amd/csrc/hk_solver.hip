@@ -2,12 +2,13 @@
 // device-resident scalars, and the complex64/complex128 refinement loop.
 //
 // The paper's P-BiCGSTAB (Section 4) copies every dot product and norm back
-// to the host.  Here each reduction ends in the last workgroup of the kernel
-// that produced its terms, which also updates the scalars (rho, alpha,
-// omega, beta), tests convergence / breakdown and writes a status word, all
-// in device memory.  The host enqueues iterations in chunks and reads the
-// status word once per chunk; kernels enqueued after the solve has ended
-// return at once.
+// to the host.  Here every reduction stays on the device: the kernel that
+// produces the terms stores one partial sum per workgroup, and a one-
+// workgroup finalize kernel sums them in a fixed order, updates the scalars
+// (rho, alpha, omega, beta), tests convergence / breakdown and writes a
+// status word.  The host enqueues iterations in chunks and reads the status
+// word once per chunk; kernels enqueued after the solve has ended return at
+// once.
 //
 // Jacobi is applied on the right by scaling the columns once per solve:
 // Ahat = A D^-1 (a workspace copy of the values), and the iteration runs the
@@ -15,7 +16,7 @@
 // Mathematically this is the preconditioned method with phat = D^-1 p and
 // shat = D^-1 s; it saves one vector pass per preconditioner application.
 //
-// One iteration is five kernels:
+// One iteration (each reduction followed by its finalize kernel):
 //   K_p   : p = r + beta (p - omega v)                      (iteration > 1)
 //   K_v   : v = Ahat p,  sigma = rhat^H v  -> alpha = rho / sigma
 //   K_s   : s = r - alpha v, ||s||^2       -> half-step convergence test
@@ -87,15 +88,14 @@ __global__ void k_scale_cols(int n, const int* __restrict__ rowptr, const int* _
 }
 
 // Start of the iteration: r = b - A x0 (already in r when use_x0) or r = b,
-// rhat = p = r, y = x0 / dinv or 0; ||b||^2 and ||r||^2 -> state.
+// rhat = p = r, y = x0 / dinv or 0; partials of ||b||^2 and ||r||^2.
 template <class R>
 __global__ __launch_bounds__(kBlock) void k_init(int n, int use_x0, const cplx<R>* __restrict__ b,
                                                  const cplx<R>* __restrict__ x0,
                                                  const cplx<R>* __restrict__ dinv,
                                                  cplx<R>* __restrict__ r, cplx<R>* __restrict__ rh,
                                                  cplx<R>* __restrict__ p, cplx<R>* __restrict__ y,
-                                                 R tol, long long maxit, SolveState<R>* st,
-                                                 R* partials, unsigned* ticket) {
+                                                 R* partials) {
   using V = cplx<R>;
   __shared__ R lds[2 * (kBlock / kWave)];
   R acc[2] = {0, 0};
@@ -120,26 +120,7 @@ __global__ __launch_bounds__(kBlock) void k_init(int n, int use_x0, const cplx<R
     acc[1] += cabs2(ri);
   }
   block_sum<2>(acc, lds);
-  R tot[2];
-  if (last_block_reduce<2>(acc, partials, ticket, tot, lds) && threadIdx.x == 0) {
-    st->bb = tot[0];
-    st->rr = tot[1];
-    st->theta2 = tol * tol * tot[0];
-    st->rho = cmake<V>(tot[1], 0);
-    st->rho_old = cmake<V>(1, 0);
-    st->alpha = cmake<V>(1, 0);
-    st->omega = cmake<V>(1, 0);
-    st->beta = czero<V>();
-    st->iter = 1;
-    st->maxit = maxit;
-    st->iters_done = 0;
-    st->bd = HK_BD_NONE;
-    if (!isfinite(tot[0]) || !isfinite(tot[1])) st->status = HK_NONFINITE;
-    else if (tot[1] <= st->theta2) st->status = HK_OK;
-    else if (maxit <= 0) st->status = HK_NOT_CONVERGED;
-    else st->status = S_RUN;
-    if (st->history) st->history[0] = tot[0] > 0 ? sqrt((double)tot[1] / (double)tot[0]) : 0.0;
-  }
+  store_block_partials<2>(acc, partials);
 }
 
 // ----------------------------------------------------------- iteration kernels
@@ -158,8 +139,8 @@ __global__ __launch_bounds__(kBlock) void k_p(int n, const SolveState<R>* __rest
   p[i] = cfma(beta, q, r[i]);
 }
 
-// v = Ahat p and sigma = rhat^H v  (DOT == 1), or
-// t = Ahat s, tau = t^H t and t^H s (DOT == 2).
+// v = Ahat p and partials of sigma = rhat^H v  (DOT == 1), or
+// t = Ahat s and partials of tau = t^H t, t^H s (DOT == 2).
 template <int L, int U, class R, int DOT>
 __global__ __launch_bounds__(kBlock) void k_spmv_dot(int n, int ntiles, const int* __restrict__ rowptr,
                                                      const int* __restrict__ col,
@@ -167,7 +148,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dot(int n, int ntiles, const in
                                                      const cplx<R>* __restrict__ x,
                                                      cplx<R>* __restrict__ y,
                                                      const cplx<R>* __restrict__ w,
-                                                     SolveState<R>* st, R* partials, unsigned* ticket) {
+                                                     const SolveState<R>* __restrict__ st, R* partials) {
   using V = cplx<R>;
   constexpr int NV = DOT == 1 ? 2 : 3;
   __shared__ R lds[NV * (kBlock / kWave)];
@@ -181,6 +162,9 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dot(int n, int ntiles, const in
   for (int k = 0; k < NV; ++k) part[k] = 0;
   for (int t = t0; t < t1; ++t) {
     const int r0 = t * RT + g * U;
+    // the epilogue operand of the row this lane will write, loaded early
+    const int rw = r0 + (lane < U ? lane : 0);
+    const V wr = w[rw < n ? rw : n - 1];
     V acc[U];
     csr_rows<L, U, V>(r0, n, rowptr, col, val, x, acc);
 #pragma unroll
@@ -188,7 +172,6 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dot(int n, int ntiles, const in
       const int r = r0 + u;
       if (lane == u && r < n) {
         y[r] = acc[u];
-        const V wr = w[r];
         if (DOT == 1) {
           // conj(rhat_r) * v_r
           part[0] = fma(wr.x, acc[u].x, fma(wr.y, acc[u].y, part[0]));
@@ -203,39 +186,14 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dot(int n, int ntiles, const in
     }
   }
   block_sum<NV>(part, lds);
-  R tot[NV];
-  if (last_block_reduce<NV>(part, partials, ticket, tot, lds) && threadIdx.x == 0) {
-    if (DOT == 1) {
-      const V sigma = cmake<V>(tot[0], tot[1]);
-      if (!cfinite(sigma)) {
-        st->status = HK_NONFINITE;
-        st->iters_done = st->iter - 1;
-      } else if (sigma.x == 0 && sigma.y == 0) {
-        st->status = HK_BREAKDOWN;
-        st->bd = HK_BD_SIGMA;
-        st->iters_done = st->iter - 1;
-      } else {
-        st->alpha = cdiv(st->rho, sigma);
-      }
-    } else {
-      const R tau = tot[0];
-      const V ts = cmake<V>(tot[1], tot[2]);
-      if (!isfinite(tau) || !cfinite(ts)) {
-        st->status = HK_NONFINITE;
-        st->iters_done = st->iter - 1;
-      } else if (tau == 0) {
-        st->status = S_TAUBD;
-      } else {
-        st->omega = cscale<V>(R(1) / tau, ts);
-      }
-    }
-  }
+  store_block_partials<NV>(part, partials);
 }
 
 template <class R>
-__global__ __launch_bounds__(kBlock) void k_s(int n, SolveState<R>* st, const cplx<R>* __restrict__ r,
+__global__ __launch_bounds__(kBlock) void k_s(int n, const SolveState<R>* __restrict__ st,
+                                              const cplx<R>* __restrict__ r,
                                               const cplx<R>* __restrict__ v, cplx<R>* __restrict__ s,
-                                              R* partials, unsigned* ticket) {
+                                              R* partials) {
   using V = cplx<R>;
   __shared__ R lds[kBlock / kWave];
   if (st->status != S_RUN) return;
@@ -264,8 +222,155 @@ __global__ __launch_bounds__(kBlock) void k_s(int n, SolveState<R>* st, const cp
     }
   }
   block_sum<1>(acc, lds);
-  R tot[1];
-  if (last_block_reduce<1>(acc, partials, ticket, tot, lds) && threadIdx.x == 0) {
+  store_block_partials<1>(acc, partials);
+}
+
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_xr(int n, const SolveState<R>* __restrict__ st,
+                                               const cplx<R>* __restrict__ rh,
+                                               cplx<R>* __restrict__ r, const cplx<R>* __restrict__ p,
+                                               const cplx<R>* __restrict__ s,
+                                               const cplx<R>* __restrict__ t, cplx<R>* __restrict__ y,
+                                               R* partials) {
+  using V = cplx<R>;
+  __shared__ R lds[3 * (kBlock / kWave)];
+  const int status = st->status;
+  if (status != S_RUN && status != S_HALF && status != S_TAUBD) return;
+  const V alpha = st->alpha, omega = st->omega;
+  const int base = blockIdx.x * (kBlock * kEw) + threadIdx.x;
+  if (status != S_RUN) {
+    // half-step exit (converged on s) or tau breakdown: y += alpha p
+#pragma unroll
+    for (int k = 0; k < kEw; ++k) {
+      const int i = base + k * kBlock;
+      if (i < n) y[i] = cfma(alpha, p[i], y[i]);
+    }
+    return;
+  }
+  R acc[3] = {0, 0, 0};
+  // y += alpha p + omega s ; r = s - omega t ; ||r||^2 ; rhat^H r
+  auto upd = [&](int i, V si, V pi, V ti, V yi, V hi) {
+    y[i] = cfma(omega, si, cfma(alpha, pi, yi));
+    const V ri = csub(si, cmul(omega, ti));
+    r[i] = ri;
+    acc[0] += cabs2(ri);
+    acc[1] = fma(hi.x, ri.x, fma(hi.y, ri.y, acc[1]));
+    acc[2] = fma(hi.x, ri.y, fma(-hi.y, ri.x, acc[2]));
+  };
+  if (base + (kEw - 1) * kBlock < n) {
+    V sv[kEw], pv[kEw], tv[kEw], yv[kEw], hv[kEw];
+#pragma unroll
+    for (int k = 0; k < kEw; ++k) {
+      const int i = base + k * kBlock;
+      sv[k] = s[i]; pv[k] = p[i]; tv[k] = t[i]; yv[k] = y[i]; hv[k] = rh[i];
+    }
+#pragma unroll
+    for (int k = 0; k < kEw; ++k) upd(base + k * kBlock, sv[k], pv[k], tv[k], yv[k], hv[k]);
+  } else {
+#pragma unroll
+    for (int k = 0; k < kEw; ++k) {
+      const int i = base + k * kBlock;
+      if (i >= n) break;
+      upd(i, s[i], p[i], t[i], y[i], rh[i]);
+    }
+  }
+  block_sum<3>(acc, lds);
+  store_block_partials<3>(acc, partials);
+}
+
+// x = dinv .* y
+template <class V>
+__global__ void k_unscale(int n, const V* __restrict__ dinv, const V* __restrict__ y, V* __restrict__ x) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) x[i] = cmul(dinv[i], y[i]);
+}
+
+// partials of ||w||^2
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_norm2_partials(int n, const cplx<R>* __restrict__ w, R* partials) {
+  __shared__ R lds[kBlock / kWave];
+  R acc[1] = {0};
+  const int base = blockIdx.x * (kBlock * kEw) + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < kEw; ++k) {
+    const int i = base + k * kBlock;
+    if (i < n) acc[0] += cabs2(w[i]);
+  }
+  block_sum<1>(acc, lds);
+  store_block_partials<1>(acc, partials);
+}
+
+// ------------------------------------------------------------ finalize kernels
+
+enum : int { F_INIT = 0, F_SIGMA = 1, F_S = 2, F_OMEGA = 3, F_XR = 4, F_TRUE = 5 };
+
+template <int F> struct FinNV { static constexpr int v = 1; };
+template <> struct FinNV<F_INIT> { static constexpr int v = 2; };
+template <> struct FinNV<F_SIGMA> { static constexpr int v = 2; };
+template <> struct FinNV<F_OMEGA> { static constexpr int v = 3; };
+template <> struct FinNV<F_XR> { static constexpr int v = 3; };
+
+// One workgroup: sums the nb partials of the preceding kernel and applies
+// the scalar update of step F.
+template <class R, int F>
+__global__ __launch_bounds__(kFinBlock) void k_fin(SolveState<R>* st, const R* partials, int nb, R tol,
+                                                   long long maxit) {
+  using V = cplx<R>;
+  constexpr int NV = FinNV<F>::v;
+  __shared__ R lds[NV * (kFinBlock / kWave)];
+  const int status = st->status;
+  if (F == F_XR) {
+    if (status == S_HALF || status == S_TAUBD) {
+      if (threadIdx.x == 0) {
+        const long long it = st->iter;
+        st->rr = st->ss;
+        st->iters_done = it;
+        if (status == S_HALF) {
+          st->status = HK_OK;
+          if (st->history) st->history[it] = st->bb > 0 ? sqrt((double)st->ss / (double)st->bb) : 0.0;
+        } else {
+          st->status = HK_BREAKDOWN;
+          st->bd = HK_BD_TAU;
+        }
+      }
+      return;
+    }
+  }
+  if (F != F_INIT && F != F_TRUE && status != S_RUN) return;
+  R tot[NV];
+  final_sum<NV>(partials, nb, tot, lds);
+  if (threadIdx.x != 0) return;
+  if (F == F_INIT) {
+    st->bb = tot[0];
+    st->rr = tot[1];
+    st->theta2 = tol * tol * tot[0];
+    st->rho = cmake<V>(tot[1], 0);
+    st->rho_old = cmake<V>(1, 0);
+    st->alpha = cmake<V>(1, 0);
+    st->omega = cmake<V>(1, 0);
+    st->beta = czero<V>();
+    st->iter = 1;
+    st->maxit = maxit;
+    st->iters_done = 0;
+    st->bd = HK_BD_NONE;
+    if (!isfinite(tot[0]) || !isfinite(tot[1])) st->status = HK_NONFINITE;
+    else if (tot[1] <= st->theta2) st->status = HK_OK;
+    else if (maxit <= 0) st->status = HK_NOT_CONVERGED;
+    else st->status = S_RUN;
+    if (st->history) st->history[0] = tot[0] > 0 ? sqrt((double)tot[1] / (double)tot[0]) : 0.0;
+  } else if (F == F_SIGMA) {
+    const V sigma = cmake<V>(tot[0], tot[1]);
+    if (!cfinite(sigma)) {
+      st->status = HK_NONFINITE;
+      st->iters_done = st->iter - 1;
+    } else if (sigma.x == 0 && sigma.y == 0) {
+      st->status = HK_BREAKDOWN;
+      st->bd = HK_BD_SIGMA;
+      st->iters_done = st->iter - 1;
+    } else {
+      st->alpha = cdiv(st->rho, sigma);
+    }
+  } else if (F == F_S) {
     st->ss = tot[0];
     if (!isfinite(tot[0])) {
       st->status = HK_NONFINITE;
@@ -273,77 +378,22 @@ __global__ __launch_bounds__(kBlock) void k_s(int n, SolveState<R>* st, const cp
     } else if (tot[0] <= st->theta2) {
       st->status = S_HALF;
     }
-  }
-}
-
-template <class R>
-__global__ __launch_bounds__(kBlock) void k_xr(int n, SolveState<R>* st, const cplx<R>* __restrict__ rh,
-                                               cplx<R>* __restrict__ r, const cplx<R>* __restrict__ p,
-                                               const cplx<R>* __restrict__ s,
-                                               const cplx<R>* __restrict__ t, cplx<R>* __restrict__ y,
-                                               R* partials, unsigned* ticket) {
-  using V = cplx<R>;
-  __shared__ R lds[3 * (kBlock / kWave)];
-  const int status = st->status;
-  if (status != S_RUN && status != S_HALF && status != S_TAUBD) return;
-  const V alpha = st->alpha, omega = st->omega;
-  R acc[3] = {0, 0, 0};
-  const int base = blockIdx.x * (kBlock * kEw) + threadIdx.x;
-  if (status == S_RUN) {
-    // y += alpha p + omega s ; r = s - omega t ; ||r||^2 ; rhat^H r
-    auto upd = [&](int i, V si, V pi, V ti, V yi, V hi) {
-      y[i] = cfma(omega, si, cfma(alpha, pi, yi));
-      const V ri = csub(si, cmul(omega, ti));
-      r[i] = ri;
-      acc[0] += cabs2(ri);
-      acc[1] = fma(hi.x, ri.x, fma(hi.y, ri.y, acc[1]));
-      acc[2] = fma(hi.x, ri.y, fma(-hi.y, ri.x, acc[2]));
-    };
-    if (base + (kEw - 1) * kBlock < n) {
-      V sv[kEw], pv[kEw], tv[kEw], yv[kEw], hv[kEw];
-#pragma unroll
-      for (int k = 0; k < kEw; ++k) {
-        const int i = base + k * kBlock;
-        sv[k] = s[i]; pv[k] = p[i]; tv[k] = t[i]; yv[k] = y[i]; hv[k] = rh[i];
-      }
-#pragma unroll
-      for (int k = 0; k < kEw; ++k) upd(base + k * kBlock, sv[k], pv[k], tv[k], yv[k], hv[k]);
+  } else if (F == F_OMEGA) {
+    const R tau = tot[0];
+    const V ts = cmake<V>(tot[1], tot[2]);
+    if (!isfinite(tau) || !cfinite(ts)) {
+      st->status = HK_NONFINITE;
+      st->iters_done = st->iter - 1;
+    } else if (tau == 0) {
+      st->status = S_TAUBD;
     } else {
-#pragma unroll
-      for (int k = 0; k < kEw; ++k) {
-        const int i = base + k * kBlock;
-        if (i >= n) break;
-        upd(i, s[i], p[i], t[i], y[i], rh[i]);
-      }
+      st->omega = cscale<V>(R(1) / tau, ts);
     }
-  } else {
-    // half-step exit (converged on s) or tau breakdown: y += alpha p
-#pragma unroll
-    for (int k = 0; k < kEw; ++k) {
-      const int i = base + k * kBlock;
-      if (i < n) y[i] = cfma(alpha, p[i], y[i]);
-    }
-  }
-  block_sum<3>(acc, lds);
-  R tot[3];
-  if (last_block_reduce<3>(acc, partials, ticket, tot, lds) && threadIdx.x == 0) {
+  } else if (F == F_XR) {
     const long long it = st->iter;
-    if (status == S_HALF) {
-      st->status = HK_OK;
-      st->rr = st->ss;
-      st->iters_done = it;
-      if (st->history) st->history[it] = st->bb > 0 ? sqrt((double)st->ss / (double)st->bb) : 0.0;
-      return;
-    }
-    if (status == S_TAUBD) {
-      st->status = HK_BREAKDOWN;
-      st->bd = HK_BD_TAU;
-      st->rr = st->ss;
-      st->iters_done = it;
-      return;
-    }
     const R rr = tot[0];
     const V rho = cmake<V>(tot[1], tot[2]);
+    const V alpha = st->alpha, omega = st->omega;
     st->rr = rr;
     st->rho_old = st->rho;
     st->rho = rho;
@@ -366,31 +416,9 @@ __global__ __launch_bounds__(kBlock) void k_xr(int n, SolveState<R>* st, const c
       st->beta = cmul(cdiv(rho, st->rho_old), cdiv(alpha, omega));
       st->iter = it + 1;
     }
+  } else {  // F_TRUE
+    st->rr_true = tot[0];
   }
-}
-
-// x = dinv .* y
-template <class V>
-__global__ void k_unscale(int n, const V* __restrict__ dinv, const V* __restrict__ y, V* __restrict__ x) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i < n) x[i] = cmul(dinv[i], y[i]);
-}
-
-// ||w||^2 -> st->rr_true
-template <class R>
-__global__ __launch_bounds__(kBlock) void k_true_norm(int n, const cplx<R>* __restrict__ w, SolveState<R>* st,
-                                                      R* partials, unsigned* ticket) {
-  __shared__ R lds[kBlock / kWave];
-  R acc[1] = {0};
-  const int base = blockIdx.x * (kBlock * kEw) + threadIdx.x;
-#pragma unroll
-  for (int k = 0; k < kEw; ++k) {
-    const int i = base + k * kBlock;
-    if (i < n) acc[0] += cabs2(w[i]);
-  }
-  block_sum<1>(acc, lds);
-  R tot[1];
-  if (last_block_reduce<1>(acc, partials, ticket, tot, lds) && threadIdx.x == 0) st->rr_true = tot[0];
 }
 
 // --------------------------------------------------------- mixed-precision helpers
@@ -419,7 +447,6 @@ template <class R> struct Work {
   using V = cplx<R>;
   V *y, *r, *rh, *p, *v, *s, *t, *dinv, *ahat;
   R* partials;
-  unsigned* ticket;
   SolveState<R>* st;
   int* flag;
 };
@@ -429,8 +456,7 @@ static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 template <class R> static size_t work_bytes(int64_t n, int64_t nnz) {
   using V = cplx<R>;
   return 8 * align_up(sizeof(V) * n) + align_up(sizeof(V) * (nnz > 0 ? nnz : 1)) +
-         align_up(sizeof(R) * 4 * partial_slots(n)) + align_up(64) + align_up(sizeof(SolveState<R>)) +
-         align_up(64);
+         align_up(sizeof(R) * 4 * partial_slots(n)) + align_up(sizeof(SolveState<R>)) + align_up(64);
 }
 
 template <class R> static Work<R> carve(void* base, int64_t n, int64_t nnz) {
@@ -448,7 +474,6 @@ template <class R> static Work<R> carve(void* base, int64_t n, int64_t nnz) {
   w.dinv = (V*)take(sizeof(V) * n);
   w.ahat = (V*)take(sizeof(V) * (nnz > 0 ? nnz : 1));
   w.partials = (R*)take(sizeof(R) * 4 * partial_slots(n));
-  w.ticket = (unsigned*)take(64);
   w.st = (SolveState<R>*)take(sizeof(SolveState<R>));
   w.flag = (int*)take(64);
   return w;
@@ -464,8 +489,6 @@ static int ensure_ws(void** ws, size_t* have, size_t need, hipStream_t s) {
   }
   if (hipMalloc(ws, need) != hipSuccess) HK_FAIL(HK_ENOMEM, "solver workspace: hipMalloc(%zu) failed", need);
   *have = need;
-  // tickets must start at zero; every reduction leaves them at zero
-  HK_HIP(hipMemsetAsync(*ws, 0, need, s));
   return HK_OK;
 }
 
@@ -479,18 +502,24 @@ static hipError_t launch_spmv_dot(const hk_csr_s* A, int L, int U, int grid, int
   if (L == LL && U == UU) {                                                                         \
     if (dot == 1)                                                                                   \
       hipLaunchKernelGGL((k_spmv_dot<LL, UU, R, 1>), dim3(grid), dim3(kBlock), 0, s, n, ntiles,     \
-                         A->rowptr, A->col, val, x, y, w, wk.st, wk.partials, wk.ticket);           \
+                         A->rowptr, A->col, val, x, y, w, wk.st, wk.partials);                      \
     else                                                                                            \
       hipLaunchKernelGGL((k_spmv_dot<LL, UU, R, 2>), dim3(grid), dim3(kBlock), 0, s, n, ntiles,     \
-                         A->rowptr, A->col, val, x, y, w, wk.st, wk.partials, wk.ticket);           \
+                         A->rowptr, A->col, val, x, y, w, wk.st, wk.partials);                      \
     return hipGetLastError();                                                                       \
   }
   HK_SD_CASE(4, 1) HK_SD_CASE(4, 2) HK_SD_CASE(4, 4)
-  HK_SD_CASE(8, 1) HK_SD_CASE(8, 2) HK_SD_CASE(8, 4)
-  HK_SD_CASE(16, 1) HK_SD_CASE(16, 2) HK_SD_CASE(16, 4)
-  HK_SD_CASE(32, 1) HK_SD_CASE(32, 2) HK_SD_CASE(32, 4)
+  HK_SD_CASE(8, 1) HK_SD_CASE(8, 2) HK_SD_CASE(8, 4) HK_SD_CASE(8, 8)
+  HK_SD_CASE(16, 1) HK_SD_CASE(16, 2) HK_SD_CASE(16, 4) HK_SD_CASE(16, 8)
+  HK_SD_CASE(32, 1) HK_SD_CASE(32, 2) HK_SD_CASE(32, 4) HK_SD_CASE(32, 8)
 #undef HK_SD_CASE
   return hipErrorInvalidValue;
+}
+
+template <class R, int F>
+static hipError_t launch_fin(const Work<R>& wk, int nb, R tol, long long maxit, hipStream_t s) {
+  hipLaunchKernelGGL((k_fin<R, F>), dim3(1), dim3(kFinBlock), 0, s, wk.st, wk.partials, nb, tol, maxit);
+  return hipGetLastError();
 }
 
 // Runs the whole solve for precision R on values `val` (A's pattern), right
@@ -523,11 +552,12 @@ static int bicgstab(const hk_csr_s* A, const cplx<R>* val, const cplx<R>* b, cpl
   }
   SolveState<R> init{};
   init.history = o.d_history;
+  init.status = S_RUN;
   HK_HIP(hipMemcpyAsync(wk.st, &init, sizeof(init), hipMemcpyHostToDevice, s));
   hipLaunchKernelGGL(k_init<R>, dim3(gv), dim3(kBlock), 0, s, n, o.use_x0 ? 1 : 0, b, x, wk.dinv,
-                     wk.r, wk.rh, wk.p, wk.y, (R)o.tol, (long long)o.max_iter, wk.st, wk.partials,
-                     wk.ticket);
+                     wk.r, wk.rh, wk.p, wk.y, wk.partials);
   HK_CHECK_LAUNCH();
+  HK_HIP((launch_fin<R, F_INIT>(wk, gv, (R)o.tol, (long long)o.max_iter, s)));
   int hflag = 0;
   HK_HIP(hipMemcpyAsync(&hflag, wk.flag, sizeof(int), hipMemcpyDeviceToHost, s));
   HK_HIP(hipStreamSynchronize(s));
@@ -549,18 +579,21 @@ static int bicgstab(const hk_csr_s* A, const cplx<R>* val, const cplx<R>* b, cpl
       hipError_t e = hipGetLastError();
       if (e == hipSuccess)
         e = launch_spmv_dot<R>(A, A->plan.L, A->plan.U, gs, 1, wk.ahat, wk.p, wk.v, wk.rh, wk, s);
+      if (e == hipSuccess) e = launch_fin<R, F_SIGMA>(wk, gs, 0, 0, s);
       if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_s<R>, dim3(gv), dim3(kBlock), 0, s, n, wk.st, wk.r, wk.v, wk.s,
-                           wk.partials, wk.ticket);
+        hipLaunchKernelGGL(k_s<R>, dim3(gv), dim3(kBlock), 0, s, n, wk.st, wk.r, wk.v, wk.s, wk.partials);
         e = hipGetLastError();
       }
+      if (e == hipSuccess) e = launch_fin<R, F_S>(wk, gv, 0, 0, s);
       if (e == hipSuccess)
         e = launch_spmv_dot<R>(A, A->plan.L, A->plan.U, gs, 2, wk.ahat, wk.s, wk.t, wk.s, wk, s);
+      if (e == hipSuccess) e = launch_fin<R, F_OMEGA>(wk, gs, 0, 0, s);
       if (e == hipSuccess) {
         hipLaunchKernelGGL(k_xr<R>, dim3(gv), dim3(kBlock), 0, s, n, wk.st, wk.rh, wk.r, wk.p, wk.s,
-                           wk.t, wk.y, wk.partials, wk.ticket);
+                           wk.t, wk.y, wk.partials);
         e = hipGetLastError();
       }
+      if (e == hipSuccess) e = launch_fin<R, F_XR>(wk, gv, 0, 0, s);
       if (e != hipSuccess) {
         set_error_text("krylov solve: launch failed: %s", hipGetErrorString(e));
         rc = HK_EHIP;
@@ -594,9 +627,9 @@ static int bicgstab(const hk_csr_s* A, const cplx<R>* val, const cplx<R>* b, cpl
     int rc2 = spmv_dispatch(&tmp, x, wk.t, b, nullptr, nullptr, 1, s);
     if (rc2 != HK_OK) return rc2;
   }
-  hipLaunchKernelGGL(k_true_norm<R>, dim3(gv), dim3(kBlock), 0, s, n, wk.t, wk.st, wk.partials,
-                     wk.ticket);
+  hipLaunchKernelGGL(k_norm2_partials<R>, dim3(gv), dim3(kBlock), 0, s, n, wk.t, wk.partials);
   HK_CHECK_LAUNCH();
+  HK_HIP((launch_fin<R, F_TRUE>(wk, gv, 0, 0, s)));
   SolveState<R> hs;
   HK_HIP(hipMemcpyAsync(&hs, wk.st, sizeof(hs), hipMemcpyDeviceToHost, s));
   HK_HIP(hipStreamSynchronize(s));

@@ -69,9 +69,15 @@ __global__ void k_csr_check(int n, int nnz, const int* __restrict__ rowptr,
 
 // ------------------------------------------------------------- dispatch
 
+// Row u of a lane group is written by lane u of the group, so U <= L.
+static bool valid_shape(int L, int U) {
+  return (L == 4 || L == 8 || L == 16 || L == 32) && (U == 1 || U == 2 || U == 4 || U == 8) && U <= L;
+}
+
 template <class V, int MODE>
 static hipError_t launch_spmv_t(const hk_csr_s* A, const SpmvPlan& p, const V* x, V* y, const V* b,
                                 V alpha, V beta, int beta_zero, hipStream_t s) {
+  if (!valid_shape(p.L, p.U)) return hipErrorInvalidValue;
   const int ntiles = spmv_tiles(A, p.L, p.U);
   const int grid = p.grid > 0 ? (p.grid < ntiles ? p.grid : ntiles) : ntiles;
   if (ntiles == 0) return hipSuccess;
@@ -84,9 +90,9 @@ static hipError_t launch_spmv_t(const hk_csr_s* A, const SpmvPlan& p, const V* x
     return hipGetLastError();                                                                  \
   }
   HK_SPMV_CASE(4, 1) HK_SPMV_CASE(4, 2) HK_SPMV_CASE(4, 4)
-  HK_SPMV_CASE(8, 1) HK_SPMV_CASE(8, 2) HK_SPMV_CASE(8, 4)
-  HK_SPMV_CASE(16, 1) HK_SPMV_CASE(16, 2) HK_SPMV_CASE(16, 4)
-  HK_SPMV_CASE(32, 1) HK_SPMV_CASE(32, 2) HK_SPMV_CASE(32, 4)
+  HK_SPMV_CASE(8, 1) HK_SPMV_CASE(8, 2) HK_SPMV_CASE(8, 4) HK_SPMV_CASE(8, 8)
+  HK_SPMV_CASE(16, 1) HK_SPMV_CASE(16, 2) HK_SPMV_CASE(16, 4) HK_SPMV_CASE(16, 8)
+  HK_SPMV_CASE(32, 1) HK_SPMV_CASE(32, 2) HK_SPMV_CASE(32, 4) HK_SPMV_CASE(32, 8)
 #undef HK_SPMV_CASE
   return hipErrorInvalidValue;
 }
@@ -98,9 +104,7 @@ int spmv_tiles(const hk_csr_s* A, int L, int U) {
 
 int default_grid(int ntiles) { return ntiles; }
 
-static bool valid_shape(int L, int U) {
-  return (L == 4 || L == 8 || L == 16 || L == 32) && (U == 1 || U == 2 || U == 4);
-}
+
 
 static SpmvPlan heuristic_plan(const hk_csr_s* A) {
   SpmvPlan p;
@@ -137,12 +141,13 @@ static int autotune(hk_csr_s* A, hipStream_t s) {
   SpmvPlan best = heuristic_plan(A);
   float best_ms = 1e30f;
   const int Ls[] = {4, 8, 16, 32};
-  const int Us[] = {1, 2, 4};
-  const int grids[] = {0, 2048, 4096};
+  const int Us[] = {1, 2, 4, 8};
+  const int grids[] = {0, 2048};
   int rc = HK_OK;
   for (int L : Ls) {
     if (L > 2 * A->max_row + 4 && L != 4) continue;
     for (int U : Us) {
+      if (!valid_shape(L, U)) continue;
       for (int gsel : grids) {
         SpmvPlan p;
         p.L = L; p.U = U; p.grid = gsel; p.tuned = 1;

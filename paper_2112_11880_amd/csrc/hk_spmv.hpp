@@ -32,8 +32,8 @@ template <class V> __device__ __forceinline__ V ldnt(const V* p) {
 }
 __device__ __forceinline__ int ldnt(const int* p) { return __builtin_nontemporal_load(p); }
 
-// Row sums of rows r0 .. r0+U-1 (rows >= n give 0).  Every lane of the
-// L-lane group returns the full sums.  Within a row, lane j accumulates
+// Row sums of rows r0 .. r0+U-1 (rows >= n give 0), U <= L.  Every lane of
+// the L-lane group returns the full sums; callers write row u from lane u.  Within a row, lane j accumulates
 // entries j, j+L, j+2L, ...; the group total is a fixed butterfly.
 // All loads are issued unconditionally from in-bounds indices (a lane past
 // the end of its row re-reads the row's last entry and contributes zero),

@@ -36,11 +36,11 @@ def main():
         f.write("# CPU-oracle adjoint gradient, 48^3 jittered P1 Helmholtz mesh, 216 speed blocks\n")
         f.write("# written by tests/golden/make_config5_gradient.py (oracle/ + synth/ only)\n")
         f.write(f"# forward solve {infos[0]}, adjoint solve {infos[1]}, {time.time() - t0:.0f} s\n")
-        f.write(f"L {L!r}\n")
+        f.write(f"L {float(L)!r}\n")
         for b, v in enumerate(gc):
-            f.write(f"grad_c {b} {v!r}\n")
+            f.write(f"grad_c {b} {float(v)!r}\n")
         for i in idx:
-            f.write(f"grad_g {i} {gg[i].real!r} {gg[i].imag!r}\n")
+            f.write(f"grad_g {int(i)} {float(gg[i].real)!r} {float(gg[i].imag)!r}\n")
     print("wrote", OUT, infos)
 
 

@@ -71,7 +71,7 @@ def small_mesh_problem(nc=(7, 5, 6), seed=3):
 
 # ------------------------------------------------------------------ SpMV
 
-SHAPES = [(L, U, g) for L in (4, 8, 16, 32) for U in (1, 2, 4) for g in (0, 3, 64)]
+SHAPES = [(L, U, g) for L in (4, 8, 16, 32) for U in (1, 2, 4, 8) for g in (0, 3, 64) if U <= L]
 
 
 def test_spmv_all_shapes_ragged(hk, oracle):
@@ -85,8 +85,11 @@ def test_spmv_all_shapes_ragged(hk, oracle):
     for L, U, g in SHAPES:
         say("spmv shape", L, U, g, "n", n)
         A.set_plan(L, U, g)
-        y = host(A.spmv(xd))
+        # NaN-filled output: a row the kernel fails to write cannot pass
+        y = host(A.spmv(xd, torch.full_like(xd, complex("nan+nanj")), beta=0.0))
         assert np.all(np.abs(y - ref) <= bound), (L, U, g)
+    with pytest.raises(hk.HKError):
+        A.set_plan(4, 8, 0)
 
 
 def test_spmv_alpha_beta_and_residual(hk, oracle):
@@ -132,7 +135,8 @@ def test_spmv_edge_structures(hk, oracle):
         for L, U, g in SHAPES[::5]:
             say("spmv edge", name, L, U, g)
             A.set_plan(L, U, g)
-            y = host(A.spmv(dev(x)))
+            xd = dev(x)
+            y = host(A.spmv(xd, torch.full_like(xd, complex("nan+nanj")), beta=0.0))
             assert np.all(np.abs(y - ref) <= bound), (name, L, U, g)
 
 
@@ -277,6 +281,22 @@ def test_solve_small_matches_oracle_iterates(hk, oracle):
         assert info["status"] == hk.HK_NOT_CONVERGED and info["iters"] == k
         assert np.linalg.norm(host(x) - xo) <= bound * np.linalg.norm(xo)
         assert abs(info["relres_rec"] - oi["relres_rec"]) <= bound * 10
+
+
+def test_solve_every_launch_shape(hk, oracle):
+    """The fused SpMV+dot kernels of the solver in every launch shape: two
+    iterations give the oracle's iterate to rounding."""
+    rowptr, col, val = small_mesh_problem((7, 6, 5), 13)
+    n = rowptr.shape[0] - 1
+    b = crandn(np.random.default_rng(4), n)
+    xo, oi = oracle.bicgstab(rowptr, col, val, b, tol=1e-14, maxit=2)
+    A = make_csr(hk, rowptr, col, val)
+    for L, U, g in SHAPES:
+        say("solve shape", L, U, g)
+        A.set_plan(L, U, g)
+        x, info = hk.krylov_solve(A, dev(b), tol=1e-14, max_iter=2)
+        assert info["iters"] == 2
+        assert np.linalg.norm(host(x) - xo) <= 1e-11 * np.linalg.norm(xo), (L, U, g)
 
 
 def test_solve_breakdowns_and_errors(hk, oracle):
