@@ -7,7 +7,8 @@
  *
  * Everything is written the slow, obvious way in double precision (complex
  * double, as the paper fixes), except the inner solve of the mixed-precision
- * refinement, which is complex float by definition.  Sums run left to right
+ * refinement, whose vectors and matrix are complex float (its dots are
+ * accumulated in double, see orc_bicgstab_c64).  Sums run left to right
  * in index order; the only parallelism is over independent rows or elements
  * (OpenMP), which leaves every result bitwise identical to a serial run.
  *
@@ -268,24 +269,36 @@ static void spmv_f(int64_t n, const int32_t *rowptr, const int32_t *col, const z
     }
 }
 
-static zf dotc_f(int64_t n, const zf *x, const zf *y)
+/* conj(x)^T y of complex-float vectors, accumulated in double (each product
+ * of two floats is exact in double) */
+static zd dotc_fd(int64_t n, const zf *x, const zf *y)
 {
-    zf s = 0.0f;
-    for (int64_t i = 0; i < n; ++i) s += conjf(x[i]) * y[i];
+    zd s = 0.0;
+    for (int64_t i = 0; i < n; ++i) s += conj((zd)x[i]) * (zd)y[i];
     return s;
 }
 
-static float nrm2_f(int64_t n, const zf *x)
+static double nrm2_fd(int64_t n, const zf *x)
 {
-    float s = 0.0f;
-    for (int64_t i = 0; i < n; ++i) s += crealf(x[i]) * crealf(x[i]) + cimagf(x[i]) * cimagf(x[i]);
-    return sqrtf(s);
+    double s = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double re = crealf(x[i]), im = cimagf(x[i]);
+        s += re * re + im * im;
+    }
+    return sqrt(s);
 }
 
 /*
- * The same right-preconditioned BiCGStab entirely in complex float with float
- * accumulation, x0 = 0, relative tolerance on ||r|| / ||b||.  On a breakdown
- * (the same exact-zero tests) the current iterate is kept and returned.
+ * The same right-preconditioned BiCGStab with complex-float vectors, matrix
+ * and matrix-vector products, x0 = 0, relative tolerance on ||r|| / ||b||.
+ * The inner products and norms are accumulated in double and the scalars
+ * (rho, sigma, alpha, omega, beta, tau) are formed in double; each vector
+ * update uses the scalar rounded to complex float.  (With float
+ * accumulation the dot of n terms carries a rounding error of order
+ * sqrt(n) 2^-24 ||rhat|| ||r||, which on these systems exceeds |rhat^H r|
+ * itself once bi-orthogonality is lost, and the iteration then breaks down
+ * or stalls depending on the summation order.)  On a breakdown (the same
+ * exact-zero tests) the current iterate is kept and returned.
  */
 int orc_bicgstab_c64(int64_t n, const int32_t *rowptr, const int32_t *col, const zf *val,
                      const zf *b, zf *x, float tol, int64_t maxit, or_info *info)
@@ -304,46 +317,48 @@ int orc_bicgstab_c64(int64_t n, const int32_t *rowptr, const int32_t *col, const
         dinv[i] = 1.0f / d;
     }
     for (int64_t i = 0; i < n; ++i) { x[i] = 0.0f; r[i] = b[i]; rh[i] = b[i]; p[i] = 0.0f; v[i] = 0.0f; }
-    float bnorm = nrm2_f(n, b), rnorm = bnorm, theta = tol * bnorm;
+    double bnorm = nrm2_fd(n, b), rnorm = bnorm, theta = (double)tol * bnorm;
     if (rnorm <= theta) { status = OR_OK; goto done; }
-    zf rho_old = 1.0f, alpha = 1.0f, omega = 1.0f;
+    zd rho_old = 1.0, alpha = 1.0, omega = 1.0;
     for (it = 1; it <= maxit; ++it) {
-        zf rho = dotc_f(n, rh, r);
-        if (!isfinite(crealf(rho)) || !isfinite(cimagf(rho))) { status = OR_NONFINITE; break; }
-        if (rho == 0.0f) { status = OR_BREAKDOWN; bd = OR_BD_RHO; it -= 1; break; }
+        zd rho = dotc_fd(n, rh, r);
+        if (!isfinite(creal(rho)) || !isfinite(cimag(rho))) { status = OR_NONFINITE; break; }
+        if (rho == 0.0) { status = OR_BREAKDOWN; bd = OR_BD_RHO; it -= 1; break; }
         if (it == 1) {
             for (int64_t i = 0; i < n; ++i) p[i] = r[i];
         } else {
-            zf beta = (rho / rho_old) * (alpha / omega);
-            for (int64_t i = 0; i < n; ++i) p[i] = r[i] + beta * (p[i] - omega * v[i]);
+            zf beta = (zf)((rho / rho_old) * (alpha / omega)), om = (zf)omega;
+            for (int64_t i = 0; i < n; ++i) p[i] = r[i] + beta * (p[i] - om * v[i]);
         }
         for (int64_t i = 0; i < n; ++i) ph[i] = dinv[i] * p[i];
         spmv_f(n, rowptr, col, val, ph, v);
-        zf sigma = dotc_f(n, rh, v);
-        if (!isfinite(crealf(sigma)) || !isfinite(cimagf(sigma))) { status = OR_NONFINITE; break; }
-        if (sigma == 0.0f) { status = OR_BREAKDOWN; bd = OR_BD_SIGMA; it -= 1; break; }
+        zd sigma = dotc_fd(n, rh, v);
+        if (!isfinite(creal(sigma)) || !isfinite(cimag(sigma))) { status = OR_NONFINITE; break; }
+        if (sigma == 0.0) { status = OR_BREAKDOWN; bd = OR_BD_SIGMA; it -= 1; break; }
         alpha = rho / sigma;
-        for (int64_t i = 0; i < n; ++i) s[i] = r[i] - alpha * v[i];
-        float snorm = nrm2_f(n, s);
+        const zf al = (zf)alpha;
+        for (int64_t i = 0; i < n; ++i) s[i] = r[i] - al * v[i];
+        double snorm = nrm2_fd(n, s);
         if (snorm <= theta) {
-            for (int64_t i = 0; i < n; ++i) x[i] += alpha * ph[i];
+            for (int64_t i = 0; i < n; ++i) x[i] += al * ph[i];
             rnorm = snorm; status = OR_OK; break;
         }
         for (int64_t i = 0; i < n; ++i) sh[i] = dinv[i] * s[i];
         spmv_f(n, rowptr, col, val, sh, t);
-        float tau = crealf(dotc_f(n, t, t));
-        if (tau == 0.0f) {
-            for (int64_t i = 0; i < n; ++i) x[i] += alpha * ph[i];
+        double tau = creal(dotc_fd(n, t, t));
+        if (tau == 0.0) {
+            for (int64_t i = 0; i < n; ++i) x[i] += al * ph[i];
             rnorm = snorm; status = OR_BREAKDOWN; bd = OR_BD_TAU; break;
         }
-        omega = dotc_f(n, t, s) / tau;
-        for (int64_t i = 0; i < n; ++i) x[i] += alpha * ph[i] + omega * sh[i];
-        for (int64_t i = 0; i < n; ++i) r[i] = s[i] - omega * t[i];
+        omega = dotc_fd(n, t, s) / tau;
+        const zf om = (zf)omega;
+        for (int64_t i = 0; i < n; ++i) x[i] += al * ph[i] + om * sh[i];
+        for (int64_t i = 0; i < n; ++i) r[i] = s[i] - om * t[i];
         rho_old = rho;
-        rnorm = nrm2_f(n, r);
+        rnorm = nrm2_fd(n, r);
         if (!isfinite(rnorm)) { status = OR_NONFINITE; break; }
         if (rnorm <= theta) { status = OR_OK; break; }
-        if (omega == 0.0f) { status = OR_BREAKDOWN; bd = OR_BD_OMEGA; break; }
+        if (omega == 0.0) { status = OR_BREAKDOWN; bd = OR_BD_OMEGA; break; }
     }
     if (it > maxit) it = maxit;
     info->relres_rec = bnorm > 0 ? rnorm / bnorm : 0.0;

@@ -214,6 +214,48 @@ def test_bicgstab_error_paths(oracle):
     assert 0 < info["relres_true"] < 1 and np.any(x != 0)
 
 
+@pytest.mark.parametrize("nc,seed", [(3, 3), (4, 5)])
+def test_bicgstab_c64_matches_dense_lu_and_complex128_steps(oracle, nc, seed):
+    """The complex-float solver (FP64-accumulated dots) reaches the LAPACK
+    solution of the same rounded system, and its first two iterates equal
+    the complex128 solver's on that matrix to float rounding."""
+    p, val = tiny_problem(nc, seed=seed)
+    v32 = val.astype(np.complex64)
+    b = crandn(np.random.default_rng(seed), p.n)
+    b[p.dirichlet] = 0
+    b32 = b.astype(np.complex64)
+    x, info = oracle.bicgstab_c64(p.rowptr, p.col, v32, b32, tol=1e-5)
+    assert info["status"] == 0 and info["relres_rec"] <= 1e-5
+    xs = np.linalg.solve(dense(p, v32.astype(np.complex128)), b32.astype(np.complex128))
+    # cond(A) is 99 and 961 here; the measured errors are 9e-6 and 3e-5
+    assert np.linalg.norm(x - xs) <= 1e-4 * np.linalg.norm(xs)
+    for k in (1, 2):
+        x1, i1 = oracle.bicgstab_c64(p.rowptr, p.col, v32, b32, tol=1e-12, maxit=k)
+        x2, _ = oracle.bicgstab(p.rowptr, p.col, v32.astype(np.complex128), b32.astype(np.complex128),
+                                tol=1e-12, maxit=k)
+        assert i1["iters"] == k and i1["status"] == oracle.NOT_CONVERGED
+        assert np.linalg.norm(x1 - x2) <= 1e-6 * np.linalg.norm(x2), k
+
+
+def test_bicgstab_c64_diagonal_and_sigma_breakdown(oracle):
+    n = 20
+    rng = np.random.default_rng(2)
+    d = (crandn(rng, n) + 3.0).astype(np.complex64)
+    b = crandn(rng, n).astype(np.complex64)
+    rowptr = np.arange(n + 1, dtype=np.int32)
+    col = np.arange(n, dtype=np.int32)
+    x, info = oracle.bicgstab_c64(rowptr, col, d, b, tol=1e-6)
+    assert info["status"] == 0 and info["iters"] == 1
+    ref = b.astype(np.complex128) / d.astype(np.complex128)
+    assert np.all(np.abs(x - ref) <= 1e-6 * np.abs(ref))
+    # the same exactly representable sigma = 0 case as the complex128 test
+    x, info = oracle.bicgstab_c64(np.array([0, 2, 4], dtype=np.int32), np.array([0, 1, 0, 1], dtype=np.int32),
+                                  np.array([1.0, -1.25, -1.25, 1.0], dtype=np.complex64),
+                                  np.array([1.0, 2.0], dtype=np.complex64), tol=1e-6)
+    assert info["status"] == oracle.BREAKDOWN and info["breakdown"] == oracle.BD_SIGMA
+    assert info["iters"] == 0 and np.all(x == 0)
+
+
 def test_mixed_refinement_config1(oracle):
     c1 = configs.config1()
     u, info = oracle.mixed_refine(c1["rowptr"], c1["col"], c1["val"], c1["g"])
