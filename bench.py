@@ -120,6 +120,32 @@ def bench_batched(hk, torch, np, dev, log):
     return res
 
 
+def bench_adjoint(hk, torch, np, dev, log):
+    """Forward + adjoint solve on the 48^3, 216-block differentiable problem."""
+    from synth import configs
+    d = configs.config5()
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    prob = hk.HelmholtzProblem(rowptr=t(d["rowptr"]), col=t(d["col"]), K=t(d["K"]), bm_ptr=t(d["bm_ptr"]),
+                               bm_blk=t(d["bm_blk"]), bm_val=t(d["bm_val"]), tet_nodes=t(d["tet_nodes"]),
+                               tet_ptr=t(d["tet_ptr"]), tet_vol=t(d["tet_vol"]),
+                               dirichlet=t(d["dirichlet"].astype(np.uint8)), omega=float(d["omega"]))
+    g = t(d["g"]).requires_grad_(True)
+    c = t(d["c"]).requires_grad_(True)
+    S = t(d["samples"].astype(np.int64))
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    u = hk.helmholtz_solve(g, c, prob, tol=1e-8)
+    L = (u[S].abs() ** 2).sum()
+    torch.cuda.synchronize()
+    tf = time.perf_counter() - ts
+    L.backward()
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - ts - tf
+    log(f"adjoint: forward {tf:.3f} s, backward {tb:.3f} s")
+    return {"adjoint": {"n": int(d["n"]), "blocks": int(d["c"].shape[0]), "tol": 1e-8,
+                        "forward_s": round(tf, 4), "backward_s": round(tb, 4)}}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -263,6 +289,7 @@ def main():
             out["solve_mixed_1e-8"]["speedup_vs_plain"] = round(out["solve_plain"]["time_s_mean"] / tm8, 3)
     if args.batched and not args.no_solve:
         out.update(bench_batched(hk, torch, np, dev, log))
+        out.update(bench_adjoint(hk, torch, np, dev, log))
     if not args.no_cpu:
         from oracle import oracle
         xh = x.cpu().numpy()

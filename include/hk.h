@@ -84,9 +84,12 @@ int hk_csr_destroy(hk_csr A);
 int hk_csr_plan(hk_csr A, int32_t* lanes_per_row, int32_t* rows_per_group, int32_t* grid,
                 int32_t* tuned);
 
-/* Override the launch shape (lanes_per_row in {4,8,16,32}, rows_per_group in
- * {1,2,4,8} and not above lanes_per_row, grid > 0 or 0 for one workgroup per
- * tile); anything else gives HK_EINVAL. */
+/* Override the launch shape: lanes_per_row in {4,8,16,32} with
+ * rows_per_group in {1,2,4,8} not above lanes_per_row (a group of lanes per
+ * row), or lanes_per_row = 64 with rows_per_group in {8,16} (the row-block
+ * scheme: one wave per 64 rows streaming their entries, rows_per_group =
+ * entries per lane per pass); grid > 0, or 0 for one workgroup per tile.
+ * Anything else gives HK_EINVAL. */
 int hk_csr_set_plan(hk_csr A, int32_t lanes_per_row, int32_t rows_per_group, int32_t grid);
 
 /*
@@ -154,7 +157,9 @@ typedef struct {
 /*
  * Preconditioned BiCGStab on A x = b (Section 4: P-BiCGSTAB, zero initial
  * guess, residual tolerance, iteration cap; Jacobi preconditioner on the
- * right).  A must be complex128.  Scalars stay in device memory; the host
+ * right).  A complex128 matrix gives a complex128 solve (double accumulation);
+ * a complex64 matrix a complex64 solve with float accumulation (b and x then
+ * complex64).  Scalars stay in device memory; the host
  * reads a status word every check_every iterations and synchronises the
  * stream once at the end to fill *info.  A zero diagonal entry with
  * precond = 1 gives HK_EINVAL.  Returns info->status (>= 0) or an error.

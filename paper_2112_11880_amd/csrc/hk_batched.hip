@@ -17,8 +17,8 @@
 // Jacobi is applied on the right through hatted vectors: phat = D^-1 p and
 // shat = D^-1 s are stored, s = D shat and D^-1 v are formed on the fly, and
 // x += alpha phat + omega shat.  Per-system scalars, statuses and iteration
-// counts live in device memory; the workgroup arriving last at a barrier
-// finishes the reductions (fixed order) and updates them.
+// counts live in device memory; at each grid barrier workgroup 0 finishes
+// the reductions (fixed order) and updates them.
 #include <algorithm>
 #include <vector>
 
@@ -186,27 +186,30 @@ template <int EPI, int NV>
 __device__ __forceinline__ void sweep_spmv(const SweepArgs& a, int r0, int r1, const double2* src,
                                            double2* dst, bool act, double2 kap, double (&part)[NV]) {
   const int j = threadIdx.x & 63;
+  // lanes of finished systems issue no loads at all
+  if (!act) return;
   for (int row = r0; row < r1; ++row) {
     const int s = a.rowptr[row], e = a.rowptr[row + 1];
     double2 acc = make_double2(0, 0);
-    int q = s;
-    for (; q + 4 <= e; q += 4) {
-      int c[4];
-      double kv[4], mv[4];
-      double2 xv[4];
+    // 8 entries at a time, all gathers in flight together; past the row's
+    // end an entry re-reads the last column with a zero coefficient
+    for (int q0 = s; q0 < e; q0 += 8) {
+      int c[8];
+      double kv[8], mv[8];
+      double2 xv[8];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) { c[u] = a.col[q + u]; kv[u] = a.K[q + u]; mv[u] = a.M[q + u]; }
+      for (int u = 0; u < 8; ++u) {
+        const bool in = q0 + u < e;
+        const int q = in ? q0 + u : e - 1;
+        c[u] = a.col[q];
+        kv[u] = in ? a.K[q] : 0.0;
+        mv[u] = in ? a.M[q] : 0.0;
+      }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) xv[u] = act ? src[(size_t)c[u] * kSys + j] : make_double2(0, 0);
+      for (int u = 0; u < 8; ++u) xv[u] = src[(size_t)c[u] * kSys + j];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) acc = cfma(make_double2(kv[u] - kap.x * mv[u], -kap.y * mv[u]), xv[u], acc);
+      for (int u = 0; u < 8; ++u) acc = cfma(make_double2(kv[u] - kap.x * mv[u], -kap.y * mv[u]), xv[u], acc);
     }
-    for (; q < e; ++q) {
-      const int c = a.col[q];
-      const double2 xv = act ? src[(size_t)c * kSys + j] : make_double2(0, 0);
-      acc = cfma(make_double2(a.K[q] - kap.x * a.M[q], -kap.y * a.M[q]), xv, acc);
-    }
-    if (!act) continue;
     const size_t o = (size_t)row * kSys + j;
     if (EPI == 3) {
       const double2 rt = csub(a.B[o], acc);
@@ -229,6 +232,7 @@ __device__ __forceinline__ void sweep_spmv(const SweepArgs& a, int r0, int r1, c
 
 __global__ __launch_bounds__(kPB) void k_sweep(SweepArgs a) {
   __shared__ double lds[4 * kPW * kSys];
+  unsigned epoch = 0;
   BatchState* st = a.st;
   const int j = threadIdx.x & 63;
   const int G = gridDim.x;
@@ -251,7 +255,7 @@ __global__ __launch_bounds__(kPB) void k_sweep(SweepArgs a) {
       part[0] += cabs2(b);
     }
     store_partials64<1>(part, a.partials, lds);
-    if (barrier_last(a.bar, [&] {
+    if (barrier_last(a.bar, epoch, [&] {
           double tot[1];
           final_partials64<1>(a.partials, tot, lds);
           if (threadIdx.x < kSys) {
@@ -275,19 +279,33 @@ __global__ __launch_bounds__(kPB) void k_sweep(SweepArgs a) {
     // ---- phat = D^-1 (r - beta omega v) + beta phat
     if (it > 1) {
       const double2 beta = st->beta[j], bo = cmul(st->beta[j], st->omega[j]);
-      for (int row = r0; row < r1 && act; ++row) {
-        const size_t o = (size_t)row * kSys + j;
-        const double2 w = csub(a.R[o], cmul(bo, a.V[o]));
-        a.PH[o] = cfma(beta, a.PH[o], cmul(crecip(sweep_diag(a, row, kap)), w));
+      if (act) {
+        int row = r0;
+        for (; row + 4 <= r1; row += 4) {
+          double2 rv[4], vv[4], pv[4], dv[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const size_t o = (size_t)(row + u) * kSys + j;
+            rv[u] = a.R[o]; vv[u] = a.V[o]; pv[u] = a.PH[o]; dv[u] = sweep_diag(a, row + u, kap);
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            a.PH[(size_t)(row + u) * kSys + j] = cfma(beta, pv[u], cmul(crecip(dv[u]), csub(rv[u], cmul(bo, vv[u]))));
+        }
+        for (; row < r1; ++row) {
+          const size_t o = (size_t)row * kSys + j;
+          const double2 w = csub(a.R[o], cmul(bo, a.V[o]));
+          a.PH[o] = cfma(beta, a.PH[o], cmul(crecip(sweep_diag(a, row, kap)), w));
+        }
       }
-      if (barrier_last(a.bar, [] {})) return;
+      if (barrier_last(a.bar, epoch, [] {})) return;
     }
     // ---- v = A phat ; sigma = rhat^H v
     {
       double part[2] = {0, 0};
       sweep_spmv<1, 2>(a, r0, r1, a.PH, a.V, act, kap, part);
       store_partials64<2>(part, a.partials, lds);
-      if (barrier_last(a.bar, [&] {
+      if (barrier_last(a.bar, epoch, [&] {
             double tot[2];
             final_partials64<2>(a.partials, tot, lds);
             if (threadIdx.x < a.nsys) upd_sigma(st, threadIdx.x, make_double2(tot[0], tot[1]));
@@ -299,14 +317,31 @@ __global__ __launch_bounds__(kPB) void k_sweep(SweepArgs a) {
     {
       double part[1] = {0};
       const double2 alpha = st->alpha[j];
-      for (int row = r0; row < r1 && act; ++row) {
-        const size_t o = (size_t)row * kSys + j;
-        const double2 s = csub(a.R[o], cmul(alpha, a.V[o]));
-        a.SH[o] = cmul(crecip(sweep_diag(a, row, kap)), s);
-        part[0] += cabs2(s);
+      if (act) {
+        int row = r0;
+        for (; row + 4 <= r1; row += 4) {
+          double2 rv[4], vv[4], dv[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const size_t o = (size_t)(row + u) * kSys + j;
+            rv[u] = a.R[o]; vv[u] = a.V[o]; dv[u] = sweep_diag(a, row + u, kap);
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const double2 s = csub(rv[u], cmul(alpha, vv[u]));
+            a.SH[(size_t)(row + u) * kSys + j] = cmul(crecip(dv[u]), s);
+            part[0] += cabs2(s);
+          }
+        }
+        for (; row < r1; ++row) {
+          const size_t o = (size_t)row * kSys + j;
+          const double2 s = csub(a.R[o], cmul(alpha, a.V[o]));
+          a.SH[o] = cmul(crecip(sweep_diag(a, row, kap)), s);
+          part[0] += cabs2(s);
+        }
       }
       store_partials64<1>(part, a.partials, lds);
-      if (barrier_last(a.bar, [&] {
+      if (barrier_last(a.bar, epoch, [&] {
             double tot[1];
             final_partials64<1>(a.partials, tot, lds);
             if (threadIdx.x < a.nsys) upd_s(st, threadIdx.x, tot[0]);
@@ -319,7 +354,7 @@ __global__ __launch_bounds__(kPB) void k_sweep(SweepArgs a) {
       double part[3] = {0, 0, 0};
       sweep_spmv<2, 3>(a, r0, r1, a.SH, a.T, act, kap, part);
       store_partials64<3>(part, a.partials, lds);
-      if (barrier_last(a.bar, [&] {
+      if (barrier_last(a.bar, epoch, [&] {
             double tot[3];
             final_partials64<3>(a.partials, tot, lds);
             if (threadIdx.x < a.nsys) upd_omega(st, threadIdx.x, tot[0], make_double2(tot[1], tot[2]));
@@ -332,16 +367,30 @@ __global__ __launch_bounds__(kPB) void k_sweep(SweepArgs a) {
       double part[3] = {0, 0, 0};
       const double2 alpha = st->alpha[j], omega = st->omega[j];
       if (sj == B_RUN) {
-        for (int row = r0; row < r1; ++row) {
+        auto upd = [&](int row, double2 sh, double2 ph, double2 xv, double2 tv, double2 h, double2 d) {
           const size_t o = (size_t)row * kSys + j;
-          const double2 sh = a.SH[o];
-          a.X[o] = cfma(omega, sh, cfma(alpha, a.PH[o], a.X[o]));
-          const double2 r = csub(cmul(sweep_diag(a, row, kap), sh), cmul(omega, a.T[o]));
+          a.X[o] = cfma(omega, sh, cfma(alpha, ph, xv));
+          const double2 r = csub(cmul(d, sh), cmul(omega, tv));
           a.R[o] = r;
           part[0] += cabs2(r);
-          const double2 h = a.RH[o];
           part[1] = fma(h.x, r.x, fma(h.y, r.y, part[1]));
           part[2] = fma(h.x, r.y, fma(-h.y, r.x, part[2]));
+        };
+        int row = r0;
+        for (; row + 2 <= r1; row += 2) {
+          double2 sh[2], ph[2], xv[2], tv[2], hv[2], dv[2];
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            const size_t o = (size_t)(row + u) * kSys + j;
+            sh[u] = a.SH[o]; ph[u] = a.PH[o]; xv[u] = a.X[o]; tv[u] = a.T[o]; hv[u] = a.RH[o];
+            dv[u] = sweep_diag(a, row + u, kap);
+          }
+#pragma unroll
+          for (int u = 0; u < 2; ++u) upd(row + u, sh[u], ph[u], xv[u], tv[u], hv[u], dv[u]);
+        }
+        for (; row < r1; ++row) {
+          const size_t o = (size_t)row * kSys + j;
+          upd(row, a.SH[o], a.PH[o], a.X[o], a.T[o], a.RH[o], sweep_diag(a, row, kap));
         }
       } else if (sj == B_HALF || sj == B_TAUBD) {
         for (int row = r0; row < r1; ++row) {
@@ -350,7 +399,7 @@ __global__ __launch_bounds__(kPB) void k_sweep(SweepArgs a) {
         }
       }
       store_partials64<3>(part, a.partials, lds);
-      if (barrier_last(a.bar, [&] {
+      if (barrier_last(a.bar, epoch, [&] {
             double tot[3];
             final_partials64<3>(a.partials, tot, lds);
             __shared__ int s_run[kSys];
@@ -374,7 +423,7 @@ __global__ __launch_bounds__(kPB) void k_sweep(SweepArgs a) {
     double part[1] = {0};
     sweep_spmv<3, 1>(a, r0, r1, a.X, nullptr, lane_ok, kap, part);
     store_partials64<1>(part, a.partials, lds);
-    barrier_last(a.bar, [&] {
+    barrier_last(a.bar, epoch, [&] {
       double tot[1];
       final_partials64<1>(a.partials, tot, lds);
       if (threadIdx.x < a.nsys) st->rr_true[threadIdx.x] = tot[0];
@@ -485,6 +534,7 @@ __device__ __forceinline__ void bd_tile_spmv(const BdArgs& a, int tile, const do
 template <int L>
 __global__ __launch_bounds__(kPB) void k_blockdiag(BdArgs a) {
   __shared__ double lds[4 * kPW + 4 * kSys + 4 * kPW * kSys];
+  unsigned epoch = 0;
   double* fin = lds + 4 * kPW + 4 * kSys;
   BatchState* st = a.st;
   const int TR = kPB;  // rows per tile: one per thread in the element-wise phases
@@ -519,7 +569,7 @@ __global__ __launch_bounds__(kPB) void k_blockdiag(BdArgs a) {
       acc[0] += cabs2(b);
     }
   });
-  if (barrier_last(a.bar, [&] {
+  if (barrier_last(a.bar, epoch, [&] {
         double tot[1];
         final_partials64<1>(a.partials, tot, fin);
         if (threadIdx.x < a.nsys) init_sys(st, threadIdx.x, tot[0], a.tol, a.maxit);
@@ -546,7 +596,7 @@ __global__ __launch_bounds__(kPB) void k_blockdiag(BdArgs a) {
           a.PH[row] = cfma(beta, a.PH[row], cmul(a.dinv[row], w));
         }
       });
-      if (barrier_last(a.bar, [] {})) return;
+      if (barrier_last(a.bar, epoch, [] {})) return;
     }
     // v = A phat ; sigma
     bd_phase<2>(a, lds, [&](int tile, int sys, double(&acc)[2]) {
@@ -557,7 +607,7 @@ __global__ __launch_bounds__(kPB) void k_blockdiag(BdArgs a) {
         acc[1] = fma(h.x, v.y, fma(-h.y, v.x, acc[1]));
       });
     });
-    if (barrier_last(a.bar, [&] {
+    if (barrier_last(a.bar, epoch, [&] {
           double tot[2];
           final_partials64<2>(a.partials, tot, fin);
           if (threadIdx.x < a.nsys) upd_sigma(st, threadIdx.x, make_double2(tot[0], tot[1]));
@@ -572,7 +622,7 @@ __global__ __launch_bounds__(kPB) void k_blockdiag(BdArgs a) {
         acc[0] += cabs2(s);
       }
     });
-    if (barrier_last(a.bar, [&] {
+    if (barrier_last(a.bar, epoch, [&] {
           double tot[1];
           final_partials64<1>(a.partials, tot, fin);
           if (threadIdx.x < a.nsys) upd_s(st, threadIdx.x, tot[0]);
@@ -589,7 +639,7 @@ __global__ __launch_bounds__(kPB) void k_blockdiag(BdArgs a) {
         acc[2] = fma(t.x, s.y, fma(-t.y, s.x, acc[2]));
       });
     });
-    if (barrier_last(a.bar, [&] {
+    if (barrier_last(a.bar, epoch, [&] {
           double tot[3];
           final_partials64<3>(a.partials, tot, fin);
           if (threadIdx.x < a.nsys) upd_omega(st, threadIdx.x, tot[0], make_double2(tot[1], tot[2]));
@@ -614,7 +664,7 @@ __global__ __launch_bounds__(kPB) void k_blockdiag(BdArgs a) {
         a.X[row] = cfma(alpha, a.PH[row], a.X[row]);
       }
     });
-    if (barrier_last(a.bar, [&] {
+    if (barrier_last(a.bar, epoch, [&] {
           double tot[3];
           final_partials64<3>(a.partials, tot, fin);
           __shared__ int s_run[kSys];
@@ -635,7 +685,7 @@ __global__ __launch_bounds__(kPB) void k_blockdiag(BdArgs a) {
       return;
   }
   // true residual: all tiles
-  if (barrier_last(a.bar, [&] {
+  if (barrier_last(a.bar, epoch, [&] {
         if (threadIdx.x == 0) st->ntiles_active = a.sys_tile0[a.nsys];
         __syncthreads();
         for (int k = threadIdx.x; k < a.sys_tile0[a.nsys]; k += kPB) a.active[k] = k;
@@ -646,7 +696,7 @@ __global__ __launch_bounds__(kPB) void k_blockdiag(BdArgs a) {
       acc[0] += cabs2(csub(a.B[row], ax));
     });
   });
-  barrier_last(a.bar, [&] {
+  barrier_last(a.bar, epoch, [&] {
     double tot[1];
     final_partials64<1>(a.partials, tot, fin);
     if (threadIdx.x < a.nsys) st->rr_true[threadIdx.x] = tot[0];
@@ -721,7 +771,7 @@ static int coop_grid(const void* kernel, int* grid) {
   if (!coop) HK_FAIL(HK_EHIP, "device does not support cooperative launches");
   HK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, kPB, 0));
   if (per < 1) HK_FAIL(HK_EHIP, "persistent kernel does not fit on a CU");
-  *grid = cus * std::min(per, 2);
+  *grid = std::min(cus * std::min(per, 2), kBarMaxBlocks);
   return HK_OK;
 }
 

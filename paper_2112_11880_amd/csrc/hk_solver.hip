@@ -10,6 +10,17 @@
 // word once per chunk; kernels enqueued after the solve has ended return at
 // once.
 //
+// The inner products, norms and scalars are double for both vector
+// precisions.  In the complex64 solve the vectors, the matrix and its
+// products stay complex64 (the bytes moved are those of complex64), but each
+// product of two floats is formed exactly in double and summed in double,
+// and each vector update uses its scalar rounded to complex64.  With float
+// sums the rounding error of a dot over n terms, about sqrt(n) 2^-24
+// ||rhat|| ||r||, exceeds |rhat^H r| itself once the iteration has lost
+// bi-orthogonality (|rhat^H r| ~ 1e-7 ||rhat|| ||r|| on the FE Helmholtz
+// systems), and the iteration then breaks down or stalls depending on the
+// summation order.
+//
 // Jacobi is applied on the right by scaling the columns once per solve:
 // Ahat = A D^-1 (a workspace copy of the values), and the iteration runs the
 // unpreconditioned recurrences on Ahat y = b with x = D^-1 y at the end.
@@ -25,6 +36,7 @@
 //           -> rho, beta, convergence / breakdown / cap tests
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <vector>
 
 #include "hk_internal.hpp"
@@ -37,9 +49,9 @@ int spmv_dispatch(const hk_csr_s* A, const void* x, void* y, const void* b, cons
 
 enum : int { S_RUN = 100, S_HALF = 101, S_TAUBD = 102 };
 
-template <class R> struct SolveState {
-  cplx<R> rho, rho_old, alpha, omega, beta;
-  R rr, ss, bb, theta2, rr_true;
+struct SolveState {
+  double2 rho, rho_old, alpha, omega, beta;
+  double rr, ss, bb, theta2, rr_true;
   int status, bd;
   long long iter, maxit, iters_done;
   double* history;
@@ -59,7 +71,21 @@ static inline int64_t partial_slots(int64_t n) {
   return e > kMaxGrid ? e : kMaxGrid;
 }
 
-template <class V> __device__ __forceinline__ V cscale(decltype(V::x) a, V v) { return cmake<V>(a * v.x, a * v.y); }
+// a solver scalar (double) rounded to the vector type
+template <class V> __device__ __forceinline__ V vscal(double2 a) {
+  return cmake<V>((decltype(V::x))a.x, (decltype(V::x))a.y);
+}
+// |a|^2 in double
+template <class V> __device__ __forceinline__ double nrm2d(V a) {
+  const double x = a.x, y = a.y;
+  return x * x + y * y;
+}
+// acc += conj(a) * b in double (two partial sums: re, im)
+template <class V> __device__ __forceinline__ void dotc_acc(V a, V b, double& re, double& im) {
+  const double ax = a.x, ay = a.y, bx = b.x, by = b.y;
+  re = fma(ax, bx, fma(ay, by, re));
+  im = fma(ax, by, fma(-ay, bx, im));
+}
 
 // ------------------------------------------------------------ set-up kernels
 
@@ -95,10 +121,10 @@ __global__ __launch_bounds__(kBlock) void k_init(int n, int use_x0, const cplx<R
                                                  const cplx<R>* __restrict__ dinv,
                                                  cplx<R>* __restrict__ r, cplx<R>* __restrict__ rh,
                                                  cplx<R>* __restrict__ p, cplx<R>* __restrict__ y,
-                                                 R* partials) {
+                                                 double* partials) {
   using V = cplx<R>;
-  __shared__ R lds[2 * (kBlock / kWave)];
-  R acc[2] = {0, 0};
+  __shared__ double lds[2 * (kBlock / kWave)];
+  double acc[2] = {0, 0};
   const int base = blockIdx.x * (kBlock * kEw) + threadIdx.x;
 #pragma unroll
   for (int k = 0; k < kEw; ++k) {
@@ -116,8 +142,8 @@ __global__ __launch_bounds__(kBlock) void k_init(int n, int use_x0, const cplx<R
     rh[i] = ri;
     p[i] = ri;
     y[i] = yi;
-    acc[0] += cabs2(bi);
-    acc[1] += cabs2(ri);
+    acc[0] += nrm2d(bi);
+    acc[1] += nrm2d(ri);
   }
   block_sum<2>(acc, lds);
   store_block_partials<2>(acc, partials);
@@ -126,12 +152,12 @@ __global__ __launch_bounds__(kBlock) void k_init(int n, int use_x0, const cplx<R
 // ----------------------------------------------------------- iteration kernels
 
 template <class R>
-__global__ __launch_bounds__(kBlock) void k_p(int n, const SolveState<R>* __restrict__ st,
+__global__ __launch_bounds__(kBlock) void k_p(int n, const SolveState* __restrict__ st,
                                               const cplx<R>* __restrict__ r, cplx<R>* __restrict__ p,
                                               const cplx<R>* __restrict__ v) {
   using V = cplx<R>;
   if (st->status != S_RUN || st->iter == 1) return;
-  const V beta = st->beta, omega = st->omega;
+  const V beta = vscal<V>(st->beta), omega = vscal<V>(st->omega);
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   // p = r + beta (p - omega v)
@@ -148,16 +174,16 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dot(int n, int ntiles, const in
                                                      const cplx<R>* __restrict__ x,
                                                      cplx<R>* __restrict__ y,
                                                      const cplx<R>* __restrict__ w,
-                                                     const SolveState<R>* __restrict__ st, R* partials) {
+                                                     const SolveState* __restrict__ st, double* partials) {
   using V = cplx<R>;
   constexpr int NV = DOT == 1 ? 2 : 3;
-  __shared__ R lds[NV * (kBlock / kWave)];
+  __shared__ double lds[NV * (kBlock / kWave)];
   if (st->status != S_RUN) return;
   constexpr int RT = (kBlock / L) * U;
   const int g = threadIdx.x / L, lane = threadIdx.x & (L - 1);
   int t0, t1;
   tile_range(ntiles, t0, t1);
-  R part[NV];
+  double part[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) part[k] = 0;
   for (int t = t0; t < t1; ++t) {
@@ -173,14 +199,10 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dot(int n, int ntiles, const in
       if (lane == u && r < n) {
         y[r] = acc[u];
         if (DOT == 1) {
-          // conj(rhat_r) * v_r
-          part[0] = fma(wr.x, acc[u].x, fma(wr.y, acc[u].y, part[0]));
-          part[1] = fma(wr.x, acc[u].y, fma(-wr.y, acc[u].x, part[1]));
+          dotc_acc(wr, acc[u], part[0], part[1]);  // conj(rhat_r) * v_r
         } else {
-          part[0] = fma(acc[u].x, acc[u].x, fma(acc[u].y, acc[u].y, part[0]));
-          // conj(t_r) * s_r
-          part[1] = fma(acc[u].x, wr.x, fma(acc[u].y, wr.y, part[1]));
-          part[2] = fma(acc[u].x, wr.y, fma(-acc[u].y, wr.x, part[2]));
+          part[0] += nrm2d(acc[u]);
+          dotc_acc(acc[u], wr, part[1], part[2]);  // conj(t_r) * s_r
         }
       }
     }
@@ -189,16 +211,56 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dot(int n, int ntiles, const in
   store_block_partials<NV>(part, partials);
 }
 
+// Row-block variant of k_spmv_dot (one wave per 64 rows, CH entries per
+// lane per pass); the row's sum lands in the lane that owns the row.
+template <int CH, class R, int DOT>
+__global__ __launch_bounds__(kBlock) void k_spmv_dot_stream(int n, int ntiles, const int* __restrict__ rowptr,
+                                                            const int* __restrict__ col,
+                                                            const cplx<R>* __restrict__ val,
+                                                            const cplx<R>* __restrict__ x,
+                                                            cplx<R>* __restrict__ y,
+                                                            const cplx<R>* __restrict__ w,
+                                                            const SolveState* __restrict__ st, double* partials) {
+  using V = cplx<R>;
+  constexpr int NV = DOT == 1 ? 2 : 3;
+  __shared__ V lds[(kBlock / kWave) * CH * kWave];
+  if (st->status != S_RUN) return;
+  V* buf = lds + (threadIdx.x / kWave) * CH * kWave;
+  int t0, t1;
+  tile_range(ntiles, t0, t1);
+  double part[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) part[k] = 0;
+  for (int t = t0; t < t1; ++t) {
+    const int r0 = t * kBlock + (threadIdx.x / kWave) * kWave;
+    const int r = r0 + (threadIdx.x & (kWave - 1));
+    const V wr = w[r < n ? r : n - 1];
+    const V acc = csr_stream_rows<CH, V>(r0, n, rowptr, col, val, x, buf);
+    if (r < n) {
+      y[r] = acc;
+      if (DOT == 1) {
+        dotc_acc(wr, acc, part[0], part[1]);
+      } else {
+        part[0] += nrm2d(acc);
+        dotc_acc(acc, wr, part[1], part[2]);
+      }
+    }
+  }
+  __syncthreads();
+  block_sum<NV>(part, reinterpret_cast<double*>(lds));
+  store_block_partials<NV>(part, partials);
+}
+
 template <class R>
-__global__ __launch_bounds__(kBlock) void k_s(int n, const SolveState<R>* __restrict__ st,
+__global__ __launch_bounds__(kBlock) void k_s(int n, const SolveState* __restrict__ st,
                                               const cplx<R>* __restrict__ r,
                                               const cplx<R>* __restrict__ v, cplx<R>* __restrict__ s,
-                                              R* partials) {
+                                              double* partials) {
   using V = cplx<R>;
-  __shared__ R lds[kBlock / kWave];
+  __shared__ double lds[kBlock / kWave];
   if (st->status != S_RUN) return;
-  const V alpha = st->alpha;
-  R acc[1] = {0};
+  const V alpha = vscal<V>(st->alpha);
+  double acc[1] = {0};
   const int base = blockIdx.x * (kBlock * kEw) + threadIdx.x;
   if (base + (kEw - 1) * kBlock < n) {
     V rv[kEw], vv[kEw];
@@ -209,7 +271,7 @@ __global__ __launch_bounds__(kBlock) void k_s(int n, const SolveState<R>* __rest
       // s = r - alpha v
       const V si = csub(rv[k], cmul(alpha, vv[k]));
       s[base + k * kBlock] = si;
-      acc[0] += cabs2(si);
+      acc[0] += nrm2d(si);
     }
   } else {
 #pragma unroll
@@ -218,7 +280,7 @@ __global__ __launch_bounds__(kBlock) void k_s(int n, const SolveState<R>* __rest
       if (i >= n) break;
       const V si = csub(r[i], cmul(alpha, v[i]));
       s[i] = si;
-      acc[0] += cabs2(si);
+      acc[0] += nrm2d(si);
     }
   }
   block_sum<1>(acc, lds);
@@ -226,17 +288,17 @@ __global__ __launch_bounds__(kBlock) void k_s(int n, const SolveState<R>* __rest
 }
 
 template <class R>
-__global__ __launch_bounds__(kBlock) void k_xr(int n, const SolveState<R>* __restrict__ st,
+__global__ __launch_bounds__(kBlock) void k_xr(int n, const SolveState* __restrict__ st,
                                                const cplx<R>* __restrict__ rh,
                                                cplx<R>* __restrict__ r, const cplx<R>* __restrict__ p,
                                                const cplx<R>* __restrict__ s,
                                                const cplx<R>* __restrict__ t, cplx<R>* __restrict__ y,
-                                               R* partials) {
+                                               double* partials) {
   using V = cplx<R>;
-  __shared__ R lds[3 * (kBlock / kWave)];
+  __shared__ double lds[3 * (kBlock / kWave)];
   const int status = st->status;
   if (status != S_RUN && status != S_HALF && status != S_TAUBD) return;
-  const V alpha = st->alpha, omega = st->omega;
+  const V alpha = vscal<V>(st->alpha), omega = vscal<V>(st->omega);
   const int base = blockIdx.x * (kBlock * kEw) + threadIdx.x;
   if (status != S_RUN) {
     // half-step exit (converged on s) or tau breakdown: y += alpha p
@@ -247,15 +309,14 @@ __global__ __launch_bounds__(kBlock) void k_xr(int n, const SolveState<R>* __res
     }
     return;
   }
-  R acc[3] = {0, 0, 0};
+  double acc[3] = {0, 0, 0};
   // y += alpha p + omega s ; r = s - omega t ; ||r||^2 ; rhat^H r
   auto upd = [&](int i, V si, V pi, V ti, V yi, V hi) {
     y[i] = cfma(omega, si, cfma(alpha, pi, yi));
     const V ri = csub(si, cmul(omega, ti));
     r[i] = ri;
-    acc[0] += cabs2(ri);
-    acc[1] = fma(hi.x, ri.x, fma(hi.y, ri.y, acc[1]));
-    acc[2] = fma(hi.x, ri.y, fma(-hi.y, ri.x, acc[2]));
+    acc[0] += nrm2d(ri);
+    dotc_acc(hi, ri, acc[1], acc[2]);
   };
   if (base + (kEw - 1) * kBlock < n) {
     V sv[kEw], pv[kEw], tv[kEw], yv[kEw], hv[kEw];
@@ -287,14 +348,14 @@ __global__ void k_unscale(int n, const V* __restrict__ dinv, const V* __restrict
 
 // partials of ||w||^2
 template <class R>
-__global__ __launch_bounds__(kBlock) void k_norm2_partials(int n, const cplx<R>* __restrict__ w, R* partials) {
-  __shared__ R lds[kBlock / kWave];
-  R acc[1] = {0};
+__global__ __launch_bounds__(kBlock) void k_norm2_partials(int n, const cplx<R>* __restrict__ w, double* partials) {
+  __shared__ double lds[kBlock / kWave];
+  double acc[1] = {0};
   const int base = blockIdx.x * (kBlock * kEw) + threadIdx.x;
 #pragma unroll
   for (int k = 0; k < kEw; ++k) {
     const int i = base + k * kBlock;
-    if (i < n) acc[0] += cabs2(w[i]);
+    if (i < n) acc[0] += nrm2d(w[i]);
   }
   block_sum<1>(acc, lds);
   store_block_partials<1>(acc, partials);
@@ -313,11 +374,11 @@ template <> struct FinNV<F_XR> { static constexpr int v = 3; };
 // One workgroup: sums the nb partials of the preceding kernel and applies
 // the scalar update of step F.
 template <class R, int F>
-__global__ __launch_bounds__(kFinBlock) void k_fin(SolveState<R>* st, const R* partials, int nb, R tol,
+__global__ __launch_bounds__(kFinBlock) void k_fin(SolveState* st, const double* partials, int nb, double tol,
                                                    long long maxit) {
-  using V = cplx<R>;
+  using V = double2;
   constexpr int NV = FinNV<F>::v;
-  __shared__ R lds[NV * (kFinBlock / kWave)];
+  __shared__ double lds[NV * (kFinBlock / kWave)];
   const int status = st->status;
   if (F == F_XR) {
     if (status == S_HALF || status == S_TAUBD) {
@@ -337,7 +398,7 @@ __global__ __launch_bounds__(kFinBlock) void k_fin(SolveState<R>* st, const R* p
     }
   }
   if (F != F_INIT && F != F_TRUE && status != S_RUN) return;
-  R tot[NV];
+  double tot[NV];
   final_sum<NV>(partials, nb, tot, lds);
   if (threadIdx.x != 0) return;
   if (F == F_INIT) {
@@ -379,7 +440,7 @@ __global__ __launch_bounds__(kFinBlock) void k_fin(SolveState<R>* st, const R* p
       st->status = S_HALF;
     }
   } else if (F == F_OMEGA) {
-    const R tau = tot[0];
+    const double tau = tot[0];
     const V ts = cmake<V>(tot[1], tot[2]);
     if (!isfinite(tau) || !cfinite(ts)) {
       st->status = HK_NONFINITE;
@@ -387,11 +448,11 @@ __global__ __launch_bounds__(kFinBlock) void k_fin(SolveState<R>* st, const R* p
     } else if (tau == 0) {
       st->status = S_TAUBD;
     } else {
-      st->omega = cscale<V>(R(1) / tau, ts);
+      st->omega = cmake<V>(ts.x / tau, ts.y / tau);
     }
   } else if (F == F_XR) {
     const long long it = st->iter;
-    const R rr = tot[0];
+    const double rr = tot[0];
     const V rho = cmake<V>(tot[1], tot[2]);
     const V alpha = st->alpha, omega = st->omega;
     st->rr = rr;
@@ -446,8 +507,8 @@ __global__ void k_add_c64(int n, const float2* __restrict__ d, double2* __restri
 template <class R> struct Work {
   using V = cplx<R>;
   V *y, *r, *rh, *p, *v, *s, *t, *dinv, *ahat;
-  R* partials;
-  SolveState<R>* st;
+  double* partials;
+  SolveState* st;
   int* flag;
 };
 
@@ -456,7 +517,7 @@ static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 template <class R> static size_t work_bytes(int64_t n, int64_t nnz) {
   using V = cplx<R>;
   return 8 * align_up(sizeof(V) * n) + align_up(sizeof(V) * (nnz > 0 ? nnz : 1)) +
-         align_up(sizeof(R) * 4 * partial_slots(n)) + align_up(sizeof(SolveState<R>)) + align_up(64);
+         align_up(sizeof(double) * 4 * partial_slots(n)) + align_up(sizeof(SolveState)) + align_up(64);
 }
 
 template <class R> static Work<R> carve(void* base, int64_t n, int64_t nnz) {
@@ -473,8 +534,8 @@ template <class R> static Work<R> carve(void* base, int64_t n, int64_t nnz) {
   w.t = (V*)take(sizeof(V) * n);
   w.dinv = (V*)take(sizeof(V) * n);
   w.ahat = (V*)take(sizeof(V) * (nnz > 0 ? nnz : 1));
-  w.partials = (R*)take(sizeof(R) * 4 * partial_slots(n));
-  w.st = (SolveState<R>*)take(sizeof(SolveState<R>));
+  w.partials = (double*)take(sizeof(double) * 4 * partial_slots(n));
+  w.st = (SolveState*)take(sizeof(SolveState));
   w.flag = (int*)take(64);
   return w;
 }
@@ -513,11 +574,23 @@ static hipError_t launch_spmv_dot(const hk_csr_s* A, int L, int U, int grid, int
   HK_SD_CASE(16, 1) HK_SD_CASE(16, 2) HK_SD_CASE(16, 4) HK_SD_CASE(16, 8)
   HK_SD_CASE(32, 1) HK_SD_CASE(32, 2) HK_SD_CASE(32, 4) HK_SD_CASE(32, 8)
 #undef HK_SD_CASE
+#define HK_SDS_CASE(CH)                                                                             \
+  if (L == kStreamL && U == CH) {                                                                   \
+    if (dot == 1)                                                                                   \
+      hipLaunchKernelGGL((k_spmv_dot_stream<CH, R, 1>), dim3(grid), dim3(kBlock), 0, s, n, ntiles,  \
+                         A->rowptr, A->col, val, x, y, w, wk.st, wk.partials);                      \
+    else                                                                                            \
+      hipLaunchKernelGGL((k_spmv_dot_stream<CH, R, 2>), dim3(grid), dim3(kBlock), 0, s, n, ntiles,  \
+                         A->rowptr, A->col, val, x, y, w, wk.st, wk.partials);                      \
+    return hipGetLastError();                                                                       \
+  }
+  HK_SDS_CASE(8) HK_SDS_CASE(16)
+#undef HK_SDS_CASE
   return hipErrorInvalidValue;
 }
 
 template <class R, int F>
-static hipError_t launch_fin(const Work<R>& wk, int nb, R tol, long long maxit, hipStream_t s) {
+static hipError_t launch_fin(const Work<R>& wk, int nb, double tol, long long maxit, hipStream_t s) {
   hipLaunchKernelGGL((k_fin<R, F>), dim3(1), dim3(kFinBlock), 0, s, wk.st, wk.partials, nb, tol, maxit);
   return hipGetLastError();
 }
@@ -550,14 +623,14 @@ static int bicgstab(const hk_csr_s* A, const cplx<R>* val, const cplx<R>* b, cpl
     int rc = spmv_dispatch(&tmp, x, wk.r, b, nullptr, nullptr, 1, s);
     if (rc != HK_OK) return rc;
   }
-  SolveState<R> init{};
+  SolveState init{};
   init.history = o.d_history;
   init.status = S_RUN;
   HK_HIP(hipMemcpyAsync(wk.st, &init, sizeof(init), hipMemcpyHostToDevice, s));
   hipLaunchKernelGGL(k_init<R>, dim3(gv), dim3(kBlock), 0, s, n, o.use_x0 ? 1 : 0, b, x, wk.dinv,
                      wk.r, wk.rh, wk.p, wk.y, wk.partials);
   HK_CHECK_LAUNCH();
-  HK_HIP((launch_fin<R, F_INIT>(wk, gv, (R)o.tol, (long long)o.max_iter, s)));
+  HK_HIP((launch_fin<R, F_INIT>(wk, gv, o.tol, (long long)o.max_iter, s)));
   int hflag = 0;
   HK_HIP(hipMemcpyAsync(&hflag, wk.flag, sizeof(int), hipMemcpyDeviceToHost, s));
   HK_HIP(hipStreamSynchronize(s));
@@ -572,7 +645,7 @@ static int bicgstab(const hk_csr_s* A, const cplx<R>* val, const cplx<R>* b, cpl
   int rc = HK_OK;
   long long enq = 0;
   int k = 0;
-  const size_t status_off = offsetof(SolveState<R>, status);
+  const size_t status_off = offsetof(SolveState, status);
   for (;;) {
     for (int j = 0; j < m && rc == HK_OK; ++j) {
       hipLaunchKernelGGL(k_p<R>, ew, dim3(kBlock), 0, s, n, wk.st, wk.r, wk.p, wk.v);
@@ -630,7 +703,7 @@ static int bicgstab(const hk_csr_s* A, const cplx<R>* val, const cplx<R>* b, cpl
   hipLaunchKernelGGL(k_norm2_partials<R>, dim3(gv), dim3(kBlock), 0, s, n, wk.t, wk.partials);
   HK_CHECK_LAUNCH();
   HK_HIP((launch_fin<R, F_TRUE>(wk, gv, 0, 0, s)));
-  SolveState<R> hs;
+  SolveState hs;
   HK_HIP(hipMemcpyAsync(&hs, wk.st, sizeof(hs), hipMemcpyDeviceToHost, s));
   HK_HIP(hipStreamSynchronize(s));
   info->status = hs.status >= S_RUN ? HK_NOT_CONVERGED : hs.status;
@@ -663,16 +736,22 @@ using namespace hk;
 extern "C" int hk_krylov_solve(hk_csr A, const void* d_b, void* d_x, const hk_solve_opts* opts,
                                hk_solve_info* info, void* stream) {
   if (!A || !d_b || !d_x || !info) HK_FAIL(HK_EINVAL, "hk_krylov_solve: null argument");
-  if (A->dtype != HK_C128) HK_FAIL(HK_EINVAL, "hk_krylov_solve: matrix must be complex128");
   int rc = check_opts(opts, "hk_krylov_solve");
   if (rc != HK_OK) return rc;
   hipStream_t s = as_stream(stream);
   rc = ensure_pinned(A);
   if (rc != HK_OK) return rc;
-  rc = ensure_ws(&A->ws, &A->ws_bytes, work_bytes<double>(A->n, A->nnz), s);
-  if (rc != HK_OK) return rc;
-  rc = bicgstab<double>(A, (const double2*)A->val, (const double2*)d_b, (double2*)d_x, *opts, A->ws,
-                        info, s);
+  if (A->dtype == HK_C64) {
+    rc = ensure_ws(&A->ws32, &A->ws32_bytes, work_bytes<float>(A->n, A->nnz), s);
+    if (rc != HK_OK) return rc;
+    rc = bicgstab<float>(A, (const float2*)A->val, (const float2*)d_b, (float2*)d_x, *opts, A->ws32,
+                         info, s);
+  } else {
+    rc = ensure_ws(&A->ws, &A->ws_bytes, work_bytes<double>(A->n, A->nnz), s);
+    if (rc != HK_OK) return rc;
+    rc = bicgstab<double>(A, (const double2*)A->val, (const double2*)d_b, (double2*)d_x, *opts, A->ws,
+                          info, s);
+  }
   if (rc != HK_OK) return rc;
   return info->status;
 }
@@ -726,6 +805,7 @@ extern "C" int hk_krylov_solve_mixed(hk_csr A, const void* d_b, void* d_x, doubl
   hk_csr_s A32 = *A;
   A32.val = A->val32;
   A32.dtype = HK_C64;
+  const bool trace = getenv("HK_TRACE") != nullptr;
   for (k = 0; k <= max_outer; ++k) {
     rc = spmv_dispatch(A, d_x, r, d_b, nullptr, nullptr, 1, s);   // r = b - A u (complex128)
     if (rc != HK_OK) return rc;
@@ -747,6 +827,9 @@ extern "C" int hk_krylov_solve_mixed(hk_csr A, const void* d_b, void* d_x, doubl
     hk_solve_info ii{};
     rc = bicgstab<float>(&A32, (const float2*)A->val32, r32, d32, io, A->ws32, &ii, s);
     if (rc != HK_OK) return rc;
+    if (trace)
+      fprintf(stderr, "[hk mixed] cycle %d: ||r||/||b|| = %.3e, inner status %d (breakdown %d) after %lld iterations, inner relres %.3e\n",
+              k, rel, ii.status, ii.breakdown, (long long)ii.iters, ii.relres_rec);
     inner_total += ii.iters;
     if (ii.status == HK_NONFINITE) { status = HK_NONFINITE; break; }
     hipLaunchKernelGGL(k_add_c64, ew, dim3(kBlock), 0, s, (int)n, (const float2*)d32, (double2*)d_x,

@@ -85,6 +85,57 @@ __device__ __forceinline__ void csr_rows(int r0, int n, const int* __restrict__ 
   }
 }
 
+// Row-block ("stream") CSR: one wave per 64 consecutive rows r0 .. r0+63.
+// The wave streams the rows' entries with all 64 lanes -- entry e of the
+// block goes to lane e % 64, CH entries per lane per pass, every column and
+// value load issued before any gather -- parks the products in its LDS slice
+// buf[CH*64], then each lane sums the products of its own row in entry
+// order.  Rows of any length are handled by passes over the block's entry
+// range (the pass count is uniform across the wave).  Returns the sum of
+// row r0 + lane (zero for rows >= n).  All 64 lanes must call it.
+template <int CH, class V>
+__device__ __forceinline__ V csr_stream_rows(int r0, int n, const int* __restrict__ rowptr,
+                                             const int* __restrict__ col, const V* __restrict__ val,
+                                             const V* __restrict__ x, V* buf) {
+  const int l = threadIdx.x & (kWave - 1);
+  const int rs = rowptr[r0 + l < n ? r0 + l : n];
+  const int rend = rowptr[r0 + kWave < n ? r0 + kWave : n];
+  const int nxt = __shfl(rs, (l + 1) & (kWave - 1), kWave);
+  const int re = l < kWave - 1 ? nxt : rend;
+  const int s0 = __shfl(rs, 0, kWave);
+  V acc = czero<V>();
+  for (int c0 = s0; c0 < rend; c0 += CH * kWave) {
+    const int cend = c0 + CH * kWave < rend ? c0 + CH * kWave : rend;
+    int c[CH];
+    V a[CH];
+#pragma unroll
+    for (int k = 0; k < CH; ++k) {
+      const int e = c0 + l + kWave * k;
+      const int p = e < cend ? e : cend - 1;
+      c[k] = ldnt(col + p);
+      a[k] = ldnt(val + p);
+    }
+    V xv[CH];
+#pragma unroll
+    for (int k = 0; k < CH; ++k) xv[k] = x[c[k]];
+#pragma unroll
+    for (int k = 0; k < CH; ++k) {
+      const int e = c0 + l + kWave * k;
+      if (e < cend) buf[e - c0] = cmul(a[k], xv[k]);
+    }
+    // LDS accesses of one wave complete in issue order; the barrier keeps the
+    // compiler from moving the reads above the writes (and the next pass's
+    // writes above these reads)
+    __builtin_amdgcn_wave_barrier();
+    const int lo = rs > c0 ? rs : c0, hi = re < cend ? re : cend;
+    for (int e = lo; e < hi; ++e) acc = cadd(acc, buf[e - c0]);
+    __builtin_amdgcn_wave_barrier();
+  }
+  return acc;
+}
+
+constexpr int kStreamL = 64;   // plan code for the row-block scheme
+
 // Tile range [t0, t1) of the calling workgroup for a launch of gridDim.x
 // workgroups over ntiles tiles (contiguous per workgroup, XCD-major).
 __device__ __forceinline__ void tile_range(int ntiles, int& t0, int& t1) {

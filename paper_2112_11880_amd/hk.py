@@ -251,10 +251,10 @@ def _opts(tol, max_iter, precond, check_every, use_x0, history):
 
 def krylov_solve(A: CSR, b, x=None, tol=1e-8, max_iter=400000, precond=True, check_every=0,
                  history=False):
-    """Jacobi right-preconditioned BiCGStab; returns (x, info dict[, history tensor])."""
-    _cvec(b, name="b")
+    """Jacobi right-preconditioned BiCGStab in A's precision; returns (x, info dict[, history])."""
+    _cvec(b, A.dtype, name="b")
     use_x0 = x is not None
-    x = torch.zeros_like(b) if x is None else _cvec(x, name="x")
+    x = torch.zeros_like(b) if x is None else _cvec(x, A.dtype, name="x")
     hist = torch.zeros(int(max_iter) + 1, dtype=torch.float64, device=b.device) if history else None
     info = SolveInfo()
     o = _opts(tol, max_iter, precond, check_every, use_x0, hist)

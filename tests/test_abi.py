@@ -7,6 +7,7 @@ import ctypes as C
 import os
 import re
 import subprocess
+import sys
 
 import pytest
 
@@ -72,3 +73,21 @@ def test_library_has_no_oracle_dependency():
             if f.endswith((".py", ".hip", ".hpp", ".h", ".cpp")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
+
+
+def test_binding_rejects_host_tensors(lib):
+    """The binding refuses host memory instead of silently computing on the CPU."""
+    import torch
+    from paper_2112_11880_amd import hk
+    x = torch.zeros(8, dtype=torch.complex128)
+    for f in (lambda: hk.zdotc(x, x), lambda: hk.dznrm2(x), lambda: hk.zaxpy(1.0, x, x),
+              lambda: hk.CSR(torch.zeros(9, dtype=torch.int32), torch.zeros(0, dtype=torch.int32),
+                             torch.zeros(0, dtype=torch.complex128))):
+        with pytest.raises(hk.HKError):
+            f()
+
+
+def test_bench_refuses_several_gpus():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr

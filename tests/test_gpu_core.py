@@ -71,7 +71,8 @@ def small_mesh_problem(nc=(7, 5, 6), seed=3):
 
 # ------------------------------------------------------------------ SpMV
 
-SHAPES = [(L, U, g) for L in (4, 8, 16, 32) for U in (1, 2, 4, 8) for g in (0, 3, 64) if U <= L]
+SHAPES = ([(L, U, g) for L in (4, 8, 16, 32) for U in (1, 2, 4, 8) for g in (0, 3, 64) if U <= L]
+          + [(64, ch, g) for ch in (8, 16) for g in (0, 3, 64)])
 
 
 def test_spmv_all_shapes_ragged(hk, oracle):
@@ -125,6 +126,11 @@ def test_spmv_edge_structures(hk, oracle):
     col = np.concatenate([np.sort(rng.choice(n, l, replace=False)) for l in lens]).astype(np.int32)
     cases.append(("ragged", rowptr, col))
     cases.append(("one", np.array([0, 1], dtype=np.int32), np.array([0], dtype=np.int32)))
+    # 30 entries per row: a 64-row block spans several passes of the row-block scheme
+    n2 = 200
+    rowptr2 = np.arange(n2 + 1, dtype=np.int32) * 30
+    col2 = np.concatenate([np.sort(rng.choice(n2, 30, replace=False)) for _ in range(n2)]).astype(np.int32)
+    cases.append(("wide", rowptr2, col2))
     for name, rowptr, col in cases:
         n = rowptr.shape[0] - 1
         val = crandn(rng, col.shape[0])
@@ -132,7 +138,7 @@ def test_spmv_edge_structures(hk, oracle):
         ref = oracle.spmv(rowptr, col, val, x)
         bound = 1e-12 * spmv_bound(rowptr, col, val, x)
         A = make_csr(hk, rowptr, col, val)
-        for L, U, g in SHAPES[::5]:
+        for L, U, g in SHAPES[::5] + SHAPES[-6:]:
             say("spmv edge", name, L, U, g)
             A.set_plan(L, U, g)
             xd = dev(x)
@@ -299,6 +305,42 @@ def test_solve_every_launch_shape(hk, oracle):
         assert np.linalg.norm(host(x) - xo) <= 1e-11 * np.linalg.norm(xo), (L, U, g)
 
 
+def test_solve_complex64_matches_oracle_iterates(hk, oracle):
+    """complex64 BiCGStab (float accumulation) vs the oracle's complex-float
+    solver: a few iterations in every launch shape, then two full solves in a
+    row on one handle (workspace reuse) with different right-hand sides."""
+    rowptr, col, val = small_mesh_problem((5, 5, 5), 11)
+    n = rowptr.shape[0] - 1
+    v32 = val.astype(np.complex64)
+    rng = np.random.default_rng(21)
+    b1 = crandn(rng, n).astype(np.complex64)
+    b2 = (1e-3 * crandn(rng, n)).astype(np.complex64)
+    A = make_csr(hk, rowptr, col, v32)
+    # On this indefinite system the oracle's own complex-float iterate
+    # differs from its complex128 iterate (same rounded matrix) by 1.0e-7
+    # after one step and 4.8e-7 after two (5.9e-6 after three, 5e-4 after
+    # five): rounding differences grow quickly, so only two steps are compared.
+    xo1, _ = oracle.bicgstab_c64(rowptr, col, v32, b1, tol=1e-9, maxit=1)
+    xo2, oi2 = oracle.bicgstab_c64(rowptr, col, v32, b1, tol=1e-9, maxit=2)
+    assert oi2["iters"] == 2
+    for L, U, g in SHAPES[::3]:
+        say("c64 solve shape", L, U, g)
+        A.set_plan(L, U, g)
+        for k, xo, bound in ((1, xo1, 1e-6), (2, xo2, 1e-5)):
+            x, info = hk.krylov_solve(A, dev(b1), tol=1e-9, max_iter=k)
+            assert info["iters"] == k and info["status"] == hk.HK_NOT_CONVERGED
+            assert np.linalg.norm(host(x) - xo) <= bound * np.linalg.norm(xo), (L, U, g, k)
+    A.set_plan(16, 1, 0)
+    for b in (b1, b2, b1):
+        say("c64 full solve", float(np.linalg.norm(b)))
+        x, info = hk.krylov_solve(A, dev(b), tol=1e-4)
+        xo, oi = oracle.bicgstab_c64(rowptr, col, v32, b, tol=1e-4)
+        say("gpu", info, "oracle", oi)
+        assert info["status"] == 0 and oi["status"] == 0
+        r = oracle.residual(rowptr, col, val, b.astype(np.complex128), host(x).astype(np.complex128))
+        assert np.linalg.norm(r) <= 2e-4 * np.linalg.norm(b)
+
+
 def test_solve_breakdowns_and_errors(hk, oracle):
     say("sigma breakdown")
     A = make_csr(hk, np.array([0, 2, 4], dtype=np.int32), np.array([0, 1, 0, 1], dtype=np.int32),
@@ -353,7 +395,7 @@ def test_solve_history(hk):
 def test_mixed_config1(hk, oracle):
     c = configs.config1()
     A = make_csr(hk, c["rowptr"], c["col"], c["val"], autotune=True)
-    say("mixed config1")
+    say("mixed config1", A.plan())
     x, info = hk.krylov_solve_mixed(A, dev(c["g"]), inner_tol=1e-4, outer_tol=1e-10)
     assert info["status"] == hk.HK_OK, info
     xh = host(x)
