@@ -11,6 +11,12 @@
 // serialised device-scope atomics); flags in separate words cost a few
 // round trips.
 //
+// Only thread 0 of a workgroup fences; the workgroup barrier that follows
+// orders the other threads after it (the usual grid-sync pattern).  On
+// gfx950 an agent-scope acquire fence invalidates caches, and executing it in
+// all 16 waves of a 1024-thread workgroup made one barrier cost ~63 us (one
+// wave: a few us).
+//
 // Every wait has a time limit: a workgroup that waits longer than
 // kSpinLimitTicks raises an abort flag and every workgroup leaves the kernel
 // at its next barrier, so a broken launch ends instead of hanging.
@@ -75,9 +81,11 @@ __device__ __forceinline__ bool barrier_last(GridBar* bar, unsigned& epoch, F&& 
     for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x) ok = wait_epoch(&bar->arrive[b], e, bar) && ok;
     if (!ok) atomicExch(&bar->abort, 1);
     __syncthreads();
-    if (threadIdx.x == 0) s_stop = ld_relaxed_i32(&bar->abort);
+    if (threadIdx.x == 0) {
+      s_stop = ld_relaxed_i32(&bar->abort);
+      __threadfence();  // acquire every workgroup's writes
+    }
     __syncthreads();
-    __threadfence();  // acquire every workgroup's writes
     if (!s_stop) on_last();
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -87,9 +95,11 @@ __device__ __forceinline__ bool barrier_last(GridBar* bar, unsigned& epoch, F&& 
   } else if (threadIdx.x == 0) {
     (void)wait_epoch(&bar->release, e, bar);
   }
-  if (threadIdx.x == 0) s_stop = ld_relaxed_i32(&bar->abort);
+  if (threadIdx.x == 0) {
+    s_stop = ld_relaxed_i32(&bar->abort);
+    __threadfence();  // acquire
+  }
   __syncthreads();
-  __threadfence();  // acquire
   return s_stop != 0;
 }
 
