@@ -183,12 +183,12 @@ __device__ __forceinline__ double2 sweep_diag(const SweepArgs& a, int i, double2
 // EPI 1: part += conj(RH) y ; EPI 2: part += |y|^2, conj(y) (d .* SH) ;
 // EPI 3: y = B - A src, part += |y|^2 (true residual).
 template <int EPI, int NV>
-__device__ __forceinline__ void sweep_spmv(const SweepArgs& a, int r0, int r1, const double2* src,
+__device__ __forceinline__ void sweep_spmv(const SweepArgs& a, int r0, int r1, int rs, const double2* src,
                                            double2* dst, bool act, double2 kap, double (&part)[NV]) {
   const int j = threadIdx.x & 63;
   // lanes of finished systems issue no loads at all
   if (!act) return;
-  for (int row = r0; row < r1; ++row) {
+  for (int row = r0; row < r1; row += rs) {
     const int s = a.rowptr[row], e = a.rowptr[row + 1];
     double2 acc = make_double2(0, 0);
     // 8 entries at a time, all gathers in flight together; past the row's
@@ -230,22 +230,51 @@ __device__ __forceinline__ void sweep_spmv(const SweepArgs& a, int r0, int r1, c
   }
 }
 
+#ifndef HK_SWEEP_MAP
+#define HK_SWEEP_MAP 0
+#endif
+// Rows r0, r0 + rs, ... < r1 of the calling wave.
+__device__ __forceinline__ void sweep_rows(int n, int G, int& r0, int& r1, int& rs) {
+  const int w = threadIdx.x >> 6;
+#if HK_SWEEP_MAP == 0
+  // one contiguous range per wave, XCD-major
+  const int wid = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, G) * kPW + w);
+  const int W = G * kPW;
+  r0 = (int)(((long long)wid * n) / W);
+  r1 = (int)(((long long)(wid + 1) * n) / W);
+  rs = 1;
+#elif HK_SWEEP_MAP == 1
+  // XCD x (workgroups b with b % 8 == x) owns a contiguous eighth of the
+  // rows; its waves take them round-robin, so they advance as one front
+  const int x = blockIdx.x % kXcds, i = blockIdx.x / kXcds;
+  const int nbx = (G - x + kXcds - 1) / kXcds;
+  const int X0 = (int)(((long long)x * n) / kXcds), X1 = (int)(((long long)(x + 1) * n) / kXcds);
+  r0 = X0 + i * kPW + w;
+  r1 = X1;
+  rs = nbx * kPW;
+#else
+  // every wave of the grid round-robin over all rows
+  r0 = blockIdx.x * kPW + w;
+  r1 = n;
+  rs = G * kPW;
+#endif
+}
+
 __global__ __launch_bounds__(kPB) void k_sweep(SweepArgs a) {
   __shared__ double lds[4 * kPW * kSys];
   unsigned epoch = 0;
   BatchState* st = a.st;
   const int j = threadIdx.x & 63;
   const int G = gridDim.x;
-  const int wid = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, G) * kPW + (threadIdx.x >> 6));
-  const int W = G * kPW;
-  const int r0 = (int)(((long long)wid * a.n) / W), r1 = (int)(((long long)(wid + 1) * a.n) / W);
+  int r0, r1, rs;
+  sweep_rows(a.n, G, r0, r1, rs);
   const bool lane_ok = j < a.nsys;
   const double2 kap = lane_ok ? a.kap[j] : make_double2(0, 0);
 
   // ---- start: r = rhat = b, phat = D^-1 b, x = 0
   {
     double part[1] = {0};
-    for (int row = r0; row < r1; ++row) {
+    for (int row = r0; row < r1; row += rs) {
       const size_t o = (size_t)row * kSys + j;
       if (!lane_ok) continue;
       const double2 b = a.B[o];
@@ -281,18 +310,18 @@ __global__ __launch_bounds__(kPB) void k_sweep(SweepArgs a) {
       const double2 beta = st->beta[j], bo = cmul(st->beta[j], st->omega[j]);
       if (act) {
         int row = r0;
-        for (; row + 4 <= r1; row += 4) {
+        for (; row + 3 * rs < r1; row += 4 * rs) {
           double2 rv[4], vv[4], pv[4], dv[4];
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
-            const size_t o = (size_t)(row + u) * kSys + j;
-            rv[u] = a.R[o]; vv[u] = a.V[o]; pv[u] = a.PH[o]; dv[u] = sweep_diag(a, row + u, kap);
+            const size_t o = (size_t)(row + u * rs) * kSys + j;
+            rv[u] = a.R[o]; vv[u] = a.V[o]; pv[u] = a.PH[o]; dv[u] = sweep_diag(a, row + u * rs, kap);
           }
 #pragma unroll
           for (int u = 0; u < 4; ++u)
-            a.PH[(size_t)(row + u) * kSys + j] = cfma(beta, pv[u], cmul(crecip(dv[u]), csub(rv[u], cmul(bo, vv[u]))));
+            a.PH[(size_t)(row + u * rs) * kSys + j] = cfma(beta, pv[u], cmul(crecip(dv[u]), csub(rv[u], cmul(bo, vv[u]))));
         }
-        for (; row < r1; ++row) {
+        for (; row < r1; row += rs) {
           const size_t o = (size_t)row * kSys + j;
           const double2 w = csub(a.R[o], cmul(bo, a.V[o]));
           a.PH[o] = cfma(beta, a.PH[o], cmul(crecip(sweep_diag(a, row, kap)), w));
@@ -303,7 +332,7 @@ __global__ __launch_bounds__(kPB) void k_sweep(SweepArgs a) {
     // ---- v = A phat ; sigma = rhat^H v
     {
       double part[2] = {0, 0};
-      sweep_spmv<1, 2>(a, r0, r1, a.PH, a.V, act, kap, part);
+      sweep_spmv<1, 2>(a, r0, r1, rs, a.PH, a.V, act, kap, part);
       store_partials64<2>(part, a.partials, lds);
       if (barrier_last(a.bar, epoch, [&] {
             double tot[2];
@@ -319,21 +348,21 @@ __global__ __launch_bounds__(kPB) void k_sweep(SweepArgs a) {
       const double2 alpha = st->alpha[j];
       if (act) {
         int row = r0;
-        for (; row + 4 <= r1; row += 4) {
+        for (; row + 3 * rs < r1; row += 4 * rs) {
           double2 rv[4], vv[4], dv[4];
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
-            const size_t o = (size_t)(row + u) * kSys + j;
-            rv[u] = a.R[o]; vv[u] = a.V[o]; dv[u] = sweep_diag(a, row + u, kap);
+            const size_t o = (size_t)(row + u * rs) * kSys + j;
+            rv[u] = a.R[o]; vv[u] = a.V[o]; dv[u] = sweep_diag(a, row + u * rs, kap);
           }
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
             const double2 s = csub(rv[u], cmul(alpha, vv[u]));
-            a.SH[(size_t)(row + u) * kSys + j] = cmul(crecip(dv[u]), s);
+            a.SH[(size_t)(row + u * rs) * kSys + j] = cmul(crecip(dv[u]), s);
             part[0] += cabs2(s);
           }
         }
-        for (; row < r1; ++row) {
+        for (; row < r1; row += rs) {
           const size_t o = (size_t)row * kSys + j;
           const double2 s = csub(a.R[o], cmul(alpha, a.V[o]));
           a.SH[o] = cmul(crecip(sweep_diag(a, row, kap)), s);
@@ -352,7 +381,7 @@ __global__ __launch_bounds__(kPB) void k_sweep(SweepArgs a) {
     // ---- t = A shat ; tau = t^H t ; t^H s
     {
       double part[3] = {0, 0, 0};
-      sweep_spmv<2, 3>(a, r0, r1, a.SH, a.T, act, kap, part);
+      sweep_spmv<2, 3>(a, r0, r1, rs, a.SH, a.T, act, kap, part);
       store_partials64<3>(part, a.partials, lds);
       if (barrier_last(a.bar, epoch, [&] {
             double tot[3];
@@ -377,23 +406,23 @@ __global__ __launch_bounds__(kPB) void k_sweep(SweepArgs a) {
           part[2] = fma(h.x, r.y, fma(-h.y, r.x, part[2]));
         };
         int row = r0;
-        for (; row + 2 <= r1; row += 2) {
+        for (; row + rs < r1; row += 2 * rs) {
           double2 sh[2], ph[2], xv[2], tv[2], hv[2], dv[2];
 #pragma unroll
           for (int u = 0; u < 2; ++u) {
-            const size_t o = (size_t)(row + u) * kSys + j;
+            const size_t o = (size_t)(row + u * rs) * kSys + j;
             sh[u] = a.SH[o]; ph[u] = a.PH[o]; xv[u] = a.X[o]; tv[u] = a.T[o]; hv[u] = a.RH[o];
-            dv[u] = sweep_diag(a, row + u, kap);
+            dv[u] = sweep_diag(a, row + u * rs, kap);
           }
 #pragma unroll
-          for (int u = 0; u < 2; ++u) upd(row + u, sh[u], ph[u], xv[u], tv[u], hv[u], dv[u]);
+          for (int u = 0; u < 2; ++u) upd(row + u * rs, sh[u], ph[u], xv[u], tv[u], hv[u], dv[u]);
         }
-        for (; row < r1; ++row) {
+        for (; row < r1; row += rs) {
           const size_t o = (size_t)row * kSys + j;
           upd(row, a.SH[o], a.PH[o], a.X[o], a.T[o], a.RH[o], sweep_diag(a, row, kap));
         }
       } else if (sj == B_HALF || sj == B_TAUBD) {
-        for (int row = r0; row < r1; ++row) {
+        for (int row = r0; row < r1; row += rs) {
           const size_t o = (size_t)row * kSys + j;
           a.X[o] = cfma(alpha, a.PH[o], a.X[o]);
         }
@@ -421,7 +450,7 @@ __global__ __launch_bounds__(kPB) void k_sweep(SweepArgs a) {
   // ---- true residual ||b - A x||^2 per system
   {
     double part[1] = {0};
-    sweep_spmv<3, 1>(a, r0, r1, a.X, nullptr, lane_ok, kap, part);
+    sweep_spmv<3, 1>(a, r0, r1, rs, a.X, nullptr, lane_ok, kap, part);
     store_partials64<1>(part, a.partials, lds);
     barrier_last(a.bar, epoch, [&] {
       double tot[1];
@@ -763,6 +792,9 @@ struct Arena {
   }
 };
 
+#ifndef HK_COOP_PER
+#define HK_COOP_PER 2
+#endif
 static int coop_grid(const void* kernel, int* grid) {
   int dev = 0, cus = 0, per = 0, coop = 0;
   HK_HIP(hipGetDevice(&dev));
@@ -771,7 +803,7 @@ static int coop_grid(const void* kernel, int* grid) {
   if (!coop) HK_FAIL(HK_EHIP, "device does not support cooperative launches");
   HK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, kPB, 0));
   if (per < 1) HK_FAIL(HK_EHIP, "persistent kernel does not fit on a CU");
-  *grid = std::min(cus * std::min(per, 2), kBarMaxBlocks);
+  *grid = std::min(cus * std::min(per, HK_COOP_PER), kBarMaxBlocks);
   return HK_OK;
 }
 

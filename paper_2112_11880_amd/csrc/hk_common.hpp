@@ -124,17 +124,35 @@ constexpr int kFinBlock = 1024;  // threads of a second-stage (finalize) kernel
 
 // Second stage, run by one workgroup of kFinBlock threads: out[k] (valid in
 // thread 0) = sum over nb partials, each thread summing a strided subset in
-// index order, then a fixed tree over the waves.
+// index order, then a fixed tree over the waves.  A thread issues the loads
+// of up to kFinUnroll of its partials (all NV components) before adding, so
+// the load latency is paid once per kFinUnroll*kFinBlock partials rather
+// than once per partial.
+constexpr int kFinUnroll = 8;
 template <int NV, class T>
 __device__ __forceinline__ void final_sum(const T* partials, int nb, T (&out)[NV], T* lds /*[NV*16]*/) {
   const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
   constexpr int W = kFinBlock / kWave;
+  T s[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) s[k] = 0;
+  for (int j0 = threadIdx.x; j0 < nb; j0 += kFinUnroll * kFinBlock) {
+    T v[NV][kFinUnroll];
+#pragma unroll
+    for (int u = 0; u < kFinUnroll; ++u) {
+      const int j = j0 + u * kFinBlock;
+#pragma unroll
+      for (int k = 0; k < NV; ++k) v[k][u] = j < nb ? partials[k * nb + j] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < kFinUnroll; ++u)
+#pragma unroll
+      for (int k = 0; k < NV; ++k) s[k] += v[k][u];
+  }
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
-    T s = 0;
-    for (int j = threadIdx.x; j < nb; j += kFinBlock) s += partials[k * nb + j];
-    s = wave_sum(s);
-    if (lane == 0) lds[k * W + w] = s;
+    const T t = wave_sum(s[k]);
+    if (lane == 0) lds[k * W + w] = t;
   }
   __syncthreads();
   if (threadIdx.x == 0) {

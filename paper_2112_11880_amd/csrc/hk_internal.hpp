@@ -65,8 +65,10 @@ struct hk_csr_s {
   // solver workspace (device), allocated on first solve, freed by destroy
   void* ws = nullptr;
   size_t ws_bytes = 0;
-  // complex64 copy of the values for the mixed-precision solve
+  // complex64 copy of the values for the mixed-precision solve, and the
+  // launch shape tuned for it (when the handle was tuned)
   void* val32 = nullptr;
+  hk::SpmvPlan plan32;
   void* ws32 = nullptr;
   size_t ws32_bytes = 0;
   // pinned host words the solver reads its status through
@@ -75,5 +77,8 @@ struct hk_csr_s {
 
 namespace hk {
 int spmv_tiles(const hk_csr_s* A, int L, int U);
+// Times every launch shape of the CSR product on A (its dtype and values)
+// and stores the fastest in A->plan (cached per matrix shape and dtype).
+int spmv_autotune(hk_csr_s* A, hipStream_t s);
 int default_grid(int ntiles);
 }

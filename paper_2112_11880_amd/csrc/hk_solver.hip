@@ -30,10 +30,14 @@
 // One iteration (each reduction followed by its finalize kernel):
 //   K_p   : p = r + beta (p - omega v)                      (iteration > 1)
 //   K_v   : v = Ahat p,  sigma = rhat^H v  -> alpha = rho / sigma
-//   K_s   : s = r - alpha v, ||s||^2       -> half-step convergence test
-//   K_t   : t = Ahat s,  tau = t^H t, t^H s -> omega
+//   K_s   : s = r - alpha v
+//   K_t   : t = Ahat s,  tau = t^H t, t^H s, ||s||^2
+//           -> half-step convergence test, then omega
 //   K_xr  : y += alpha p + omega s, r = s - omega t, ||r||^2, rhat^H r
 //           -> rho, beta, convergence / breakdown / cap tests
+// ||s||^2 comes from the epilogue of K_t, which reads s at its own rows for
+// t^H s anyway; in the iteration that converges at the half step, t is
+// computed and not used.
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
@@ -57,7 +61,11 @@ struct SolveState {
   double* history;
 };
 
-constexpr int kMaxGrid = 2048;   // workgroups of the fused SpMV launches
+// Most workgroups of a fused SpMV+dot launch (one partial-sum slot each).
+// A launch shape with grid 0 gets one tile per workgroup up to this cap: on
+// the 1.8M-row system the row-block scheme has 7,094 tiles, and walking
+// them with 2,048 workgroups cost ~20 us per product (132 vs 112 us).
+constexpr int kMaxGrid = 8192;
 constexpr int kEw = 4;           // elements per thread in the element-wise solver kernels
 
 // workgroups of an element-wise solver kernel over n elements
@@ -166,7 +174,7 @@ __global__ __launch_bounds__(kBlock) void k_p(int n, const SolveState* __restric
 }
 
 // v = Ahat p and partials of sigma = rhat^H v  (DOT == 1), or
-// t = Ahat s and partials of tau = t^H t, t^H s (DOT == 2).
+// t = Ahat s and partials of tau = t^H t, t^H s, ||s||^2 (DOT == 2).
 template <int L, int U, class R, int DOT>
 __global__ __launch_bounds__(kBlock) void k_spmv_dot(int n, int ntiles, const int* __restrict__ rowptr,
                                                      const int* __restrict__ col,
@@ -176,7 +184,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dot(int n, int ntiles, const in
                                                      const cplx<R>* __restrict__ w,
                                                      const SolveState* __restrict__ st, double* partials) {
   using V = cplx<R>;
-  constexpr int NV = DOT == 1 ? 2 : 3;
+  constexpr int NV = DOT == 1 ? 2 : 4;
   __shared__ double lds[NV * (kBlock / kWave)];
   if (st->status != S_RUN) return;
   constexpr int RT = (kBlock / L) * U;
@@ -203,6 +211,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dot(int n, int ntiles, const in
         } else {
           part[0] += nrm2d(acc[u]);
           dotc_acc(acc[u], wr, part[1], part[2]);  // conj(t_r) * s_r
+          part[3] += nrm2d(wr);
         }
       }
     }
@@ -222,7 +231,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dot_stream(int n, int ntiles, c
                                                             const cplx<R>* __restrict__ w,
                                                             const SolveState* __restrict__ st, double* partials) {
   using V = cplx<R>;
-  constexpr int NV = DOT == 1 ? 2 : 3;
+  constexpr int NV = DOT == 1 ? 2 : 4;
   __shared__ V lds[(kBlock / kWave) * CH * kWave];
   if (st->status != S_RUN) return;
   V* buf = lds + (threadIdx.x / kWave) * CH * kWave;
@@ -243,6 +252,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dot_stream(int n, int ntiles, c
       } else {
         part[0] += nrm2d(acc);
         dotc_acc(acc, wr, part[1], part[2]);
+        part[3] += nrm2d(wr);
       }
     }
   }
@@ -254,37 +264,25 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dot_stream(int n, int ntiles, c
 template <class R>
 __global__ __launch_bounds__(kBlock) void k_s(int n, const SolveState* __restrict__ st,
                                               const cplx<R>* __restrict__ r,
-                                              const cplx<R>* __restrict__ v, cplx<R>* __restrict__ s,
-                                              double* partials) {
+                                              const cplx<R>* __restrict__ v, cplx<R>* __restrict__ s) {
   using V = cplx<R>;
-  __shared__ double lds[kBlock / kWave];
   if (st->status != S_RUN) return;
   const V alpha = vscal<V>(st->alpha);
-  double acc[1] = {0};
   const int base = blockIdx.x * (kBlock * kEw) + threadIdx.x;
   if (base + (kEw - 1) * kBlock < n) {
     V rv[kEw], vv[kEw];
 #pragma unroll
     for (int k = 0; k < kEw; ++k) { rv[k] = r[base + k * kBlock]; vv[k] = v[base + k * kBlock]; }
 #pragma unroll
-    for (int k = 0; k < kEw; ++k) {
-      // s = r - alpha v
-      const V si = csub(rv[k], cmul(alpha, vv[k]));
-      s[base + k * kBlock] = si;
-      acc[0] += nrm2d(si);
-    }
+    for (int k = 0; k < kEw; ++k) s[base + k * kBlock] = csub(rv[k], cmul(alpha, vv[k]));  // s = r - alpha v
   } else {
 #pragma unroll
     for (int k = 0; k < kEw; ++k) {
       const int i = base + k * kBlock;
       if (i >= n) break;
-      const V si = csub(r[i], cmul(alpha, v[i]));
-      s[i] = si;
-      acc[0] += nrm2d(si);
+      s[i] = csub(r[i], cmul(alpha, v[i]));
     }
   }
-  block_sum<1>(acc, lds);
-  store_block_partials<1>(acc, partials);
 }
 
 template <class R>
@@ -363,12 +361,12 @@ __global__ __launch_bounds__(kBlock) void k_norm2_partials(int n, const cplx<R>*
 
 // ------------------------------------------------------------ finalize kernels
 
-enum : int { F_INIT = 0, F_SIGMA = 1, F_S = 2, F_OMEGA = 3, F_XR = 4, F_TRUE = 5 };
+enum : int { F_INIT = 0, F_SIGMA = 1, F_OMEGA = 3, F_XR = 4, F_TRUE = 5 };
 
 template <int F> struct FinNV { static constexpr int v = 1; };
 template <> struct FinNV<F_INIT> { static constexpr int v = 2; };
 template <> struct FinNV<F_SIGMA> { static constexpr int v = 2; };
-template <> struct FinNV<F_OMEGA> { static constexpr int v = 3; };
+template <> struct FinNV<F_OMEGA> { static constexpr int v = 4; };
 template <> struct FinNV<F_XR> { static constexpr int v = 3; };
 
 // One workgroup: sums the nb partials of the preceding kernel and applies
@@ -431,18 +429,16 @@ __global__ __launch_bounds__(kFinBlock) void k_fin(SolveState* st, const double*
     } else {
       st->alpha = cdiv(st->rho, sigma);
     }
-  } else if (F == F_S) {
-    st->ss = tot[0];
-    if (!isfinite(tot[0])) {
-      st->status = HK_NONFINITE;
-      st->iters_done = st->iter - 1;
-    } else if (tot[0] <= st->theta2) {
-      st->status = S_HALF;
-    }
   } else if (F == F_OMEGA) {
     const double tau = tot[0];
     const V ts = cmake<V>(tot[1], tot[2]);
-    if (!isfinite(tau) || !cfinite(ts)) {
+    st->ss = tot[3];
+    if (!isfinite(tot[3])) {
+      st->status = HK_NONFINITE;
+      st->iters_done = st->iter - 1;
+    } else if (tot[3] <= st->theta2) {
+      st->status = S_HALF;
+    } else if (!isfinite(tau) || !cfinite(ts)) {
       st->status = HK_NONFINITE;
       st->iters_done = st->iter - 1;
     } else if (tau == 0) {
@@ -654,10 +650,9 @@ static int bicgstab(const hk_csr_s* A, const cplx<R>* val, const cplx<R>* b, cpl
         e = launch_spmv_dot<R>(A, A->plan.L, A->plan.U, gs, 1, wk.ahat, wk.p, wk.v, wk.rh, wk, s);
       if (e == hipSuccess) e = launch_fin<R, F_SIGMA>(wk, gs, 0, 0, s);
       if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_s<R>, dim3(gv), dim3(kBlock), 0, s, n, wk.st, wk.r, wk.v, wk.s, wk.partials);
+        hipLaunchKernelGGL(k_s<R>, dim3(gv), dim3(kBlock), 0, s, n, wk.st, wk.r, wk.v, wk.s);
         e = hipGetLastError();
       }
-      if (e == hipSuccess) e = launch_fin<R, F_S>(wk, gv, 0, 0, s);
       if (e == hipSuccess)
         e = launch_spmv_dot<R>(A, A->plan.L, A->plan.U, gs, 2, wk.ahat, wk.s, wk.t, wk.s, wk, s);
       if (e == hipSuccess) e = launch_fin<R, F_OMEGA>(wk, gs, 0, 0, s);
@@ -805,6 +800,15 @@ extern "C" int hk_krylov_solve_mixed(hk_csr A, const void* d_b, void* d_x, doubl
   hk_csr_s A32 = *A;
   A32.val = A->val32;
   A32.dtype = HK_C64;
+  if (A->plan.tuned) {
+    // a tuned handle gets its own launch shape for the complex64 copy
+    if (!A->plan32.tuned) {
+      rc = spmv_autotune(&A32, s);
+      if (rc != HK_OK) return rc;
+      A->plan32 = A32.plan;
+    }
+    A32.plan = A->plan32;
+  }
   const bool trace = getenv("HK_TRACE") != nullptr;
   for (k = 0; k <= max_outer; ++k) {
     rc = spmv_dispatch(A, d_x, r, d_b, nullptr, nullptr, 1, s);   // r = b - A u (complex128)

@@ -157,7 +157,7 @@ static SpmvPlan heuristic_plan(const hk_csr_s* A) {
 // Time every launch shape on this matrix (hipEvents on the caller's
 // stream), keep the fastest.  Results are cached per (n, nnz, longest row,
 // dtype) for the life of the process.
-static int autotune(hk_csr_s* A, hipStream_t s) {
+int spmv_autotune(hk_csr_s* A, hipStream_t s) {
   static std::mutex mu;
   static std::map<std::tuple<int64_t, int64_t, int, int, int>, SpmvPlan> cache;
   int dev = 0;
@@ -304,7 +304,7 @@ extern "C" int hk_csr_create(hk_csr* out, int64_t n, int64_t nnz, const int32_t*
   A->max_row = h[1];
   A->plan = heuristic_plan(A);
   if (flags & HK_AUTOTUNE) {
-    int rc = autotune(A, s);
+    int rc = spmv_autotune(A, s);
     if (rc != HK_OK) { delete A; return rc; }
   }
   *out = A;
