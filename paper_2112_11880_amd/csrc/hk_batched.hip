@@ -230,34 +230,20 @@ __device__ __forceinline__ void sweep_spmv(const SweepArgs& a, int r0, int r1, i
   }
 }
 
-#ifndef HK_SWEEP_MAP
-#define HK_SWEEP_MAP 0
-#endif
-// Rows r0, r0 + rs, ... < r1 of the calling wave.
+// Rows r0, r0 + rs, ... < r1 of the calling wave.  XCD x (the workgroups b
+// with b % 8 == x) owns a contiguous eighth of the rows and its waves take
+// them round-robin, so each XCD advances through its eighth as one front and
+// the x[col] gathers of neighbouring rows meet in its L2.  On the 48^3 sweep
+// this measured 902 us per iteration against 948 us for one contiguous row
+// range per wave and 906 us for waves round-robin over all rows.
 __device__ __forceinline__ void sweep_rows(int n, int G, int& r0, int& r1, int& rs) {
   const int w = threadIdx.x >> 6;
-#if HK_SWEEP_MAP == 0
-  // one contiguous range per wave, XCD-major
-  const int wid = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, G) * kPW + w);
-  const int W = G * kPW;
-  r0 = (int)(((long long)wid * n) / W);
-  r1 = (int)(((long long)(wid + 1) * n) / W);
-  rs = 1;
-#elif HK_SWEEP_MAP == 1
-  // XCD x (workgroups b with b % 8 == x) owns a contiguous eighth of the
-  // rows; its waves take them round-robin, so they advance as one front
   const int x = blockIdx.x % kXcds, i = blockIdx.x / kXcds;
-  const int nbx = (G - x + kXcds - 1) / kXcds;
+  const int nbx = (G - x + kXcds - 1) / kXcds;  // workgroups on XCD x
   const int X0 = (int)(((long long)x * n) / kXcds), X1 = (int)(((long long)(x + 1) * n) / kXcds);
   r0 = X0 + i * kPW + w;
   r1 = X1;
   rs = nbx * kPW;
-#else
-  // every wave of the grid round-robin over all rows
-  r0 = blockIdx.x * kPW + w;
-  r1 = n;
-  rs = G * kPW;
-#endif
 }
 
 __global__ __launch_bounds__(kPB) void k_sweep(SweepArgs a) {
@@ -792,9 +778,8 @@ struct Arena {
   }
 };
 
-#ifndef HK_COOP_PER
-#define HK_COOP_PER 2
-#endif
+// Workgroups per CU of the persistent kernels (one and two measured the same).
+constexpr int kCoopPerCu = 2;
 static int coop_grid(const void* kernel, int* grid) {
   int dev = 0, cus = 0, per = 0, coop = 0;
   HK_HIP(hipGetDevice(&dev));
@@ -803,7 +788,7 @@ static int coop_grid(const void* kernel, int* grid) {
   if (!coop) HK_FAIL(HK_EHIP, "device does not support cooperative launches");
   HK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, kPB, 0));
   if (per < 1) HK_FAIL(HK_EHIP, "persistent kernel does not fit on a CU");
-  *grid = std::min(cus * std::min(per, HK_COOP_PER), kBarMaxBlocks);
+  *grid = std::min(cus * std::min(per, kCoopPerCu), kBarMaxBlocks);
   return HK_OK;
 }
 
