@@ -86,10 +86,11 @@ int hk_csr_plan(hk_csr A, int32_t* lanes_per_row, int32_t* rows_per_group, int32
 
 /* Override the launch shape: lanes_per_row in {4,8,16,32} with
  * rows_per_group in {1,2,4,8} not above lanes_per_row (a group of lanes per
- * row), or lanes_per_row = 64 with rows_per_group in {8,16} (the row-block
- * scheme: one wave per 64 rows streaming their entries, rows_per_group =
- * entries per lane per pass); grid > 0, or 0 for one workgroup per tile.
- * Anything else gives HK_EINVAL. */
+ * row), or lanes_per_row = 64 with rows_per_group in {16,32,64} (the
+ * row-block scheme: one wave per rows_per_group consecutive rows, all 64
+ * lanes streaming their entries); grid > 0 (tiles dealt to workgroups with a
+ * grid stride), or 0 for one workgroup per tile.  Anything else gives
+ * HK_EINVAL. */
 int hk_csr_set_plan(hk_csr A, int32_t lanes_per_row, int32_t rows_per_group, int32_t grid);
 
 /*

@@ -902,7 +902,11 @@ extern "C" int hk_blockdiag_solve(hk_csr A, int32_t nsys, const int64_t* row_off
   for (int k = 0; k < nsys; ++k)
     if (row_off[k + 1] <= row_off[k]) HK_FAIL(HK_EINVAL, "hk_blockdiag_solve: empty or decreasing system %d", k);
   hipStream_t s = as_stream(stream);
-  const int L = A->plan.L;
+  // lanes per row of the tile products: the handle's lane-group shape, or
+  // (row-block or untuned handles) the group that matches the mean row length
+  const double mean_row = (double)A->nnz / (double)A->n;
+  const int L = (A->plan.L >= 4 && A->plan.L <= 32) ? A->plan.L
+                : mean_row > 24 ? 32 : mean_row > 12 ? 16 : mean_row > 6 ? 8 : 4;
   const int TR = kPB;
   // static tiles
   std::vector<int> tsys, trow, sys_end(kSys, 0), sys_begin(kSys, 0), tile0(kSys + 1, 0);

@@ -86,22 +86,24 @@ template <int L, class T> __device__ __forceinline__ T group_sum(T v) {
   return v;
 }
 
-// Block-wide sum of NV values per thread (blockDim.x == kBlock); the result
-// is valid in thread 0.  Order: butterfly within each wave, then waves 0..3.
-template <int NV, class T> __device__ __forceinline__ void block_sum(T (&v)[NV], T* lds /*[NV*4]*/) {
+// Block-wide sum of NV values per thread over a workgroup of NW waves
+// (blockDim.x == NW * 64); the result is valid in thread 0.  Order:
+// butterfly within each wave, then waves 0..NW-1.
+template <int NV, class T, int NW = kBlock / kWave>
+__device__ __forceinline__ void block_sum(T (&v)[NV], T* lds /*[NV*NW]*/) {
   const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
 #pragma unroll
   for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
   if (lane == 0) {
 #pragma unroll
-    for (int k = 0; k < NV; ++k) lds[k * (kBlock / kWave) + w] = v[k];
+    for (int k = 0; k < NV; ++k) lds[k * NW + w] = v[k];
   }
   __syncthreads();
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
-      T s = lds[k * (kBlock / kWave)];
-      for (int j = 1; j < kBlock / kWave; ++j) s += lds[k * (kBlock / kWave) + j];
+      T s = lds[k * NW];
+      for (int j = 1; j < NW; ++j) s += lds[k * NW + j];
       v[k] = s;
     }
   }

@@ -48,6 +48,7 @@ struct SpmvPlan {
   int U = 2;
   int grid = 0;     // workgroups per launch (0: one per tile)
   int tuned = 0;    // 1 if chosen by timing on the device
+  int nw = 0;       // row-block fused solver kernels: waves per workgroup (0: the fewest that fit)
 };
 
 }  // namespace hk
@@ -71,6 +72,9 @@ struct hk_csr_s {
   hk::SpmvPlan plan32;
   void* ws32 = nullptr;
   size_t ws32_bytes = 0;
+  // launch shapes of the solver's fused SpMV+dot kernels, tuned on the
+  // first solve of a tuned handle ([0] complex128, [1] complex64)
+  hk::SpmvPlan dot_plan[2];
   // pinned host words the solver reads its status through
   int* pinned = nullptr;
 };

@@ -63,8 +63,11 @@ struct SolveState {
 
 // Most workgroups of a fused SpMV+dot launch (one partial-sum slot each).
 // A launch shape with grid 0 gets one tile per workgroup up to this cap: on
-// the 1.8M-row system the row-block scheme has 7,094 tiles, and walking
-// them with 2,048 workgroups cost ~20 us per product (132 vs 112 us).
+// the 1.8M-row system, walking 7,094 tiles with 2,048 workgroups cost ~20 us
+// per product (132 vs 116 us).  Row-block shapes widen their workgroups (2,
+// 4 or 8 waves) until the tiles fit under the cap, because a finalize kernel
+// over 28,374 partials (32-row blocks in 2-wave workgroups) took 8.8-15.5 us
+// instead of 4.6-6.6.
 constexpr int kMaxGrid = 8192;
 constexpr int kEw = 4;           // elements per thread in the element-wise solver kernels
 
@@ -189,12 +192,10 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dot(int n, int ntiles, const in
   if (st->status != S_RUN) return;
   constexpr int RT = (kBlock / L) * U;
   const int g = threadIdx.x / L, lane = threadIdx.x & (L - 1);
-  int t0, t1;
-  tile_range(ntiles, t0, t1);
   double part[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) part[k] = 0;
-  for (int t = t0; t < t1; ++t) {
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int r0 = t * RT + g * U;
     // the epilogue operand of the row this lane will write, loaded early
     const int rw = r0 + (lane < U ? lane : 0);
@@ -220,10 +221,10 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dot(int n, int ntiles, const in
   store_block_partials<NV>(part, partials);
 }
 
-// Row-block variant of k_spmv_dot (one wave per 64 rows, CH entries per
-// lane per pass); the row's sum lands in the lane that owns the row.
-template <int CH, class R, int DOT>
-__global__ __launch_bounds__(kBlock) void k_spmv_dot_stream(int n, int ntiles, const int* __restrict__ rowptr,
+// Row-block variant of k_spmv_dot (one wave per RW rows); the row's sum
+// lands in the lane that owns the row.
+template <int RW, int NW, class R, int DOT>
+__global__ __launch_bounds__(NW * kWave) void k_spmv_dot_rb(int n, int ntiles, const int* __restrict__ rowptr,
                                                             const int* __restrict__ col,
                                                             const cplx<R>* __restrict__ val,
                                                             const cplx<R>* __restrict__ x,
@@ -232,20 +233,21 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dot_stream(int n, int ntiles, c
                                                             const SolveState* __restrict__ st, double* partials) {
   using V = cplx<R>;
   constexpr int NV = DOT == 1 ? 2 : 4;
-  __shared__ V lds[(kBlock / kWave) * CH * kWave];
+  constexpr int CH = RbCh<RW>::v;
+  __shared__ V lds[NW * CH * kWave];
   if (st->status != S_RUN) return;
   V* buf = lds + (threadIdx.x / kWave) * CH * kWave;
-  int t0, t1;
-  tile_range(ntiles, t0, t1);
+  const int l = threadIdx.x & (kWave - 1);
   double part[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) part[k] = 0;
-  for (int t = t0; t < t1; ++t) {
-    const int r0 = t * kBlock + (threadIdx.x / kWave) * kWave;
-    const int r = r0 + (threadIdx.x & (kWave - 1));
+  for (int tb = blockIdx.x; tb < ntiles; tb += gridDim.x) {
+    const int t = tile_of(tb, ntiles);
+    const int r0 = t * (NW * RW) + (threadIdx.x / kWave) * RW;
+    const int r = r0 + l;
     const V wr = w[r < n ? r : n - 1];
-    const V acc = csr_stream_rows<CH, V>(r0, n, rowptr, col, val, x, buf);
-    if (r < n) {
+    const V acc = csr_block_rows<RW, CH, V>(r0, n, rowptr, col, val, x, buf);
+    if (l < RW && r < n) {
       y[r] = acc;
       if (DOT == 1) {
         dotc_acc(wr, acc, part[0], part[1]);
@@ -257,7 +259,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dot_stream(int n, int ntiles, c
     }
   }
   __syncthreads();
-  block_sum<NV>(part, reinterpret_cast<double*>(lds));
+  block_sum<NV, double, NW>(part, reinterpret_cast<double*>(lds));
   store_block_partials<NV>(part, partials);
 }
 
@@ -361,11 +363,12 @@ __global__ __launch_bounds__(kBlock) void k_norm2_partials(int n, const cplx<R>*
 
 // ------------------------------------------------------------ finalize kernels
 
-enum : int { F_INIT = 0, F_SIGMA = 1, F_OMEGA = 3, F_XR = 4, F_TRUE = 5 };
+enum : int { F_INIT = 0, F_SIGMA = 1, F_OMEGA = 3, F_XR = 4, F_TRUE = 5, F_TUNE = 6 };
 
 template <int F> struct FinNV { static constexpr int v = 1; };
 template <> struct FinNV<F_INIT> { static constexpr int v = 2; };
 template <> struct FinNV<F_SIGMA> { static constexpr int v = 2; };
+template <> struct FinNV<F_TUNE> { static constexpr int v = 2; };
 template <> struct FinNV<F_OMEGA> { static constexpr int v = 4; };
 template <> struct FinNV<F_XR> { static constexpr int v = 3; };
 
@@ -395,7 +398,7 @@ __global__ __launch_bounds__(kFinBlock) void k_fin(SolveState* st, const double*
       return;
     }
   }
-  if (F != F_INIT && F != F_TRUE && status != S_RUN) return;
+  if (F != F_INIT && F != F_TRUE && F != F_TUNE && status != S_RUN) return;
   double tot[NV];
   final_sum<NV>(partials, nb, tot, lds);
   if (threadIdx.x != 0) return;
@@ -473,8 +476,10 @@ __global__ __launch_bounds__(kFinBlock) void k_fin(SolveState* st, const double*
       st->beta = cmul(cdiv(rho, st->rho_old), cdiv(alpha, omega));
       st->iter = it + 1;
     }
-  } else {  // F_TRUE
+  } else if (F == F_TRUE) {
     st->rr_true = tot[0];
+  } else {  // F_TUNE: the summation of F_SIGMA without its scalar updates
+    st->rr_true = tot[0] + tot[1];
   }
 }
 
@@ -549,11 +554,40 @@ static int ensure_ws(void** ws, size_t* have, size_t need, hipStream_t s) {
   return HK_OK;
 }
 
+// Tiles of the fused SpMV+dot launches for launch shape p, and for
+// row-block shapes the waves per workgroup: p.nw when set, else the fewest
+// of 2, 4, 8 that keep the tiles within kMaxGrid.
+static int dot_tiles(const hk_csr_s* A, const SpmvPlan& p, int* nw_out) {
+  int nw = 0;
+  int64_t tiles = spmv_tiles(A, p.L, p.U);
+  if (p.L == kRowBlockL) {
+    if (p.nw == 2 || p.nw == 4 || p.nw == 8) {
+      nw = p.nw;
+    } else {
+      for (nw = 2; nw < 8; nw *= 2)
+        if ((A->n + (int64_t)nw * p.U - 1) / ((int64_t)nw * p.U) <= kMaxGrid) break;
+    }
+    tiles = (A->n + (int64_t)nw * p.U - 1) / ((int64_t)nw * p.U);
+  }
+  if (nw_out) *nw_out = nw;
+  return (int)tiles;
+}
+
+// workgroups of a fused launch for shape p
+static int dot_grid(const hk_csr_s* A, const SpmvPlan& p) {
+  const int ntiles = dot_tiles(A, p, nullptr);
+  const int g = p.grid > 0 ? p.grid : kMaxGrid;
+  return std::max(1, std::min(g, std::min(ntiles, kMaxGrid)));
+}
+
 template <class R>
-static hipError_t launch_spmv_dot(const hk_csr_s* A, int L, int U, int grid, int dot, const cplx<R>* val,
+static hipError_t launch_spmv_dot(const hk_csr_s* A, const SpmvPlan& p, int dot, const cplx<R>* val,
                                   const cplx<R>* x, cplx<R>* y, const cplx<R>* w, const Work<R>& wk,
                                   hipStream_t s) {
-  const int ntiles = spmv_tiles(A, L, U);
+  int nw = 0;
+  const int ntiles = dot_tiles(A, p, &nw);
+  const int grid = dot_grid(A, p);
+  const int L = p.L, U = p.U;
   const int n = (int)A->n;
 #define HK_SD_CASE(LL, UU)                                                                          \
   if (L == LL && U == UU) {                                                                         \
@@ -570,18 +604,20 @@ static hipError_t launch_spmv_dot(const hk_csr_s* A, int L, int U, int grid, int
   HK_SD_CASE(16, 1) HK_SD_CASE(16, 2) HK_SD_CASE(16, 4) HK_SD_CASE(16, 8)
   HK_SD_CASE(32, 1) HK_SD_CASE(32, 2) HK_SD_CASE(32, 4) HK_SD_CASE(32, 8)
 #undef HK_SD_CASE
-#define HK_SDS_CASE(CH)                                                                             \
-  if (L == kStreamL && U == CH) {                                                                   \
-    if (dot == 1)                                                                                   \
-      hipLaunchKernelGGL((k_spmv_dot_stream<CH, R, 1>), dim3(grid), dim3(kBlock), 0, s, n, ntiles,  \
-                         A->rowptr, A->col, val, x, y, w, wk.st, wk.partials);                      \
-    else                                                                                            \
-      hipLaunchKernelGGL((k_spmv_dot_stream<CH, R, 2>), dim3(grid), dim3(kBlock), 0, s, n, ntiles,  \
-                         A->rowptr, A->col, val, x, y, w, wk.st, wk.partials);                      \
-    return hipGetLastError();                                                                       \
+#define HK_SDRB_CASE(RR, NWW)                                                                          \
+  if (L == kRowBlockL && U == RR && nw == NWW) {                                                       \
+    if (dot == 1)                                                                                      \
+      hipLaunchKernelGGL((k_spmv_dot_rb<RR, NWW, R, 1>), dim3(grid), dim3(NWW * kWave), 0, s, n, ntiles, \
+                         A->rowptr, A->col, val, x, y, w, wk.st, wk.partials);                         \
+    else                                                                                               \
+      hipLaunchKernelGGL((k_spmv_dot_rb<RR, NWW, R, 2>), dim3(grid), dim3(NWW * kWave), 0, s, n, ntiles, \
+                         A->rowptr, A->col, val, x, y, w, wk.st, wk.partials);                         \
+    return hipGetLastError();                                                                          \
   }
-  HK_SDS_CASE(8) HK_SDS_CASE(16)
-#undef HK_SDS_CASE
+  HK_SDRB_CASE(16, 2) HK_SDRB_CASE(32, 2) HK_SDRB_CASE(64, 2)
+  HK_SDRB_CASE(16, 4) HK_SDRB_CASE(32, 4) HK_SDRB_CASE(64, 4)
+  HK_SDRB_CASE(16, 8) HK_SDRB_CASE(32, 8) HK_SDRB_CASE(64, 8)
+#undef HK_SDRB_CASE
   return hipErrorInvalidValue;
 }
 
@@ -591,19 +627,75 @@ static hipError_t launch_fin(const Work<R>& wk, int nb, double tol, long long ma
   return hipGetLastError();
 }
 
+// Times the fused SpMV+dot kernel (with its finalize) in every launch shape
+// on A's pattern and keeps the fastest in *out (HIP events on stream s).
+// Row-block shapes are tried with 2, 4 and 8 waves per workgroup where the
+// tiles fit under kMaxGrid.  The workspace vectors serve as operands (their
+// values do not matter for timing); the scalar state is set to running here,
+// left so by the F_TUNE finalize, and re-initialised by the solve afterwards.
+template <class R>
+static int tune_dot(const hk_csr_s* A, const Work<R>& wk, SpmvPlan* out, hipStream_t s) {
+  std::vector<SpmvPlan> cands;
+  for (int L : {4, 8, 16, 32})
+    for (int U : {1, 2, 4, 8})
+      if (U <= L) { SpmvPlan p; p.L = L; p.U = U; cands.push_back(p); }
+  for (int U : {16, 32, 64})
+    for (int nw : {2, 4, 8}) {
+      SpmvPlan p; p.L = kRowBlockL; p.U = U; p.nw = nw;
+      if ((A->n + (int64_t)nw * U - 1) / ((int64_t)nw * U) <= kMaxGrid || nw == 8) cands.push_back(p);
+    }
+  SolveState run{};
+  run.status = S_RUN;
+  HK_HIP(hipMemcpyAsync(wk.st, &run, sizeof(run), hipMemcpyHostToDevice, s));
+  hipEvent_t e0, e1;
+  HK_HIP(hipEventCreate(&e0));
+  HK_HIP(hipEventCreate(&e1));
+  SpmvPlan best = cands[0];
+  float best_ms = 1e30f;
+  int rc = HK_OK;
+  for (const SpmvPlan& p : cands) {
+    const int g = dot_grid(A, p);
+    hipError_t err = hipSuccess;
+    const int reps = 5;
+    for (int it = 0; it < reps + 1 && err == hipSuccess; ++it) {
+      if (it == 1) err = hipEventRecord(e0, s);
+      if (err == hipSuccess) err = launch_spmv_dot<R>(A, p, 1, wk.ahat, wk.p, wk.v, wk.rh, wk, s);
+      if (err == hipSuccess) err = launch_fin<R, F_TUNE>(wk, g, 0, 0, s);
+    }
+    if (err == hipSuccess) err = hipEventRecord(e1, s);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    float ms = 0;
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+    if (err != hipSuccess) {
+      set_error_text("solver tuning: %s", hipGetErrorString(err));
+      rc = HK_EHIP;
+      break;
+    }
+    if (ms < best_ms) { best_ms = ms; best = p; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != HK_OK) return rc;
+  if (best.L == kRowBlockL) {
+    int nw = 0;
+    (void)dot_tiles(A, best, &nw);
+    best.nw = nw;
+  }
+  best.tuned = 1;
+  *out = best;
+  return HK_OK;
+}
+
 // Runs the whole solve for precision R on values `val` (A's pattern), right
 // side b, solution x (input when use_x0).  Fills info (host), synchronises.
 template <class R>
-static int bicgstab(const hk_csr_s* A, const cplx<R>* val, const cplx<R>* b, cplx<R>* x,
+static int bicgstab(hk_csr_s* A, const cplx<R>* val, const cplx<R>* b, cplx<R>* x,
                     const hk_solve_opts& o, void* wsbase, hk_solve_info* info, hipStream_t s) {
   using V = cplx<R>;
   const int n = (int)A->n;
   const Work<R> wk = carve<R>(wsbase, A->n, A->nnz);
   const dim3 ew((unsigned)((n + kBlock - 1) / kBlock));
   const int gv = ew_blocks(n);
-  const int ntiles = spmv_tiles(A, A->plan.L, A->plan.U);
-  int gs = A->plan.grid > 0 ? A->plan.grid : kMaxGrid;
-  gs = std::max(1, std::min(gs, std::min(ntiles, kMaxGrid)));
 
   // set-up: D^-1, Ahat = A D^-1, initial residual
   HK_HIP(hipMemsetAsync(wk.flag, 0, sizeof(int), s));
@@ -619,6 +711,17 @@ static int bicgstab(const hk_csr_s* A, const cplx<R>* val, const cplx<R>* b, cpl
     int rc = spmv_dispatch(&tmp, x, wk.r, b, nullptr, nullptr, 1, s);
     if (rc != HK_OK) return rc;
   }
+  SpmvPlan dp = A->plan;
+  dp.nw = 0;
+  if (A->plan.tuned) {
+    SpmvPlan& cached = A->dot_plan[sizeof(R) == 4 ? 1 : 0];
+    if (!cached.tuned) {
+      int rc = tune_dot<R>(A, wk, &cached, s);
+      if (rc != HK_OK) return rc;
+    }
+    dp = cached;
+  }
+  const int gs = dot_grid(A, dp);
   SolveState init{};
   init.history = o.d_history;
   init.status = S_RUN;
@@ -647,14 +750,14 @@ static int bicgstab(const hk_csr_s* A, const cplx<R>* val, const cplx<R>* b, cpl
       hipLaunchKernelGGL(k_p<R>, ew, dim3(kBlock), 0, s, n, wk.st, wk.r, wk.p, wk.v);
       hipError_t e = hipGetLastError();
       if (e == hipSuccess)
-        e = launch_spmv_dot<R>(A, A->plan.L, A->plan.U, gs, 1, wk.ahat, wk.p, wk.v, wk.rh, wk, s);
+        e = launch_spmv_dot<R>(A, dp, 1, wk.ahat, wk.p, wk.v, wk.rh, wk, s);
       if (e == hipSuccess) e = launch_fin<R, F_SIGMA>(wk, gs, 0, 0, s);
       if (e == hipSuccess) {
         hipLaunchKernelGGL(k_s<R>, dim3(gv), dim3(kBlock), 0, s, n, wk.st, wk.r, wk.v, wk.s);
         e = hipGetLastError();
       }
       if (e == hipSuccess)
-        e = launch_spmv_dot<R>(A, A->plan.L, A->plan.U, gs, 2, wk.ahat, wk.s, wk.t, wk.s, wk, s);
+        e = launch_spmv_dot<R>(A, dp, 2, wk.ahat, wk.s, wk.t, wk.s, wk, s);
       if (e == hipSuccess) e = launch_fin<R, F_OMEGA>(wk, gs, 0, 0, s);
       if (e == hipSuccess) {
         hipLaunchKernelGGL(k_xr<R>, dim3(gv), dim3(kBlock), 0, s, n, wk.st, wk.rh, wk.r, wk.p, wk.s,
@@ -830,6 +933,7 @@ extern "C" int hk_krylov_solve_mixed(hk_csr A, const void* d_b, void* d_x, doubl
     HK_CHECK_LAUNCH();
     hk_solve_info ii{};
     rc = bicgstab<float>(&A32, (const float2*)A->val32, r32, d32, io, A->ws32, &ii, s);
+    A->dot_plan[1] = A32.dot_plan[1];  // the inner solve's tuned fused shape
     if (rc != HK_OK) return rc;
     if (trace)
       fprintf(stderr, "[hk mixed] cycle %d: ||r||/||b|| = %.3e, inner status %d (breakdown %d) after %lld iterations, inner relres %.3e\n",

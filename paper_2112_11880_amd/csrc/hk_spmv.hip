@@ -21,9 +21,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int n, int ntiles, const int* _
                                                  V alpha, V beta, int beta_zero) {
   constexpr int RT = (kBlock / L) * U;
   const int g = threadIdx.x / L, lane = threadIdx.x & (L - 1);
-  int t0, t1;
-  tile_range(ntiles, t0, t1);
-  for (int t = t0; t < t1; ++t) {
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int r0 = t * RT + g * U;
     V acc[U];
     csr_rows<L, U, V>(r0, n, rowptr, col, val, x, acc);
@@ -44,22 +42,23 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int n, int ntiles, const int* _
   }
 }
 
-// Row-block variant: a tile is 256 rows, 64 per wave.
-template <int CH, class V, int MODE>
-__global__ __launch_bounds__(kBlock) void k_spmv_stream(int n, int ntiles, const int* __restrict__ rowptr,
+// Row-block variant: R rows per wave, a tile is kRbWaves * R rows.
+template <int R, class V, int MODE>
+__global__ __launch_bounds__(kRbThreads) void k_spmv_rb(int n, int ntiles, const int* __restrict__ rowptr,
                                                         const int* __restrict__ col,
                                                         const V* __restrict__ val, const V* __restrict__ x,
                                                         V* __restrict__ y, const V* __restrict__ b,
                                                         V alpha, V beta, int beta_zero) {
-  __shared__ V lds[(kBlock / kWave) * CH * kWave];
+  constexpr int CH = RbCh<R>::v;
+  __shared__ V lds[kRbWaves * CH * kWave];
   V* buf = lds + (threadIdx.x / kWave) * CH * kWave;
-  int t0, t1;
-  tile_range(ntiles, t0, t1);
-  for (int t = t0; t < t1; ++t) {
-    const int r0 = t * kBlock + (threadIdx.x / kWave) * kWave;
-    const V acc = csr_stream_rows<CH, V>(r0, n, rowptr, col, val, x, buf);
-    const int r = r0 + (threadIdx.x & (kWave - 1));
-    if (r < n) {
+  const int l = threadIdx.x & (kWave - 1);
+  for (int tb = blockIdx.x; tb < ntiles; tb += gridDim.x) {
+    const int t = tile_of(tb, ntiles);
+    const int r0 = t * (kRbWaves * R) + (threadIdx.x / kWave) * R;
+    const V acc = csr_block_rows<R, CH, V>(r0, n, rowptr, col, val, x, buf);
+    const int r = r0 + l;
+    if (l < R && r < n) {
       V out;
       if (MODE == 1) {
         out = csub(b[r], acc);
@@ -98,9 +97,9 @@ __global__ void k_csr_check(int n, int nnz, const int* __restrict__ rowptr,
 // ------------------------------------------------------------- dispatch
 
 // Row u of a lane group is written by lane u of the group, so U <= L.
-// L == 64 selects the row-block scheme, U = entries per lane per pass.
+// L == 64 selects the row-block scheme, U = rows per wave.
 static bool valid_shape(int L, int U) {
-  if (L == kStreamL) return U == 8 || U == 16;
+  if (L == kRowBlockL) return U == 16 || U == 32 || U == 64;
   return (L == 4 || L == 8 || L == 16 || L == 32) && (U == 1 || U == 2 || U == 4 || U == 8) && U <= L;
 }
 
@@ -124,19 +123,19 @@ static hipError_t launch_spmv_t(const hk_csr_s* A, const SpmvPlan& p, const V* x
   HK_SPMV_CASE(16, 1) HK_SPMV_CASE(16, 2) HK_SPMV_CASE(16, 4) HK_SPMV_CASE(16, 8)
   HK_SPMV_CASE(32, 1) HK_SPMV_CASE(32, 2) HK_SPMV_CASE(32, 4) HK_SPMV_CASE(32, 8)
 #undef HK_SPMV_CASE
-#define HK_STREAM_CASE(CH)                                                                     \
-  if (p.L == kStreamL && p.U == CH) {                                                          \
-    hipLaunchKernelGGL((k_spmv_stream<CH, V, MODE>), dim3(grid), dim3(kBlock), 0, s, n, ntiles, \
-                       A->rowptr, A->col, val, x, y, b, alpha, beta, beta_zero);               \
-    return hipGetLastError();                                                                  \
+#define HK_RB_CASE(RR)                                                                          \
+  if (p.L == kRowBlockL && p.U == RR) {                                                         \
+    hipLaunchKernelGGL((k_spmv_rb<RR, V, MODE>), dim3(grid), dim3(kRbThreads), 0, s, n, ntiles,  \
+                       A->rowptr, A->col, val, x, y, b, alpha, beta, beta_zero);                \
+    return hipGetLastError();                                                                   \
   }
-  HK_STREAM_CASE(8) HK_STREAM_CASE(16)
-#undef HK_STREAM_CASE
+  HK_RB_CASE(16) HK_RB_CASE(32) HK_RB_CASE(64)
+#undef HK_RB_CASE
   return hipErrorInvalidValue;
 }
 
 int spmv_tiles(const hk_csr_s* A, int L, int U) {
-  const long long rt = L == kStreamL ? kBlock : (long long)(kBlock / L) * U;
+  const long long rt = L == kRowBlockL ? (long long)kRbWaves * U : (long long)(kBlock / L) * U;
   return (int)((A->n + rt - 1) / rt);
 }
 
@@ -178,12 +177,12 @@ int spmv_autotune(hk_csr_s* A, hipStream_t s) {
   HK_HIP(hipEventCreate(&e1));
   SpmvPlan best = heuristic_plan(A);
   float best_ms = 1e30f;
-  const int Ls[] = {4, 8, 16, 32, kStreamL};
-  const int Us[] = {1, 2, 4, 8, 16};
+  const int Ls[] = {4, 8, 16, 32, kRowBlockL};
+  const int Us[] = {1, 2, 4, 8, 16, 32, 64};
   const int grids[] = {0, 2048};
   int rc = HK_OK;
   for (int L : Ls) {
-    if (L > 2 * A->max_row + 4 && L != 4 && L != kStreamL) continue;
+    if (L > 2 * A->max_row + 4 && L != 4 && L != kRowBlockL) continue;
     for (int U : Us) {
       if (!valid_shape(L, U)) continue;
       for (int gsel : grids) {

@@ -11,7 +11,9 @@
 // in flight per wave.  Matrix streams use non-temporal loads so they do not
 // evict the x window from L2.  A workgroup of 256 threads covers
 // (256/L)*U consecutive rows ("tile"); a launch of G workgroups walks the
-// tiles in contiguous ranges, one range per workgroup, in launch order.
+// tiles with a grid stride, in launch order.
+// The row-block scheme (csr_block_rows) instead gives a whole wave a block
+// of 16-64 rows and streams the block's entries with all lanes.
 #pragma once
 
 #include "hk_common.hpp"
@@ -85,21 +87,27 @@ __device__ __forceinline__ void csr_rows(int r0, int n, const int* __restrict__ 
   }
 }
 
-// Row-block ("stream") CSR: one wave per 64 consecutive rows r0 .. r0+63.
-// The wave streams the rows' entries with all 64 lanes -- entry e of the
-// block goes to lane e % 64, CH entries per lane per pass, every column and
-// value load issued before any gather -- parks the products in its LDS slice
-// buf[CH*64], then each lane sums the products of its own row in entry
-// order.  Rows of any length are handled by passes over the block's entry
-// range (the pass count is uniform across the wave).  Returns the sum of
-// row r0 + lane (zero for rows >= n).  All 64 lanes must call it.
-template <int CH, class V>
-__device__ __forceinline__ V csr_stream_rows(int r0, int n, const int* __restrict__ rowptr,
-                                             const int* __restrict__ col, const V* __restrict__ val,
-                                             const V* __restrict__ x, V* buf) {
+// Row-block CSR: one wave per R consecutive rows r0 .. r0+R-1 (R in
+// {16, 32, 64}).  The wave streams the rows' entries with all 64 lanes --
+// entry e of the block goes to lane e % 64, CH entries per lane per pass,
+// every column and value load issued before any gather -- parks the
+// products in its LDS slice buf[CH*64], then lane l < R sums the products
+// of row r0 + l in entry order.  Rows of any length are handled by passes
+// over the block's entry range (the pass count is uniform across the wave).
+// Returns the sum of row r0 + lane for lanes < R with r0 + lane < n, zero
+// otherwise.  All 64 lanes must call it.
+template <int R, int CH, class V>
+__device__ __forceinline__ V csr_block_rows(int r0, int n, const int* __restrict__ rowptr,
+                                            const int* __restrict__ col, const V* __restrict__ val,
+                                            const V* __restrict__ x, V* buf) {
+  static_assert(R == 16 || R == 32 || R == 64, "rows per wave");
   const int l = threadIdx.x & (kWave - 1);
-  const int rs = rowptr[r0 + l < n ? r0 + l : n];
-  const int rend = rowptr[r0 + kWave < n ? r0 + kWave : n];
+  // lane l <= R holds rowptr[r0 + l] (clamped to n): lane R the block's end
+  const int li = l < R ? l : R;
+  const int rs = rowptr[r0 + li < n ? r0 + li : n];
+  int rend;
+  if constexpr (R == kWave) rend = rowptr[r0 + kWave < n ? r0 + kWave : n];
+  else rend = __shfl(rs, R, kWave);
   const int nxt = __shfl(rs, (l + 1) & (kWave - 1), kWave);
   const int re = l < kWave - 1 ? nxt : rend;
   const int s0 = __shfl(rs, 0, kWave);
@@ -127,28 +135,51 @@ __device__ __forceinline__ V csr_stream_rows(int r0, int n, const int* __restric
     // compiler from moving the reads above the writes (and the next pass's
     // writes above these reads)
     __builtin_amdgcn_wave_barrier();
-    const int lo = rs > c0 ? rs : c0, hi = re < cend ? re : cend;
-    for (int e = lo; e < hi; ++e) acc = cadd(acc, buf[e - c0]);
+    if (l < R) {
+      const int lo = rs > c0 ? rs : c0, hi = re < cend ? re : cend;
+      for (int e = lo; e < hi; ++e) acc = cadd(acc, buf[e - c0]);
+    }
     __builtin_amdgcn_wave_barrier();
   }
   return acc;
 }
 
-constexpr int kStreamL = 64;   // plan code for the row-block scheme
-
-// Tile range [t0, t1) of the calling workgroup for a launch of gridDim.x
-// workgroups over ntiles tiles (contiguous per workgroup, in launch order).
-// Workgroups are dealt to the 8 XCDs round-robin, so consecutive tiles run
-// on different XCDs and the whole chip advances through the matrix as one
-// front.  Giving each XCD its own contiguous range instead (eight fronts, x
-// windows private to each L2) measured ~10% slower on the 1.8M-row system
-// (row-block scheme: 107.7 vs 118.0 us with 8 entries per lane, 112.9 vs
-// 119.7 us with 16).
-__device__ __forceinline__ void tile_range(int ntiles, int& t0, int& t1) {
-  const int nb = gridDim.x;
-  t0 = (int)(((long long)blockIdx.x * ntiles) / nb);
-  t1 = (int)(((long long)(blockIdx.x + 1) * ntiles) / nb);
+// Row-block launch shapes: plan L = kRowBlockL selects the scheme and plan U
+// the rows per wave.  Workgroups are kRbWaves waves (128 threads); entries
+// per lane per pass: 8 (4 for 16-row blocks), so a block of 15-entry rows
+// takes one pass at R <= 32.  On the 1.8M-row system, 32 rows per wave in
+// two-wave workgroups measured 106 us per product, against 109-110 us for
+// four or eight waves and 110.6 us for 64 rows per wave with 4 waves.
+// Row-block tile of virtual block b: within every run of 8*kTileChunk
+// consecutive tiles, XCD x (virtual blocks b with b % 8 == x) takes the x-th
+// chunk of kTileChunk tiles, so neighbouring tiles -- which gather the same
+// x entries -- share an L2 while the chip still advances as one front.  A
+// trailing partial run keeps the identity order.  Chunks of 8 measured
+// ~2 us faster per product than chunks of 1, 32 or 128 on the 1.8M-row
+// system.
+constexpr int kTileChunk = 8;
+__device__ __forceinline__ int tile_of(int b, int ntiles) {
+  constexpr int S = kXcds * kTileChunk;
+  const int q = b / S;
+  if ((q + 1) * S > ntiles) return b;
+  const int r = b - q * S;
+  return q * S + (r % kXcds) * kTileChunk + r / kXcds;
 }
+
+constexpr int kRowBlockL = 64;
+constexpr int kRbWaves = 2;
+constexpr int kRbThreads = kRbWaves * kWave;
+template <int R> struct RbCh { static constexpr int v = R == 16 ? 4 : 8; };
+
+// Tiles are dealt to workgroups in launch order with a grid stride: the
+// calling workgroup takes tiles blockIdx.x, blockIdx.x + gridDim.x, ...
+// Workgroups are placed on the 8 XCDs round-robin, so the resident
+// workgroups always cover a narrow run of consecutive tiles and the whole
+// chip advances through the matrix as one front.  Two alternatives measured
+// slower on the 1.8M-row system: each XCD taking its own contiguous range
+// (eight fronts, x windows private to each L2: 118-120 us against 108-113
+// us per product) and each workgroup taking a contiguous range of tiles
+// (a wide front: 132 against 116 us for the fused product).
 
 // Shape of one SpMV variant.
 struct SpmvShape {

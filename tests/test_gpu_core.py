@@ -72,7 +72,7 @@ def small_mesh_problem(nc=(7, 5, 6), seed=3):
 # ------------------------------------------------------------------ SpMV
 
 SHAPES = ([(L, U, g) for L in (4, 8, 16, 32) for U in (1, 2, 4, 8) for g in (0, 3, 64) if U <= L]
-          + [(64, ch, g) for ch in (8, 16) for g in (0, 3, 64)])
+          + [(64, rw, g) for rw in (16, 32, 64) for g in (0, 3, 64)])
 
 
 def test_spmv_all_shapes_ragged(hk, oracle):
@@ -89,8 +89,9 @@ def test_spmv_all_shapes_ragged(hk, oracle):
         # NaN-filled output: a row the kernel fails to write cannot pass
         y = host(A.spmv(xd, torch.full_like(xd, complex("nan+nanj")), beta=0.0))
         assert np.all(np.abs(y - ref) <= bound), (L, U, g)
-    with pytest.raises(hk.HKError):
-        A.set_plan(4, 8, 0)
+    for bad in ((4, 8, 0), (64, 8, 0), (64, 128, 0), (2, 1, 0)):
+        with pytest.raises(hk.HKError):
+            A.set_plan(*bad)
 
 
 def test_spmv_alpha_beta_and_residual(hk, oracle):
@@ -138,7 +139,7 @@ def test_spmv_edge_structures(hk, oracle):
         ref = oracle.spmv(rowptr, col, val, x)
         bound = 1e-12 * spmv_bound(rowptr, col, val, x)
         A = make_csr(hk, rowptr, col, val)
-        for L, U, g in SHAPES[::5] + SHAPES[-6:]:
+        for L, U, g in SHAPES[::5] + SHAPES[-9:]:
             say("spmv edge", name, L, U, g)
             A.set_plan(L, U, g)
             xd = dev(x)
@@ -416,3 +417,23 @@ def test_solve_config2(hk, oracle):
     assert info["status"] == hk.HK_OK, info
     r = oracle.residual(c["rowptr"], c["col"], c["val"], c["g"], host(x))
     assert np.linalg.norm(r) / np.linalg.norm(c["g"]) <= 1.05e-8
+
+
+def test_solve_config2_wide_workgroup_shapes(hk, oracle):
+    """The fused products of the 1.8M-row solve in row-block shapes whose
+    workgroups widen to stay under the workgroup cap (64-row blocks: 4 waves;
+    16-row blocks: 8 waves and a grid-stride walk); 6 iterations each give
+    the same iterate as the oracle to rounding.  (On this indefinite system
+    iterates from different summation orders separate quickly: numpy vs the
+    oracle differ by 6e-14 after 6 iterations, 8e-13 after 8, 2e-9 after 10
+    and 0.44 after 20.)"""
+    c = configs.config2()
+    A = make_csr(hk, c["rowptr"], c["col"], c["val"])
+    g = dev(c["g"])
+    xo, _ = oracle.bicgstab(c["rowptr"], c["col"], c["val"], c["g"], tol=1e-14, maxit=6)
+    for plan in ((64, 32, 0), (64, 64, 0), (64, 16, 0), (16, 1, 0)):
+        say("config2 6 iterations, plan", plan)
+        A.set_plan(*plan)
+        x, info = hk.krylov_solve(A, g, tol=1e-14, max_iter=6)
+        assert info["iters"] == 6 and info["status"] == hk.HK_NOT_CONVERGED, info
+        assert np.linalg.norm(host(x) - xo) <= 1e-10 * np.linalg.norm(xo), plan
