@@ -233,7 +233,7 @@ __global__ __launch_bounds__(NW * kWave) void k_spmv_dot_rb(int n, int ntiles, c
                                                             const SolveState* __restrict__ st, double* partials) {
   using V = cplx<R>;
   constexpr int NV = DOT == 1 ? 2 : 4;
-  constexpr int CH = RbCh<RW>::v;
+  constexpr int CH = RbCh<RW, V>::v;
   __shared__ V lds[NW * CH * kWave];
   if (st->status != S_RUN) return;
   V* buf = lds + (threadIdx.x / kWave) * CH * kWave;
@@ -630,20 +630,23 @@ static hipError_t launch_fin(const Work<R>& wk, int nb, double tol, long long ma
 // Times the fused SpMV+dot kernel (with its finalize) in every launch shape
 // on A's pattern and keeps the fastest in *out (HIP events on stream s).
 // Row-block shapes are tried with 2, 4 and 8 waves per workgroup where the
-// tiles fit under kMaxGrid.  The workspace vectors serve as operands (their
+// tiles fit under kMaxGrid; every shape with one workgroup per tile and with
+// 2,048 workgroups walking the tiles (fewer partials for the finalize).  The workspace vectors serve as operands (their
 // values do not matter for timing); the scalar state is set to running here,
 // left so by the F_TUNE finalize, and re-initialised by the solve afterwards.
 template <class R>
 static int tune_dot(const hk_csr_s* A, const Work<R>& wk, SpmvPlan* out, hipStream_t s) {
   std::vector<SpmvPlan> cands;
-  for (int L : {4, 8, 16, 32})
-    for (int U : {1, 2, 4, 8})
-      if (U <= L) { SpmvPlan p; p.L = L; p.U = U; cands.push_back(p); }
-  for (int U : {16, 32, 64})
-    for (int nw : {2, 4, 8}) {
-      SpmvPlan p; p.L = kRowBlockL; p.U = U; p.nw = nw;
-      if ((A->n + (int64_t)nw * U - 1) / ((int64_t)nw * U) <= kMaxGrid || nw == 8) cands.push_back(p);
-    }
+  for (int grid : {0, 2048}) {
+    for (int L : {4, 8, 16, 32})
+      for (int U : {1, 2, 4, 8})
+        if (U <= L) { SpmvPlan p; p.L = L; p.U = U; p.grid = grid; cands.push_back(p); }
+    for (int U : {16, 32, 64})
+      for (int nw : {2, 4, 8}) {
+        SpmvPlan p; p.L = kRowBlockL; p.U = U; p.nw = nw; p.grid = grid;
+        if ((A->n + (int64_t)nw * U - 1) / ((int64_t)nw * U) <= kMaxGrid || nw == 8) cands.push_back(p);
+      }
+  }
   SolveState run{};
   run.status = S_RUN;
   HK_HIP(hipMemcpyAsync(wk.st, &run, sizeof(run), hipMemcpyHostToDevice, s));

@@ -49,7 +49,7 @@ __global__ __launch_bounds__(kRbThreads) void k_spmv_rb(int n, int ntiles, const
                                                         const V* __restrict__ val, const V* __restrict__ x,
                                                         V* __restrict__ y, const V* __restrict__ b,
                                                         V alpha, V beta, int beta_zero) {
-  constexpr int CH = RbCh<R>::v;
+  constexpr int CH = RbCh<R, V>::v;
   __shared__ V lds[kRbWaves * CH * kWave];
   V* buf = lds + (threadIdx.x / kWave) * CH * kWave;
   const int l = threadIdx.x & (kWave - 1);

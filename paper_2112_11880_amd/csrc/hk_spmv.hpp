@@ -144,12 +144,6 @@ __device__ __forceinline__ V csr_block_rows(int r0, int n, const int* __restrict
   return acc;
 }
 
-// Row-block launch shapes: plan L = kRowBlockL selects the scheme and plan U
-// the rows per wave.  Workgroups are kRbWaves waves (128 threads); entries
-// per lane per pass: 8 (4 for 16-row blocks), so a block of 15-entry rows
-// takes one pass at R <= 32.  On the 1.8M-row system, 32 rows per wave in
-// two-wave workgroups measured 106 us per product, against 109-110 us for
-// four or eight waves and 110.6 us for 64 rows per wave with 4 waves.
 // Row-block tile of virtual block b: within every run of 8*kTileChunk
 // consecutive tiles, XCD x (virtual blocks b with b % 8 == x) takes the x-th
 // chunk of kTileChunk tiles, so neighbouring tiles -- which gather the same
@@ -166,10 +160,21 @@ __device__ __forceinline__ int tile_of(int b, int ntiles) {
   return q * S + (r % kXcds) * kTileChunk + r / kXcds;
 }
 
+// Row-block launch shapes: plan L = kRowBlockL selects the scheme and plan U
+// the rows per wave.  Workgroups are kRbWaves waves (128 threads).  Entries
+// per lane per pass fill 8 KB of LDS per wave: 8 complex128 or 16 complex64
+// products per lane (half that for 16-row blocks), so each wave keeps the
+// same bytes in flight in both precisions.  On the 1.8M-row system, 32 rows
+// per wave in two-wave workgroups measured 106 us per complex128 product,
+// against 109-110 us for four or eight waves and 110.6 us for 64 rows per
+// wave with 4 waves; 16 complex128 entries per lane (16 KB of LDS per wave)
+// measured 113 against 108 us at 64 rows per wave.
 constexpr int kRowBlockL = 64;
 constexpr int kRbWaves = 2;
 constexpr int kRbThreads = kRbWaves * kWave;
-template <int R> struct RbCh { static constexpr int v = R == 16 ? 4 : 8; };
+template <int R, class V> struct RbCh {
+  static constexpr int v = (8192 / (kWave * (int)sizeof(V))) / (R == 16 ? 2 : 1);
+};
 
 // Tiles are dealt to workgroups in launch order with a grid stride: the
 // calling workgroup takes tiles blockIdx.x, blockIdx.x + gridDim.x, ...
