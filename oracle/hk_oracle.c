@@ -255,6 +255,118 @@ done:
     return status;
 }
 
+/*
+ * Right-preconditioned transpose-free QMR (Freund's method, as given in
+ * Saad's book which the paper cites for P-TFQMR), preconditioner M = diag(A)
+ * when precond != 0, identity otherwise.  The recurrences run on
+ * Ahat = A M^-1; the iterate is kept in x directly (x += eta M^-1 d).
+ *
+ * Start: w = y_1 = r_0 = b - A x_0, rhat = r_0, u_1 = Ahat y_1, v = u_1,
+ * d = 0, theta = eta = 0, tau = ||r_0||, rho = rhat^H r_0.  Iteration k:
+ *   alpha = rho / (rhat^H v),  y_2 = y_1 - alpha v,  u_2 = Ahat y_2
+ *   half-steps j = 1, 2 (overall half-step m = 2k - 2 + j):
+ *     w = w - alpha u_j
+ *     d = y_j + (theta^2 eta / alpha) d
+ *     theta = ||w|| / tau,  c = (1 + theta^2)^(-1/2)
+ *     tau = tau theta c,  eta = c^2 alpha
+ *     x += eta M^-1 d
+ *   rho' = rhat^H w,  beta = rho' / rho,  rho = rho'
+ *   y_1 = w + beta y_2,  u_1 = Ahat y_1,  v = u_1 + beta (u_2 + beta v)
+ * Two products with Ahat per iteration.  The solve stops as soon as the
+ * quasi-residual bound sqrt(m+1) tau <= tol ||b|| (an exit after the first
+ * half-step counts the iteration).  A breakdown is declared when rhat^H v
+ * (OR_BD_SIGMA, before the iteration counts) or rhat^H w (OR_BD_RHO, after
+ * it) is exactly zero; a non-finite scalar ends the solve with OR_NONFINITE.
+ * relres_rec is the last bound divided by ||b||; history (optional, maxit+1
+ * entries) receives it at the end of every iteration.
+ */
+int orc_tfqmr(int64_t n, const int32_t *rowptr, const int32_t *col, const zd *val,
+              const zd *b, zd *x, double tol, int64_t maxit, int precond,
+              or_info *info, double *history)
+{
+    memset(info, 0, sizeof(*info));
+    for (int64_t i = 0; i < n; ++i)
+        if (!isfinite_z(b[i]) || !isfinite_z(x[i])) { info->status = OR_NONFINITE; return OR_NONFINITE; }
+
+    zd *dinv = malloc(sizeof(zd) * n), *w = malloc(sizeof(zd) * n), *rh = malloc(sizeof(zd) * n);
+    zd *y1 = malloc(sizeof(zd) * n), *y2 = malloc(sizeof(zd) * n), *u1 = malloc(sizeof(zd) * n);
+    zd *u2 = malloc(sizeof(zd) * n), *v = malloc(sizeof(zd) * n), *d = malloc(sizeof(zd) * n);
+    zd *tmp = malloc(sizeof(zd) * n);
+    int status = OR_NOT_CONVERGED, bd = OR_BD_NONE;
+    int64_t it = 0;
+    double bnorm = 0.0, bound = 0.0;
+
+    if (precond) {
+        if (!diag_inverse(n, rowptr, col, val, dinv)) { status = OR_EINVAL; goto done; }
+    } else {
+        for (int64_t i = 0; i < n; ++i) dinv[i] = 1.0;
+    }
+
+    bnorm = orc_dznrm2(n, b);
+    orc_residual(n, rowptr, col, val, b, x, w);
+    for (int64_t i = 0; i < n; ++i) { rh[i] = w[i]; y1[i] = w[i]; d[i] = 0.0; }
+    double tau = orc_dznrm2(n, w), theta = 0.0;
+    const double thr = tol * bnorm;
+    zd eta = 0.0, rho = orc_zdotc_v(n, rh, w);
+    bound = tau;
+    if (history) history[0] = bnorm > 0 ? tau / bnorm : 0.0;
+    if (tau <= thr) { status = OR_OK; goto done; }
+
+    for (int64_t i = 0; i < n; ++i) tmp[i] = dinv[i] * y1[i];
+    orc_spmv(n, rowptr, col, val, tmp, u1);
+    for (int64_t i = 0; i < n; ++i) v[i] = u1[i];
+
+    for (it = 1; it <= maxit; ++it) {
+        zd sigma = orc_zdotc_v(n, rh, v);
+        if (!isfinite_z(sigma)) { status = OR_NONFINITE; it -= 1; break; }
+        if (sigma == 0.0) { status = OR_BREAKDOWN; bd = OR_BD_SIGMA; it -= 1; break; }
+        const zd alpha = rho / sigma;
+        for (int64_t i = 0; i < n; ++i) y2[i] = y1[i] - alpha * v[i];
+        for (int64_t i = 0; i < n; ++i) tmp[i] = dinv[i] * y2[i];
+        orc_spmv(n, rowptr, col, val, tmp, u2);
+        int stop = 0;
+        for (int j = 1; j <= 2 && !stop; ++j) {
+            const zd *yj = j == 1 ? y1 : y2, *uj = j == 1 ? u1 : u2;
+            const int64_t m = 2 * it - 2 + j;
+            for (int64_t i = 0; i < n; ++i) w[i] -= alpha * uj[i];
+            const zd coef = theta * theta * eta / alpha;
+            for (int64_t i = 0; i < n; ++i) d[i] = yj[i] + coef * d[i];
+            theta = orc_dznrm2(n, w) / tau;
+            const double c = 1.0 / sqrt(1.0 + theta * theta);
+            tau = tau * theta * c;
+            eta = c * c * alpha;
+            for (int64_t i = 0; i < n; ++i) x[i] += eta * (dinv[i] * d[i]);
+            bound = tau * sqrt((double)(m + 1));
+            if (!isfinite(tau) || !isfinite_z(eta)) { status = OR_NONFINITE; stop = 1; }
+            else if (bound <= thr) { status = OR_OK; stop = 1; }
+        }
+        if (history) history[it] = bnorm > 0 ? bound / bnorm : bound;
+        if (stop) break;
+        zd rho_new = orc_zdotc_v(n, rh, w);
+        if (!isfinite_z(rho_new)) { status = OR_NONFINITE; break; }
+        if (rho_new == 0.0) { status = OR_BREAKDOWN; bd = OR_BD_RHO; break; }
+        const zd beta = rho_new / rho;
+        rho = rho_new;
+        for (int64_t i = 0; i < n; ++i) y1[i] = w[i] + beta * y2[i];
+        for (int64_t i = 0; i < n; ++i) tmp[i] = dinv[i] * y1[i];
+        orc_spmv(n, rowptr, col, val, tmp, u1);
+        for (int64_t i = 0; i < n; ++i) v[i] = u1[i] + beta * (u2[i] + beta * v[i]);
+    }
+    if (it > maxit) it = maxit;
+
+done:
+    info->relres_rec = bnorm > 0 ? bound / bnorm : bound;
+    info->iters = it;
+    info->status = status;
+    info->breakdown = bd;
+    if (status != OR_EINVAL) {
+        orc_residual(n, rowptr, col, val, b, x, w);
+        info->relres_true = bnorm > 0 ? orc_dznrm2(n, w) / bnorm : orc_dznrm2(n, w);
+    }
+    free(dinv); free(w); free(rh); free(y1); free(y2); free(u1); free(u2); free(v); free(d); free(tmp);
+    return status;
+}
+
 /* ------------------------------------------ complex-float inner BiCGStab */
 
 static void spmv_f(int64_t n, const int32_t *rowptr, const int32_t *col, const zf *val,

@@ -62,6 +62,7 @@ def lib():
         L.orc_zaxmy.argtypes = [i64, P, P]
         L.orc_zcopy.argtypes = [i64, P, P]
         L.orc_bicgstab.argtypes = [i64, P, P, P, P, P, dbl, i64, i32, C.POINTER(Info), P]
+        L.orc_tfqmr.argtypes = [i64, P, P, P, P, P, dbl, i64, i32, C.POINTER(Info), P]
         L.orc_bicgstab_c64.argtypes = [i64, P, P, P, P, P, C.c_float, i64, C.POINTER(Info)]
         L.orc_mixed_refine.argtypes = [i64, P, P, P, P, P, dbl, dbl, i32, i64, C.POINTER(Info),
                                        C.POINTER(C.c_int64)]
@@ -152,6 +153,23 @@ def bicgstab(rowptr, col, val, b, x0=None, tol=1e-8, maxit=400000, precond=True,
     hist = np.zeros(maxit + 1) if history else None
     lib().orc_bicgstab(n, _p(rowptr), _p(col), _p(val), _p(b), _p(x), float(tol), int(maxit),
                        1 if precond else 0, C.byref(info), _p(hist) if history else None)
+    d = info.as_dict()
+    if history:
+        return x, d, hist[: d["iters"] + 1]
+    return x, d
+
+
+def tfqmr(rowptr, col, val, b, x0=None, tol=1e-8, maxit=400000, precond=True, history=False):
+    """Jacobi right-preconditioned TFQMR; returns (x, info dict[, history]).
+    iters counts pairs of half-steps; relres_rec is the quasi-residual bound."""
+    rowptr, col, val = _csr(rowptr, col, val)
+    b = np.ascontiguousarray(b, dtype=np.complex128)
+    n = b.shape[0]
+    x = np.zeros(n, dtype=np.complex128) if x0 is None else np.array(x0, dtype=np.complex128)
+    info = Info()
+    hist = np.zeros(maxit + 1) if history else None
+    lib().orc_tfqmr(n, _p(rowptr), _p(col), _p(val), _p(b), _p(x), float(tol), int(maxit),
+                    1 if precond else 0, C.byref(info), _p(hist) if history else None)
     d = info.as_dict()
     if history:
         return x, d, hist[: d["iters"] + 1]

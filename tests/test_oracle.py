@@ -214,6 +214,62 @@ def test_bicgstab_error_paths(oracle):
     assert 0 < info["relres_true"] < 1 and np.any(x != 0)
 
 
+# ------------------------------------------------------------- TFQMR
+
+@pytest.mark.parametrize("nc,seed", [(3, 3), (4, 5)])
+def test_tfqmr_matches_scipy_steps_and_dense_lu(oracle, nc, seed):
+    """Right-preconditioned TFQMR: after k iterations (2k half-steps) the
+    iterate equals SciPy's unpreconditioned TFQMR on the explicitly scaled
+    operator A D^-1, mapped back by D^-1; to tolerance it reaches the LAPACK
+    solution."""
+    p, val = tiny_problem(nc, seed=seed)
+    b = crandn(np.random.default_rng(seed), p.n)
+    b[p.dirichlet] = 0
+    A = sp.csr_matrix((val, p.col, p.rowptr), shape=(p.n, p.n))
+    dinv = 1.0 / A.diagonal()
+    Ah = (A @ sp.diags(dinv)).tocsr()
+    for k in (1, 2, 3, 5):
+        xo, info = oracle.tfqmr(p.rowptr, p.col, val, b, tol=1e-15, maxit=k)
+        assert info["iters"] == k and info["status"] == oracle.NOT_CONVERGED
+        ys, _ = spla.tfqmr(Ah, b, rtol=1e-15, atol=0.0, maxiter=2 * k)
+        assert np.linalg.norm(dinv * ys - xo) <= 1e-11 * np.linalg.norm(xo), k
+    # the quasi-residual bound bounds the true residual (in exact arithmetic:
+    # checked at 1e-6, far above the rounding level of the recurrences)
+    x, info = oracle.tfqmr(p.rowptr, p.col, val, b, tol=1e-6)
+    assert info["status"] == 0 and info["relres_true"] <= info["relres_rec"] <= 1e-6
+    x, info = oracle.tfqmr(p.rowptr, p.col, val, b, tol=1e-12)
+    assert info["status"] == 0 and info["relres_true"] <= 2e-12
+    xs = np.linalg.solve(dense(p, val), b)
+    assert np.linalg.norm(x - xs) <= 1e-9 * np.linalg.norm(xs)
+
+
+def test_tfqmr_config1_diagonal_breakdown_and_errors(oracle):
+    c1 = configs.config1()
+    x, info = oracle.tfqmr(c1["rowptr"], c1["col"], c1["val"], c1["g"], tol=1e-8)
+    assert info["status"] == 0 and info["relres_true"] <= 1e-8 <= 1e-8 + info["relres_rec"]
+    xb, _ = oracle.bicgstab(c1["rowptr"], c1["col"], c1["val"], c1["g"], tol=1e-12)
+    x10, i10 = oracle.tfqmr(c1["rowptr"], c1["col"], c1["val"], c1["g"], tol=1e-12)
+    assert i10["status"] == 0 and np.linalg.norm(x10 - xb) <= 1e-8 * np.linalg.norm(xb)
+    # D = A: the first half-step gives x = b / d exactly, tau = 0
+    n = 20
+    rng = np.random.default_rng(2)
+    d = crandn(rng, n) + 3.0
+    b = crandn(rng, n)
+    x, info = oracle.tfqmr(np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), d, b, tol=1e-12)
+    assert info["status"] == 0 and info["iters"] == 1
+    assert np.allclose(x, b / d, rtol=1e-14, atol=0)
+    # g^H A g = 0 at the first step (D = I): sigma breakdown before any iteration
+    x, info = oracle.tfqmr(np.array([0, 2, 4], dtype=np.int32), np.array([0, 1, 0, 1], dtype=np.int32),
+                           np.array([1.0, -1.25, -1.25, 1.0], dtype=np.complex128), np.array([1.0, 2.0]))
+    assert info["status"] == oracle.BREAKDOWN and info["breakdown"] == oracle.BD_SIGMA
+    assert info["iters"] == 0 and np.all(x == 0)
+    g = c1["g"].copy()
+    g[3] = np.nan
+    assert oracle.tfqmr(c1["rowptr"], c1["col"], c1["val"], g)[1]["status"] == oracle.NONFINITE
+    x, info = oracle.tfqmr(c1["rowptr"], c1["col"], c1["val"], c1["g"], maxit=1)
+    assert info["status"] == oracle.NOT_CONVERGED and info["iters"] == 1 and np.any(x != 0)
+
+
 @pytest.mark.parametrize("nc,seed", [(3, 3), (4, 5)])
 def test_bicgstab_c64_matches_dense_lu_and_complex128_steps(oracle, nc, seed):
     """The complex-float solver (FP64-accumulated dots) reaches the LAPACK
