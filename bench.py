@@ -335,6 +335,19 @@ def main():
                               "time_s_mean": round(float(np.mean(solve_s)) - args.spmv_reps * ms_spmv * 1e-3, 4),
                               "us_per_iter": round((float(np.mean(solve_s)) - args.spmv_reps * ms_spmv * 1e-3)
                                                    / max(st["iters"], 1) * 1e6, 2)}
+    if not args.no_solve:
+        # P-TFQMR (the paper's third method) on the same system and tolerance
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        _, iq = hk.krylov_solve(A, g, tol=1e-8, method="tfqmr")
+        torch.cuda.synchronize()
+        tq = time.perf_counter() - ts
+        log("tfqmr", iq, f"{tq:.3f}s")
+        out["solve_tfqmr"] = {"tol": 1e-8, "iters": iq["iters"], "status": iq["status"],
+                              "relres_true": iq["relres_true"], "time_s": round(tq, 4),
+                              "us_per_iter": round(tq / max(iq["iters"], 1) * 1e6, 2)}
+        if "solve_plain" in out:
+            out["solve_tfqmr"]["speedup_vs_bicgstab"] = round(out["solve_plain"]["time_s_mean"] / tq, 3)
     if not args.no_mixed and not args.no_solve:
         torch.cuda.synchronize()
         ts = time.perf_counter()

@@ -142,13 +142,17 @@ typedef struct {
   int32_t precond;       /* 0: none, 1: Jacobi (diagonal), applied on the right */
   int32_t check_every;   /* iterations enqueued between host status reads (0: automatic) */
   int32_t use_x0;        /* 0: start from x = 0 (the paper's choice), 1: from d_x */
-  int32_t reserved;
-  double* d_history;     /* optional device buffer of max_iter+1 doubles: ||r_k||/||b|| */
+  int32_t method;        /* hk_method: HK_BICGSTAB (0) or HK_TFQMR (1, complex128 only) */
+  double* d_history;     /* optional device buffer of max_iter+1 doubles: ||r_k||/||b||
+                            (TFQMR: the quasi-residual bound sqrt(m+1) tau / ||b||) */
 } hk_solve_opts;
+
+/* Krylov method of hk_krylov_solve (Section 4 implements three). */
+typedef enum { HK_BICGSTAB = 0, HK_TFQMR = 1 } hk_method;
 
 typedef struct {
   int64_t iters;         /* completed iterations (a half-step exit counts as one) */
-  double relres_rec;     /* recursive ||r|| / ||b|| at exit */
+  double relres_rec;     /* recursive ||r|| / ||b|| at exit (TFQMR: the quasi-residual bound) */
   double relres_true;    /* ||b - A x|| / ||b|| recomputed at exit */
   int32_t status;        /* HK_OK / HK_NOT_CONVERGED / HK_BREAKDOWN / HK_NONFINITE */
   int32_t breakdown;     /* hk_breakdown: which scalar vanished */
@@ -156,15 +160,19 @@ typedef struct {
 } hk_solve_info;
 
 /*
- * Preconditioned BiCGStab on A x = b (Section 4: P-BiCGSTAB, zero initial
- * guess, residual tolerance, iteration cap; Jacobi preconditioner on the
- * right).  A complex128 matrix gives a complex128 solve (double accumulation);
- * a complex64 matrix a complex64 solve with float accumulation (b and x then
- * complex64).  Scalars stay in device memory; the host
- * reads a status word every check_every iterations and synchronises the
- * stream once at the end to fill *info.  A zero diagonal entry with
- * precond = 1 gives HK_EINVAL.  Returns info->status (>= 0) or an error.
- * x always holds the last iterate.
+ * Preconditioned Krylov solve of A x = b (Section 4: zero initial guess,
+ * residual tolerance, iteration cap; Jacobi preconditioner on the right).
+ * opts->method selects P-BiCGSTAB (van der Vorst's recurrences; stops on
+ * ||r|| <= tol ||b|| after a half or full step) or P-TFQMR (Freund's method
+ * as in Saad's book; two products per iteration; stops when the
+ * quasi-residual bound sqrt(m+1) tau <= tol ||b||, m the half-step).  A
+ * complex128 matrix gives a complex128 solve; a complex64 matrix (BiCGStab
+ * only) a complex64 solve whose vectors and products are complex64 and whose
+ * dots and scalars are double (b and x then complex64).  Scalars stay in
+ * device memory; the host reads a status word every check_every iterations
+ * and synchronises the stream once at the end to fill *info.  A zero
+ * diagonal entry with precond = 1, or an unknown method, gives HK_EINVAL.
+ * Returns info->status (>= 0) or an error.  x always holds the last iterate.
  */
 int hk_krylov_solve(hk_csr A, const void* d_b, void* d_x, const hk_solve_opts* opts,
                     hk_solve_info* info, void* stream);
@@ -173,10 +181,11 @@ int hk_krylov_solve(hk_csr A, const void* d_b, void* d_x, const hk_solve_opts* o
  * Mixed-precision iterative refinement (not in the paper): r = b - A u, its
  * norm, the stopping test ||r|| <= outer_tol ||b|| and the update u += d run
  * in complex128; d solves A d = r with Jacobi BiCGStab in complex64 (values
- * of A rounded to nearest per component, float accumulation) to inner_tol
- * relative to ||r||.  At most max_outer cycles; a cycle that does not lower
- * ||r|| ends the loop (HK_NOT_CONVERGED).  opts->max_iter caps each inner
- * solve.  The complex64 copy of A is kept in the handle.
+ * of A rounded to nearest per component; complex64 vectors and products,
+ * dots and scalars in double) to inner_tol relative to ||r||.  At most
+ * max_outer cycles; a cycle that does not lower ||r|| ends the loop
+ * (HK_NOT_CONVERGED).  opts->max_iter caps each inner solve; opts->method
+ * must be HK_BICGSTAB.  The complex64 copy of A is kept in the handle.
  */
 int hk_krylov_solve_mixed(hk_csr A, const void* d_b, void* d_x, double inner_tol,
                           double outer_tol, int32_t max_outer, const hk_solve_opts* opts,

@@ -51,7 +51,9 @@ namespace hk {
 int spmv_dispatch(const hk_csr_s* A, const void* x, void* y, const void* b, const void* alpha,
                   const void* beta, int mode, hipStream_t s);
 
-enum : int { S_RUN = 100, S_HALF = 101, S_TAUBD = 102 };
+// Transient statuses (>= S_RUN): the solve goes on, or an exit is pending
+// until the kernels of the current iteration have applied their last update.
+enum : int { S_RUN = 100, S_HALF = 101, S_TAUBD = 102, S_HALF2 = 103, S_RHOBD = 104 };
 
 struct SolveState {
   double2 rho, rho_old, alpha, omega, beta;
@@ -59,6 +61,10 @@ struct SolveState {
   int status, bd;
   long long iter, maxit, iters_done;
   double* history;
+  // TFQMR: theta, tau, the two half-steps' eta (their x updates are applied
+  // by the next kernel that reads d) and the d-update coefficients
+  double tq_theta, tq_tau;
+  double2 tq_eta1, tq_eta2, tq_coef1, tq_coef2;
 };
 
 // Most workgroups of a fused SpMV+dot launch (one partial-sum slot each).
@@ -125,14 +131,15 @@ __global__ void k_scale_cols(int n, const int* __restrict__ rowptr, const int* _
 }
 
 // Start of the iteration: r = b - A x0 (already in r when use_x0) or r = b,
-// rhat = p = r, y = x0 / dinv or 0; partials of ||b||^2 and ||r||^2.
+// rhat = p = r, y = x0 / dinv or 0, zero = 0 (when given); partials of
+// ||b||^2 and ||r||^2.
 template <class R>
 __global__ __launch_bounds__(kBlock) void k_init(int n, int use_x0, const cplx<R>* __restrict__ b,
                                                  const cplx<R>* __restrict__ x0,
                                                  const cplx<R>* __restrict__ dinv,
                                                  cplx<R>* __restrict__ r, cplx<R>* __restrict__ rh,
                                                  cplx<R>* __restrict__ p, cplx<R>* __restrict__ y,
-                                                 double* partials) {
+                                                 cplx<R>* __restrict__ zero, double* partials) {
   using V = cplx<R>;
   __shared__ double lds[2 * (kBlock / kWave)];
   double acc[2] = {0, 0};
@@ -153,6 +160,7 @@ __global__ __launch_bounds__(kBlock) void k_init(int n, int use_x0, const cplx<R
     rh[i] = ri;
     p[i] = ri;
     y[i] = yi;
+    if (zero) zero[i] = czero<V>();
     acc[0] += nrm2d(bi);
     acc[1] += nrm2d(ri);
   }
@@ -508,6 +516,7 @@ __global__ void k_add_c64(int n, const float2* __restrict__ d, double2* __restri
 template <class R> struct Work {
   using V = cplx<R>;
   V *y, *r, *rh, *p, *v, *s, *t, *dinv, *ahat;
+  V *u, *d;  // TFQMR only
   double* partials;
   SolveState* st;
   int* flag;
@@ -517,7 +526,7 @@ static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 template <class R> static size_t work_bytes(int64_t n, int64_t nnz) {
   using V = cplx<R>;
-  return 8 * align_up(sizeof(V) * n) + align_up(sizeof(V) * (nnz > 0 ? nnz : 1)) +
+  return 10 * align_up(sizeof(V) * n) + align_up(sizeof(V) * (nnz > 0 ? nnz : 1)) +
          align_up(sizeof(double) * 4 * partial_slots(n)) + align_up(sizeof(SolveState)) + align_up(64);
 }
 
@@ -534,6 +543,8 @@ template <class R> static Work<R> carve(void* base, int64_t n, int64_t nnz) {
   w.s = (V*)take(sizeof(V) * n);
   w.t = (V*)take(sizeof(V) * n);
   w.dinv = (V*)take(sizeof(V) * n);
+  w.u = (V*)take(sizeof(V) * n);
+  w.d = (V*)take(sizeof(V) * n);
   w.ahat = (V*)take(sizeof(V) * (nnz > 0 ? nnz : 1));
   w.partials = (double*)take(sizeof(double) * 4 * partial_slots(n));
   w.st = (SolveState*)take(sizeof(SolveState));
@@ -689,6 +700,39 @@ static int tune_dot(const hk_csr_s* A, const Work<R>& wk, SpmvPlan* out, hipStre
   return HK_OK;
 }
 
+// End of a solve: x = D^-1 y, the true residual ||b - A x|| with the
+// original values, and *info from the device state (synchronises).
+template <class R>
+static int finish_solve(const hk_csr_s* A, const cplx<R>* val, const cplx<R>* b, cplx<R>* x, const Work<R>& wk,
+                        hk_solve_info* info, hipStream_t s) {
+  using V = cplx<R>;
+  const int n = (int)A->n;
+  const dim3 ew((unsigned)((n + kBlock - 1) / kBlock));
+  const int gv = ew_blocks(n);
+  hipLaunchKernelGGL(k_unscale<V>, ew, dim3(kBlock), 0, s, n, wk.dinv, wk.y, x);
+  HK_CHECK_LAUNCH();
+  {
+    hk_csr_s tmp = *A;
+    tmp.val = val;
+    int rc2 = spmv_dispatch(&tmp, x, wk.t, b, nullptr, nullptr, 1, s);
+    if (rc2 != HK_OK) return rc2;
+  }
+  hipLaunchKernelGGL(k_norm2_partials<R>, dim3(gv), dim3(kBlock), 0, s, n, wk.t, wk.partials);
+  HK_CHECK_LAUNCH();
+  HK_HIP((launch_fin<R, F_TRUE>(wk, gv, 0, 0, s)));
+  SolveState hs;
+  HK_HIP(hipMemcpyAsync(&hs, wk.st, sizeof(hs), hipMemcpyDeviceToHost, s));
+  HK_HIP(hipStreamSynchronize(s));
+  info->status = hs.status >= S_RUN ? HK_NOT_CONVERGED : hs.status;
+  info->breakdown = hs.bd;
+  info->iters = hs.status >= S_RUN ? hs.iter : hs.iters_done;
+  const double bb = (double)hs.bb;
+  info->relres_rec = bb > 0 ? std::sqrt((double)hs.rr / bb) : std::sqrt((double)hs.rr);
+  info->relres_true = bb > 0 ? std::sqrt((double)hs.rr_true / bb) : std::sqrt((double)hs.rr_true);
+  info->inner_iters = 0;
+  return HK_OK;
+}
+
 // Runs the whole solve for precision R on values `val` (A's pattern), right
 // side b, solution x (input when use_x0).  Fills info (host), synchronises.
 template <class R>
@@ -730,7 +774,7 @@ static int bicgstab(hk_csr_s* A, const cplx<R>* val, const cplx<R>* b, cplx<R>* 
   init.status = S_RUN;
   HK_HIP(hipMemcpyAsync(wk.st, &init, sizeof(init), hipMemcpyHostToDevice, s));
   hipLaunchKernelGGL(k_init<R>, dim3(gv), dim3(kBlock), 0, s, n, o.use_x0 ? 1 : 0, b, x, wk.dinv,
-                     wk.r, wk.rh, wk.p, wk.y, wk.partials);
+                     wk.r, wk.rh, wk.p, wk.y, (cplx<R>*)nullptr, wk.partials);
   HK_CHECK_LAUNCH();
   HK_HIP((launch_fin<R, F_INIT>(wk, gv, o.tol, (long long)o.max_iter, s)));
   int hflag = 0;
@@ -792,29 +836,439 @@ static int bicgstab(hk_csr_s* A, const cplx<R>* val, const cplx<R>* b, cplx<R>* 
   (void)hipEventDestroy(ev[1]);
   if (rc != HK_OK) return rc;
 
-  // x = D^-1 y; true residual with the original values
-  hipLaunchKernelGGL(k_unscale<V>, ew, dim3(kBlock), 0, s, n, wk.dinv, wk.y, x);
+  return finish_solve<R>(A, val, b, x, wk, info, s);
+}
+
+// =================================================================== TFQMR
+//
+// Right-preconditioned TFQMR (Section 4: P-TFQMR, after Saad's book) on
+// Ahat = A D^-1 for y, x = D^-1 y at the end.  Iteration k, in the notation
+// of Freund's method (two products with Ahat):
+//   alpha = rho / (rhat^H v);  y2 = y1 - alpha v;  u2 = Ahat y2
+//   half-step j = 1, 2:  w -= alpha u_j;  d = y_j + (theta^2 eta / alpha) d;
+//     theta = ||w|| / tau;  c = (1 + theta^2)^-1/2;  tau *= theta c;
+//     eta = c^2 alpha;  y += eta d;  stop when sqrt(m+1) tau <= tol ||b||
+//   rho' = rhat^H w;  beta = rho' / rho;  y1 = w + beta y2;  u1 = Ahat y1;
+//   v = u1 + beta (u2 + beta v)
+// Kernels of one iteration (each reduction followed by its finalize):
+//   K_a  : y2 = y1 - alpha v, w -= alpha u1, d = y1 + coef1 d, ||w||^2
+//          -> half-step 1 scalars (theta, tau, eta1), stop test
+//   K_b  : u2 = Ahat y2 fused with half-step 2: y += eta1 d (the deferred
+//          update of half-step 1), w -= alpha u2, d = y2 + coef2 d,
+//          ||w||^2, rhat^H w  -> half-step 2 scalars, stop test, rho, beta
+//   K_c  : y += eta2 d (or eta1 d after a half-step-1 exit), y1 = w + beta y2
+//   K_d  : u1 = Ahat y1 fused with v = u1 + beta (u2 + beta v), rhat^H v
+//          -> end of the iteration, alpha and coef1 for the next one
+// Workspace roles: w = r, y1 = p, y2 = s, u2 = t, u1 = u, plus d.
+
+// Products of Ahat and x handed row by row to an epilogue E (in the lane
+// that owns the row).  E provides: V, NV (partial sums), Pre load(int r)
+// (operands of row r, loaded before the product), static Sc scalars(st),
+// static bool active(st), and apply(r, pre, acc, sc, part).
+template <class E, int L, int U>
+__global__ __launch_bounds__(kBlock) void k_fused_lg(int n, int ntiles, const int* __restrict__ rowptr,
+                                                     const int* __restrict__ col,
+                                                     const typename E::V* __restrict__ val,
+                                                     const typename E::V* __restrict__ x, E e,
+                                                     const SolveState* __restrict__ st, double* partials) {
+  using V = typename E::V;
+  constexpr int NV = E::NV;
+  __shared__ double lds[NV * (kBlock / kWave)];
+  if (!E::active(st)) return;
+  const typename E::Sc sc = E::scalars(st);
+  constexpr int RT = (kBlock / L) * U;
+  const int g = threadIdx.x / L, lane = threadIdx.x & (L - 1);
+  double part[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) part[k] = 0;
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int r0 = t * RT + g * U;
+    const int rw = r0 + (lane < U ? lane : 0);
+    const typename E::Pre pre = e.load(rw < n ? rw : n - 1);
+    V acc[U];
+    csr_rows<L, U, V>(r0, n, rowptr, col, val, x, acc);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (lane == u && r0 + u < n) e.apply(r0 + u, pre, acc[u], sc, part);
+  }
+  block_sum<NV>(part, lds);
+  store_block_partials<NV>(part, partials);
+}
+
+template <class E, int RW, int NW>
+__global__ __launch_bounds__(NW * kWave) void k_fused_rb(int n, int ntiles, const int* __restrict__ rowptr,
+                                                         const int* __restrict__ col,
+                                                         const typename E::V* __restrict__ val,
+                                                         const typename E::V* __restrict__ x, E e,
+                                                         const SolveState* __restrict__ st, double* partials) {
+  using V = typename E::V;
+  constexpr int NV = E::NV;
+  constexpr int CH = RbCh<RW, V>::v;
+  __shared__ V lds[NW * CH * kWave];
+  if (!E::active(st)) return;
+  const typename E::Sc sc = E::scalars(st);
+  V* buf = lds + (threadIdx.x / kWave) * CH * kWave;
+  const int l = threadIdx.x & (kWave - 1);
+  double part[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) part[k] = 0;
+  for (int tb = blockIdx.x; tb < ntiles; tb += gridDim.x) {
+    const int t = tile_of(tb, ntiles);
+    const int r0 = t * (NW * RW) + (threadIdx.x / kWave) * RW;
+    const int r = r0 + l;
+    const typename E::Pre pre = e.load(r < n ? r : n - 1);
+    const V acc = csr_block_rows<RW, CH, V>(r0, n, rowptr, col, val, x, buf);
+    if (l < RW && r < n) e.apply(r, pre, acc, sc, part);
+  }
+  __syncthreads();
+  block_sum<NV, double, NW>(part, reinterpret_cast<double*>(lds));
+  store_block_partials<NV>(part, partials);
+}
+
+template <class E>
+static hipError_t launch_fused(const hk_csr_s* A, const SpmvPlan& p, const typename E::V* val,
+                               const typename E::V* x, const E& e, const SolveState* st, double* partials,
+                               hipStream_t s) {
+  int nw = 0;
+  const int ntiles = dot_tiles(A, p, &nw);
+  const int grid = dot_grid(A, p);
+  const int n = (int)A->n;
+#define HK_FLG(LL, UU)                                                                               \
+  if (p.L == LL && p.U == UU) {                                                                      \
+    hipLaunchKernelGGL((k_fused_lg<E, LL, UU>), dim3(grid), dim3(kBlock), 0, s, n, ntiles, A->rowptr, \
+                       A->col, val, x, e, st, partials);                                             \
+    return hipGetLastError();                                                                        \
+  }
+  HK_FLG(4, 1) HK_FLG(4, 2) HK_FLG(4, 4)
+  HK_FLG(8, 1) HK_FLG(8, 2) HK_FLG(8, 4) HK_FLG(8, 8)
+  HK_FLG(16, 1) HK_FLG(16, 2) HK_FLG(16, 4) HK_FLG(16, 8)
+  HK_FLG(32, 1) HK_FLG(32, 2) HK_FLG(32, 4) HK_FLG(32, 8)
+#undef HK_FLG
+#define HK_FRB(RR, NWW)                                                                              \
+  if (p.L == kRowBlockL && p.U == RR && nw == NWW) {                                                 \
+    hipLaunchKernelGGL((k_fused_rb<E, RR, NWW>), dim3(grid), dim3(NWW * kWave), 0, s, n, ntiles,     \
+                       A->rowptr, A->col, val, x, e, st, partials);                                  \
+    return hipGetLastError();                                                                        \
+  }
+  HK_FRB(16, 2) HK_FRB(32, 2) HK_FRB(64, 2)
+  HK_FRB(16, 4) HK_FRB(32, 4) HK_FRB(64, 4)
+  HK_FRB(16, 8) HK_FRB(32, 8) HK_FRB(64, 8)
+#undef HK_FRB
+  return hipErrorInvalidValue;
+}
+
+// K_b epilogue: u2 = acc; y += eta1 d; w -= alpha u2; d = y2 + coef2 d;
+// partials ||w||^2, rhat^H w.
+template <class R> struct EpiTqB {
+  using V = cplx<R>;
+  static constexpr int NV = 3;
+  struct Pre { V w, d, y, rh, y2; };
+  struct Sc { V alpha, eta1, coef2; };
+  V *w, *d, *y, *u2;
+  const V *rh, *y2;
+  __device__ static bool active(const SolveState* st) { return st->status == S_RUN; }
+  __device__ static Sc scalars(const SolveState* st) {
+    return Sc{vscal<V>(st->alpha), vscal<V>(st->tq_eta1), vscal<V>(st->tq_coef2)};
+  }
+  __device__ Pre load(int r) const { return Pre{w[r], d[r], y[r], rh[r], y2[r]}; }
+  __device__ void apply(int r, const Pre& q, V acc, const Sc& c, double (&part)[NV]) const {
+    u2[r] = acc;
+    y[r] = cfma(c.eta1, q.d, q.y);
+    const V wn = csub(q.w, cmul(c.alpha, acc));
+    w[r] = wn;
+    d[r] = cfma(c.coef2, q.d, q.y2);
+    part[0] += nrm2d(wn);
+    dotc_acc(q.rh, wn, part[1], part[2]);
+  }
+};
+
+// K_d epilogue: u1 = acc; v = u1 + beta (u2 + beta v) (v = u1 on the first
+// product, INIT); partials rhat^H v.
+template <class R, int INIT> struct EpiTqD {
+  using V = cplx<R>;
+  static constexpr int NV = 2;
+  struct Pre { V u2, v, rh; };
+  struct Sc { V beta; };
+  V *u1, *v;
+  const V *u2, *rh;
+  __device__ static bool active(const SolveState* st) { return st->status == S_RUN; }
+  __device__ static Sc scalars(const SolveState* st) { return Sc{vscal<V>(st->beta)}; }
+  __device__ Pre load(int r) const {
+    if (INIT) return Pre{czero<V>(), czero<V>(), rh[r]};
+    return Pre{u2[r], v[r], rh[r]};
+  }
+  __device__ void apply(int r, const Pre& q, V acc, const Sc& c, double (&part)[NV]) const {
+    u1[r] = acc;
+    const V vn = INIT ? acc : cfma(c.beta, cfma(c.beta, q.v, q.u2), acc);
+    v[r] = vn;
+    dotc_acc(q.rh, vn, part[0], part[1]);
+  }
+};
+
+// K_a: y2 = y1 - alpha v; w -= alpha u1; d = y1 + coef1 d; partials ||w||^2.
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_tq_a(int n, const SolveState* __restrict__ st,
+                                                 const cplx<R>* __restrict__ y1, const cplx<R>* __restrict__ v,
+                                                 const cplx<R>* __restrict__ u1, cplx<R>* __restrict__ y2,
+                                                 cplx<R>* __restrict__ w, cplx<R>* __restrict__ d,
+                                                 double* partials) {
+  using V = cplx<R>;
+  __shared__ double lds[kBlock / kWave];
+  if (st->status != S_RUN) return;
+  const V alpha = vscal<V>(st->alpha), coef = vscal<V>(st->tq_coef1);
+  double acc[1] = {0};
+  const int base = blockIdx.x * (kBlock * kEw) + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < kEw; ++k) {
+    const int i = base + k * kBlock;
+    if (i >= n) break;
+    const V y1i = y1[i], vi = v[i], ui = u1[i], wi = w[i], di = d[i];
+    y2[i] = csub(y1i, cmul(alpha, vi));
+    const V wn = csub(wi, cmul(alpha, ui));
+    w[i] = wn;
+    d[i] = cfma(coef, di, y1i);
+    acc[0] += nrm2d(wn);
+  }
+  block_sum<1>(acc, lds);
+  store_block_partials<1>(acc, partials);
+}
+
+// K_c: the deferred x update of the iteration's last half-step (y += eta d)
+// and, while running, y1 = w + beta y2.
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_tq_c(int n, const SolveState* __restrict__ st,
+                                                 const cplx<R>* __restrict__ w, const cplx<R>* __restrict__ y2,
+                                                 const cplx<R>* __restrict__ d, cplx<R>* __restrict__ y,
+                                                 cplx<R>* __restrict__ y1) {
+  using V = cplx<R>;
+  const int status = st->status;
+  if (status != S_RUN && status != S_HALF && status != S_HALF2 && status != S_RHOBD) return;
+  const V eta = vscal<V>(status == S_HALF ? st->tq_eta1 : st->tq_eta2), beta = vscal<V>(st->beta);
+  const int base = blockIdx.x * (kBlock * kEw) + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < kEw; ++k) {
+    const int i = base + k * kBlock;
+    if (i >= n) break;
+    y[i] = cfma(eta, d[i], y[i]);
+    if (status == S_RUN) y1[i] = cfma(beta, y2[i], w[i]);
+  }
+}
+
+enum : int { TQ_INIT = 0, TQ_SIGMA0 = 1, TQ_H1 = 2, TQ_H2 = 3, TQ_SIGMA = 4 };
+template <int F> struct TqNV { static constexpr int v = 2; };
+template <> struct TqNV<TQ_H1> { static constexpr int v = 1; };
+template <> struct TqNV<TQ_H2> { static constexpr int v = 3; };
+
+// One workgroup: sums the partials of the preceding kernel and applies the
+// TFQMR scalar step F.
+template <int F>
+__global__ __launch_bounds__(kFinBlock) void k_tq_fin(SolveState* st, const double* partials, int nb, double tol,
+                                                      long long maxit) {
+  using V = double2;
+  constexpr int NV = TqNV<F>::v;
+  __shared__ double lds[NV * (kFinBlock / kWave)];
+  const int status = st->status;
+  if (F == TQ_H1 && status != S_RUN) return;
+  if (F == TQ_H2 && status != S_RUN) return;
+  if (F == TQ_SIGMA0 && status != S_RUN) return;
+  if (F == TQ_SIGMA) {
+    if (status == S_HALF || status == S_HALF2 || status == S_RHOBD) {
+      if (threadIdx.x == 0) {
+        st->status = status == S_RHOBD ? HK_BREAKDOWN : HK_OK;
+        if (status == S_RHOBD) st->bd = HK_BD_RHO;
+      }
+      return;
+    }
+    if (status != S_RUN) return;
+  }
+  double tot[NV];
+  final_sum<NV>(partials, nb, tot, lds);
+  if (threadIdx.x != 0) return;
+  const long long k = st->iter;
+  if (F == TQ_INIT) {
+    st->bb = tot[0];
+    st->rr = tot[1];
+    st->theta2 = tol * tol * tot[0];
+    st->rho = cmake<V>(tot[1], 0);
+    st->tq_tau = sqrt(tot[1]);
+    st->tq_theta = 0;
+    st->tq_eta1 = st->tq_eta2 = st->tq_coef1 = st->tq_coef2 = czero<V>();
+    st->alpha = st->beta = czero<V>();
+    st->iter = 1;
+    st->maxit = maxit;
+    st->iters_done = 0;
+    st->bd = HK_BD_NONE;
+    if (!isfinite(tot[0]) || !isfinite(tot[1])) st->status = HK_NONFINITE;
+    else if (tot[1] <= st->theta2) st->status = HK_OK;
+    else if (maxit <= 0) st->status = HK_NOT_CONVERGED;
+    else st->status = S_RUN;
+    if (st->history) st->history[0] = tot[0] > 0 ? sqrt(tot[1] / tot[0]) : 0.0;
+  } else if (F == TQ_SIGMA0 || F == TQ_SIGMA) {
+    if (F == TQ_SIGMA) {
+      // the iteration ended without an exit
+      if (k >= st->maxit) { st->status = HK_NOT_CONVERGED; st->iters_done = k; return; }
+      st->iter = k + 1;
+    }
+    const V sigma = cmake<V>(tot[0], tot[1]);
+    if (!cfinite(sigma)) {
+      st->status = HK_NONFINITE;
+      st->iters_done = st->iter - 1;
+    } else if (sigma.x == 0 && sigma.y == 0) {
+      st->status = HK_BREAKDOWN;
+      st->bd = HK_BD_SIGMA;
+      st->iters_done = st->iter - 1;
+    } else {
+      const V alpha = cdiv(st->rho, sigma);
+      st->alpha = alpha;
+      const double th = st->tq_theta;
+      st->tq_coef1 = cdiv(cmul(cmake<V>(th * th, 0), st->tq_eta2), alpha);
+    }
+  } else {  // TQ_H1, TQ_H2: a half-step's theta, tau, eta and stop test
+    const double theta = sqrt(tot[0]) / st->tq_tau;
+    const double c = 1.0 / sqrt(1.0 + theta * theta);
+    const double tau = st->tq_tau * theta * c;
+    const V alpha = st->alpha;
+    const V eta = cmake<V>(c * c * alpha.x, c * c * alpha.y);
+    st->tq_theta = theta;
+    st->tq_tau = tau;
+    const long long m = F == TQ_H1 ? 2 * k - 1 : 2 * k;  // half-step index, from 1
+    const double bound = tau * sqrt((double)(m + 1));
+    st->rr = bound * bound;
+    if (st->history) st->history[k] = st->bb > 0 ? bound / sqrt(st->bb) : 0.0;
+    if (F == TQ_H1) {
+      st->tq_eta1 = eta;
+      st->tq_coef2 = cdiv(cmul(cmake<V>(theta * theta, 0), eta), alpha);
+    } else {
+      st->tq_eta2 = eta;
+    }
+    if (!isfinite(tau) || !cfinite(eta)) {
+      st->status = HK_NONFINITE;
+      st->iters_done = k;
+    } else if (bound * bound <= st->theta2) {
+      st->status = F == TQ_H1 ? S_HALF : S_HALF2;
+      st->iters_done = k;
+    } else if (F == TQ_H2) {
+      const V rho = cmake<V>(tot[1], tot[2]);
+      st->iters_done = k;
+      if (!cfinite(rho)) {
+        st->status = HK_NONFINITE;
+      } else if (rho.x == 0 && rho.y == 0) {
+        st->status = S_RHOBD;
+      } else {
+        st->beta = cdiv(rho, st->rho);
+        st->rho = rho;
+      }
+    }
+  }
+}
+
+template <int F>
+static hipError_t launch_tq_fin(SolveState* st, const double* partials, int nb, double tol, long long maxit,
+                                hipStream_t s) {
+  hipLaunchKernelGGL((k_tq_fin<F>), dim3(1), dim3(kFinBlock), 0, s, st, partials, nb, tol, maxit);
+  return hipGetLastError();
+}
+
+// Whole TFQMR solve (complex128), the same contract as bicgstab<R>.
+static int tfqmr(hk_csr_s* A, const double2* val, const double2* b, double2* x, const hk_solve_opts& o,
+                 void* wsbase, hk_solve_info* info, hipStream_t s) {
+  using R = double;
+  using V = double2;
+  const int n = (int)A->n;
+  const Work<R> wk = carve<R>(wsbase, A->n, A->nnz);
+  const dim3 ew((unsigned)((n + kBlock - 1) / kBlock));
+  const int gv = ew_blocks(n);
+  V *w = wk.r, *y1 = wk.p, *y2 = wk.s, *u2 = wk.t, *u1 = wk.u, *d = wk.d, *v = wk.v;
+
+  HK_HIP(hipMemsetAsync(wk.flag, 0, sizeof(int), s));
+  hipLaunchKernelGGL(k_diag_inv<V>, ew, dim3(kBlock), 0, s, n, A->rowptr, A->col, val, wk.dinv,
+                     o.precond ? 1 : 0, wk.flag);
   HK_CHECK_LAUNCH();
-  {
+  hipLaunchKernelGGL(k_scale_cols<V>, ew, dim3(kBlock), 0, s, n, A->rowptr, A->col, val, wk.dinv, wk.ahat);
+  HK_CHECK_LAUNCH();
+  if (o.use_x0) {
     hk_csr_s tmp = *A;
     tmp.val = val;
-    int rc2 = spmv_dispatch(&tmp, x, wk.t, b, nullptr, nullptr, 1, s);
-    if (rc2 != HK_OK) return rc2;
+    int rc = spmv_dispatch(&tmp, x, wk.r, b, nullptr, nullptr, 1, s);
+    if (rc != HK_OK) return rc;
   }
-  hipLaunchKernelGGL(k_norm2_partials<R>, dim3(gv), dim3(kBlock), 0, s, n, wk.t, wk.partials);
+  SpmvPlan dp = A->plan;
+  dp.nw = 0;
+  if (A->plan.tuned) {
+    SpmvPlan& cached = A->dot_plan[0];
+    if (!cached.tuned) {
+      int rc = tune_dot<R>(A, wk, &cached, s);
+      if (rc != HK_OK) return rc;
+    }
+    dp = cached;
+  }
+  const int gs = dot_grid(A, dp);
+  SolveState init{};
+  init.history = o.d_history;
+  init.status = S_RUN;
+  HK_HIP(hipMemcpyAsync(wk.st, &init, sizeof(init), hipMemcpyHostToDevice, s));
+  // w = r0, rhat = y1 = r0, y = x0 / dinv or 0, d = 0
+  hipLaunchKernelGGL(k_init<R>, dim3(gv), dim3(kBlock), 0, s, n, o.use_x0 ? 1 : 0, b, x, wk.dinv, w, wk.rh,
+                     y1, wk.y, d, wk.partials);
   HK_CHECK_LAUNCH();
-  HK_HIP((launch_fin<R, F_TRUE>(wk, gv, 0, 0, s)));
-  SolveState hs;
-  HK_HIP(hipMemcpyAsync(&hs, wk.st, sizeof(hs), hipMemcpyDeviceToHost, s));
+  HK_HIP(launch_tq_fin<TQ_INIT>(wk.st, wk.partials, gv, o.tol, (long long)o.max_iter, s));
+  {
+    EpiTqD<R, 1> e0{u1, v, u2, wk.rh};
+    HK_HIP(launch_fused(A, dp, wk.ahat, y1, e0, wk.st, wk.partials, s));
+    HK_HIP(launch_tq_fin<TQ_SIGMA0>(wk.st, wk.partials, gs, 0, 0, s));
+  }
+  int hflag = 0;
+  HK_HIP(hipMemcpyAsync(&hflag, wk.flag, sizeof(int), hipMemcpyDeviceToHost, s));
   HK_HIP(hipStreamSynchronize(s));
-  info->status = hs.status >= S_RUN ? HK_NOT_CONVERGED : hs.status;
-  info->breakdown = hs.bd;
-  info->iters = hs.status >= S_RUN ? hs.iter : hs.iters_done;
-  const double bb = (double)hs.bb;
-  info->relres_rec = bb > 0 ? std::sqrt((double)hs.rr / bb) : std::sqrt((double)hs.rr);
-  info->relres_true = bb > 0 ? std::sqrt((double)hs.rr_true / bb) : std::sqrt((double)hs.rr_true);
-  info->inner_iters = 0;
-  return HK_OK;
+  if (hflag) HK_FAIL(HK_EINVAL, "krylov solve: zero diagonal entry (Jacobi undefined)");
+
+  const EpiTqB<R> eb{w, d, wk.y, u2, wk.rh, y2};
+  const EpiTqD<R, 0> ed{u1, v, u2, wk.rh};
+  int m = o.check_every > 0 ? o.check_every : (n < 200000 ? 64 : 16);
+  int* pin = A->pinned;
+  hipEvent_t ev[2];
+  HK_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+  HK_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+  int rc = HK_OK;
+  long long enq = 0;
+  int k = 0;
+  const size_t status_off = offsetof(SolveState, status);
+  for (;;) {
+    for (int j = 0; j < m && rc == HK_OK; ++j) {
+      hipLaunchKernelGGL(k_tq_a<R>, dim3(gv), dim3(kBlock), 0, s, n, wk.st, y1, v, u1, y2, w, d, wk.partials);
+      hipError_t e = hipGetLastError();
+      if (e == hipSuccess) e = launch_tq_fin<TQ_H1>(wk.st, wk.partials, gv, 0, 0, s);
+      if (e == hipSuccess) e = launch_fused(A, dp, wk.ahat, y2, eb, wk.st, wk.partials, s);
+      if (e == hipSuccess) e = launch_tq_fin<TQ_H2>(wk.st, wk.partials, gs, 0, 0, s);
+      if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_tq_c<R>, dim3(gv), dim3(kBlock), 0, s, n, wk.st, w, y2, d, wk.y, y1);
+        e = hipGetLastError();
+      }
+      if (e == hipSuccess) e = launch_fused(A, dp, wk.ahat, y1, ed, wk.st, wk.partials, s);
+      if (e == hipSuccess) e = launch_tq_fin<TQ_SIGMA>(wk.st, wk.partials, gs, 0, 0, s);
+      if (e != hipSuccess) {
+        set_error_text("krylov solve: launch failed: %s", hipGetErrorString(e));
+        rc = HK_EHIP;
+      }
+    }
+    if (rc != HK_OK) break;
+    enq += m;
+    hipError_t e = hipMemcpyAsync(&pin[k & 1], (char*)wk.st + status_off, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipEventRecord(ev[k & 1], s);
+    if (e == hipSuccess && k > 0) e = hipEventSynchronize(ev[(k - 1) & 1]);
+    if (e != hipSuccess) {
+      set_error_text("krylov solve: %s", hipGetErrorString(e));
+      rc = HK_EHIP;
+      break;
+    }
+    if (k > 0 && pin[(k - 1) & 1] < S_RUN) break;
+    if (enq >= o.max_iter) break;
+    ++k;
+  }
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
+  if (rc != HK_OK) return rc;
+  return finish_solve<R>(A, val, b, x, wk, info, s);
 }
 
 static int ensure_pinned(hk_csr_s* A) {
@@ -827,6 +1281,8 @@ static int check_opts(const hk_solve_opts* o, const char* who) {
   if (!o) HK_FAIL(HK_EINVAL, "%s: opts is NULL", who);
   if (!(o->tol >= 0) || o->max_iter < 0 || o->check_every < 0)
     HK_FAIL(HK_EINVAL, "%s: bad options (tol=%g max_iter=%lld)", who, o->tol, (long long)o->max_iter);
+  if (o->method != HK_BICGSTAB && o->method != HK_TFQMR)
+    HK_FAIL(HK_EINVAL, "%s: unknown method %d", who, (int)o->method);
   return HK_OK;
 }
 
@@ -843,6 +1299,7 @@ extern "C" int hk_krylov_solve(hk_csr A, const void* d_b, void* d_x, const hk_so
   rc = ensure_pinned(A);
   if (rc != HK_OK) return rc;
   if (A->dtype == HK_C64) {
+    if (opts->method != HK_BICGSTAB) HK_FAIL(HK_EINVAL, "hk_krylov_solve: complex64 solves use BiCGStab only");
     rc = ensure_ws(&A->ws32, &A->ws32_bytes, work_bytes<float>(A->n, A->nnz), s);
     if (rc != HK_OK) return rc;
     rc = bicgstab<float>(A, (const float2*)A->val, (const float2*)d_b, (float2*)d_x, *opts, A->ws32,
@@ -850,8 +1307,11 @@ extern "C" int hk_krylov_solve(hk_csr A, const void* d_b, void* d_x, const hk_so
   } else {
     rc = ensure_ws(&A->ws, &A->ws_bytes, work_bytes<double>(A->n, A->nnz), s);
     if (rc != HK_OK) return rc;
-    rc = bicgstab<double>(A, (const double2*)A->val, (const double2*)d_b, (double2*)d_x, *opts, A->ws,
-                          info, s);
+    if (opts->method == HK_TFQMR)
+      rc = tfqmr(A, (const double2*)A->val, (const double2*)d_b, (double2*)d_x, *opts, A->ws, info, s);
+    else
+      rc = bicgstab<double>(A, (const double2*)A->val, (const double2*)d_b, (double2*)d_x, *opts, A->ws,
+                            info, s);
   }
   if (rc != HK_OK) return rc;
   return info->status;
@@ -866,6 +1326,7 @@ extern "C" int hk_krylov_solve_mixed(hk_csr A, const void* d_b, void* d_x, doubl
   if (rc != HK_OK) return rc;
   if (!(inner_tol > 0) || !(outer_tol >= 0) || max_outer < 0)
     HK_FAIL(HK_EINVAL, "hk_krylov_solve_mixed: bad tolerances");
+  if (opts->method != HK_BICGSTAB) HK_FAIL(HK_EINVAL, "hk_krylov_solve_mixed: the inner solve is BiCGStab");
   hipStream_t s = as_stream(stream);
   const int64_t n = A->n;
   // complex64 workspace + r (c128) + r32, d32 (c64) + norm scratch

@@ -31,7 +31,7 @@ class HKError(RuntimeError):
 
 class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int64), ("precond", C.c_int32),
-                ("check_every", C.c_int32), ("use_x0", C.c_int32), ("reserved", C.c_int32),
+                ("check_every", C.c_int32), ("use_x0", C.c_int32), ("method", C.c_int32),
                 ("d_history", C.c_void_p)]
 
 
@@ -238,8 +238,14 @@ def zconj(x, y=None):
     return y
 
 
-def _opts(tol, max_iter, precond, check_every, use_x0, history):
+METHODS = {"bicgstab": 0, "tfqmr": 1}
+
+
+def _opts(tol, max_iter, precond, check_every, use_x0, history, method="bicgstab"):
+    if method not in METHODS:
+        raise HKError(HK_EINVAL, f"unknown method {method!r}; one of {sorted(METHODS)}")
     o = SolveOpts()
+    o.method = METHODS[method]
     o.tol = float(tol)
     o.max_iter = int(max_iter)
     o.precond = 1 if precond else 0
@@ -250,14 +256,15 @@ def _opts(tol, max_iter, precond, check_every, use_x0, history):
 
 
 def krylov_solve(A: CSR, b, x=None, tol=1e-8, max_iter=400000, precond=True, check_every=0,
-                 history=False):
-    """Jacobi right-preconditioned BiCGStab in A's precision; returns (x, info dict[, history])."""
+                 history=False, method="bicgstab"):
+    """Jacobi right-preconditioned BiCGStab (or TFQMR, complex128) in A's precision;
+    returns (x, info dict[, history])."""
     _cvec(b, A.dtype, name="b")
     use_x0 = x is not None
     x = torch.zeros_like(b) if x is None else _cvec(x, A.dtype, name="x")
     hist = torch.zeros(int(max_iter) + 1, dtype=torch.float64, device=b.device) if history else None
     info = SolveInfo()
-    o = _opts(tol, max_iter, precond, check_every, use_x0, hist)
+    o = _opts(tol, max_iter, precond, check_every, use_x0, hist, method)
     _check(load().hk_krylov_solve(A.h, _ptr(b), _ptr(x), C.byref(o), C.byref(info), _stream()),
            allow_positive=True)
     d = info.as_dict()
