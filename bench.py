@@ -184,6 +184,40 @@ def bench_batched(hk, torch, np, dev, log):
     return res
 
 
+def bench_hex(hk, torch, np, dev, stream, log, reps=20):
+    """Q1 hexahedra on an 86^3 jittered cube (658,503 rows, 17.2M nonzeros, up
+    to 27 per row -- the row length of the paper's car-cavity matrices): CSR
+    product in the tuned shape, and BiCGStab / TFQMR to 1e-8."""
+    from synth import configs
+    c = configs.config_hex()
+    n, nnz = int(c["n"]), int(c["col"].shape[0])
+    t = lambda a: torch.from_numpy(a).to(dev)
+    A = hk.CSR(t(c["rowptr"]), t(c["col"]), t(c["val"]), autotune=True)
+    x = t(np.random.default_rng(3).standard_normal(n) + 0j)
+    y = torch.empty_like(x)
+    A.spmv(x, y)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        A.spmv(x, y)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) / reps * 1e3
+    nbytes = spmv_bytes(n, nnz)
+    res = {"n": n, "nnz": nnz, "spmv_plan": A.plan(), "spmv_us": round(us, 2),
+           "spmv_gbs": round(nbytes / (us * 1e-6) / 1e9, 1), "spmv_frac": round(nbytes / (us * 1e-6) / 8e12, 4)}
+    g = t(c["g"])
+    for method in ("bicgstab", "tfqmr"):
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        _, info = hk.krylov_solve(A, g, tol=1e-8, method=method)
+        torch.cuda.synchronize()
+        res[method] = {"iters": info["iters"], "status": info["status"], "relres_true": info["relres_true"],
+                       "time_s": round(time.perf_counter() - ts, 4)}
+    log("hex", res)
+    return {"hex86": res}
+
+
 def bench_adjoint(hk, torch, np, dev, log):
     """Forward + adjoint solve on the 48^3, 216-block differentiable problem."""
     from synth import configs
@@ -387,6 +421,7 @@ def main():
     if not args.no_solve:
         out.update(bench_blas1(hk, torch, dev, stream, log))
     if args.batched and not args.no_solve:
+        out.update(bench_hex(hk, torch, np, dev, stream, log))
         out.update(bench_batched(hk, torch, np, dev, log))
         out.update(bench_adjoint(hk, torch, np, dev, log))
     if not args.no_cpu:

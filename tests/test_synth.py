@@ -119,3 +119,46 @@ def test_block_mass_lists_reassemble_mass():
     Mw = np.bincount(seg, weights=bv / c[bb] ** 2, minlength=pu.nnz)
     assert np.max(np.abs(Mu - pu.M)) <= 1e-15 * np.max(pu.M) * 4
     assert np.max(np.abs(Mw - pw.M)) <= 1e-15 * np.max(pw.M) * 4
+
+
+# ------------------------------------------------------------ Q1 hexahedra
+
+def test_hex_interior_closed_form_stencils_and_invariants():
+    """Unjittered interior rows equal the Q1 tensor-product stencils (stiffness
+    8h/3, 0, -h/6, -h/12 and mass 8h^3/27, 2h^3/27, h^3/54, h^3/216 for the
+    centre, face, edge and corner neighbours); K rows sum to zero and the
+    mass sums to the volume, also on a jittered mesh."""
+    from synth import hexahedra as Q
+    h = 0.2
+    m = H.make_mesh(5, 5, 5, h)
+    VK, VM = Q.assemble_hex(m)
+    i, j, k = m.ijk()
+    interior = np.where((i > 0) & (i < 5) & (j > 0) & (j < 5) & (k > 0) & (k < 5))[0]
+    kd = {0: 8 * h / 3, 1: 0.0, 2: -h / 6, 3: -h / 12}
+    md = {0: 8 * h ** 3 / 27, 1: 2 * h ** 3 / 27, 2: h ** 3 / 54, 3: h ** 3 / 216}
+    nnzo = np.count_nonzero(Q.OFFSETS27, axis=1)
+    for r in interior:
+        assert np.allclose(VK[r], [kd[c] for c in nnzo], rtol=0, atol=1e-14)
+        assert np.allclose(VM[r], [md[c] for c in nnzo], rtol=0, atol=1e-16)
+    mj = H.make_mesh(6, 5, 4, 0.25, jitter=0.2, rng=np.random.default_rng(3))
+    VK, VM = Q.assemble_hex(mj)
+    assert np.abs(VK.sum(axis=1)).max() <= 1e-13
+    assert abs(VM.sum() - 6 * 5 * 4 * 0.25 ** 3) <= 1e-13
+
+
+def test_hex_problem_symmetric_sorted_dirichlet():
+    from synth import hexahedra as Q
+    m = H.make_mesh(5, 4, 6, 0.2, jitter=0.2, rng=np.random.default_rng(4))
+    p = Q.build_hex_problem(m)
+    A = sp.csr_matrix((p.K + 1j * p.M, p.col, p.rowptr), shape=(p.n, p.n))
+    assert (A != A.T).nnz == 0
+    lens = np.diff(p.rowptr)
+    assert lens.max() == 27
+    for r in range(p.n):
+        c = p.col[p.rowptr[r]:p.rowptr[r + 1]]
+        assert np.all(np.diff(c) > 0)
+    for r in np.where(p.dirichlet)[0]:
+        assert lens[r] == 1 and p.col[p.rowptr[r]] == r and p.K[p.rowptr[r]] == 1.0 and p.M[p.rowptr[r]] == 0.0
+    dcols = np.isin(p.col, np.where(p.dirichlet)[0])
+    rows = np.repeat(np.arange(p.n), lens)
+    assert np.all(rows[dcols] == p.col[dcols])
