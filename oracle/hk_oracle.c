@@ -367,6 +367,152 @@ done:
     return status;
 }
 
+/*
+ * Right-preconditioned BiCGStab(l) (Sleijpen and Fokkema's method; the
+ * paper's P-BiCGSTAB(l) with l = 8 in Section 4), preconditioner M = diag(A)
+ * when precond != 0, identity otherwise, on Ahat = A M^-1 with the iterate
+ * kept in x (x += M^-1 ...).  One iteration is a cycle of l BiCG steps and
+ * one minimal-residual step (2 l products with Ahat):
+ *
+ *   rho0 = -omega rho0
+ *   for j = 0 .. l-1:
+ *     rho1 = rt^H r_j,  beta = alpha rho1 / rho0,  rho0 = rho1
+ *     u_i = r_i - beta u_i (i <= j);   u_{j+1} = Ahat u_j
+ *     alpha = rho0 / (rt^H u_{j+1})
+ *     r_i = r_i - alpha u_{i+1} (i <= j);   r_{j+1} = Ahat r_j
+ *     x += alpha M^-1 u_0
+ *   MR: gamma minimises ||r_0 - sum_{j>=1} gamma_j r_j||, taken from the
+ *   normal equations Z gamma = z with Z_ij = r_i^H r_j, z_i = r_i^H r_0
+ *   (i, j = 1..l; Cholesky), then
+ *     x += sum_j gamma_j M^-1 r_{j-1},  r_0 -= sum_j gamma_j r_j,
+ *     u_0 -= sum_j gamma_j u_j,  omega = gamma_l
+ *
+ * starting from r_0 = b - A x_0, rt = r_0, u_0 = 0, rho0 = omega = 1,
+ * alpha = 0.  (For l = 1 this is BiCGStab.)  Stops when ||r_0|| <= tol ||b||,
+ * tested after every BiCG step and after the minimal-residual step (an exit
+ * inside a cycle counts the cycle).  Breakdown when rt^H r_j (OR_BD_RHO) or rt^H u_{j+1}
+ * (OR_BD_SIGMA) is exactly zero (the cycle does not count), when a Cholesky
+ * pivot of Z is not positive (OR_BD_TAU), or when omega = 0 (OR_BD_OMEGA).
+ * history (optional, maxit+1 entries) receives ||r_0|| / ||b|| per cycle.
+ */
+#define OR_MAXL 16
+int orc_bicgstab_l(int64_t n, const int32_t *rowptr, const int32_t *col, const zd *val,
+                   const zd *b, zd *x, double tol, int64_t maxit, int ell, int precond,
+                   or_info *info, double *history)
+{
+    memset(info, 0, sizeof(*info));
+    if (ell < 1 || ell > OR_MAXL) { info->status = OR_EINVAL; return OR_EINVAL; }
+    for (int64_t i = 0; i < n; ++i)
+        if (!isfinite_z(b[i]) || !isfinite_z(x[i])) { info->status = OR_NONFINITE; return OR_NONFINITE; }
+
+    zd *r[OR_MAXL + 1], *u[OR_MAXL + 1];
+    for (int j = 0; j <= ell; ++j) { r[j] = malloc(sizeof(zd) * n); u[j] = malloc(sizeof(zd) * n); }
+    zd *dinv = malloc(sizeof(zd) * n), *rt = malloc(sizeof(zd) * n), *tmp = malloc(sizeof(zd) * n);
+    int status = OR_NOT_CONVERGED, bd = OR_BD_NONE;
+    int64_t it = 0;
+    double bnorm = 0.0, rnorm = 0.0;
+
+    if (precond) {
+        if (!diag_inverse(n, rowptr, col, val, dinv)) { status = OR_EINVAL; goto done; }
+    } else {
+        for (int64_t i = 0; i < n; ++i) dinv[i] = 1.0;
+    }
+    bnorm = orc_dznrm2(n, b);
+    orc_residual(n, rowptr, col, val, b, x, r[0]);
+    for (int64_t i = 0; i < n; ++i) { rt[i] = r[0][i]; u[0][i] = 0.0; }
+    rnorm = orc_dznrm2(n, r[0]);
+    const double thr = tol * bnorm;
+    if (history) history[0] = bnorm > 0 ? rnorm / bnorm : 0.0;
+    if (rnorm <= thr) { status = OR_OK; goto done; }
+
+    zd rho0 = 1.0, alpha = 0.0, omega = 1.0;
+    for (it = 1; it <= maxit; ++it) {
+        rho0 = -omega * rho0;
+        int fail = 0;
+        for (int j = 0; j < ell && !fail; ++j) {
+            zd rho1 = orc_zdotc_v(n, rt, r[j]);
+            if (!isfinite_z(rho1)) { status = OR_NONFINITE; fail = 1; break; }
+            if (rho1 == 0.0) { status = OR_BREAKDOWN; bd = OR_BD_RHO; fail = 1; break; }
+            const zd beta = alpha * rho1 / rho0;
+            rho0 = rho1;
+            for (int i = 0; i <= j; ++i)
+                for (int64_t q = 0; q < n; ++q) u[i][q] = r[i][q] - beta * u[i][q];
+            for (int64_t q = 0; q < n; ++q) tmp[q] = dinv[q] * u[j][q];
+            orc_spmv(n, rowptr, col, val, tmp, u[j + 1]);
+            zd gam = orc_zdotc_v(n, rt, u[j + 1]);
+            if (!isfinite_z(gam)) { status = OR_NONFINITE; fail = 1; break; }
+            if (gam == 0.0) { status = OR_BREAKDOWN; bd = OR_BD_SIGMA; fail = 1; break; }
+            alpha = rho0 / gam;
+            for (int i = 0; i <= j; ++i)
+                for (int64_t q = 0; q < n; ++q) r[i][q] -= alpha * u[i + 1][q];
+            for (int64_t q = 0; q < n; ++q) tmp[q] = dinv[q] * r[j][q];
+            orc_spmv(n, rowptr, col, val, tmp, r[j + 1]);
+            for (int64_t q = 0; q < n; ++q) x[q] += alpha * (dinv[q] * u[0][q]);
+            rnorm = orc_dznrm2(n, r[0]);
+            if (rnorm <= thr) { status = OR_OK; fail = 2; }
+        }
+        if (fail == 2) { if (history) history[it] = rnorm / bnorm; break; }
+        if (fail) { it -= 1; break; }
+        /* minimal-residual step through the normal equations */
+        zd Z[OR_MAXL][OR_MAXL], z[OR_MAXL], L[OR_MAXL][OR_MAXL], g[OR_MAXL], w[OR_MAXL];
+        for (int i = 1; i <= ell; ++i) {
+            z[i - 1] = orc_zdotc_v(n, r[i], r[0]);
+            for (int j = 1; j <= ell; ++j) Z[i - 1][j - 1] = orc_zdotc_v(n, r[i], r[j]);
+        }
+        /* Z = L L^H */
+        for (int j = 0; j < ell && !fail; ++j) {
+            double d = creal(Z[j][j]);
+            for (int k = 0; k < j; ++k) d -= creal(L[j][k] * conj(L[j][k]));
+            if (!(d > 0.0)) { status = OR_BREAKDOWN; bd = OR_BD_TAU; fail = 1; break; }
+            L[j][j] = sqrt(d);
+            for (int i = j + 1; i < ell; ++i) {
+                zd sij = Z[i][j];
+                for (int k = 0; k < j; ++k) sij -= L[i][k] * conj(L[j][k]);
+                L[i][j] = sij / L[j][j];
+            }
+        }
+        if (fail) break;
+        for (int i = 0; i < ell; ++i) {          /* L w = z */
+            zd sum = z[i];
+            for (int k = 0; k < i; ++k) sum -= L[i][k] * w[k];
+            w[i] = sum / L[i][i];
+        }
+        for (int i = ell - 1; i >= 0; --i) {     /* L^H g = w */
+            zd sum = w[i];
+            for (int k = i + 1; k < ell; ++k) sum -= conj(L[k][i]) * g[k];
+            g[i] = sum / L[i][i];
+        }
+        for (int j = 1; j <= ell; ++j) {
+            const zd gj = g[j - 1];
+            for (int64_t q = 0; q < n; ++q) {
+                x[q] += gj * (dinv[q] * r[j - 1][q]);
+                r[0][q] -= gj * r[j][q];
+                u[0][q] -= gj * u[j][q];
+            }
+        }
+        omega = g[ell - 1];
+        rnorm = orc_dznrm2(n, r[0]);
+        if (history) history[it] = bnorm > 0 ? rnorm / bnorm : 0.0;
+        if (!isfinite(rnorm) || !isfinite_z(omega)) { status = OR_NONFINITE; break; }
+        if (rnorm <= thr) { status = OR_OK; break; }
+        if (omega == 0.0) { status = OR_BREAKDOWN; bd = OR_BD_OMEGA; break; }
+    }
+    if (it > maxit) it = maxit;
+
+done:
+    info->relres_rec = bnorm > 0 ? rnorm / bnorm : rnorm;
+    info->iters = it;
+    info->status = status;
+    info->breakdown = bd;
+    if (status != OR_EINVAL) {
+        orc_residual(n, rowptr, col, val, b, x, tmp);
+        info->relres_true = bnorm > 0 ? orc_dznrm2(n, tmp) / bnorm : orc_dznrm2(n, tmp);
+    }
+    for (int j = 0; j <= ell; ++j) { free(r[j]); free(u[j]); }
+    free(dinv); free(rt); free(tmp);
+    return status;
+}
+
 /* ------------------------------------------ complex-float inner BiCGStab */
 
 static void spmv_f(int64_t n, const int32_t *rowptr, const int32_t *col, const zf *val,

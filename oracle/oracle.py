@@ -63,6 +63,7 @@ def lib():
         L.orc_zcopy.argtypes = [i64, P, P]
         L.orc_bicgstab.argtypes = [i64, P, P, P, P, P, dbl, i64, i32, C.POINTER(Info), P]
         L.orc_tfqmr.argtypes = [i64, P, P, P, P, P, dbl, i64, i32, C.POINTER(Info), P]
+        L.orc_bicgstab_l.argtypes = [i64, P, P, P, P, P, dbl, i64, i32, i32, C.POINTER(Info), P]
         L.orc_bicgstab_c64.argtypes = [i64, P, P, P, P, P, C.c_float, i64, C.POINTER(Info)]
         L.orc_mixed_refine.argtypes = [i64, P, P, P, P, P, dbl, dbl, i32, i64, C.POINTER(Info),
                                        C.POINTER(C.c_int64)]
@@ -170,6 +171,22 @@ def tfqmr(rowptr, col, val, b, x0=None, tol=1e-8, maxit=400000, precond=True, hi
     hist = np.zeros(maxit + 1) if history else None
     lib().orc_tfqmr(n, _p(rowptr), _p(col), _p(val), _p(b), _p(x), float(tol), int(maxit),
                     1 if precond else 0, C.byref(info), _p(hist) if history else None)
+    d = info.as_dict()
+    if history:
+        return x, d, hist[: d["iters"] + 1]
+    return x, d
+
+
+def bicgstab_l(rowptr, col, val, b, ell=8, x0=None, tol=1e-8, maxit=400000, precond=True, history=False):
+    """Jacobi right-preconditioned BiCGStab(l); iters counts cycles of l BiCG steps."""
+    rowptr, col, val = _csr(rowptr, col, val)
+    b = np.ascontiguousarray(b, dtype=np.complex128)
+    n = b.shape[0]
+    x = np.zeros(n, dtype=np.complex128) if x0 is None else np.array(x0, dtype=np.complex128)
+    info = Info()
+    hist = np.zeros(maxit + 1) if history else None
+    lib().orc_bicgstab_l(n, _p(rowptr), _p(col), _p(val), _p(b), _p(x), float(tol), int(maxit), int(ell),
+                         1 if precond else 0, C.byref(info), _p(hist) if history else None)
     d = info.as_dict()
     if history:
         return x, d, hist[: d["iters"] + 1]

@@ -270,6 +270,118 @@ def test_tfqmr_config1_diagonal_breakdown_and_errors(oracle):
     assert info["status"] == oracle.NOT_CONVERGED and info["iters"] == 1 and np.any(x != 0)
 
 
+# ----------------------------------------------------------- BiCGStab(l)
+
+def _bicgstab_l_mgs(A, dinv, b, ell, cycles):
+    """Sleijpen-Fokkema BiCGStab(l) with the minimal-residual step by modified
+    Gram-Schmidt (their original form), right-preconditioned, dense numpy:
+    an independent route to the same iterates as the oracle's
+    normal-equations form."""
+    Ah = A * dinv[None, :]
+    r = [b.copy()] + [None] * ell
+    u = [np.zeros_like(b)] + [None] * ell
+    rt = b.copy()
+    y = np.zeros_like(b)
+    rho0, alpha, omega = 1.0 + 0j, 0j, 1.0 + 0j
+    for _ in range(cycles):
+        rho0 = -omega * rho0
+        for j in range(ell):
+            rho1 = np.vdot(rt, r[j])
+            beta = alpha * rho1 / rho0
+            rho0 = rho1
+            for i in range(j + 1):
+                u[i] = r[i] - beta * u[i]
+            u[j + 1] = Ah @ u[j]
+            alpha = rho0 / np.vdot(rt, u[j + 1])
+            for i in range(j + 1):
+                r[i] = r[i] - alpha * u[i + 1]
+            r[j + 1] = Ah @ r[j]
+            y = y + alpha * u[0]
+        tau = np.zeros((ell + 1, ell + 1), dtype=complex)
+        sigma = np.zeros(ell + 1)
+        gp = np.zeros(ell + 1, dtype=complex)
+        for j in range(1, ell + 1):
+            for i in range(1, j):
+                tau[i, j] = np.vdot(r[i], r[j]) / sigma[i]
+                r[j] = r[j] - tau[i, j] * r[i]
+            sigma[j] = np.vdot(r[j], r[j]).real
+            gp[j] = np.vdot(r[j], r[0]) / sigma[j]
+        g = np.zeros(ell + 1, dtype=complex)
+        g[ell] = gp[ell]
+        for j in range(ell - 1, 0, -1):
+            g[j] = gp[j] - sum(tau[j, i] * g[i] for i in range(j + 1, ell + 1))
+        g2 = np.zeros(ell + 1, dtype=complex)
+        for j in range(1, ell):
+            g2[j] = g[j + 1] + sum(tau[j, i] * g[i + 1] for i in range(j + 1, ell))
+        omega = g[ell]
+        y = y + g[1] * r[0]
+        r[0] = r[0] - gp[ell] * r[ell]
+        u[0] = u[0] - g[ell] * u[ell]
+        for j in range(1, ell):
+            u[0] = u[0] - g[j] * u[j]
+            y = y + g2[j] * r[j]
+            r[0] = r[0] - gp[j] * r[j]
+    return dinv * y
+
+
+@pytest.mark.parametrize("nc,seed", [(3, 3), (4, 5)])
+def test_bicgstab_l_pins(oracle, nc, seed):
+    """l = 1 reproduces BiCGStab's iterates; l = 2, 4 the iterates of the
+    Gram-Schmidt form of the method; every l reaches the LAPACK solution."""
+    p, val = tiny_problem(nc, seed=seed)
+    b = crandn(np.random.default_rng(seed), p.n)
+    b[p.dirichlet] = 0
+    # (rounding differences grow with the steps on these indefinite systems:
+    # 2e-14 after 4 iterations, 2e-10 after 6)
+    for k in (1, 2, 3, 4):
+        x1, i1 = oracle.bicgstab_l(p.rowptr, p.col, val, b, ell=1, tol=1e-15, maxit=k)
+        xb, ib = oracle.bicgstab(p.rowptr, p.col, val, b, tol=1e-15, maxit=k)
+        assert i1["iters"] == ib["iters"] == k
+        assert np.linalg.norm(x1 - xb) <= 1e-12 * np.linalg.norm(xb), k
+    Ad = dense(p, val)
+    dinv = 1.0 / np.diag(Ad)
+    for ell in (2, 4):
+        for k in (1, 2):
+            xo, io = oracle.bicgstab_l(p.rowptr, p.col, val, b, ell=ell, tol=1e-15, maxit=k)
+            assert io["iters"] == k and io["status"] == oracle.NOT_CONVERGED
+            xm = _bicgstab_l_mgs(Ad, dinv, b, ell, k)
+            assert np.linalg.norm(xo - xm) <= 1e-9 * np.linalg.norm(xm), (ell, k)
+    xs = np.linalg.solve(Ad, b)
+    for ell in (2, 4, 8):
+        x, info = oracle.bicgstab_l(p.rowptr, p.col, val, b, ell=ell, tol=1e-12)
+        assert info["status"] == 0 and info["relres_true"] <= 1e-11, (ell, info)
+        assert np.linalg.norm(x - xs) <= 1e-9 * np.linalg.norm(xs)
+
+
+def test_bicgstab_l_config1_edges_and_errors(oracle):
+    c1 = configs.config1()
+    x, info = oracle.bicgstab_l(c1["rowptr"], c1["col"], c1["val"], c1["g"], ell=8, tol=1e-8)
+    assert info["status"] == 0 and info["relres_true"] <= 1e-8
+    xb, _ = oracle.bicgstab(c1["rowptr"], c1["col"], c1["val"], c1["g"], tol=1e-12)
+    x12, i12 = oracle.bicgstab_l(c1["rowptr"], c1["col"], c1["val"], c1["g"], ell=8, tol=1e-12)
+    assert i12["status"] == 0 and np.linalg.norm(x12 - xb) <= 1e-8 * np.linalg.norm(xb)
+    n = 20
+    rng = np.random.default_rng(2)
+    d = crandn(rng, n) + 3.0
+    b = crandn(rng, n)
+    rp, cl = np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32)
+    for ell in (1, 8):
+        # D = A: the first BiCG step solves the system exactly (exit inside the cycle)
+        x, info = oracle.bicgstab_l(rp, cl, d, b, ell=ell, tol=1e-12)
+        assert info["status"] == 0 and info["iters"] == 1
+        assert np.allclose(x, b / d, rtol=1e-14, atol=0)
+    x, info = oracle.bicgstab_l(np.array([0, 2, 4], dtype=np.int32), np.array([0, 1, 0, 1], dtype=np.int32),
+                                np.array([1.0, -1.25, -1.25, 1.0], dtype=np.complex128), np.array([1.0, 2.0]),
+                                ell=4)
+    assert info["status"] == oracle.BREAKDOWN and info["breakdown"] == oracle.BD_SIGMA
+    assert info["iters"] == 0 and np.all(x == 0)
+    for bad in (0, 17):
+        assert oracle.bicgstab_l(rp, cl, d, b, ell=bad)[1]["status"] == oracle.EINVAL
+    g = c1["g"].copy()
+    g[0] = np.nan
+    assert oracle.bicgstab_l(c1["rowptr"], c1["col"], c1["val"], g)[1]["status"] == oracle.NONFINITE
+
+
 @pytest.mark.parametrize("nc,seed", [(3, 3), (4, 5)])
 def test_bicgstab_c64_matches_dense_lu_and_complex128_steps(oracle, nc, seed):
     """The complex-float solver (FP64-accumulated dots) reaches the LAPACK
