@@ -142,13 +142,15 @@ typedef struct {
   int32_t precond;       /* 0: none, 1: Jacobi (diagonal), applied on the right */
   int32_t check_every;   /* iterations enqueued between host status reads (0: automatic) */
   int32_t use_x0;        /* 0: start from x = 0 (the paper's choice), 1: from d_x */
-  int32_t method;        /* hk_method: HK_BICGSTAB (0) or HK_TFQMR (1, complex128 only) */
+  int32_t method;        /* hk_method; HK_TFQMR and HK_BICGSTAB_L are complex128 only */
   double* d_history;     /* optional device buffer of max_iter+1 doubles: ||r_k||/||b||
                             (TFQMR: the quasi-residual bound sqrt(m+1) tau / ||b||) */
+  int32_t ell;           /* HK_BICGSTAB_L: BiCG steps per cycle, 1, 2, 4 or 8 (the paper: 8) */
+  int32_t reserved;      /* must be 0 */
 } hk_solve_opts;
 
-/* Krylov method of hk_krylov_solve (Section 4 implements three). */
-typedef enum { HK_BICGSTAB = 0, HK_TFQMR = 1 } hk_method;
+/* Krylov method of hk_krylov_solve (Section 4 implements all three). */
+typedef enum { HK_BICGSTAB = 0, HK_TFQMR = 1, HK_BICGSTAB_L = 2 } hk_method;
 
 typedef struct {
   int64_t iters;         /* completed iterations (a half-step exit counts as one) */
@@ -163,9 +165,13 @@ typedef struct {
  * Preconditioned Krylov solve of A x = b (Section 4: zero initial guess,
  * residual tolerance, iteration cap; Jacobi preconditioner on the right).
  * opts->method selects P-BiCGSTAB (van der Vorst's recurrences; stops on
- * ||r|| <= tol ||b|| after a half or full step) or P-TFQMR (Freund's method
+ * ||r|| <= tol ||b|| after a half or full step), P-TFQMR (Freund's method
  * as in Saad's book; two products per iteration; stops when the
- * quasi-residual bound sqrt(m+1) tau <= tol ||b||, m the half-step).  A
+ * quasi-residual bound sqrt(m+1) tau <= tol ||b||, m the half-step) or
+ * P-BiCGSTAB(l) (Sleijpen and Fokkema's method, l = opts->ell BiCG steps and
+ * one minimal-residual step per iteration, the MR step through the normal
+ * equations of the Gram matrix of r_1..r_l; stops on ||r|| <= tol ||b||
+ * after any BiCG step or MR step; info->iters counts cycles).  A
  * complex128 matrix gives a complex128 solve; a complex64 matrix (BiCGStab
  * only) a complex64 solve whose vectors and products are complex64 and whose
  * dots and scalars are double (b and x then complex64).  Scalars stay in

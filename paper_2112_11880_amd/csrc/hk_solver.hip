@@ -65,6 +65,8 @@ struct SolveState {
   // by the next kernel that reads d) and the d-update coefficients
   double tq_theta, tq_tau;
   double2 tq_eta1, tq_eta2, tq_coef1, tq_coef2;
+  // BiCGStab(l): the minimal-residual coefficients gamma_1..gamma_l
+  double2 bl_gamma[8];
 };
 
 // Most workgroups of a fused SpMV+dot launch (one partial-sum slot each).
@@ -1271,6 +1273,486 @@ static int tfqmr(hk_csr_s* A, const double2* val, const double2* b, double2* x, 
   return finish_solve<R>(A, val, b, x, wk, info, s);
 }
 
+// ============================================================ BiCGStab(l)
+//
+// Right-preconditioned BiCGStab(l) (Section 4: P-BiCGSTAB(l), l = 8 in the
+// paper; Sleijpen and Fokkema's method) on Ahat = A D^-1 for y, x = D^-1 y.
+// A cycle (one iteration) is l BiCG steps and a minimal-residual step:
+//   step j: beta (from rho) -> u_i = r_i - beta u_i (i <= j)      [k_bl_u]
+//           u_{j+1} = Ahat u_j, rt^H u_{j+1} -> alpha             [fused]
+//           r_i -= alpha u_{i+1} (i <= j), y += alpha u_0, ||r_0||^2
+//             -> stop test                                         [k_bl_r]
+//           r_{j+1} = Ahat r_j, rt^H r_{j+1} -> rho, beta          [fused]
+//   MR:     Z_ij = r_i^H r_j, z_i = r_i^H r_0 (i, j = 1..l) in one pass
+//             -> gamma = Z^-1 z by Cholesky (one thread)           [k_bl_gram]
+//           y += sum gamma_j r_{j-1}, r_0 -= sum gamma_j r_j,
+//           u_0 -= sum gamma_j u_j; ||r_0||^2, rt^H r_0
+//             -> stop test, omega = gamma_l, next cycle's rho, beta [k_bl_mr]
+// The minimal-residual coefficients come from the normal equations of the
+// Gram matrix (one multi-vector reduction on the GPU) rather than modified
+// Gram-Schmidt (l(l+1)/2 dependent reductions); the oracle uses the same
+// form and its pins tie it to the Gram-Schmidt form.
+
+constexpr int kMaxEll = 8;
+template <class R> struct BlVecs {
+  cplx<R>* r[kMaxEll + 1];
+  cplx<R>* u[kMaxEll + 1];
+};
+
+template <int ELL> struct BlNV { static constexpr int v = 2 * (ELL + ELL * (ELL + 1) / 2); };
+
+template <class R> struct BlWork {
+  using V = cplx<R>;
+  V *y, *rt, *dinv, *ahat;
+  BlVecs<R> vec;
+  double* partials;
+  SolveState* st;
+  int* flag;
+};
+
+template <class R> static size_t bl_partial_doubles(int64_t n) {
+  const int64_t gv = ew_blocks(n);
+  const int64_t a = 4 * partial_slots(n), b = (int64_t)BlNV<kMaxEll>::v * gv;
+  return (size_t)(a > b ? a : b);
+}
+
+template <class R> static size_t bl_work_bytes(int64_t n, int64_t nnz, int ell) {
+  using V = cplx<R>;
+  return (size_t)(3 + 2 * (ell + 1)) * align_up(sizeof(V) * n) + align_up(sizeof(V) * (nnz > 0 ? nnz : 1)) +
+         align_up(sizeof(double) * bl_partial_doubles<R>(n)) + align_up(sizeof(SolveState)) + align_up(64);
+}
+
+template <class R> static BlWork<R> bl_carve(void* base, int64_t n, int64_t nnz, int ell) {
+  using V = cplx<R>;
+  char* q = static_cast<char*>(base);
+  auto take = [&](size_t bytes) { char* r = q; q += align_up(bytes); return r; };
+  BlWork<R> w{};
+  w.y = (V*)take(sizeof(V) * n);
+  w.rt = (V*)take(sizeof(V) * n);
+  w.dinv = (V*)take(sizeof(V) * n);
+  for (int j = 0; j <= ell; ++j) {
+    w.vec.r[j] = (V*)take(sizeof(V) * n);
+    w.vec.u[j] = (V*)take(sizeof(V) * n);
+  }
+  w.ahat = (V*)take(sizeof(V) * (nnz > 0 ? nnz : 1));
+  w.partials = (double*)take(sizeof(double) * bl_partial_doubles<R>(n));
+  w.st = (SolveState*)take(sizeof(SolveState));
+  w.flag = (int*)take(64);
+  return w;
+}
+
+// u_i = r_i - beta u_i, i = 0..j
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_bl_u(int n, const SolveState* __restrict__ st, int j, BlVecs<R> v) {
+  using V = cplx<R>;
+  if (st->status != S_RUN) return;
+  const V beta = vscal<V>(st->beta);
+  const int base = blockIdx.x * (kBlock * kEw) + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < kEw; ++k) {
+    const int q = base + k * kBlock;
+    if (q >= n) break;
+    for (int i = 0; i <= j; ++i) v.u[i][q] = csub(v.r[i][q], cmul(beta, v.u[i][q]));
+  }
+}
+
+// r_i -= alpha u_{i+1} (i = 0..j); y += alpha u_0; partials ||r_0||^2
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_bl_r(int n, const SolveState* __restrict__ st, int j, BlVecs<R> v,
+                                                 cplx<R>* __restrict__ y, double* partials) {
+  using V = cplx<R>;
+  __shared__ double lds[kBlock / kWave];
+  if (st->status != S_RUN) return;
+  const V alpha = vscal<V>(st->alpha);
+  double acc[1] = {0};
+  const int base = blockIdx.x * (kBlock * kEw) + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < kEw; ++k) {
+    const int q = base + k * kBlock;
+    if (q >= n) break;
+    for (int i = 0; i <= j; ++i) v.r[i][q] = csub(v.r[i][q], cmul(alpha, v.u[i + 1][q]));
+    y[q] = cfma(alpha, v.u[0][q], y[q]);
+    acc[0] += nrm2d(v.r[0][q]);
+  }
+  block_sum<1>(acc, lds);
+  store_block_partials<1>(acc, partials);
+}
+
+// Gram partials: z_i = r_i^H r_0 (i = 1..ELL), then Z_ij = r_i^H r_j
+// (1 <= i <= j <= ELL), as (re, im) pairs.
+template <class R, int ELL>
+__global__ __launch_bounds__(kBlock) void k_bl_gram(int n, const SolveState* __restrict__ st, BlVecs<R> v,
+                                                    double* partials) {
+  using V = cplx<R>;
+  constexpr int NV = BlNV<ELL>::v;
+  __shared__ double lds[NV * (kBlock / kWave)];
+  if (st->status != S_RUN) return;
+  double acc[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) acc[k] = 0;
+  const int base = blockIdx.x * (kBlock * kEw) + threadIdx.x;
+  for (int k = 0; k < kEw; ++k) {
+    const int q = base + k * kBlock;
+    if (q >= n) break;
+    V x[ELL + 1];
+#pragma unroll
+    for (int i = 0; i <= ELL; ++i) x[i] = v.r[i][q];
+    int m = 0;
+#pragma unroll
+    for (int i = 1; i <= ELL; ++i, m += 2) dotc_acc(x[i], x[0], acc[m], acc[m + 1]);
+#pragma unroll
+    for (int i = 1; i <= ELL; ++i)
+#pragma unroll
+      for (int jj = i; jj <= ELL; ++jj, m += 2) dotc_acc(x[i], x[jj], acc[m], acc[m + 1]);
+  }
+  block_sum<NV>(acc, lds);
+  store_block_partials<NV>(acc, partials);
+}
+
+// y += sum gamma_j r_{j-1}; r_0 -= sum gamma_j r_j; u_0 -= sum gamma_j u_j;
+// partials ||r_0||^2, rt^H r_0
+template <class R, int ELL>
+__global__ __launch_bounds__(kBlock) void k_bl_mr(int n, const SolveState* __restrict__ st, BlVecs<R> v,
+                                                  cplx<R>* __restrict__ y, const cplx<R>* __restrict__ rt,
+                                                  double* partials) {
+  using V = cplx<R>;
+  __shared__ double lds[3 * (kBlock / kWave)];
+  if (st->status != S_RUN) return;
+  V g[ELL];
+#pragma unroll
+  for (int j = 0; j < ELL; ++j) g[j] = vscal<V>(st->bl_gamma[j]);
+  double acc[3] = {0, 0, 0};
+  const int base = blockIdx.x * (kBlock * kEw) + threadIdx.x;
+  for (int k = 0; k < kEw; ++k) {
+    const int q = base + k * kBlock;
+    if (q >= n) break;
+    V yq = y[q], r0 = v.r[0][q], u0 = v.u[0][q];
+    V rprev = r0;
+#pragma unroll
+    for (int j = 1; j <= ELL; ++j) {
+      const V rj = v.r[j][q];
+      yq = cfma(g[j - 1], rprev, yq);
+      r0 = csub(r0, cmul(g[j - 1], rj));
+      u0 = csub(u0, cmul(g[j - 1], v.u[j][q]));
+      rprev = rj;
+    }
+    y[q] = yq;
+    v.r[0][q] = r0;
+    v.u[0][q] = u0;
+    acc[0] += nrm2d(r0);
+    dotc_acc(rt[q], r0, acc[1], acc[2]);
+  }
+  block_sum<3>(acc, lds);
+  store_block_partials<3>(acc, partials);
+}
+
+// out = Ahat x (fused product); partials rt^H out
+template <class R> struct EpiStoreDot {
+  using V = cplx<R>;
+  static constexpr int NV = 2;
+  struct Pre { V rt; };
+  struct Sc {};
+  V* out;
+  const V* rt;
+  __device__ static bool active(const SolveState* st) { return st->status == S_RUN; }
+  __device__ static Sc scalars(const SolveState*) { return Sc{}; }
+  __device__ Pre load(int r) const { return Pre{rt[r]}; }
+  __device__ void apply(int r, const Pre& q, V acc, const Sc&, double (&part)[NV]) const {
+    out[r] = acc;
+    dotc_acc(q.rt, acc, part[0], part[1]);
+  }
+};
+
+enum : int { BL_INIT = 0, BL_ALPHA = 1, BL_R = 2, BL_RHO = 3, BL_MR = 5 };
+template <int F, int ELL> struct BlFinNV { static constexpr int v = 2; };
+template <int ELL> struct BlFinNV<BL_R, ELL> { static constexpr int v = 1; };
+template <int ELL> struct BlFinNV<BL_MR, ELL> { static constexpr int v = 3; };
+
+// Start of a BiCG sequence with rho1 = rt^H r_0: rho0 = -omega rho0 at the
+// cycle start, then beta = alpha rho1 / rho0, rho0 = rho1.  (rho0 is kept in
+// rho, rho1 arrives in tot.)
+__device__ __forceinline__ void bl_cycle_start(SolveState* st, double2 rho1) {
+  const double2 rho0 = cmul(cmake<double2>(-1, 0), cmul(st->omega, st->rho));
+  if (!cfinite(rho1)) {
+    st->status = HK_NONFINITE;
+    st->iters_done = st->iter - 1;
+  } else if (rho1.x == 0 && rho1.y == 0) {
+    st->status = HK_BREAKDOWN;
+    st->bd = HK_BD_RHO;
+    st->iters_done = st->iter - 1;
+  } else {
+    st->beta = cdiv(cmul(st->alpha, rho1), rho0);
+    st->rho = rho1;
+  }
+}
+
+template <int F, int ELL>
+__global__ __launch_bounds__(kFinBlock) void k_bl_fin(SolveState* st, const double* partials, int nb, double tol,
+                                                      long long maxit) {
+  using V = double2;
+  constexpr int NV = BlFinNV<F, ELL>::v;
+  __shared__ double lds[NV * (kFinBlock / kWave)];
+  if (F != BL_INIT && st->status != S_RUN) return;
+  double tot[NV];
+  final_sum<NV>(partials, nb, tot, lds);
+  if (threadIdx.x != 0) return;
+  const long long k = st->iter;
+  if (F == BL_INIT) {
+    st->bb = tot[0];
+    st->rr = tot[1];
+    st->theta2 = tol * tol * tot[0];
+    st->alpha = czero<V>();
+    st->omega = cmake<V>(1, 0);
+    st->rho = cmake<V>(1, 0);
+    st->iter = 1;
+    st->maxit = maxit;
+    st->iters_done = 0;
+    st->bd = HK_BD_NONE;
+    if (st->history) st->history[0] = tot[0] > 0 ? sqrt(tot[1] / tot[0]) : 0.0;
+    if (!isfinite(tot[0]) || !isfinite(tot[1])) st->status = HK_NONFINITE;
+    else if (tot[1] <= st->theta2) st->status = HK_OK;
+    else if (maxit <= 0) st->status = HK_NOT_CONVERGED;
+    else { st->status = S_RUN; bl_cycle_start(st, cmake<V>(tot[1], 0)); }
+  } else if (F == BL_ALPHA) {
+    const V gam = cmake<V>(tot[0], tot[1]);
+    if (!cfinite(gam)) { st->status = HK_NONFINITE; st->iters_done = k - 1; }
+    else if (gam.x == 0 && gam.y == 0) { st->status = HK_BREAKDOWN; st->bd = HK_BD_SIGMA; st->iters_done = k - 1; }
+    else st->alpha = cdiv(st->rho, gam);
+  } else if (F == BL_R) {
+    st->rr = tot[0];
+    if (!isfinite(tot[0])) { st->status = HK_NONFINITE; st->iters_done = k; }
+    else if (tot[0] <= st->theta2) {
+      st->status = HK_OK;
+      st->iters_done = k;
+      if (st->history) st->history[k] = st->bb > 0 ? sqrt(tot[0] / st->bb) : 0.0;
+    }
+  } else if (F == BL_RHO) {
+    const V rho1 = cmake<V>(tot[0], tot[1]);
+    if (!cfinite(rho1)) { st->status = HK_NONFINITE; st->iters_done = k - 1; }
+    else if (rho1.x == 0 && rho1.y == 0) { st->status = HK_BREAKDOWN; st->bd = HK_BD_RHO; st->iters_done = k - 1; }
+    else { st->beta = cdiv(cmul(st->alpha, rho1), st->rho); st->rho = rho1; }
+  } else {  // BL_MR: end of a cycle
+    st->rr = tot[0];
+    st->iters_done = k;
+    if (st->history) st->history[k] = st->bb > 0 ? sqrt(tot[0] / st->bb) : 0.0;
+    const V om = st->omega;
+    if (!isfinite(tot[0])) st->status = HK_NONFINITE;
+    else if (tot[0] <= st->theta2) st->status = HK_OK;
+    else if (om.x == 0 && om.y == 0) { st->status = HK_BREAKDOWN; st->bd = HK_BD_OMEGA; }
+    else if (k >= st->maxit) st->status = HK_NOT_CONVERGED;
+    else { st->iter = k + 1; bl_cycle_start(st, cmake<V>(tot[1], tot[2])); }
+  }
+}
+
+// Finalize of the Gram partials (NV = l(l+3) sums): wave w sums components
+// w, w+16, ... over the nb partials (lanes stride the partials, then a fixed
+// butterfly), into LDS; thread 0 then solves Z gamma = z by Cholesky.
+template <int ELL>
+__global__ __launch_bounds__(kFinBlock) void k_bl_fin_gram(SolveState* st, const double* partials, int nb) {
+  using V = double2;
+  constexpr int NV = BlNV<ELL>::v;
+  constexpr int W = kFinBlock / kWave;
+  __shared__ double tot[NV];
+  if (st->status != S_RUN) return;
+  const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+  for (int c = wv; c < NV; c += W) {
+    double sacc = 0;
+    for (int j = lane; j < nb; j += kWave) sacc += partials[(size_t)c * nb + j];
+    sacc = wave_sum(sacc);
+    if (lane == 0) tot[c] = sacc;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  const long long k = st->iter;
+  {
+    // Z gamma = z by Cholesky, Z = L L^H (Hermitian positive definite)
+    V z[ELL], Z[ELL][ELL], L[ELL][ELL], w[ELL], g[ELL];
+    int m = 0;
+    for (int i = 0; i < ELL; ++i, m += 2) z[i] = cmake<V>(tot[m], tot[m + 1]);
+    for (int i = 0; i < ELL; ++i)
+      for (int j = i; j < ELL; ++j, m += 2) {
+        Z[i][j] = cmake<V>(tot[m], tot[m + 1]);
+        Z[j][i] = cconj(Z[i][j]);
+      }
+    for (int j = 0; j < ELL; ++j) {
+      double d = Z[j][j].x;
+      for (int q = 0; q < j; ++q) d -= cabs2(L[j][q]);
+      if (!(d > 0.0)) { st->status = HK_BREAKDOWN; st->bd = HK_BD_TAU; st->iters_done = k; return; }
+      const double ljj = sqrt(d);
+      L[j][j] = cmake<V>(ljj, 0);
+      for (int i = j + 1; i < ELL; ++i) {
+        V sij = Z[i][j];
+        for (int q = 0; q < j; ++q) sij = csub(sij, cmul(L[i][q], cconj(L[j][q])));
+        L[i][j] = cmake<V>(sij.x / ljj, sij.y / ljj);
+      }
+    }
+    for (int i = 0; i < ELL; ++i) {
+      V sum = z[i];
+      for (int q = 0; q < i; ++q) sum = csub(sum, cmul(L[i][q], w[q]));
+      w[i] = cmake<V>(sum.x / L[i][i].x, sum.y / L[i][i].x);
+    }
+    for (int i = ELL - 1; i >= 0; --i) {
+      V sum = w[i];
+      for (int q = i + 1; q < ELL; ++q) sum = csub(sum, cmul(cconj(L[q][i]), g[q]));
+      g[i] = cmake<V>(sum.x / L[i][i].x, sum.y / L[i][i].x);
+    }
+    for (int i = 0; i < ELL; ++i) st->bl_gamma[i] = g[i];
+    st->omega = g[ELL - 1];
+    if (!cfinite(st->omega)) { st->status = HK_NONFINITE; st->iters_done = k; }
+  }
+}
+
+template <int F, int ELL>
+static hipError_t launch_bl_fin(SolveState* st, const double* partials, int nb, double tol, long long maxit,
+                                hipStream_t s) {
+  hipLaunchKernelGGL((k_bl_fin<F, ELL>), dim3(1), dim3(kFinBlock), 0, s, st, partials, nb, tol, maxit);
+  return hipGetLastError();
+}
+
+// Whole BiCGStab(ELL) solve (complex128), the same contract as bicgstab<R>.
+template <int ELL>
+static int bicgstab_l(hk_csr_s* A, const double2* val, const double2* b, double2* x, const hk_solve_opts& o,
+                      void* wsbase, hk_solve_info* info, hipStream_t s) {
+  using R = double;
+  using V = double2;
+  const int n = (int)A->n;
+  const BlWork<R> wk = bl_carve<R>(wsbase, A->n, A->nnz, ELL);
+  const dim3 ew((unsigned)((n + kBlock - 1) / kBlock));
+  const int gv = ew_blocks(n);
+
+  HK_HIP(hipMemsetAsync(wk.flag, 0, sizeof(int), s));
+  hipLaunchKernelGGL(k_diag_inv<V>, ew, dim3(kBlock), 0, s, n, A->rowptr, A->col, val, wk.dinv,
+                     o.precond ? 1 : 0, wk.flag);
+  HK_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_scale_cols<V>, ew, dim3(kBlock), 0, s, n, A->rowptr, A->col, val, wk.dinv, wk.ahat);
+  HK_CHECK_LAUNCH();
+  if (o.use_x0) {
+    hk_csr_s tmp = *A;
+    tmp.val = val;
+    int rc = spmv_dispatch(&tmp, x, wk.vec.r[0], b, nullptr, nullptr, 1, s);
+    if (rc != HK_OK) return rc;
+  }
+  SpmvPlan dp = A->plan;
+  dp.nw = 0;
+  if (A->plan.tuned) {
+    SpmvPlan& cached = A->dot_plan[0];
+    if (!cached.tuned) {
+      // the workspace vectors serve as tuning operands before the solve starts
+      Work<R> tv{};
+      tv.ahat = wk.ahat;
+      tv.p = wk.vec.r[1];
+      tv.v = wk.vec.u[1];
+      tv.rh = wk.rt;
+      tv.partials = wk.partials;
+      tv.st = wk.st;
+      int rc = tune_dot<R>(A, tv, &cached, s);
+      if (rc != HK_OK) return rc;
+    }
+    dp = cached;
+  }
+  const int gs = dot_grid(A, dp);
+  SolveState init{};
+  init.history = o.d_history;
+  init.status = S_RUN;
+  HK_HIP(hipMemcpyAsync(wk.st, &init, sizeof(init), hipMemcpyHostToDevice, s));
+  // r_0 = b - A x0, rt = r_0, y = x0 / dinv or 0, u_0 = 0
+  hipLaunchKernelGGL(k_init<R>, dim3(gv), dim3(kBlock), 0, s, n, o.use_x0 ? 1 : 0, b, x, wk.dinv, wk.vec.r[0],
+                     wk.rt, wk.vec.u[1], wk.y, wk.vec.u[0], wk.partials);
+  HK_CHECK_LAUNCH();
+  HK_HIP((launch_bl_fin<BL_INIT, ELL>(wk.st, wk.partials, gv, o.tol, (long long)o.max_iter, s)));
+  int hflag = 0;
+  HK_HIP(hipMemcpyAsync(&hflag, wk.flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  HK_HIP(hipStreamSynchronize(s));
+  if (hflag) HK_FAIL(HK_EINVAL, "krylov solve: zero diagonal entry (Jacobi undefined)");
+
+  const int m = o.check_every > 0 ? o.check_every : std::max(1, (n < 200000 ? 64 : 16) / ELL);
+  int* pin = A->pinned;
+  hipEvent_t ev[2];
+  HK_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+  HK_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+  int rc = HK_OK;
+  long long enq = 0;
+  int kk = 0;
+  const size_t status_off = offsetof(SolveState, status);
+  for (;;) {
+    for (int c = 0; c < m && rc == HK_OK; ++c) {
+      hipError_t e = hipSuccess;
+      for (int j = 0; j < ELL && e == hipSuccess; ++j) {
+        hipLaunchKernelGGL(k_bl_u<R>, dim3(gv), dim3(kBlock), 0, s, n, wk.st, j, wk.vec);
+        e = hipGetLastError();
+        if (e == hipSuccess) {
+          EpiStoreDot<R> eu{wk.vec.u[j + 1], wk.rt};
+          e = launch_fused(A, dp, wk.ahat, wk.vec.u[j], eu, wk.st, wk.partials, s);
+        }
+        if (e == hipSuccess) e = launch_bl_fin<BL_ALPHA, ELL>(wk.st, wk.partials, gs, 0, 0, s);
+        if (e == hipSuccess) {
+          hipLaunchKernelGGL(k_bl_r<R>, dim3(gv), dim3(kBlock), 0, s, n, wk.st, j, wk.vec, wk.y, wk.partials);
+          e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = launch_bl_fin<BL_R, ELL>(wk.st, wk.partials, gv, 0, 0, s);
+        if (e == hipSuccess) {
+          EpiStoreDot<R> er{wk.vec.r[j + 1], wk.rt};
+          e = launch_fused(A, dp, wk.ahat, wk.vec.r[j], er, wk.st, wk.partials, s);
+        }
+        if (e == hipSuccess && j + 1 < ELL) e = launch_bl_fin<BL_RHO, ELL>(wk.st, wk.partials, gs, 0, 0, s);
+      }
+      if (e == hipSuccess) {
+        hipLaunchKernelGGL((k_bl_gram<R, ELL>), dim3(gv), dim3(kBlock), 0, s, n, wk.st, wk.vec, wk.partials);
+        e = hipGetLastError();
+      }
+      if (e == hipSuccess) {
+        hipLaunchKernelGGL((k_bl_fin_gram<ELL>), dim3(1), dim3(kFinBlock), 0, s, wk.st, wk.partials, gv);
+        e = hipGetLastError();
+      }
+      if (e == hipSuccess) {
+        hipLaunchKernelGGL((k_bl_mr<R, ELL>), dim3(gv), dim3(kBlock), 0, s, n, wk.st, wk.vec, wk.y, wk.rt,
+                           wk.partials);
+        e = hipGetLastError();
+      }
+      if (e == hipSuccess) e = launch_bl_fin<BL_MR, ELL>(wk.st, wk.partials, gv, 0, 0, s);
+      if (e != hipSuccess) {
+        set_error_text("krylov solve: launch failed: %s", hipGetErrorString(e));
+        rc = HK_EHIP;
+      }
+    }
+    if (rc != HK_OK) break;
+    enq += m;
+    hipError_t e = hipMemcpyAsync(&pin[kk & 1], (char*)wk.st + status_off, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipEventRecord(ev[kk & 1], s);
+    if (e == hipSuccess && kk > 0) e = hipEventSynchronize(ev[(kk - 1) & 1]);
+    if (e != hipSuccess) {
+      set_error_text("krylov solve: %s", hipGetErrorString(e));
+      rc = HK_EHIP;
+      break;
+    }
+    if (kk > 0 && pin[(kk - 1) & 1] < S_RUN) break;
+    if (enq >= o.max_iter) break;
+    ++kk;
+  }
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
+  if (rc != HK_OK) return rc;
+  // the common ending (x = D^-1 y, true residual, info) through a Work view
+  Work<R> view{};
+  view.y = wk.y;
+  view.dinv = wk.dinv;
+  view.t = wk.vec.u[1];
+  view.partials = wk.partials;
+  view.st = wk.st;
+  return finish_solve<R>(A, val, b, x, view, info, s);
+}
+
+static int bicgstab_l_dispatch(hk_csr_s* A, int ell, const double2* val, const double2* b, double2* x,
+                               const hk_solve_opts& o, void* ws, hk_solve_info* info, hipStream_t s) {
+  switch (ell) {
+    case 1: return bicgstab_l<1>(A, val, b, x, o, ws, info, s);
+    case 2: return bicgstab_l<2>(A, val, b, x, o, ws, info, s);
+    case 4: return bicgstab_l<4>(A, val, b, x, o, ws, info, s);
+    case 8: return bicgstab_l<8>(A, val, b, x, o, ws, info, s);
+    default: HK_FAIL(HK_EINVAL, "hk_krylov_solve: BiCGStab(l) needs l in {1, 2, 4, 8} (got %d)", ell);
+  }
+}
+
 static int ensure_pinned(hk_csr_s* A) {
   if (A->pinned) return HK_OK;
   HK_HIP(hipHostMalloc((void**)&A->pinned, 64, hipHostMallocDefault));
@@ -1281,8 +1763,10 @@ static int check_opts(const hk_solve_opts* o, const char* who) {
   if (!o) HK_FAIL(HK_EINVAL, "%s: opts is NULL", who);
   if (!(o->tol >= 0) || o->max_iter < 0 || o->check_every < 0)
     HK_FAIL(HK_EINVAL, "%s: bad options (tol=%g max_iter=%lld)", who, o->tol, (long long)o->max_iter);
-  if (o->method != HK_BICGSTAB && o->method != HK_TFQMR)
+  if (o->method != HK_BICGSTAB && o->method != HK_TFQMR && o->method != HK_BICGSTAB_L)
     HK_FAIL(HK_EINVAL, "%s: unknown method %d", who, (int)o->method);
+  if (o->method == HK_BICGSTAB_L && o->ell != 1 && o->ell != 2 && o->ell != 4 && o->ell != 8)
+    HK_FAIL(HK_EINVAL, "%s: BiCGStab(l) needs l in {1, 2, 4, 8} (got %d)", who, (int)o->ell);
   return HK_OK;
 }
 
@@ -1305,9 +1789,14 @@ extern "C" int hk_krylov_solve(hk_csr A, const void* d_b, void* d_x, const hk_so
     rc = bicgstab<float>(A, (const float2*)A->val, (const float2*)d_b, (float2*)d_x, *opts, A->ws32,
                          info, s);
   } else {
-    rc = ensure_ws(&A->ws, &A->ws_bytes, work_bytes<double>(A->n, A->nnz), s);
+    const size_t need = opts->method == HK_BICGSTAB_L ? bl_work_bytes<double>(A->n, A->nnz, opts->ell)
+                                                      : work_bytes<double>(A->n, A->nnz);
+    rc = ensure_ws(&A->ws, &A->ws_bytes, need, s);
     if (rc != HK_OK) return rc;
-    if (opts->method == HK_TFQMR)
+    if (opts->method == HK_BICGSTAB_L)
+      rc = bicgstab_l_dispatch(A, opts->ell, (const double2*)A->val, (const double2*)d_b, (double2*)d_x, *opts,
+                               A->ws, info, s);
+    else if (opts->method == HK_TFQMR)
       rc = tfqmr(A, (const double2*)A->val, (const double2*)d_b, (double2*)d_x, *opts, A->ws, info, s);
     else
       rc = bicgstab<double>(A, (const double2*)A->val, (const double2*)d_b, (double2*)d_x, *opts, A->ws,

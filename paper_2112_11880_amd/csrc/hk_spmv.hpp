@@ -163,8 +163,9 @@ __device__ __forceinline__ int tile_of(int b, int ntiles) {
 // Row-block launch shapes: plan L = kRowBlockL selects the scheme and plan U
 // the rows per wave.  Workgroups are kRbWaves waves (128 threads).  Entries
 // per lane per pass fill 8 KB of LDS per wave: 8 complex128 or 16 complex64
-// products per lane (half that for 16-row blocks), so each wave keeps the
-// same bytes in flight in both precisions.  On the 1.8M-row system, 32 rows
+// products per lane, so each wave keeps the same bytes in flight in both
+// precisions, and a 16-row block of 27-entry rows (Q1 hexahedra) takes one
+// pass.  On the 1.8M-row system, 32 rows
 // per wave in two-wave workgroups measured 106 us per complex128 product,
 // against 109-110 us for four or eight waves and 110.6 us for 64 rows per
 // wave with 4 waves; 16 complex128 entries per lane (16 KB of LDS per wave)
@@ -173,7 +174,7 @@ constexpr int kRowBlockL = 64;
 constexpr int kRbWaves = 2;
 constexpr int kRbThreads = kRbWaves * kWave;
 template <int R, class V> struct RbCh {
-  static constexpr int v = (8192 / (kWave * (int)sizeof(V))) / (R == 16 ? 2 : 1);
+  static constexpr int v = 8192 / (kWave * (int)sizeof(V));
 };
 
 // Tiles are dealt to workgroups in launch order with a grid stride: the

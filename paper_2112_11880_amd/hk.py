@@ -32,7 +32,7 @@ class HKError(RuntimeError):
 class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int64), ("precond", C.c_int32),
                 ("check_every", C.c_int32), ("use_x0", C.c_int32), ("method", C.c_int32),
-                ("d_history", C.c_void_p)]
+                ("d_history", C.c_void_p), ("ell", C.c_int32), ("reserved", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -238,14 +238,15 @@ def zconj(x, y=None):
     return y
 
 
-METHODS = {"bicgstab": 0, "tfqmr": 1}
+METHODS = {"bicgstab": 0, "tfqmr": 1, "bicgstab_l": 2}
 
 
-def _opts(tol, max_iter, precond, check_every, use_x0, history, method="bicgstab"):
+def _opts(tol, max_iter, precond, check_every, use_x0, history, method="bicgstab", ell=8):
     if method not in METHODS:
         raise HKError(HK_EINVAL, f"unknown method {method!r}; one of {sorted(METHODS)}")
     o = SolveOpts()
     o.method = METHODS[method]
+    o.ell = int(ell)
     o.tol = float(tol)
     o.max_iter = int(max_iter)
     o.precond = 1 if precond else 0
@@ -256,15 +257,16 @@ def _opts(tol, max_iter, precond, check_every, use_x0, history, method="bicgstab
 
 
 def krylov_solve(A: CSR, b, x=None, tol=1e-8, max_iter=400000, precond=True, check_every=0,
-                 history=False, method="bicgstab"):
-    """Jacobi right-preconditioned BiCGStab (or TFQMR, complex128) in A's precision;
-    returns (x, info dict[, history])."""
+                 history=False, method="bicgstab", ell=8):
+    """Jacobi right-preconditioned BiCGStab, TFQMR or BiCGStab(ell) (the last two
+    complex128) in A's precision; returns (x, info dict[, history]).  For
+    BiCGStab(ell), iters counts cycles of ell BiCG steps."""
     _cvec(b, A.dtype, name="b")
     use_x0 = x is not None
     x = torch.zeros_like(b) if x is None else _cvec(x, A.dtype, name="x")
     hist = torch.zeros(int(max_iter) + 1, dtype=torch.float64, device=b.device) if history else None
     info = SolveInfo()
-    o = _opts(tol, max_iter, precond, check_every, use_x0, hist, method)
+    o = _opts(tol, max_iter, precond, check_every, use_x0, hist, method, ell)
     _check(load().hk_krylov_solve(A.h, _ptr(b), _ptr(x), C.byref(o), C.byref(info), _stream()),
            allow_positive=True)
     d = info.as_dict()
