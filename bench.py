@@ -8,9 +8,11 @@ nonzeros, complex128 CSR, Jacobi BiCGStab to a relative residual of 1e-8.
 One step = one pass over the hot path on that system: R back-to-back CSR
 products (timed with HIP events on the launch stream), a zdotc and a
 dznrm2, then one full Jacobi-BiCGStab solve to 1e-8 from x = 0.
-`value` is the CSR product's achieved algorithmic bandwidth (GB/s):
-20 B per nonzero (int32 col + complex128 value) + 36 B per row (int32
-rowptr + complex128 x and y) divided by the mean kernel time.
+`value` is the CSR product's achieved algorithmic bandwidth (GB/s): the
+bytes of the format the kernel reads -- 18 B per nonzero (16-bit column
+offset + complex128 value; 20 B with int32 columns) + 36 B per row (int32
+rowptr + complex128 x and y) -- divided by the mean kernel time.  The same
+product reading the int32 column indices is timed beside it.
 After the timed steps (untimed for ms_per_step): the mixed-precision
 refinement on the same matrix (complex64 inner to 1e-4, complex128 outer to
 1e-10) and, unless --no-cpu, the CPU oracle's CSR product on the same matrix
@@ -35,8 +37,8 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def spmv_bytes(n, nnz):
-    return 4 * (n + 1) + 20 * nnz + 32 * n
+def spmv_bytes(n, nnz, col_bytes=4):
+    return 4 * (n + 1) + (16 + col_bytes) * nnz + 32 * n
 
 
 # rocprofv3 counter summary of the CSR kernel on this workload (committed text)
@@ -52,12 +54,13 @@ def spmv_source_digest():
     return h.hexdigest()[:16]
 
 
-def pmc_traffic(plan):
-    """HBM bytes per launch of the CSR kernel in launch shape `plan`, from the
-    FETCH_SIZE / WRITE_SIZE counters in the committed profile summary, each
-    scaled by the factor a plain copy kernel of known size gives for that
-    counter.  None when there is no summary line for this launch shape or when
-    the kernel sources changed after the counters were taken."""
+def pmc_traffic(plan, col_bytes):
+    """HBM bytes per launch of the CSR kernel in launch shape `plan` reading
+    `col_bytes`-byte column entries, from the FETCH_SIZE / WRITE_SIZE counters
+    in the committed profile summary, each scaled by the factor a plain copy
+    kernel of known size gives for that counter.  None when there is no
+    summary line for this launch shape and column stream or when the kernel
+    sources changed after the counters were taken."""
     try:
         with open(PMC_SUMMARY) as fh:
             text = fh.read()
@@ -65,9 +68,9 @@ def pmc_traffic(plan):
         return None
     key = f"{plan['lanes_per_row']},{plan['rows_per_group']},{plan['grid']}"
     digest = spmv_source_digest()
-    for m in re.finditer(r"pmc-traffic plan=(\S+) src=(\S+) bytes_per_launch=(\d+)", text):
-        if m.group(1) == key and m.group(2) == digest:
-            return int(m.group(3))
+    for m in re.finditer(r"pmc-traffic plan=(\S+) cols=(\d) src=(\S+) bytes_per_launch=(\d+)", text):
+        if m.group(1) == key and int(m.group(2)) == col_bytes and m.group(3) == digest:
+            return int(m.group(4))
     return None
 
 
@@ -203,8 +206,9 @@ def bench_hex(hk, torch, np, dev, stream, log, reps=20):
     e1.record(stream)
     torch.cuda.synchronize()
     us = e0.elapsed_time(e1) / reps * 1e3
-    nbytes = spmv_bytes(n, nnz)
-    res = {"n": n, "nnz": nnz, "spmv_plan": A.plan(), "spmv_us": round(us, 2),
+    cb = A.info()["col_bytes"]
+    nbytes = spmv_bytes(n, nnz, cb)
+    res = {"n": n, "nnz": nnz, "spmv_plan": A.plan(), "column_bytes": cb, "spmv_us": round(us, 2),
            "spmv_gbs": round(nbytes / (us * 1e-6) / 1e9, 1), "spmv_frac": round(nbytes / (us * 1e-6) / 8e12, 4)}
     g = t(c["g"])
     for method in ("bicgstab", "tfqmr", "bicgstab_l"):
@@ -287,9 +291,10 @@ def main():
     if args.plan:
         A.set_plan(*[int(v) for v in args.plan.split(",")])
     plan = A.plan()
-    log("plan", plan)
+    col_bytes = A.info()["col_bytes"]
+    log("plan", plan, "column bytes", col_bytes)
     stream = torch.cuda.current_stream()
-    nbytes = spmv_bytes(n, nnz)
+    nbytes = spmv_bytes(n, nnz, col_bytes)
 
     def step(timed_spmv):
         ev0 = torch.cuda.Event(enable_timing=True)
@@ -351,12 +356,32 @@ def main():
                    "n": n, "nnz": nnz, "spmv_plan": plan, "spmv_reps_per_step": args.spmv_reps},
         "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k_spmv (complex128 CSR product)",
+                     "kernel": "k_spmv_rb (complex128 CSR product)" if plan["lanes_per_row"] == 64
+                     else "k_spmv (complex128 CSR product)", "column_bytes": col_bytes,
                      "algorithmic_bytes_per_launch": nbytes, "mean_kernel_us": round(ms_spmv * 1e3, 2),
                      "gflops": round(8 * nnz / (ms_spmv * 1e-3) / 1e9, 1),
                      "copy_kernel_gbs": round(copy_gbs, 1)},
     }
-    traffic = pmc_traffic(plan)
+    if col_bytes == 2:
+        # the same product reading the int32 column indices (same launch shape)
+        Ai = hk.CSR(rowptr, col, val, compact_cols=False)
+        Ai.set_plan(plan["lanes_per_row"], plan["rows_per_group"], plan["grid"])
+        Ai.spmv(x, y)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.spmv_reps):
+            Ai.spmv(x, y)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_i = e0.elapsed_time(e1) / args.spmv_reps
+        b_i = spmv_bytes(n, nnz, 4)
+        out["roofline"]["int32_cols"] = {"mean_kernel_us": round(ms_i * 1e3, 2), "algorithmic_bytes_per_launch": b_i,
+                                         "gbs": round(b_i / (ms_i * 1e-3) / 1e9, 1),
+                                         "frac": round(b_i / (ms_i * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                         "traffic": pmc_traffic(plan, 4)}
+        log(f"int32 columns: {ms_i * 1e3:.1f} us, {b_i / (ms_i * 1e-3) / 1e9:.0f} GB/s")
+        Ai.close()
+    traffic = pmc_traffic(plan, col_bytes)
     out["roofline"]["traffic"] = traffic
     if traffic is None:
         log("no counter summary for this launch shape and kernel source; traffic = null")

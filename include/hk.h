@@ -50,7 +50,8 @@ enum hk_dtype { HK_C128 = 0, HK_C64 = 1 };
 
 enum hk_csr_flags {
   HK_VALIDATE = 1,   /* structure check at creation (always done) */
-  HK_AUTOTUNE = 2    /* time the SpMV launch shapes on this matrix and keep the fastest */
+  HK_AUTOTUNE = 2,   /* time the SpMV launch shapes on this matrix and keep the fastest */
+  HK_INT32_COLS = 4  /* do not build the 16-bit column stream (products read d_col itself) */
 };
 
 enum hk_breakdown { HK_BD_NONE = 0, HK_BD_RHO = 1, HK_BD_SIGMA = 2, HK_BD_TAU = 3, HK_BD_OMEGA = 4 };
@@ -65,13 +66,18 @@ const char* hk_last_error(void);
 /*
  * Wrap a CSR matrix that lives in caller-owned device memory (Section 2:
  * FE matrices in CSR).  d_val holds nnz complex values of type dtype.  The
- * buffers must stay valid and unchanged in layout while the handle lives;
- * values may be updated between calls.  The structure is always checked on
- * the device (rowptr non-decreasing from 0 to nnz, every col in [0, n) and
- * strictly ascending within its row; HK_EINVAL otherwise), which also finds
- * the longest row; this synchronises `stream` once.  HK_VALIDATE is
- * accepted and implied.  HK_AUTOTUNE times the candidate launch shapes on
- * this matrix (values are not modified) and keeps the fastest.
+ * buffers must stay valid while the handle lives, and rowptr and col must
+ * not change; values may be updated between calls.  The structure is always
+ * checked on the device (rowptr non-decreasing from 0 to nnz, every col in
+ * [0, n) and strictly ascending within its row; HK_EINVAL otherwise), which
+ * also finds the longest row; this synchronises `stream`.  HK_VALIDATE is
+ * accepted and implied.  When every entry lies within 32767 columns of its
+ * row's 64-aligned base (row & ~63), as in a banded FE matrix, the handle
+ * also keeps the column indices as 16-bit offsets from that base (2 bytes
+ * per entry, device memory it owns), which the row-block products stream
+ * instead of col; HK_INT32_COLS turns this off.  Results are the same bits
+ * either way.  HK_AUTOTUNE times the candidate launch shapes on this matrix
+ * (values are not modified) and keeps the fastest.
  */
 int hk_csr_create(hk_csr* out, int64_t n, int64_t nnz, const int32_t* d_rowptr,
                   const int32_t* d_col, const void* d_val, int dtype, int flags, void* stream);
@@ -83,6 +89,11 @@ int hk_csr_destroy(hk_csr A);
  * workgroups per launch, and whether it was chosen by timing. */
 int hk_csr_plan(hk_csr A, int32_t* lanes_per_row, int32_t* rows_per_group, int32_t* grid,
                 int32_t* tuned);
+
+/* Size and storage of the matrix: n, nnz, longest row, and the bytes per
+ * entry of the column stream the row-block products read (2: 16-bit
+ * offsets, 4: the int32 indices).  Null outputs are skipped. */
+int hk_csr_info(hk_csr A, int64_t* n, int64_t* nnz, int32_t* max_row, int32_t* col_bytes);
 
 /* Override the launch shape: lanes_per_row in {4,8,16,32} with
  * rows_per_group in {1,2,4,8} not above lanes_per_row (a group of lanes per

@@ -59,6 +59,10 @@ struct hk_csr_s {
   const int32_t* rowptr = nullptr;
   const int32_t* col = nullptr;
   const void* val = nullptr;
+  // 16-bit column offsets from each row's 64-aligned base (owned; null when
+  // an offset exceeds 32767 or HK_INT32_COLS was given): the column stream
+  // of the row-block products
+  int16_t* col16 = nullptr;
   int dtype = HK_C128;
   int device = 0;
   int max_row = 0;         // longest row (host copy, from the validation pass)

@@ -233,9 +233,9 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dot(int n, int ntiles, const in
 
 // Row-block variant of k_spmv_dot (one wave per RW rows); the row's sum
 // lands in the lane that owns the row.
-template <int RW, int NW, class R, int DOT>
+template <int RW, int NW, class R, int DOT, class CI>
 __global__ __launch_bounds__(NW * kWave) void k_spmv_dot_rb(int n, int ntiles, const int* __restrict__ rowptr,
-                                                            const int* __restrict__ col,
+                                                            const CI* __restrict__ col,
                                                             const cplx<R>* __restrict__ val,
                                                             const cplx<R>* __restrict__ x,
                                                             cplx<R>* __restrict__ y,
@@ -256,7 +256,7 @@ __global__ __launch_bounds__(NW * kWave) void k_spmv_dot_rb(int n, int ntiles, c
     const int r0 = t * (NW * RW) + (threadIdx.x / kWave) * RW;
     const int r = r0 + l;
     const V wr = w[r < n ? r : n - 1];
-    const V acc = csr_block_rows<RW, CH, V>(r0, n, rowptr, col, val, x, buf);
+    const V acc = csr_block_rows<RW, CH, V, CI>(r0, n, rowptr, col, val, x, buf);
     if (l < RW && r < n) {
       y[r] = acc;
       if (DOT == 1) {
@@ -617,20 +617,26 @@ static hipError_t launch_spmv_dot(const hk_csr_s* A, const SpmvPlan& p, int dot,
   HK_SD_CASE(16, 1) HK_SD_CASE(16, 2) HK_SD_CASE(16, 4) HK_SD_CASE(16, 8)
   HK_SD_CASE(32, 1) HK_SD_CASE(32, 2) HK_SD_CASE(32, 4) HK_SD_CASE(32, 8)
 #undef HK_SD_CASE
+#define HK_SDRB_LAUNCH(RR, NWW, DD, CI, COL)                                                            \
+  hipLaunchKernelGGL((k_spmv_dot_rb<RR, NWW, R, DD, CI>), dim3(grid), dim3(NWW * kWave), 0, s, n, ntiles, \
+                     A->rowptr, COL, val, x, y, w, wk.st, wk.partials)
 #define HK_SDRB_CASE(RR, NWW)                                                                          \
   if (L == kRowBlockL && U == RR && nw == NWW) {                                                       \
-    if (dot == 1)                                                                                      \
-      hipLaunchKernelGGL((k_spmv_dot_rb<RR, NWW, R, 1>), dim3(grid), dim3(NWW * kWave), 0, s, n, ntiles, \
-                         A->rowptr, A->col, val, x, y, w, wk.st, wk.partials);                         \
-    else                                                                                               \
-      hipLaunchKernelGGL((k_spmv_dot_rb<RR, NWW, R, 2>), dim3(grid), dim3(NWW * kWave), 0, s, n, ntiles, \
-                         A->rowptr, A->col, val, x, y, w, wk.st, wk.partials);                         \
+    const short* c16 = (const short*)A->col16;                                                         \
+    if (dot == 1) {                                                                                    \
+      if (c16) HK_SDRB_LAUNCH(RR, NWW, 1, short, c16);                                                 \
+      else HK_SDRB_LAUNCH(RR, NWW, 1, int, A->col);                                                    \
+    } else {                                                                                           \
+      if (c16) HK_SDRB_LAUNCH(RR, NWW, 2, short, c16);                                                 \
+      else HK_SDRB_LAUNCH(RR, NWW, 2, int, A->col);                                                    \
+    }                                                                                                  \
     return hipGetLastError();                                                                          \
   }
   HK_SDRB_CASE(16, 2) HK_SDRB_CASE(32, 2) HK_SDRB_CASE(64, 2)
   HK_SDRB_CASE(16, 4) HK_SDRB_CASE(32, 4) HK_SDRB_CASE(64, 4)
   HK_SDRB_CASE(16, 8) HK_SDRB_CASE(32, 8) HK_SDRB_CASE(64, 8)
 #undef HK_SDRB_CASE
+#undef HK_SDRB_LAUNCH
   return hipErrorInvalidValue;
 }
 
@@ -897,9 +903,9 @@ __global__ __launch_bounds__(kBlock) void k_fused_lg(int n, int ntiles, const in
   store_block_partials<NV>(part, partials);
 }
 
-template <class E, int RW, int NW>
+template <class E, int RW, int NW, class CI>
 __global__ __launch_bounds__(NW * kWave) void k_fused_rb(int n, int ntiles, const int* __restrict__ rowptr,
-                                                         const int* __restrict__ col,
+                                                         const CI* __restrict__ col,
                                                          const typename E::V* __restrict__ val,
                                                          const typename E::V* __restrict__ x, E e,
                                                          const SolveState* __restrict__ st, double* partials) {
@@ -919,7 +925,7 @@ __global__ __launch_bounds__(NW * kWave) void k_fused_rb(int n, int ntiles, cons
     const int r0 = t * (NW * RW) + (threadIdx.x / kWave) * RW;
     const int r = r0 + l;
     const typename E::Pre pre = e.load(r < n ? r : n - 1);
-    const V acc = csr_block_rows<RW, CH, V>(r0, n, rowptr, col, val, x, buf);
+    const V acc = csr_block_rows<RW, CH, V, CI>(r0, n, rowptr, col, val, x, buf);
     if (l < RW && r < n) e.apply(r, pre, acc, sc, part);
   }
   __syncthreads();
@@ -948,8 +954,12 @@ static hipError_t launch_fused(const hk_csr_s* A, const SpmvPlan& p, const typen
 #undef HK_FLG
 #define HK_FRB(RR, NWW)                                                                              \
   if (p.L == kRowBlockL && p.U == RR && nw == NWW) {                                                 \
-    hipLaunchKernelGGL((k_fused_rb<E, RR, NWW>), dim3(grid), dim3(NWW * kWave), 0, s, n, ntiles,     \
-                       A->rowptr, A->col, val, x, e, st, partials);                                  \
+    if (A->col16)                                                                                    \
+      hipLaunchKernelGGL((k_fused_rb<E, RR, NWW, short>), dim3(grid), dim3(NWW * kWave), 0, s, n,    \
+                         ntiles, A->rowptr, (const short*)A->col16, val, x, e, st, partials);        \
+    else                                                                                             \
+      hipLaunchKernelGGL((k_fused_rb<E, RR, NWW, int>), dim3(grid), dim3(NWW * kWave), 0, s, n,      \
+                         ntiles, A->rowptr, A->col, val, x, e, st, partials);                        \
     return hipGetLastError();                                                                        \
   }
   HK_FRB(16, 2) HK_FRB(32, 2) HK_FRB(64, 2)

@@ -43,9 +43,9 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int n, int ntiles, const int* _
 }
 
 // Row-block variant: R rows per wave, a tile is kRbWaves * R rows.
-template <int R, class V, int MODE>
+template <int R, class V, int MODE, class CI>
 __global__ __launch_bounds__(kRbThreads) void k_spmv_rb(int n, int ntiles, const int* __restrict__ rowptr,
-                                                        const int* __restrict__ col,
+                                                        const CI* __restrict__ col,
                                                         const V* __restrict__ val, const V* __restrict__ x,
                                                         V* __restrict__ y, const V* __restrict__ b,
                                                         V alpha, V beta, int beta_zero) {
@@ -56,7 +56,7 @@ __global__ __launch_bounds__(kRbThreads) void k_spmv_rb(int n, int ntiles, const
   for (int tb = blockIdx.x; tb < ntiles; tb += gridDim.x) {
     const int t = tile_of(tb, ntiles);
     const int r0 = t * (kRbWaves * R) + (threadIdx.x / kWave) * R;
-    const V acc = csr_block_rows<R, CH, V>(r0, n, rowptr, col, val, x, buf);
+    const V acc = csr_block_rows<R, CH, V, CI>(r0, n, rowptr, col, val, x, buf);
     const int r = r0 + l;
     if (l < R && r < n) {
       V out;
@@ -72,26 +72,40 @@ __global__ __launch_bounds__(kRbThreads) void k_spmv_rb(int n, int ntiles, const
 }
 
 // Structure check of a CSR matrix.  flags[0] |= 1 on any violation,
-// flags[1] = longest row.
+// flags[1] = longest row, flags[2] = largest |col - (row & ~63)|.
 __global__ void k_csr_check(int n, int nnz, const int* __restrict__ rowptr,
-                            const int* __restrict__ col, int* flags, int full) {
+                            const int* __restrict__ col, int* flags) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int s = rowptr[i], e = rowptr[i + 1];
-  int bad = 0;
+  int bad = 0, far = 0;
   if (i == 0 && s != 0) bad = 1;
   if (i == n - 1 && e != nnz) bad = 1;
   if (e < s || s < 0 || e > nnz) bad = 1;
-  if (!bad && full) {
+  if (!bad) {
+    const int base = i & ~63;
     int prev = -1;
     for (int p = s; p < e; ++p) {
       const int c = col[p];
       if (c < 0 || c >= n || c <= prev) { bad = 1; break; }
       prev = c;
+      far = max(far, abs(c - base));
     }
   }
   if (bad) atomicOr(&flags[0], 1);
-  if (!bad) atomicMax(&flags[1], e - s);
+  if (!bad) {
+    atomicMax(&flags[1], e - s);
+    atomicMax(&flags[2], far);
+  }
+}
+
+// col16[p] = col[p] - (row & ~63) for every entry (offsets checked to fit).
+__global__ void k_col16(int n, const int* __restrict__ rowptr, const int* __restrict__ col,
+                        int16_t* __restrict__ col16) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int base = i & ~63;
+  for (int p = rowptr[i]; p < rowptr[i + 1]; ++p) col16[p] = (int16_t)(col[p] - base);
 }
 
 // ------------------------------------------------------------- dispatch
@@ -125,8 +139,13 @@ static hipError_t launch_spmv_t(const hk_csr_s* A, const SpmvPlan& p, const V* x
 #undef HK_SPMV_CASE
 #define HK_RB_CASE(RR)                                                                          \
   if (p.L == kRowBlockL && p.U == RR) {                                                         \
-    hipLaunchKernelGGL((k_spmv_rb<RR, V, MODE>), dim3(grid), dim3(kRbThreads), 0, s, n, ntiles,  \
-                       A->rowptr, A->col, val, x, y, b, alpha, beta, beta_zero);                \
+    if (A->col16)                                                                               \
+      hipLaunchKernelGGL((k_spmv_rb<RR, V, MODE, short>), dim3(grid), dim3(kRbThreads), 0, s, n, \
+                         ntiles, A->rowptr, (const short*)A->col16, val, x, y, b, alpha, beta,   \
+                         beta_zero);                                                            \
+    else                                                                                        \
+      hipLaunchKernelGGL((k_spmv_rb<RR, V, MODE, int>), dim3(grid), dim3(kRbThreads), 0, s, n,   \
+                         ntiles, A->rowptr, A->col, val, x, y, b, alpha, beta, beta_zero);      \
     return hipGetLastError();                                                                   \
   }
   HK_RB_CASE(16) HK_RB_CASE(32) HK_RB_CASE(64)
@@ -155,13 +174,13 @@ static SpmvPlan heuristic_plan(const hk_csr_s* A) {
 
 // Time every launch shape on this matrix (hipEvents on the caller's
 // stream), keep the fastest.  Results are cached per (n, nnz, longest row,
-// dtype) for the life of the process.
+// dtype, column stream) for the life of the process.
 int spmv_autotune(hk_csr_s* A, hipStream_t s) {
   static std::mutex mu;
-  static std::map<std::tuple<int64_t, int64_t, int, int, int>, SpmvPlan> cache;
+  static std::map<std::tuple<int64_t, int64_t, int, int, int, bool>, SpmvPlan> cache;
   int dev = 0;
   HK_HIP(hipGetDevice(&dev));
-  auto key = std::make_tuple(A->n, A->nnz, A->max_row, A->dtype, dev);
+  auto key = std::make_tuple(A->n, A->nnz, A->max_row, A->dtype, dev, A->col16 != nullptr);
   {
     std::lock_guard<std::mutex> lock(mu);
     auto it = cache.find(key);
@@ -274,19 +293,21 @@ extern "C" int hk_csr_create(hk_csr* out, int64_t n, int64_t nnz, const int32_t*
     HK_FAIL(HK_EINVAL, "hk_csr_create: null device pointer");
   if (dtype != HK_C128 && dtype != HK_C64) HK_FAIL(HK_EINVAL, "hk_csr_create: bad dtype %d", dtype);
   hipStream_t s = as_stream(stream);
+  int device = 0;
+  HK_HIP(hipGetDevice(&device));
   hk_csr_s* A = new hk_csr_s();
   A->n = n; A->nnz = nnz; A->rowptr = d_rowptr; A->col = d_col; A->val = d_val; A->dtype = dtype;
-  HK_HIP(hipGetDevice(&A->device));
+  A->device = device;
   int* flags_d = nullptr;
-  if (hipMalloc(&flags_d, 2 * sizeof(int)) != hipSuccess) {
+  if (hipMalloc(&flags_d, 3 * sizeof(int)) != hipSuccess) {
     delete A;
     HK_FAIL(HK_ENOMEM, "hk_csr_create: hipMalloc failed");
   }
-  int h[2] = {0, 0};
-  hipError_t err = hipMemsetAsync(flags_d, 0, 2 * sizeof(int), s);
+  int h[3] = {0, 0, 0};
+  hipError_t err = hipMemsetAsync(flags_d, 0, 3 * sizeof(int), s);
   if (err == hipSuccess) {
     hipLaunchKernelGGL(k_csr_check, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, (int)n,
-                       (int)nnz, d_rowptr, d_col, flags_d, 1);
+                       (int)nnz, d_rowptr, d_col, flags_d);
     err = hipGetLastError();
   }
   if (err == hipSuccess) err = hipMemcpyAsync(h, flags_d, sizeof(h), hipMemcpyDeviceToHost, s);
@@ -301,10 +322,28 @@ extern "C" int hk_csr_create(hk_csr* out, int64_t n, int64_t nnz, const int32_t*
     HK_FAIL(HK_EINVAL, "hk_csr_create: malformed CSR (rowptr/col out of range or unsorted)");
   }
   A->max_row = h[1];
+  if (!(flags & HK_INT32_COLS) && nnz > 0 && h[2] <= 32767) {
+    if (hipMalloc(&A->col16, 2 * (size_t)nnz) != hipSuccess) {
+      delete A;
+      HK_FAIL(HK_ENOMEM, "hk_csr_create: hipMalloc failed");
+    }
+    hipLaunchKernelGGL(k_col16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, (int)n, d_rowptr,
+                       d_col, A->col16);
+    err = hipGetLastError();
+    if (err == hipSuccess) err = hipStreamSynchronize(s);
+    if (err != hipSuccess) {
+      (void)hipFree(A->col16);
+      delete A;
+      HK_FAIL(HK_EHIP, "hk_csr_create: %s", hipGetErrorString(err));
+    }
+  }
   A->plan = heuristic_plan(A);
   if (flags & HK_AUTOTUNE) {
     int rc = spmv_autotune(A, s);
-    if (rc != HK_OK) { delete A; return rc; }
+    if (rc != HK_OK) {
+      (void)hk_csr_destroy(A);
+      return rc;
+    }
   }
   *out = A;
   return HK_OK;
@@ -313,7 +352,7 @@ extern "C" int hk_csr_create(hk_csr* out, int64_t n, int64_t nnz, const int32_t*
 extern "C" int hk_csr_destroy(hk_csr A) {
   if (!A) return HK_OK;
   int rc = HK_OK;
-  if (A->ws || A->ws32 || A->val32) {
+  if (A->ws || A->ws32 || A->val32 || A->col16) {
     int cur = 0;
     (void)hipGetDevice(&cur);
     (void)hipSetDevice(A->device);
@@ -321,6 +360,7 @@ extern "C" int hk_csr_destroy(hk_csr A) {
     if (A->ws) (void)hipFree(A->ws);
     if (A->ws32) (void)hipFree(A->ws32);
     if (A->val32) (void)hipFree(A->val32);
+    if (A->col16) (void)hipFree(A->col16);
     (void)hipSetDevice(cur);
   }
   if (A->pinned) (void)hipHostFree(A->pinned);
@@ -335,6 +375,15 @@ extern "C" int hk_csr_plan(hk_csr A, int32_t* L, int32_t* U, int32_t* grid, int3
   if (U) *U = A->plan.U;
   if (grid) *grid = A->plan.grid;
   if (tuned) *tuned = A->plan.tuned;
+  return HK_OK;
+}
+
+extern "C" int hk_csr_info(hk_csr A, int64_t* n, int64_t* nnz, int32_t* max_row, int32_t* col_bytes) {
+  if (!A) HK_FAIL(HK_EINVAL, "hk_csr_info: NULL handle");
+  if (n) *n = A->n;
+  if (nnz) *nnz = A->nnz;
+  if (max_row) *max_row = A->max_row;
+  if (col_bytes) *col_bytes = A->col16 ? 2 : 4;
   return HK_OK;
 }
 

@@ -33,6 +33,17 @@ template <class V> __device__ __forceinline__ V ldnt(const V* p) {
   return cmake<V>(v.x, v.y);
 }
 __device__ __forceinline__ int ldnt(const int* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ int ldnt(const short* p) { return (int)__builtin_nontemporal_load(p); }
+
+// Column stream of the row-block products.  A matrix whose every entry lies
+// within 32767 columns of its row's 64-aligned base (row & ~63) -- a banded
+// FE matrix, for one -- is streamed as 16-bit offsets from that base, 2 bytes
+// per entry instead of 4; otherwise as the int32 indices themselves.  Every
+// row of a row block (16, 32 or 64 rows starting at a multiple of the block
+// size) has the same base, so a lane decodes any entry of its block without
+// knowing the entry's row.
+__device__ __forceinline__ int col_at(const int* col, int p, int) { return ldnt(col + p); }
+__device__ __forceinline__ int col_at(const short* col, int p, int base) { return base + ldnt(col + p); }
 
 // Row sums of rows r0 .. r0+U-1 (rows >= n give 0), U <= L.  Every lane of
 // the L-lane group returns the full sums; callers write row u from lane u.  Within a row, lane j accumulates
@@ -88,7 +99,7 @@ __device__ __forceinline__ void csr_rows(int r0, int n, const int* __restrict__ 
 }
 
 // Row-block CSR: one wave per R consecutive rows r0 .. r0+R-1 (R in
-// {16, 32, 64}).  The wave streams the rows' entries with all 64 lanes --
+// {16, 32, 64}, r0 a multiple of R); col is either column stream (col_at).  The wave streams the rows' entries with all 64 lanes --
 // entry e of the block goes to lane e % 64, CH entries per lane per pass,
 // every column and value load issued before any gather -- parks the
 // products in its LDS slice buf[CH*64], then lane l < R sums the products
@@ -96,12 +107,13 @@ __device__ __forceinline__ void csr_rows(int r0, int n, const int* __restrict__ 
 // over the block's entry range (the pass count is uniform across the wave).
 // Returns the sum of row r0 + lane for lanes < R with r0 + lane < n, zero
 // otherwise.  All 64 lanes must call it.
-template <int R, int CH, class V>
+template <int R, int CH, class V, class CI>
 __device__ __forceinline__ V csr_block_rows(int r0, int n, const int* __restrict__ rowptr,
-                                            const int* __restrict__ col, const V* __restrict__ val,
+                                            const CI* __restrict__ col, const V* __restrict__ val,
                                             const V* __restrict__ x, V* buf) {
   static_assert(R == 16 || R == 32 || R == 64, "rows per wave");
   const int l = threadIdx.x & (kWave - 1);
+  const int base = r0 & ~63;
   // lane l <= R holds rowptr[r0 + l] (clamped to n): lane R the block's end
   const int li = l < R ? l : R;
   const int rs = rowptr[r0 + li < n ? r0 + li : n];
@@ -120,7 +132,7 @@ __device__ __forceinline__ V csr_block_rows(int r0, int n, const int* __restrict
     for (int k = 0; k < CH; ++k) {
       const int e = c0 + l + kWave * k;
       const int p = e < cend ? e : cend - 1;
-      c[k] = ldnt(col + p);
+      c[k] = col_at(col, p, base);
       a[k] = ldnt(val + p);
     }
     V xv[CH];

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libhk.so")
 HK_OK, HK_EINVAL, HK_EHIP, HK_ENOMEM = 0, -1, -2, -3
 HK_NOT_CONVERGED, HK_BREAKDOWN, HK_NONFINITE = 1, 2, 3
 HK_C128, HK_C64 = 0, 1
-HK_VALIDATE, HK_AUTOTUNE = 1, 2
+HK_VALIDATE, HK_AUTOTUNE, HK_INT32_COLS = 1, 2, 4
 BD_NAMES = {0: "none", 1: "rho", 2: "sigma", 3: "tau", 4: "omega"}
 
 
@@ -51,6 +51,7 @@ SIGNATURES = {
     "hk_csr_destroy": ([P], C.c_int),
     "hk_csr_plan": ([P, C.POINTER(I32), C.POINTER(I32), C.POINTER(I32), C.POINTER(I32)], C.c_int),
     "hk_csr_set_plan": ([P, I32, I32, I32], C.c_int),
+    "hk_csr_info": ([P, C.POINTER(I64), C.POINTER(I64), C.POINTER(I32), C.POINTER(I32)], C.c_int),
     "hk_spmv": ([P, P, P, P, P, P], C.c_int),
     "hk_residual": ([P, P, P, P, P], C.c_int),
     "hk_zdotc": ([I64, P, P, P, P], C.c_int),
@@ -121,7 +122,7 @@ def _scalar(z, dtype=torch.complex128):
 class CSR:
     """Handle on a CSR matrix in device memory (rowptr/col int32, val complex)."""
 
-    def __init__(self, rowptr, col, val, autotune=False):
+    def __init__(self, rowptr, col, val, autotune=False, compact_cols=True):
         lib = load()
         self.rowptr = rowptr.contiguous()
         self.col = col.contiguous()
@@ -137,7 +138,7 @@ class CSR:
         self.nnz = self.col.numel()
         self.dtype = self.val.dtype
         h = C.c_void_p()
-        flags = HK_VALIDATE | (HK_AUTOTUNE if autotune else 0)
+        flags = HK_VALIDATE | (HK_AUTOTUNE if autotune else 0) | (0 if compact_cols else HK_INT32_COLS)
         dt = HK_C128 if self.dtype == torch.complex128 else HK_C64
         _check(lib.hk_csr_create(C.byref(h), self.n, self.nnz, _ptr(self.rowptr), _ptr(self.col),
                                  _ptr(self.val), dt, flags, _stream()))
@@ -153,6 +154,11 @@ class CSR:
             self.close()
         except Exception:
             pass
+
+    def info(self):
+        n, nnz, mr, cb = C.c_int64(), C.c_int64(), I32(), I32()
+        _check(load().hk_csr_info(self.h, C.byref(n), C.byref(nnz), C.byref(mr), C.byref(cb)))
+        return {"n": n.value, "nnz": nnz.value, "max_row": mr.value, "col_bytes": cb.value}
 
     def plan(self):
         L, U, g, t = I32(), I32(), I32(), I32()

@@ -76,22 +76,64 @@ SHAPES = ([(L, U, g) for L in (4, 8, 16, 32) for U in (1, 2, 4, 8) for g in (0, 
 
 
 def test_spmv_all_shapes_ragged(hk, oracle):
+    """Every launch shape, with the 16-bit column stream (the default for
+    this banded matrix) and with the int32 indices: oracle parity, and the
+    row-block shapes give the same bits from either stream."""
     rowptr, col, val = small_mesh_problem()
     n = rowptr.shape[0] - 1
     x = crandn(np.random.default_rng(1), n)
     ref = oracle.spmv(rowptr, col, val, x)
     bound = 1e-12 * spmv_bound(rowptr, col, val, x)
-    A = make_csr(hk, rowptr, col, val)
     xd = dev(x)
+    outs = {}
+    for compact in (True, False):
+        A = hk.CSR(dev(rowptr), dev(col), dev(val), compact_cols=compact)
+        assert A.info() == {"n": n, "nnz": col.shape[0], "max_row": int(np.diff(rowptr).max()),
+                            "col_bytes": 2 if compact else 4}
+        for L, U, g in SHAPES:
+            say("spmv shape", L, U, g, "n", n, "compact", compact)
+            A.set_plan(L, U, g)
+            # NaN-filled output: a row the kernel fails to write cannot pass
+            y = host(A.spmv(xd, torch.full_like(xd, complex("nan+nanj")), beta=0.0))
+            assert np.all(np.abs(y - ref) <= bound), (L, U, g, compact)
+            outs[(L, U, g, compact)] = y
+        for bad in ((4, 8, 0), (64, 8, 0), (64, 128, 0), (2, 1, 0)):
+            with pytest.raises(hk.HKError):
+                A.set_plan(*bad)
     for L, U, g in SHAPES:
-        say("spmv shape", L, U, g, "n", n)
-        A.set_plan(L, U, g)
-        # NaN-filled output: a row the kernel fails to write cannot pass
-        y = host(A.spmv(xd, torch.full_like(xd, complex("nan+nanj")), beta=0.0))
-        assert np.all(np.abs(y - ref) <= bound), (L, U, g)
-    for bad in ((4, 8, 0), (64, 8, 0), (64, 128, 0), (2, 1, 0)):
-        with pytest.raises(hk.HKError):
-            A.set_plan(*bad)
+        if L == 64:
+            assert np.array_equal(outs[(L, U, g, True)], outs[(L, U, g, False)]), (U, g)
+
+
+def test_spmv_column_stream_limits(hk, oracle):
+    """The 16-bit column stream is built exactly when every |col - (row &
+    ~63)| <= 32767; at the limit, one past it and with offsets of both signs
+    the row-block products match the oracle."""
+    rng = np.random.default_rng(8)
+    n = 40000
+    for name, extra, want in (("limit +32767", (100, 64 + 32767), 2),
+                              ("past +32768", (100, 64 + 32768), 4),
+                              ("limit -32767", (39999, 39936 - 32767), 2),
+                              ("past -32768", (39999, 39936 - 32768), 4)):
+        rows = [np.array([i - 1, i, i + 1]) for i in range(n)]
+        rows[0], rows[-1] = np.array([0, 1]), np.array([n - 2, n - 1])
+        r, c = extra
+        rows[r] = np.unique(np.append(rows[r], c))
+        rows = [q[(q >= 0) & (q < n)] for q in rows]
+        rowptr = np.zeros(n + 1, dtype=np.int32)
+        rowptr[1:] = np.cumsum([len(q) for q in rows])
+        col = np.concatenate(rows).astype(np.int32)
+        val = crandn(rng, col.shape[0])
+        x = crandn(rng, n)
+        ref = oracle.spmv(rowptr, col, val, x)
+        bound = 1e-12 * spmv_bound(rowptr, col, val, x)
+        A = make_csr(hk, rowptr, col, val)
+        assert A.info()["col_bytes"] == want, name
+        for U in (16, 32, 64):
+            say("column stream", name, "rows per wave", U)
+            A.set_plan(64, U, 0)
+            y = host(A.spmv(dev(x)))
+            assert np.all(np.abs(y - ref) <= bound), (name, U)
 
 
 def test_spmv_alpha_beta_and_residual(hk, oracle):
@@ -437,3 +479,21 @@ def test_solve_config2_wide_workgroup_shapes(hk, oracle):
         x, info = hk.krylov_solve(A, g, tol=1e-14, max_iter=6)
         assert info["iters"] == 6 and info["status"] == hk.HK_NOT_CONVERGED, info
         assert np.linalg.norm(host(x) - xo) <= 1e-10 * np.linalg.norm(xo), plan
+
+
+def test_solvers_same_bits_from_either_column_stream(hk):
+    """The three methods give the same iterate bits whether the row-block
+    products stream 16-bit column offsets or int32 indices (same shape on
+    both handles)."""
+    rowptr, col, val = small_mesh_problem((9, 8, 7), 6)
+    n = rowptr.shape[0] - 1
+    b = dev(crandn(np.random.default_rng(9), n))
+    for method in ("bicgstab", "tfqmr", "bicgstab_l"):
+        xs = []
+        for compact in (True, False):
+            say("solver column streams", method, "compact", compact)
+            A = hk.CSR(dev(rowptr), dev(col), dev(val), compact_cols=compact)
+            A.set_plan(64, 32, 0)
+            x, info = hk.krylov_solve(A, b, tol=1e-12, max_iter=25, method=method, ell=4)
+            xs.append((host(x), info["iters"], info["relres_rec"]))
+        assert xs[0][1:] == xs[1][1:] and np.array_equal(xs[0][0], xs[1][0]), method
