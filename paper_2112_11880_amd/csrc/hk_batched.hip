@@ -68,16 +68,35 @@ __device__ __forceinline__ void store_partials64(const double (&v)[NV], double* 
 }
 
 // Second stage: out[k] (valid in threads 0..63, thread j = system j) = sum
-// over workgroups in a fixed order.
+// over workgroups in a fixed order.  Thread (g, j) sums workgroups g, g +
+// kPW, g + 2 kPW, ... in that order; the loads of kFinBatch of them (for all
+// NV sums) are issued before any is added, since the partials come from
+// memory after the barrier's acquire and a load-add chain would wait out
+// every load in turn.
+constexpr int kFinBatch = 8;
 template <int NV>
 __device__ __forceinline__ void final_partials64(const double* partials, double (&out)[NV], double* lds) {
   const int j = threadIdx.x & 63, g = threadIdx.x >> 6, G = gridDim.x;
+  double s[NV];
 #pragma unroll
-  for (int k = 0; k < NV; ++k) {
-    double s = 0;
-    for (int b = g; b < G; b += kPW) s += partials[((size_t)k * G + b) * kSys + j];
-    lds[(k * kPW + g) * kSys + j] = s;
+  for (int k = 0; k < NV; ++k) s[k] = 0;
+  for (int b0 = g; b0 < G; b0 += kFinBatch * kPW) {
+    double v[NV][kFinBatch];
+#pragma unroll
+    for (int u = 0; u < kFinBatch; ++u) {
+      const int b = b0 + u * kPW < G ? b0 + u * kPW : b0;
+#pragma unroll
+      for (int k = 0; k < NV; ++k) v[k][u] = partials[((size_t)k * G + b) * kSys + j];
+    }
+#pragma unroll
+    for (int u = 0; u < kFinBatch; ++u)
+      if (b0 + u * kPW < G) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) s[k] += v[k][u];
+      }
   }
+#pragma unroll
+  for (int k = 0; k < NV; ++k) lds[(k * kPW + g) * kSys + j] = s[k];
   __syncthreads();
   if (threadIdx.x < kSys) {
 #pragma unroll
@@ -546,13 +565,42 @@ __device__ __forceinline__ void bd_tile_spmv(const BdArgs& a, int tile, const do
   }
 }
 
+// Row-block variant: wave w of the workgroup owns rows trow + 64 w ..
+// trow + 64 w + 63 of the tile (kPW waves x 64 rows = one tile) and streams
+// their entries with all its lanes (csr_block_rows); each row's sum goes to
+// callback g(row, acc) in the lane that owns the row.  `stage` is the
+// workgroup's staging area (kPW slices of kBdCh * 64 products).
+constexpr int kBdCh = 4;  // entries per lane per pass: 8 needs more than the 128 VGPRs of a 1024-thread workgroup
+template <class G2>
+__device__ __forceinline__ void bd_tile_spmv_rb(const BdArgs& a, int tile, const double2* src, double2* stage,
+                                                G2&& g) {
+  const int end = a.sys_end[a.tsys[tile]];
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int r0 = a.trow[tile] + w * 64;
+  if (r0 >= end) return;  // uniform across the wave
+  const double2 acc = csr_block_rows<64, kBdCh, double2, int>(r0, end, a.rowptr, a.col, a.val, src,
+                                                              stage + w * kBdCh * kWave);
+  if (r0 + l < end) g(r0 + l, acc);
+}
+
+// L in {4, 8, 16, 32}: lane-group tile products; L == kRowBlockL: row blocks.
 template <int L>
 __global__ __launch_bounds__(kPB) void k_blockdiag(BdArgs a) {
-  __shared__ double lds[4 * kPW + 4 * kSys + 4 * kPW * kSys];
+  // [4 kPW] wave sums | [4 kSys] per-system sums | scratch shared by the
+  // barrier callbacks (4 kPW kSys doubles) and the row-block staging area,
+  // which are never live at the same time
+  constexpr int kFin = 4 * kPW * kSys;
+  constexpr int kStage = L == kRowBlockL ? kPW * kBdCh * kWave * 2 : 0;
+  __shared__ __align__(16) double lds[4 * kPW + 4 * kSys + (kFin > kStage ? kFin : kStage)];
   unsigned epoch = 0;
   double* fin = lds + 4 * kPW + 4 * kSys;
+  double2* stage = reinterpret_cast<double2*>(fin);
   BatchState* st = a.st;
   const int TR = kPB;  // rows per tile: one per thread in the element-wise phases
+  auto tile_spmv = [&](int tile, const double2* src, auto&& g) {
+    if constexpr (L == kRowBlockL) bd_tile_spmv_rb(a, tile, src, stage, g);
+    else bd_tile_spmv<L>(a, tile, src, g);
+  };
 
   // rebuild the active tile list from the statuses (last workgroup only)
   auto rebuild = [&] {
@@ -615,7 +663,7 @@ __global__ __launch_bounds__(kPB) void k_blockdiag(BdArgs a) {
     }
     // v = A phat ; sigma
     bd_phase<2>(a, lds, [&](int tile, int sys, double(&acc)[2]) {
-      bd_tile_spmv<L>(a, tile, a.PH, [&](int row, double2 v) {
+      tile_spmv(tile, a.PH, [&](int row, double2 v) {
         a.V[row] = v;
         const double2 h = a.RH[row];
         acc[0] = fma(h.x, v.x, fma(h.y, v.y, acc[0]));
@@ -646,7 +694,7 @@ __global__ __launch_bounds__(kPB) void k_blockdiag(BdArgs a) {
     // t = A shat ; tau ; t^H s
     bd_phase<3>(a, lds, [&](int tile, int sys, double(&acc)[3]) {
       if (st->status[sys] != B_RUN) return;
-      bd_tile_spmv<L>(a, tile, a.SH, [&](int row, double2 t) {
+      tile_spmv(tile, a.SH, [&](int row, double2 t) {
         a.T[row] = t;
         const double2 s = cmul(a.d[row], a.SH[row]);
         acc[0] = fma(t.x, t.x, fma(t.y, t.y, acc[0]));
@@ -707,7 +755,7 @@ __global__ __launch_bounds__(kPB) void k_blockdiag(BdArgs a) {
       }))
     return;
   bd_phase<1>(a, lds, [&](int tile, int sys, double(&acc)[1]) {
-    bd_tile_spmv<L>(a, tile, a.X, [&](int row, double2 ax) {
+    tile_spmv(tile, a.X, [&](int row, double2 ax) {
       acc[0] += cabs2(csub(a.B[row], ax));
     });
   });
@@ -902,11 +950,10 @@ extern "C" int hk_blockdiag_solve(hk_csr A, int32_t nsys, const int64_t* row_off
   for (int k = 0; k < nsys; ++k)
     if (row_off[k + 1] <= row_off[k]) HK_FAIL(HK_EINVAL, "hk_blockdiag_solve: empty or decreasing system %d", k);
   hipStream_t s = as_stream(stream);
-  // lanes per row of the tile products: the handle's lane-group shape, or
-  // (row-block or untuned handles) the group that matches the mean row length
+  // tile products: row blocks (one wave per 64 rows) unless the rows are
+  // long (mean above 32 entries), then 32-lane groups per row
   const double mean_row = (double)A->nnz / (double)A->n;
-  const int L = (A->plan.L >= 4 && A->plan.L <= 32) ? A->plan.L
-                : mean_row > 24 ? 32 : mean_row > 12 ? 16 : mean_row > 6 ? 8 : 4;
+  const int L = mean_row > 32 ? 32 : kRowBlockL;
   const int TR = kPB;
   // static tiles
   std::vector<int> tsys, trow, sys_end(kSys, 0), sys_begin(kSys, 0), tile0(kSys + 1, 0);
@@ -925,9 +972,7 @@ extern "C" int hk_blockdiag_solve(hk_csr A, int32_t nsys, const int64_t* row_off
   for (int k = nsys + 1; k <= kSys; ++k) tile0[k] = tile0[nsys];
   const int nt = (int)tsys.size();
   const void* kern = nullptr;
-  if (L == 4) kern = (const void*)k_blockdiag<4>;
-  else if (L == 8) kern = (const void*)k_blockdiag<8>;
-  else if (L == 16) kern = (const void*)k_blockdiag<16>;
+  if (L == kRowBlockL) kern = (const void*)k_blockdiag<kRowBlockL>;
   else kern = (const void*)k_blockdiag<32>;
   int grid = 0;
   int rc = coop_grid(kern, &grid);

@@ -162,11 +162,21 @@ int default_grid(int ntiles) { return ntiles; }
 
 
 
+// Shape of an untuned handle: row blocks of the most rows whose mean entry
+// count fits one pass of the wave (512 complex128 or 1024 complex64
+// entries), which every FE matrix measured here preferred; 32-lane groups
+// when even 16 rows overflow a pass.
 static SpmvPlan heuristic_plan(const hk_csr_s* A) {
   SpmvPlan p;
   const double mean = A->n > 0 ? (double)A->nnz / (double)A->n : 0.0;
-  p.L = mean > 24 ? 32 : mean > 12 ? 16 : mean > 6 ? 8 : 4;
-  p.U = 2;
+  const double pass = A->dtype == HK_C128 ? RbCh<64, double2>::v * kWave : RbCh<64, float2>::v * kWave;
+  if (16 * mean > pass) {
+    p.L = 32;
+    p.U = 2;
+  } else {
+    p.L = kRowBlockL;
+    p.U = 64 * mean <= pass ? 64 : 32 * mean <= pass ? 32 : 16;
+  }
   p.grid = 0;
   p.tuned = 0;
   return p;

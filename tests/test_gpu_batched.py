@@ -119,11 +119,63 @@ def blockdiag_inputs(sizes, seed=2):
 
 
 def test_blockdiag_small_matches_oracle(hk, oracle):
+    """Seven cubes of 2..8 cells: every system's iterate after 4 iterations
+    is the oracle's to 1e-11, and the solves to 1e-10 reach the oracle's
+    solutions.  Iteration counts are only sanity-checked (within 2x): on
+    the 6-cell cube, summation order alone moves the count between 72 (the
+    oracle) and 103 (numpy with permuted dot sums)."""
     sizes = [5, 3, 8, 4, 6, 2, 7]
     rowptr, col, val, b, offs = blockdiag_inputs(sizes)
     A = hk.CSR(dev(rowptr), dev(col), dev(val))
-    say("blockdiag small", sizes)
+
+    def system(k):
+        lo, hi = offs[k], offs[k + 1]
+        return (rowptr[lo:hi + 1] - rowptr[lo], col[rowptr[lo]:rowptr[hi]] - lo,
+                val[rowptr[lo]:rowptr[hi]], b[lo:hi], lo, hi)
+
+    say("blockdiag small, 4 iterations", sizes)
+    x, infos = hk.blockdiag_solve(A, offs, dev(b), tol=1e-14, max_iter=4)
+    xh = host(x)
+    for k in range(len(sizes)):
+        rp, cc, vv, bk, lo, hi = system(k)
+        xo, oi = oracle.bicgstab(rp, cc, vv, bk, tol=1e-14, maxit=4)
+        assert infos[k]["iters"] == oi["iters"] == 4 and infos[k]["status"] == oi["status"], (k, infos[k], oi)
+        assert np.linalg.norm(xh[lo:hi] - xo) <= 1e-11 * np.linalg.norm(xo), k
+    say("blockdiag small, tol 1e-10", sizes)
     x, infos = hk.blockdiag_solve(A, offs, dev(b), tol=1e-10)
+    xh = host(x)
+    for k in range(len(sizes)):
+        rp, cc, vv, bk, lo, hi = system(k)
+        xo, oi = oracle.bicgstab(rp, cc, vv, bk, tol=1e-10)
+        assert infos[k]["status"] == 0, (k, infos[k])
+        assert np.linalg.norm(xh[lo:hi] - xo) <= 1e-7 * np.linalg.norm(xo), k
+        assert infos[k]["iters"] <= 2 * oi["iters"] + 10 and oi["iters"] <= 2 * infos[k]["iters"] + 10, (k, infos[k], oi)
+
+
+def test_blockdiag_long_rows_matches_oracle(hk, oracle):
+    """Rows of 41 entries (mean above 32: the 32-lane tile products) in
+    systems of 200, 130 and 77 rows, diagonally dominant."""
+    rng = np.random.default_rng(12)
+    sizes = [200, 130, 77]
+    rows, cols, vals, offs = [], [], [], [0]
+    nnz = 0
+    for m in sizes:
+        for i in range(m):
+            c = np.sort(np.append(rng.choice(np.delete(np.arange(m), i), 40, replace=False), i))
+            v = 0.5 * crandn(rng, 41)
+            v[np.searchsorted(c, i)] = 60.0 + 5j
+            rows.append(nnz)
+            cols.append(c + offs[-1])
+            vals.append(v)
+            nnz += 41
+        offs.append(offs[-1] + m)
+    rowptr = np.array(rows + [nnz], dtype=np.int32)
+    col = np.concatenate(cols).astype(np.int32)
+    val = np.concatenate(vals)
+    b = crandn(rng, offs[-1])
+    A = hk.CSR(dev(rowptr), dev(col), dev(val))
+    say("blockdiag long rows", sizes)
+    x, infos = hk.blockdiag_solve(A, np.array(offs, dtype=np.int64), dev(b), tol=1e-10)
     xh = host(x)
     for k in range(len(sizes)):
         lo, hi = offs[k], offs[k + 1]
@@ -132,8 +184,7 @@ def test_blockdiag_small_matches_oracle(hk, oracle):
         vv = val[rowptr[lo]:rowptr[hi]]
         xo, oi = oracle.bicgstab(rp, cc, vv, b[lo:hi], tol=1e-10)
         assert infos[k]["status"] == 0, (k, infos[k])
-        assert np.linalg.norm(xh[lo:hi] - xo) <= 1e-7 * np.linalg.norm(xo), k
-        assert abs(infos[k]["iters"] - oi["iters"]) <= max(10, 0.25 * oi["iters"]), (k, infos[k], oi)
+        assert np.linalg.norm(xh[lo:hi] - xo) <= 1e-9 * np.linalg.norm(xo), k
 
 
 def test_blockdiag_rejects_coupled_systems(hk):
