@@ -477,11 +477,14 @@ struct BdArgs {
   const double2* B;
   double2* X;
   double2 *R, *RH, *PH, *V, *SH, *T;
-  const int* tsys;       // static tile -> system
-  const int* trow;       // static tile -> first row
+  const int* sys_begin;  // system -> first row
   const int* sys_end;    // system -> one past its last row
   const int* sys_tile0;  // system -> first static tile (nsys+1 entries)
-  int* active;           // active tile list (static tile ids)
+  // active tile list: tile t (of ntiles_active) covers rows act_row0[t] ..
+  // min(act_row0[t] + kPB, act_end[t]) - 1 of system act_sys[t]
+  int* act_sys;
+  int* act_row0;
+  int* act_end;
   double* partials;
   BatchState* st;
   GridBar* bar;
@@ -515,30 +518,61 @@ __device__ __forceinline__ void bd_flush(double (&acc)[NV], int sys, double* red
   for (int k = 0; k < NV; ++k) acc[k] = 0;
 }
 
-// Walk this workgroup's share of the active tiles.  For each tile, f(row,
-// lane_in_group, group, sys, acc) handles rows of the tile; per-system sums
-// end in partials[(k*G + block)*64 + sys].
+// A tile of the active list as the phases see it, and the per-system
+// scalars the phases read, both staged in LDS at the start of a phase.
+struct BdTile {
+  int row0, end, sys;
+};
+constexpr int kBdTileBatch = 64;  // active tiles staged in LDS at a time
+struct BdShared {
+  int tsys[kBdTileBatch], trow0[kBdTileBatch], tend[kBdTileBatch];
+  double2 alpha[kSys], omega[kSys], beta[kSys];
+  int status[kSys];
+};
+
+// Walk this workgroup's share of the active tiles: f(tile, acc) for each,
+// with the metadata of up to kBdTileBatch tiles and every system's scalars
+// loaded into LDS together (one round of loads instead of a dependent chain
+// per tile); per-system sums end in partials[(k*G + block)*64 + sys].
 template <int NV, class F>
-__device__ __forceinline__ void bd_phase(const BdArgs& a, double* lds, F&& f) {
+__device__ __forceinline__ void bd_phase(const BdArgs& a, double* lds, BdShared& sh, F&& f) {
   double* red = lds;                    // NV * kPW
   double* sysacc = lds + 4 * kPW;       // NV * 64
   const int G = gridDim.x;
   const int lb = xcd_block(blockIdx.x, G);
-  const int na = a.st->ntiles_active;
+  const BatchState* st = a.st;
+  const int na = st->ntiles_active;
   const int t0 = (int)(((long long)lb * na) / G), t1 = (int)(((long long)(lb + 1) * na) / G);
   for (int k = threadIdx.x; k < NV * kSys; k += kPB) sysacc[k] = 0;
+  if (threadIdx.x < a.nsys) {
+    const int j = threadIdx.x;
+    sh.alpha[j] = st->alpha[j];
+    sh.omega[j] = st->omega[j];
+    sh.beta[j] = st->beta[j];
+    sh.status[j] = st->status[j];
+  }
   double acc[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) acc[k] = 0;
   int cur = -1;
-  for (int t = t0; t < t1; ++t) {
-    const int tile = a.active[t];
-    const int sys = a.tsys[tile];
-    if (sys != cur) {
-      if (cur >= 0) bd_flush<NV>(acc, cur, red, sysacc);
-      cur = sys;
+  for (int c = t0; c < t1; c += kBdTileBatch) {
+    const int cnt = t1 - c < kBdTileBatch ? t1 - c : kBdTileBatch;
+    __syncthreads();  // the previous batch is done with the staged tiles
+    if (threadIdx.x >= kSys && threadIdx.x < kSys + cnt) {
+      const int t = c + threadIdx.x - kSys;
+      sh.tsys[t - c] = a.act_sys[t];
+      sh.trow0[t - c] = a.act_row0[t];
+      sh.tend[t - c] = a.act_end[t];
     }
-    f(tile, sys, acc);
+    __syncthreads();
+    for (int k = 0; k < cnt; ++k) {
+      const BdTile tile{sh.trow0[k], sh.tend[k], sh.tsys[k]};
+      if (tile.sys != cur) {
+        if (cur >= 0) bd_flush<NV>(acc, cur, red, sysacc);
+        cur = tile.sys;
+      }
+      f(tile, acc);
+    }
   }
   bd_flush<NV>(acc, cur, red, sysacc);
   __syncthreads();
@@ -552,10 +586,10 @@ __device__ __forceinline__ void bd_phase(const BdArgs& a, double* lds, F&& f) {
 // group per row); each sum goes to callback g(row, acc) on the group's
 // first lane.
 template <int L, class G2>
-__device__ __forceinline__ void bd_tile_spmv(const BdArgs& a, int tile, const double2* src, G2&& g) {
+__device__ __forceinline__ void bd_tile_spmv(const BdArgs& a, const BdTile& tile, const double2* src, G2&& g) {
   const int grp = threadIdx.x / L, lane = threadIdx.x & (L - 1);
-  const int end = a.sys_end[a.tsys[tile]];
-  const int base = a.trow[tile];
+  const int end = tile.end;
+  const int base = tile.row0;
   for (int sub = 0; sub < L; ++sub) {
     const int row = base + sub * (kPB / L) + grp;
     if (base + sub * (kPB / L) >= end) break;
@@ -572,11 +606,11 @@ __device__ __forceinline__ void bd_tile_spmv(const BdArgs& a, int tile, const do
 // workgroup's staging area (kPW slices of kBdCh * 64 products).
 constexpr int kBdCh = 4;  // entries per lane per pass: 8 needs more than the 128 VGPRs of a 1024-thread workgroup
 template <class G2>
-__device__ __forceinline__ void bd_tile_spmv_rb(const BdArgs& a, int tile, const double2* src, double2* stage,
-                                                G2&& g) {
-  const int end = a.sys_end[a.tsys[tile]];
+__device__ __forceinline__ void bd_tile_spmv_rb(const BdArgs& a, const BdTile& tile, const double2* src,
+                                                double2* stage, G2&& g) {
+  const int end = tile.end;
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const int r0 = a.trow[tile] + w * 64;
+  const int r0 = tile.row0 + w * 64;
   if (r0 >= end) return;  // uniform across the wave
   const double2 acc = csr_block_rows<64, kBdCh, double2, int>(r0, end, a.rowptr, a.col, a.val, src,
                                                               stage + w * kBdCh * kWave);
@@ -595,38 +629,49 @@ __global__ __launch_bounds__(kPB) void k_blockdiag(BdArgs a) {
   unsigned epoch = 0;
   double* fin = lds + 4 * kPW + 4 * kSys;
   double2* stage = reinterpret_cast<double2*>(fin);
+  __shared__ BdShared sh;
   BatchState* st = a.st;
-  const int TR = kPB;  // rows per tile: one per thread in the element-wise phases
-  auto tile_spmv = [&](int tile, const double2* src, auto&& g) {
+  auto tile_spmv = [&](const BdTile& tile, const double2* src, auto&& g) {
     if constexpr (L == kRowBlockL) bd_tile_spmv_rb(a, tile, src, stage, g);
     else bd_tile_spmv<L>(a, tile, src, g);
   };
+  // the row of the calling thread in an element-wise phase (one per thread), or -1
+  auto my_row = [](const BdTile& tile) {
+    const int row = tile.row0 + (int)threadIdx.x;
+    return row < tile.end ? row : -1;
+  };
 
-  // rebuild the active tile list from the statuses (last workgroup only)
-  auto rebuild = [&] {
+  // (workgroup 0, all threads) rebuild the active tile list: the tiles of
+  // the systems still running, or of every system when `all`
+  auto fill_active = [&](bool all) {
     __shared__ int s_off[kSys + 1];
     if (threadIdx.x == 0) {
       int off = 0;
-      for (int s = 0; s < a.nsys; ++s) {
-        s_off[s] = off;
-        if (st->status[s] == B_RUN) off += a.sys_tile0[s + 1] - a.sys_tile0[s];
+      for (int q = 0; q < a.nsys; ++q) {
+        s_off[q] = off;
+        if (all || st->status[q] == B_RUN) off += a.sys_tile0[q + 1] - a.sys_tile0[q];
       }
       s_off[a.nsys] = off;
       st->ntiles_active = off;
       st->changed = 0;
     }
     __syncthreads();
-    for (int s = 0; s < a.nsys; ++s) {
-      if (st->status[s] != B_RUN) continue;
-      const int base = s_off[s], t0 = a.sys_tile0[s], cnt = a.sys_tile0[s + 1] - t0;
-      for (int k = threadIdx.x; k < cnt; k += kPB) a.active[base + k] = t0 + k;
+    for (int q = 0; q < a.nsys; ++q) {
+      if (!all && st->status[q] != B_RUN) continue;
+      const int base = s_off[q], cnt = a.sys_tile0[q + 1] - a.sys_tile0[q];
+      const int r0 = a.sys_begin[q], end = a.sys_end[q];
+      for (int k = threadIdx.x; k < cnt; k += kPB) {
+        a.act_sys[base + k] = q;
+        a.act_row0[base + k] = r0 + k * kPB;
+        a.act_end[base + k] = end;
+      }
     }
   };
 
   // ---- start: r = rhat = b, phat = D^-1 b, x = 0 (all tiles are active)
-  bd_phase<1>(a, lds, [&](int tile, int sys, double(&acc)[1]) {
-    const int row = a.trow[tile] + threadIdx.x;
-    if (threadIdx.x < TR && row < a.sys_end[sys]) {
+  bd_phase<1>(a, lds, sh, [&](const BdTile& tile, double(&acc)[1]) {
+    const int row = my_row(tile);
+    if (row >= 0) {
       const double2 b = a.B[row];
       a.R[row] = b; a.RH[row] = b; a.PH[row] = cmul(a.dinv[row], b); a.X[row] = make_double2(0, 0);
       acc[0] += cabs2(b);
@@ -644,17 +689,17 @@ __global__ __launch_bounds__(kPB) void k_blockdiag(BdArgs a) {
           st->running = run;
         }
         __syncthreads();
-        rebuild();
+        fill_active(false);
       }))
     return;
 
   while (st->running > 0) {
     const long long it = st->iter;
     if (it > 1) {
-      bd_phase<1>(a, lds, [&](int tile, int sys, double(&)[1]) {
-        const int row = a.trow[tile] + threadIdx.x;
-        if (threadIdx.x < TR && row < a.sys_end[sys]) {
-          const double2 beta = st->beta[sys], bo = cmul(beta, st->omega[sys]);
+      bd_phase<1>(a, lds, sh, [&](const BdTile& tile, double(&)[1]) {
+        const int row = my_row(tile);
+        if (row >= 0) {
+          const double2 beta = sh.beta[tile.sys], bo = cmul(beta, sh.omega[tile.sys]);
           const double2 w = csub(a.R[row], cmul(bo, a.V[row]));
           a.PH[row] = cfma(beta, a.PH[row], cmul(a.dinv[row], w));
         }
@@ -662,7 +707,7 @@ __global__ __launch_bounds__(kPB) void k_blockdiag(BdArgs a) {
       if (barrier_last(a.bar, epoch, [] {})) return;
     }
     // v = A phat ; sigma
-    bd_phase<2>(a, lds, [&](int tile, int sys, double(&acc)[2]) {
+    bd_phase<2>(a, lds, sh, [&](const BdTile& tile, double(&acc)[2]) {
       tile_spmv(tile, a.PH, [&](int row, double2 v) {
         a.V[row] = v;
         const double2 h = a.RH[row];
@@ -677,10 +722,10 @@ __global__ __launch_bounds__(kPB) void k_blockdiag(BdArgs a) {
         }))
       return;
     // s = r - alpha v ; shat ; ||s||^2
-    bd_phase<1>(a, lds, [&](int tile, int sys, double(&acc)[1]) {
-      const int row = a.trow[tile] + threadIdx.x;
-      if (threadIdx.x < TR && row < a.sys_end[sys] && st->status[sys] == B_RUN) {
-        const double2 s = csub(a.R[row], cmul(st->alpha[sys], a.V[row]));
+    bd_phase<1>(a, lds, sh, [&](const BdTile& tile, double(&acc)[1]) {
+      const int row = my_row(tile);
+      if (row >= 0 && sh.status[tile.sys] == B_RUN) {
+        const double2 s = csub(a.R[row], cmul(sh.alpha[tile.sys], a.V[row]));
         a.SH[row] = cmul(a.dinv[row], s);
         acc[0] += cabs2(s);
       }
@@ -692,8 +737,8 @@ __global__ __launch_bounds__(kPB) void k_blockdiag(BdArgs a) {
         }))
       return;
     // t = A shat ; tau ; t^H s
-    bd_phase<3>(a, lds, [&](int tile, int sys, double(&acc)[3]) {
-      if (st->status[sys] != B_RUN) return;
+    bd_phase<3>(a, lds, sh, [&](const BdTile& tile, double(&acc)[3]) {
+      if (sh.status[tile.sys] != B_RUN) return;
       tile_spmv(tile, a.SH, [&](int row, double2 t) {
         a.T[row] = t;
         const double2 s = cmul(a.d[row], a.SH[row]);
@@ -709,15 +754,15 @@ __global__ __launch_bounds__(kPB) void k_blockdiag(BdArgs a) {
         }))
       return;
     // x, r updates ; ||r||^2 ; rhat^H r
-    bd_phase<3>(a, lds, [&](int tile, int sys, double(&acc)[3]) {
-      const int row = a.trow[tile] + threadIdx.x;
-      if (threadIdx.x >= TR || row >= a.sys_end[sys]) return;
-      const int ss = st->status[sys];
-      const double2 alpha = st->alpha[sys], omega = st->omega[sys];
+    bd_phase<3>(a, lds, sh, [&](const BdTile& tile, double(&acc)[3]) {
+      const int row = my_row(tile);
+      if (row < 0) return;
+      const int ss = sh.status[tile.sys];
+      const double2 alpha = sh.alpha[tile.sys], omega = sh.omega[tile.sys];
       if (ss == B_RUN) {
-        const double2 sh = a.SH[row];
-        a.X[row] = cfma(omega, sh, cfma(alpha, a.PH[row], a.X[row]));
-        const double2 r = csub(cmul(a.d[row], sh), cmul(omega, a.T[row]));
+        const double2 shat = a.SH[row];
+        a.X[row] = cfma(omega, shat, cfma(alpha, a.PH[row], a.X[row]));
+        const double2 r = csub(cmul(a.d[row], shat), cmul(omega, a.T[row]));
         a.R[row] = r;
         acc[0] += cabs2(r);
         const double2 h = a.RH[row];
@@ -743,18 +788,13 @@ __global__ __launch_bounds__(kPB) void k_blockdiag(BdArgs a) {
             st->iter = st->iter + 1;
           }
           __syncthreads();
-          if (st->changed) rebuild();
+          if (st->changed) fill_active(false);
         }))
       return;
   }
   // true residual: all tiles
-  if (barrier_last(a.bar, epoch, [&] {
-        if (threadIdx.x == 0) st->ntiles_active = a.sys_tile0[a.nsys];
-        __syncthreads();
-        for (int k = threadIdx.x; k < a.sys_tile0[a.nsys]; k += kPB) a.active[k] = k;
-      }))
-    return;
-  bd_phase<1>(a, lds, [&](int tile, int sys, double(&acc)[1]) {
+  if (barrier_last(a.bar, epoch, [&] { fill_active(true); })) return;
+  bd_phase<1>(a, lds, sh, [&](const BdTile& tile, double(&acc)[1]) {
     tile_spmv(tile, a.X, [&](int row, double2 ax) {
       acc[0] += cabs2(csub(a.B[row], ax));
     });
@@ -979,7 +1019,7 @@ extern "C" int hk_blockdiag_solve(hk_csr A, int32_t nsys, const int64_t* row_off
   if (rc != HK_OK) return rc;
   const int64_t n = A->n;
   Arena ar;
-  const size_t bytes = 8 * a256(16 * (size_t)n) + 2 * a256(4 * (size_t)nt) + a256(4 * (size_t)nt) +
+  const size_t bytes = 8 * a256(16 * (size_t)n) + 3 * a256(4 * (size_t)nt) +
                        a256(4 * (size_t)n) + 4 * a256(4 * (kSys + 1)) + a256(8 * 4 * (size_t)grid * kSys) +
                        a256(sizeof(BatchState)) + a256(sizeof(GridBar)) + a256(64);
   if (hipMalloc((void**)&ar.base, bytes) != hipSuccess) HK_FAIL(HK_ENOMEM, "hk_blockdiag_solve: hipMalloc(%zu)", bytes);
@@ -990,9 +1030,9 @@ extern "C" int hk_blockdiag_solve(hk_csr A, int32_t nsys, const int64_t* row_off
   a.V = ar.take<double2>(n); a.SH = ar.take<double2>(n); a.T = ar.take<double2>(n);
   double2* d = ar.take<double2>(n);
   double2* dinv = ar.take<double2>(n);
-  int* d_tsys = ar.take<int>(nt);
-  int* d_trow = ar.take<int>(nt);
-  a.active = ar.take<int>(nt);
+  a.act_sys = ar.take<int>(nt);
+  a.act_row0 = ar.take<int>(nt);
+  a.act_end = ar.take<int>(nt);
   int* d_sor = ar.take<int>(n);
   int* d_send = ar.take<int>(kSys + 1);
   int* d_sbeg = ar.take<int>(kSys + 1);
@@ -1002,12 +1042,16 @@ extern "C" int hk_blockdiag_solve(hk_csr A, int32_t nsys, const int64_t* row_off
   a.st = ar.take<BatchState>(1);
   a.bar = ar.take<GridBar>(1);
   int* flag = ar.take<int>(16);
-  a.d = d; a.dinv = dinv; a.tsys = d_tsys; a.trow = d_trow; a.sys_end = d_send; a.sys_tile0 = d_t0;
+  a.d = d; a.dinv = dinv; a.sys_begin = d_sbeg; a.sys_end = d_send; a.sys_tile0 = d_t0;
   a.B = (const double2*)d_b; a.X = (double2*)d_x; a.tol = opts->tol; a.maxit = opts->max_iter;
   a.tile_rows = TR;
   int hflag = 0;
-  hipError_t e = hipMemcpyAsync(d_tsys, tsys.data(), 4 * (size_t)nt, hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(d_trow, trow.data(), 4 * (size_t)nt, hipMemcpyHostToDevice, s);
+  // the start phase walks every tile
+  std::vector<int> tend(nt);
+  for (int k = 0; k < nt; ++k) tend[k] = sys_end[tsys[k]];
+  hipError_t e = hipMemcpyAsync(a.act_sys, tsys.data(), 4 * (size_t)nt, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(a.act_row0, trow.data(), 4 * (size_t)nt, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(a.act_end, tend.data(), 4 * (size_t)nt, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(d_sor, sys_of_row.data(), 4 * (size_t)n, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(d_send, sys_end.data(), 4 * kSys, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(d_sbeg, sys_begin.data(), 4 * kSys, hipMemcpyHostToDevice, s);
@@ -1015,16 +1059,10 @@ extern "C" int hk_blockdiag_solve(hk_csr A, int32_t nsys, const int64_t* row_off
   if (e == hipSuccess) e = hipMemsetAsync(a.bar, 0, sizeof(GridBar), s);
   if (e == hipSuccess) e = hipMemsetAsync(flag, 0, 64, s);
   if (e == hipSuccess) e = hipMemsetAsync(a.st, 0, sizeof(BatchState), s);
-  if (e == hipSuccess) {
-    // the start phase walks every tile
-    std::vector<int> all(nt);
-    for (int k = 0; k < nt; ++k) all[k] = k;
-    BatchState init{};
-    init.ntiles_active = nt;
-    e = hipMemcpyAsync(a.active, all.data(), 4 * (size_t)nt, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(a.st, &init, sizeof(init), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);  // host vectors above go out of scope
-  }
+  BatchState init{};
+  init.ntiles_active = nt;
+  if (e == hipSuccess) e = hipMemcpyAsync(a.st, &init, sizeof(init), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);  // host vectors above go out of scope
   if (e == hipSuccess) {
     hipLaunchKernelGGL(k_bd_diag, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, (int)n,
                        A->rowptr, A->col, (const double2*)A->val, d_sor, d_sbeg, d_send, d, dinv, flag);
