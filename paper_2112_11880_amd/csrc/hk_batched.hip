@@ -193,8 +193,19 @@ struct SweepArgs {
   long long maxit;
 };
 
+// The shared matrix (rowptr, col, K, M and the diagonals) is read-only
+// during the kernel and every lane of a wave reads the same entry (lanes are
+// systems), so it is read through the scalar unit: constant-address-space
+// pointers indexed by wave-uniform values (readfirstlane) compile to scalar
+// loads, which keep the matrix stream out of the vector registers and the
+// vector memory pipeline.
+template <class T> using cptr = const __attribute__((address_space(4))) T*;
+template <class T> __device__ __forceinline__ cptr<T> as_const(const T* p) { return (cptr<T>)p; }
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
 __device__ __forceinline__ double2 sweep_diag(const SweepArgs& a, int i, double2 kap) {
-  const double k = a.kd[i], m = a.md[i];
+  const int iu = uni(i);
+  const double k = as_const(a.kd)[iu], m = as_const(a.md)[iu];
   return make_double2(k - kap.x * m, -kap.y * m);
 }
 
@@ -207,8 +218,10 @@ __device__ __forceinline__ void sweep_spmv(const SweepArgs& a, int r0, int r1, i
   const int j = threadIdx.x & 63;
   // lanes of finished systems issue no loads at all
   if (!act) return;
-  for (int row = r0; row < r1; row += rs) {
-    const int s = a.rowptr[row], e = a.rowptr[row + 1];
+  const cptr<int> rowptr = as_const(a.rowptr), col = as_const(a.col);
+  const cptr<double> Kc = as_const(a.K), Mc = as_const(a.M);
+  for (int row = uni(r0); row < r1; row += rs) {
+    const int s = rowptr[row], e = rowptr[row + 1];
     double2 acc = make_double2(0, 0);
     // 8 entries at a time, all gathers in flight together; past the row's
     // end an entry re-reads the last column with a zero coefficient
@@ -220,9 +233,9 @@ __device__ __forceinline__ void sweep_spmv(const SweepArgs& a, int r0, int r1, i
       for (int u = 0; u < 8; ++u) {
         const bool in = q0 + u < e;
         const int q = in ? q0 + u : e - 1;
-        c[u] = a.col[q];
-        kv[u] = in ? a.K[q] : 0.0;
-        mv[u] = in ? a.M[q] : 0.0;
+        c[u] = col[q];
+        kv[u] = in ? Kc[q] : 0.0;
+        mv[u] = in ? Mc[q] : 0.0;
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) xv[u] = src[(size_t)c[u] * kSys + j];
