@@ -49,6 +49,7 @@ struct SpmvPlan {
   int grid = 0;     // workgroups per launch (0: one per tile)
   int tuned = 0;    // 1 if chosen by timing on the device
   int nw = 0;       // row-block fused solver kernels: waves per workgroup (0: the fewest that fit)
+  int pairs = 0;    // row-block fused solver kernels: paired-entry layout (16-bit column stream only)
 };
 
 }  // namespace hk
@@ -61,7 +62,7 @@ struct hk_csr_s {
   const void* val = nullptr;
   // 16-bit column offsets from each row's 64-aligned base (owned; null when
   // an offset exceeds 32767 or HK_INT32_COLS was given): the column stream
-  // of the row-block products
+  // of the row-block products, nnz entries plus one zero padding entry
   int16_t* col16 = nullptr;
   int dtype = HK_C128;
   int device = 0;

@@ -233,7 +233,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dot(int n, int ntiles, const in
 
 // Row-block variant of k_spmv_dot (one wave per RW rows); the row's sum
 // lands in the lane that owns the row.
-template <int RW, int NW, class R, int DOT, class CI>
+template <int RW, int NW, class R, int DOT, class CI, bool PAIRS>
 __global__ __launch_bounds__(NW * kWave) void k_spmv_dot_rb(int n, int ntiles, const int* __restrict__ rowptr,
                                                             const CI* __restrict__ col,
                                                             const cplx<R>* __restrict__ val,
@@ -256,7 +256,9 @@ __global__ __launch_bounds__(NW * kWave) void k_spmv_dot_rb(int n, int ntiles, c
     const int r0 = t * (NW * RW) + (threadIdx.x / kWave) * RW;
     const int r = r0 + l;
     const V wr = w[r < n ? r : n - 1];
-    const V acc = csr_block_rows<RW, CH, V, CI>(r0, n, rowptr, col, val, x, buf);
+    V acc;
+    if constexpr (PAIRS) acc = csr_block_rows_pairs<RW, CH, V>(r0, n, rowptr, col, val, x, buf);
+    else acc = csr_block_rows<RW, CH, V, CI>(r0, n, rowptr, col, val, x, buf);
     if (l < RW && r < n) {
       y[r] = acc;
       if (DOT == 1) {
@@ -528,7 +530,7 @@ static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 template <class R> static size_t work_bytes(int64_t n, int64_t nnz) {
   using V = cplx<R>;
-  return 10 * align_up(sizeof(V) * n) + align_up(sizeof(V) * (nnz > 0 ? nnz : 1)) +
+  return 10 * align_up(sizeof(V) * n) + align_up(sizeof(V) * (nnz + 1)) +
          align_up(sizeof(double) * 4 * partial_slots(n)) + align_up(sizeof(SolveState)) + align_up(64);
 }
 
@@ -547,7 +549,7 @@ template <class R> static Work<R> carve(void* base, int64_t n, int64_t nnz) {
   w.dinv = (V*)take(sizeof(V) * n);
   w.u = (V*)take(sizeof(V) * n);
   w.d = (V*)take(sizeof(V) * n);
-  w.ahat = (V*)take(sizeof(V) * (nnz > 0 ? nnz : 1));
+  w.ahat = (V*)take(sizeof(V) * (nnz + 1));  // one padding entry (paired-entry products)
   w.partials = (double*)take(sizeof(double) * 4 * partial_slots(n));
   w.st = (SolveState*)take(sizeof(SolveState));
   w.flag = (int*)take(64);
@@ -617,18 +619,20 @@ static hipError_t launch_spmv_dot(const hk_csr_s* A, const SpmvPlan& p, int dot,
   HK_SD_CASE(16, 1) HK_SD_CASE(16, 2) HK_SD_CASE(16, 4) HK_SD_CASE(16, 8)
   HK_SD_CASE(32, 1) HK_SD_CASE(32, 2) HK_SD_CASE(32, 4) HK_SD_CASE(32, 8)
 #undef HK_SD_CASE
-#define HK_SDRB_LAUNCH(RR, NWW, DD, CI, COL)                                                            \
-  hipLaunchKernelGGL((k_spmv_dot_rb<RR, NWW, R, DD, CI>), dim3(grid), dim3(NWW * kWave), 0, s, n, ntiles, \
-                     A->rowptr, COL, val, x, y, w, wk.st, wk.partials)
+#define HK_SDRB_LAUNCH(RR, NWW, DD, CI, PP, COL)                                                        \
+  hipLaunchKernelGGL((k_spmv_dot_rb<RR, NWW, R, DD, CI, PP>), dim3(grid), dim3(NWW * kWave), 0, s, n,    \
+                     ntiles, A->rowptr, COL, val, x, y, w, wk.st, wk.partials)
+#define HK_SDRB_DOT(RR, NWW, DD)                                                                       \
+  if (c16 && p.pairs) HK_SDRB_LAUNCH(RR, NWW, DD, short, true, c16);                                   \
+  else if (c16) HK_SDRB_LAUNCH(RR, NWW, DD, short, false, c16);                                        \
+  else HK_SDRB_LAUNCH(RR, NWW, DD, int, false, A->col);
 #define HK_SDRB_CASE(RR, NWW)                                                                          \
   if (L == kRowBlockL && U == RR && nw == NWW) {                                                       \
     const short* c16 = (const short*)A->col16;                                                         \
     if (dot == 1) {                                                                                    \
-      if (c16) HK_SDRB_LAUNCH(RR, NWW, 1, short, c16);                                                 \
-      else HK_SDRB_LAUNCH(RR, NWW, 1, int, A->col);                                                    \
+      HK_SDRB_DOT(RR, NWW, 1)                                                                          \
     } else {                                                                                           \
-      if (c16) HK_SDRB_LAUNCH(RR, NWW, 2, short, c16);                                                 \
-      else HK_SDRB_LAUNCH(RR, NWW, 2, int, A->col);                                                    \
+      HK_SDRB_DOT(RR, NWW, 2)                                                                          \
     }                                                                                                  \
     return hipGetLastError();                                                                          \
   }
@@ -636,6 +640,7 @@ static hipError_t launch_spmv_dot(const hk_csr_s* A, const SpmvPlan& p, int dot,
   HK_SDRB_CASE(16, 4) HK_SDRB_CASE(32, 4) HK_SDRB_CASE(64, 4)
   HK_SDRB_CASE(16, 8) HK_SDRB_CASE(32, 8) HK_SDRB_CASE(64, 8)
 #undef HK_SDRB_CASE
+#undef HK_SDRB_DOT
 #undef HK_SDRB_LAUNCH
   return hipErrorInvalidValue;
 }
@@ -649,8 +654,10 @@ static hipError_t launch_fin(const Work<R>& wk, int nb, double tol, long long ma
 // Times the fused SpMV+dot kernel (with its finalize) in every launch shape
 // on A's pattern and keeps the fastest in *out (HIP events on stream s).
 // Row-block shapes are tried with 2, 4 and 8 waves per workgroup where the
-// tiles fit under kMaxGrid; every shape with one workgroup per tile and with
-// 2,048 workgroups walking the tiles (fewer partials for the finalize).  The workspace vectors serve as operands (their
+// tiles fit under kMaxGrid, and on the 16-bit column stream in both entry
+// layouts (the products read the solver's padded copy of the values); every
+// shape with one workgroup per tile and with 2,048 workgroups walking the
+// tiles (fewer partials for the finalize).  The workspace vectors serve as operands (their
 // values do not matter for timing); the scalar state is set to running here,
 // left so by the F_TUNE finalize, and re-initialised by the solve afterwards.
 template <class R>
@@ -661,10 +668,12 @@ static int tune_dot(const hk_csr_s* A, const Work<R>& wk, SpmvPlan* out, hipStre
       for (int U : {1, 2, 4, 8})
         if (U <= L) { SpmvPlan p; p.L = L; p.U = U; p.grid = grid; cands.push_back(p); }
     for (int U : {16, 32, 64})
-      for (int nw : {2, 4, 8}) {
-        SpmvPlan p; p.L = kRowBlockL; p.U = U; p.nw = nw; p.grid = grid;
-        if ((A->n + (int64_t)nw * U - 1) / ((int64_t)nw * U) <= kMaxGrid || nw == 8) cands.push_back(p);
-      }
+      for (int nw : {2, 4, 8})
+        for (int pairs : {0, 1}) {
+          if (pairs && !A->col16) continue;
+          SpmvPlan p; p.L = kRowBlockL; p.U = U; p.nw = nw; p.grid = grid; p.pairs = pairs;
+          if ((A->n + (int64_t)nw * U - 1) / ((int64_t)nw * U) <= kMaxGrid || nw == 8) cands.push_back(p);
+        }
   }
   SolveState run{};
   run.status = S_RUN;
@@ -903,7 +912,7 @@ __global__ __launch_bounds__(kBlock) void k_fused_lg(int n, int ntiles, const in
   store_block_partials<NV>(part, partials);
 }
 
-template <class E, int RW, int NW, class CI>
+template <class E, int RW, int NW, class CI, bool PAIRS>
 __global__ __launch_bounds__(NW * kWave) void k_fused_rb(int n, int ntiles, const int* __restrict__ rowptr,
                                                          const CI* __restrict__ col,
                                                          const typename E::V* __restrict__ val,
@@ -925,7 +934,9 @@ __global__ __launch_bounds__(NW * kWave) void k_fused_rb(int n, int ntiles, cons
     const int r0 = t * (NW * RW) + (threadIdx.x / kWave) * RW;
     const int r = r0 + l;
     const typename E::Pre pre = e.load(r < n ? r : n - 1);
-    const V acc = csr_block_rows<RW, CH, V, CI>(r0, n, rowptr, col, val, x, buf);
+    V acc;
+    if constexpr (PAIRS) acc = csr_block_rows_pairs<RW, CH, V>(r0, n, rowptr, col, val, x, buf);
+    else acc = csr_block_rows<RW, CH, V, CI>(r0, n, rowptr, col, val, x, buf);
     if (l < RW && r < n) e.apply(r, pre, acc, sc, part);
   }
   __syncthreads();
@@ -954,12 +965,15 @@ static hipError_t launch_fused(const hk_csr_s* A, const SpmvPlan& p, const typen
 #undef HK_FLG
 #define HK_FRB(RR, NWW)                                                                              \
   if (p.L == kRowBlockL && p.U == RR && nw == NWW) {                                                 \
-    if (A->col16)                                                                                    \
-      hipLaunchKernelGGL((k_fused_rb<E, RR, NWW, short>), dim3(grid), dim3(NWW * kWave), 0, s, n,    \
-                         ntiles, A->rowptr, (const short*)A->col16, val, x, e, st, partials);        \
+    if (A->col16 && p.pairs)                                                                         \
+      hipLaunchKernelGGL((k_fused_rb<E, RR, NWW, short, true>), dim3(grid), dim3(NWW * kWave), 0, s, \
+                         n, ntiles, A->rowptr, (const short*)A->col16, val, x, e, st, partials);     \
+    else if (A->col16)                                                                               \
+      hipLaunchKernelGGL((k_fused_rb<E, RR, NWW, short, false>), dim3(grid), dim3(NWW * kWave), 0,   \
+                         s, n, ntiles, A->rowptr, (const short*)A->col16, val, x, e, st, partials);  \
     else                                                                                             \
-      hipLaunchKernelGGL((k_fused_rb<E, RR, NWW, int>), dim3(grid), dim3(NWW * kWave), 0, s, n,      \
-                         ntiles, A->rowptr, A->col, val, x, e, st, partials);                        \
+      hipLaunchKernelGGL((k_fused_rb<E, RR, NWW, int, false>), dim3(grid), dim3(NWW * kWave), 0, s,  \
+                         n, ntiles, A->rowptr, A->col, val, x, e, st, partials);                     \
     return hipGetLastError();                                                                        \
   }
   HK_FRB(16, 2) HK_FRB(32, 2) HK_FRB(64, 2)
@@ -1344,7 +1358,7 @@ template <class R> static BlWork<R> bl_carve(void* base, int64_t n, int64_t nnz,
     w.vec.r[j] = (V*)take(sizeof(V) * n);
     w.vec.u[j] = (V*)take(sizeof(V) * n);
   }
-  w.ahat = (V*)take(sizeof(V) * (nnz > 0 ? nnz : 1));
+  w.ahat = (V*)take(sizeof(V) * (nnz + 1));  // one padding entry (paired-entry products)
   w.partials = (double*)take(sizeof(double) * bl_partial_doubles<R>(n));
   w.st = (SolveState*)take(sizeof(SolveState));
   w.flag = (int*)take(64);

@@ -333,13 +333,16 @@ extern "C" int hk_csr_create(hk_csr* out, int64_t n, int64_t nnz, const int32_t*
   }
   A->max_row = h[1];
   if (!(flags & HK_INT32_COLS) && nnz > 0 && h[2] <= 32767) {
-    if (hipMalloc(&A->col16, 2 * (size_t)nnz) != hipSuccess) {
+    if (hipMalloc(&A->col16, 2 * ((size_t)nnz + 1)) != hipSuccess) {
       delete A;
       HK_FAIL(HK_ENOMEM, "hk_csr_create: hipMalloc failed");
     }
-    hipLaunchKernelGGL(k_col16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, (int)n, d_rowptr,
-                       d_col, A->col16);
-    err = hipGetLastError();
+    err = hipMemsetAsync(A->col16 + nnz, 0, 2, s);
+    if (err == hipSuccess) {
+      hipLaunchKernelGGL(k_col16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, (int)n, d_rowptr,
+                         d_col, A->col16);
+      err = hipGetLastError();
+    }
     if (err == hipSuccess) err = hipStreamSynchronize(s);
     if (err != hipSuccess) {
       (void)hipFree(A->col16);

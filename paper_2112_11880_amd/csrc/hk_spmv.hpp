@@ -156,6 +156,73 @@ __device__ __forceinline__ V csr_block_rows(int r0, int n, const int* __restrict
   return acc;
 }
 
+// Paired layout of the same product for the 16-bit column stream: lane l
+// takes entries c0 + 2l + 128k and the next one, with one 4-byte load for
+// both column offsets and one load of both values (16 bytes for complex64),
+// half the load instructions of the lane-per-entry layout.  Passes start
+// at even entries, so the first pass may load the entry before the block
+// and the last may load the entry after the end of the matrix: `val` and
+// `col` must hold one padding entry after the last, and any entry outside
+// the block decodes with the block's base, so every decoded column is
+// clamped to [0, n).  Sums are taken in entry order, as in csr_block_rows.
+template <class V> struct pair_of;
+template <> struct pair_of<float2> { typedef float type __attribute__((ext_vector_type(4))); };
+
+template <int R, int CH, class V>
+__device__ __forceinline__ V csr_block_rows_pairs(int r0, int n, const int* __restrict__ rowptr,
+                                                  const short* __restrict__ col, const V* __restrict__ val,
+                                                  const V* __restrict__ x, V* buf) {
+  static_assert(R == 16 || R == 32 || R == 64, "rows per wave");
+  static_assert(CH % 2 == 0, "pairs");
+  const int l = threadIdx.x & (kWave - 1);
+  const int base = r0 & ~63;
+  const int li = l < R ? l : R;
+  const int rs = rowptr[r0 + li < n ? r0 + li : n];
+  int rend;
+  if constexpr (R == kWave) rend = rowptr[r0 + kWave < n ? r0 + kWave : n];
+  else rend = __shfl(rs, R, kWave);
+  const int nxt = __shfl(rs, (l + 1) & (kWave - 1), kWave);
+  const int re = l < kWave - 1 ? nxt : rend;
+  const int s0 = __shfl(rs, 0, kWave) & ~1;
+  V acc = czero<V>();
+  for (int c0 = s0; c0 < rend; c0 += CH * kWave) {
+    const int cend = c0 + CH * kWave < rend ? c0 + CH * kWave : rend;
+    int c[CH];
+    V a[CH];
+#pragma unroll
+    for (int k = 0; k < CH / 2; ++k) {
+      const int e = c0 + 2 * l + 2 * kWave * k;
+      const int p = e < cend ? e : ((cend - 1) & ~1);  // even, in [c0, cend)
+      const int pr = __builtin_nontemporal_load(reinterpret_cast<const int*>(col + p));
+      c[2 * k] = min(max(base + (int)(short)(pr & 0xffff), 0), n - 1);
+      c[2 * k + 1] = min(max(base + (pr >> 16), 0), n - 1);
+      if constexpr (sizeof(V) == 8) {
+        const auto v = __builtin_nontemporal_load(reinterpret_cast<const typename pair_of<V>::type*>(val + p));
+        a[2 * k] = cmake<V>(v.x, v.y);
+        a[2 * k + 1] = cmake<V>(v.z, v.w);
+      } else {
+        a[2 * k] = ldnt(val + p);
+        a[2 * k + 1] = ldnt(val + p + 1);
+      }
+    }
+    V xv[CH];
+#pragma unroll
+    for (int k = 0; k < CH; ++k) xv[k] = x[c[k]];
+#pragma unroll
+    for (int k = 0; k < CH; ++k) {
+      const int e = c0 + 2 * l + 2 * kWave * (k / 2) + (k & 1);
+      if (e < cend) buf[e - c0] = cmul(a[k], xv[k]);
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (l < R) {
+      const int lo = rs > c0 ? rs : c0, hi = re < cend ? re : cend;
+      for (int e = lo; e < hi; ++e) acc = cadd(acc, buf[e - c0]);
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  return acc;
+}
+
 // Row-block tile of virtual block b: within every run of 8*kTileChunk
 // consecutive tiles, XCD x (virtual blocks b with b % 8 == x) takes the x-th
 // chunk of kTileChunk tiles, so neighbouring tiles -- which gather the same
