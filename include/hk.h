@@ -104,6 +104,18 @@ int hk_csr_info(hk_csr A, int64_t* n, int64_t* nnz, int32_t* max_row, int32_t* c
  * HK_EINVAL. */
 int hk_csr_set_plan(hk_csr A, int32_t lanes_per_row, int32_t rows_per_group, int32_t grid);
 
+/* Fix the launch shape of the solvers' fused products (the CSR products
+ * with a dot or vector-update epilogue inside hk_krylov_solve and the
+ * mixed solve's inner iteration), for both precisions: the row-block scheme
+ * with rows_per_wave in {16,32,64} consecutive rows per wave, waves in
+ * {2,4,8} per workgroup, grid workgroups (0: one per tile, at most 8192),
+ * and paired = 1 for the paired-entry layout (each lane loads two
+ * consecutive entries; needs the 16-bit column stream, see hk_csr_info).
+ * Without it, a tuned handle times the candidates on its first solve and an
+ * untuned one uses its CSR shape.  hk_csr_set_plan clears it.  Anything
+ * else gives HK_EINVAL. */
+int hk_csr_set_solver_plan(hk_csr A, int32_t rows_per_wave, int32_t waves, int32_t grid, int32_t paired);
+
 /*
  * y = alpha * A x + beta * y (Section 3, Table 8: CSR SpMV).  alpha and
  * beta are host complex scalars {re, im} of A's precision (double[2] for

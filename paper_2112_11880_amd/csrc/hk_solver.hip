@@ -775,16 +775,16 @@ static int bicgstab(hk_csr_s* A, const cplx<R>* val, const cplx<R>* b, cplx<R>* 
     int rc = spmv_dispatch(&tmp, x, wk.r, b, nullptr, nullptr, 1, s);
     if (rc != HK_OK) return rc;
   }
+  // fused-product shape: one fixed by hk_csr_set_solver_plan or tuned (on
+  // the first solve of a tuned handle), else the handle's CSR shape
   SpmvPlan dp = A->plan;
   dp.nw = 0;
-  if (A->plan.tuned) {
-    SpmvPlan& cached = A->dot_plan[sizeof(R) == 4 ? 1 : 0];
-    if (!cached.tuned) {
-      int rc = tune_dot<R>(A, wk, &cached, s);
-      if (rc != HK_OK) return rc;
-    }
-    dp = cached;
+  SpmvPlan& cached = A->dot_plan[sizeof(R) == 4 ? 1 : 0];
+  if (!cached.tuned && A->plan.tuned) {
+    int rc = tune_dot<R>(A, wk, &cached, s);
+    if (rc != HK_OK) return rc;
   }
+  if (cached.tuned) dp = cached;
   const int gs = dot_grid(A, dp);
   SolveState init{};
   init.history = o.d_history;
@@ -1220,14 +1220,12 @@ static int tfqmr(hk_csr_s* A, const double2* val, const double2* b, double2* x, 
   }
   SpmvPlan dp = A->plan;
   dp.nw = 0;
-  if (A->plan.tuned) {
-    SpmvPlan& cached = A->dot_plan[0];
-    if (!cached.tuned) {
-      int rc = tune_dot<R>(A, wk, &cached, s);
-      if (rc != HK_OK) return rc;
-    }
-    dp = cached;
+  SpmvPlan& cached = A->dot_plan[0];
+  if (!cached.tuned && A->plan.tuned) {
+    int rc = tune_dot<R>(A, wk, &cached, s);
+    if (rc != HK_OK) return rc;
   }
+  if (cached.tuned) dp = cached;
   const int gs = dot_grid(A, dp);
   SolveState init{};
   init.history = o.d_history;
@@ -1658,22 +1656,20 @@ static int bicgstab_l(hk_csr_s* A, const double2* val, const double2* b, double2
   }
   SpmvPlan dp = A->plan;
   dp.nw = 0;
-  if (A->plan.tuned) {
-    SpmvPlan& cached = A->dot_plan[0];
-    if (!cached.tuned) {
-      // the workspace vectors serve as tuning operands before the solve starts
-      Work<R> tv{};
-      tv.ahat = wk.ahat;
-      tv.p = wk.vec.r[1];
-      tv.v = wk.vec.u[1];
-      tv.rh = wk.rt;
-      tv.partials = wk.partials;
-      tv.st = wk.st;
-      int rc = tune_dot<R>(A, tv, &cached, s);
-      if (rc != HK_OK) return rc;
-    }
-    dp = cached;
+  SpmvPlan& cached = A->dot_plan[0];
+  if (!cached.tuned && A->plan.tuned) {
+    // the workspace vectors serve as tuning operands before the solve starts
+    Work<R> tv{};
+    tv.ahat = wk.ahat;
+    tv.p = wk.vec.r[1];
+    tv.v = wk.vec.u[1];
+    tv.rh = wk.rt;
+    tv.partials = wk.partials;
+    tv.st = wk.st;
+    int rc = tune_dot<R>(A, tv, &cached, s);
+    if (rc != HK_OK) return rc;
   }
+  if (cached.tuned) dp = cached;
   const int gs = dot_grid(A, dp);
   SolveState init{};
   init.history = o.d_history;

@@ -404,6 +404,22 @@ extern "C" int hk_csr_set_plan(hk_csr A, int32_t L, int32_t U, int32_t grid) {
   if (!A) HK_FAIL(HK_EINVAL, "hk_csr_set_plan: NULL handle");
   if (!valid_shape(L, U) || grid < 0) HK_FAIL(HK_EINVAL, "hk_csr_set_plan: bad shape L=%d U=%d grid=%d", L, U, grid);
   A->plan.L = L; A->plan.U = U; A->plan.grid = grid; A->plan.tuned = 0;
+  A->dot_plan[0] = A->dot_plan[1] = SpmvPlan{};  // the solvers' products follow the new shape
+  return HK_OK;
+}
+
+extern "C" int hk_csr_set_solver_plan(hk_csr A, int32_t rows_per_wave, int32_t waves, int32_t grid,
+                                      int32_t paired) {
+  if (!A) HK_FAIL(HK_EINVAL, "hk_csr_set_solver_plan: NULL handle");
+  if (!(rows_per_wave == 16 || rows_per_wave == 32 || rows_per_wave == 64) ||
+      !(waves == 2 || waves == 4 || waves == 8) || grid < 0 || (paired != 0 && paired != 1))
+    HK_FAIL(HK_EINVAL, "hk_csr_set_solver_plan: bad shape rows_per_wave=%d waves=%d grid=%d paired=%d",
+            rows_per_wave, waves, grid, paired);
+  if (paired && !A->col16)
+    HK_FAIL(HK_EINVAL, "hk_csr_set_solver_plan: the paired layout needs the 16-bit column stream");
+  SpmvPlan p;
+  p.L = kRowBlockL; p.U = rows_per_wave; p.nw = waves; p.grid = grid; p.pairs = paired; p.tuned = 2;
+  A->dot_plan[0] = A->dot_plan[1] = p;
   return HK_OK;
 }
 

@@ -52,6 +52,7 @@ SIGNATURES = {
     "hk_csr_plan": ([P, C.POINTER(I32), C.POINTER(I32), C.POINTER(I32), C.POINTER(I32)], C.c_int),
     "hk_csr_set_plan": ([P, I32, I32, I32], C.c_int),
     "hk_csr_info": ([P, C.POINTER(I64), C.POINTER(I64), C.POINTER(I32), C.POINTER(I32)], C.c_int),
+    "hk_csr_set_solver_plan": ([P, I32, I32, I32, I32], C.c_int),
     "hk_spmv": ([P, P, P, P, P, P], C.c_int),
     "hk_residual": ([P, P, P, P, P], C.c_int),
     "hk_zdotc": ([I64, P, P, P, P], C.c_int),
@@ -168,6 +169,9 @@ class CSR:
 
     def set_plan(self, lanes_per_row, rows_per_group, grid=0):
         _check(load().hk_csr_set_plan(self.h, lanes_per_row, rows_per_group, grid))
+
+    def set_solver_plan(self, rows_per_wave, waves, grid=0, paired=False):
+        _check(load().hk_csr_set_solver_plan(self.h, int(rows_per_wave), int(waves), int(grid), int(bool(paired))))
 
     def spmv(self, x, y=None, alpha=1.0, beta=0.0):
         """y = alpha A x + beta y (y allocated when None)."""

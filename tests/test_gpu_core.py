@@ -497,3 +497,50 @@ def test_solvers_same_bits_from_either_column_stream(hk):
             x, info = hk.krylov_solve(A, b, tol=1e-12, max_iter=25, method=method, ell=4)
             xs.append((host(x), info["iters"], info["relres_rec"]))
         assert xs[0][1:] == xs[1][1:] and np.array_equal(xs[0][0], xs[1][0]), method
+
+
+def test_solver_plans_every_shape(hk, oracle):
+    """Every fixed shape of the solvers' fused products (16/32/64 rows per
+    wave, 2/4/8 waves, lane-per-entry and paired layouts, one workgroup per
+    tile and a 3-workgroup grid stride) gives the oracle's iterate: two
+    BiCGStab and two TFQMR steps and one BiCGStab(2) cycle in complex128,
+    one BiCGStab step in complex64.  The matrix has an odd entry count, so
+    the paired layout's last pass reads the padding entry, and its blocks
+    start at odd entries."""
+    rowptr, col, val = small_mesh_problem((8, 6, 4), 3)
+    n = rowptr.shape[0] - 1
+    assert col.shape[0] % 2 == 1 and np.any(rowptr[::16] % 2 == 1)
+    rng = np.random.default_rng(31)
+    b = crandn(rng, n)
+    b32 = b.astype(np.complex64)
+    v32 = val.astype(np.complex64)
+    ref = {"bicgstab": oracle.bicgstab(rowptr, col, val, b, tol=1e-14, maxit=2)[0],
+           "tfqmr": oracle.tfqmr(rowptr, col, val, b, tol=1e-14, maxit=2)[0],
+           "bicgstab_l": oracle.bicgstab_l(rowptr, col, val, b, ell=2, tol=1e-14, maxit=1)[0]}
+    ref64 = oracle.bicgstab_c64(rowptr, col, v32, b32, tol=1e-9, maxit=1)[0]
+    A = make_csr(hk, rowptr, col, val)
+    A32 = make_csr(hk, rowptr, col, v32)
+    for rw in (16, 32, 64):
+        for nw in (2, 4, 8):
+            for paired in (False, True):
+                for grid in (0, 3):
+                    say("solver plan", rw, nw, "paired" if paired else "lanes", grid)
+                    A.set_solver_plan(rw, nw, grid, paired)
+                    for method, its in (("bicgstab", 2), ("tfqmr", 2), ("bicgstab_l", 1)):
+                        x, info = hk.krylov_solve(A, dev(b), tol=1e-14, max_iter=its, method=method, ell=2)
+                        assert info["iters"] == its, (method, info)
+                        xo = ref[method]
+                        assert np.linalg.norm(host(x) - xo) <= 1e-10 * np.linalg.norm(xo), (method, rw, nw, paired, grid)
+                    A32.set_solver_plan(rw, nw, grid, paired)
+                    x, info = hk.krylov_solve(A32, dev(b32), tol=1e-9, max_iter=1)
+                    assert info["iters"] == 1
+                    assert np.linalg.norm(host(x) - ref64) <= 1e-6 * np.linalg.norm(ref64), (rw, nw, paired, grid)
+    for bad in ((8, 4, 0, False), (32, 3, 0, False), (32, 4, -1, False)):
+        with pytest.raises(hk.HKError):
+            A.set_solver_plan(*bad)
+    Ai = hk.CSR(dev(rowptr), dev(col), dev(val), compact_cols=False)
+    with pytest.raises(hk.HKError):
+        Ai.set_solver_plan(32, 4, 0, True)
+    Ai.set_solver_plan(32, 4, 0, False)
+    x, info = hk.krylov_solve(Ai, dev(b), tol=1e-14, max_iter=2)
+    assert np.linalg.norm(host(x) - ref["bicgstab"]) <= 1e-10 * np.linalg.norm(ref["bicgstab"])
