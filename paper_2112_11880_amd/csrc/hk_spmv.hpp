@@ -223,20 +223,24 @@ __device__ __forceinline__ V csr_block_rows_pairs(int r0, int n, const int* __re
   return acc;
 }
 
-// Row-block tile of virtual block b: within every run of 8*kTileChunk
+// Row-block tile of virtual block b: within every run of 8*CHUNK
 // consecutive tiles, XCD x (virtual blocks b with b % 8 == x) takes the x-th
-// chunk of kTileChunk tiles, so neighbouring tiles -- which gather the same
-// x entries -- share an L2 while the chip still advances as one front.  A
-// trailing partial run keeps the identity order.  Chunks of 8 measured
-// ~2 us faster per product than chunks of 1, 32 or 128 on the 1.8M-row
-// system.
+// chunk of CHUNK tiles, so neighbouring tiles -- which gather the same x
+// entries -- share an L2 while the chip still advances as one front.  A
+// trailing partial run keeps the identity order.  For the fused solver
+// products chunks of 8 measured ~2 us faster per product than chunks of 1,
+// 32 or 128 on the 1.8M-row system; the plain product with 32 rows per wave
+// and 16-bit columns measured 94.4 us with chunks of 512 tiles against 95.9
+// us with 8 (and 95.1-96.4 us with 128, 256, 1024 or 2048).
 constexpr int kTileChunk = 8;
+constexpr int kSpmvTileChunk = 512;
+template <int CHUNK = kTileChunk>
 __device__ __forceinline__ int tile_of(int b, int ntiles) {
-  constexpr int S = kXcds * kTileChunk;
+  constexpr int S = kXcds * CHUNK;
   const int q = b / S;
   if ((q + 1) * S > ntiles) return b;
   const int r = b - q * S;
-  return q * S + (r % kXcds) * kTileChunk + r / kXcds;
+  return q * S + (r % kXcds) * CHUNK + r / kXcds;
 }
 
 // Row-block launch shapes: plan L = kRowBlockL selects the scheme and plan U
