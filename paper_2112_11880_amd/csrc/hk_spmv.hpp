@@ -231,7 +231,8 @@ __device__ __forceinline__ V csr_block_rows_pairs(int r0, int n, const int* __re
 // products chunks of 8 measured ~2 us faster per product than chunks of 1,
 // 32 or 128 on the 1.8M-row system; the plain product with 32 rows per wave
 // and 16-bit columns measured 94.4 us with chunks of 512 tiles against 95.9
-// us with 8 (and 95.1-96.4 us with 128, 256, 1024 or 2048).
+// us with 8 (and 95.1-96.4 us with 128, 256, 1024 or 2048), so it uses 512;
+// with 64 rows per wave 512 was no better, and the other shapes keep 8.
 constexpr int kTileChunk = 8;
 constexpr int kSpmvTileChunk = 512;
 template <int CHUNK = kTileChunk>
