@@ -114,7 +114,7 @@ def bench_batched(hk, torch, np, dev, log):
     """
     from synth import configs
     res = {}
-    c = configs.config4a()
+    c = configs.sweep48()
     kap = [complex(a, b) for a, b in c["kappa2"]]
     B = torch.from_numpy(np.repeat(c["g"][:, None], 64, axis=1)).to(dev)
     rp, cl = torch.from_numpy(c["rowptr"]).to(dev), torch.from_numpy(c["col"]).to(dev)
@@ -147,7 +147,7 @@ def bench_batched(hk, torch, np, dev, log):
                           "relres_true_max": max(i["relres_true"] for i in infos),
                           "plain_time_s_extrapolated": round(8 * t_plain, 4),
                           "speedup_vs_plain": round(8 * t_plain / t_sweep, 3)}
-    systems = configs.config4b_systems()
+    systems = configs.uneven_systems()
     offs, rows, cols, vals, bs = [0], [], [], [], []
     for sy in systems:
         rows.append(sy["rowptr"][:-1] + sum(x.shape[0] for x in cols))
@@ -192,7 +192,7 @@ def bench_hex(hk, torch, np, dev, stream, log, reps=20):
     to 27 per row -- the row length of the paper's car-cavity matrices): CSR
     product in the tuned shape, and BiCGStab / TFQMR to 1e-8."""
     from synth import configs
-    c = configs.config_hex()
+    c = configs.hex_box()
     n, nnz = int(c["n"]), int(c["col"].shape[0])
     t = lambda a: torch.from_numpy(a).to(dev)
     A = hk.CSR(t(c["rowptr"]), t(c["col"]), t(c["val"]), autotune=True)
@@ -225,7 +225,7 @@ def bench_hex(hk, torch, np, dev, stream, log, reps=20):
 def bench_adjoint(hk, torch, np, dev, log):
     """Forward + adjoint solve on the 48^3, 216-block differentiable problem."""
     from synth import configs
-    d = configs.config5()
+    d = configs.adjoint48()
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     prob = hk.HelmholtzProblem(rowptr=t(d["rowptr"]), col=t(d["col"]), K=t(d["K"]), bm_ptr=t(d["bm_ptr"]),
                                bm_blk=t(d["bm_blk"]), bm_val=t(d["bm_val"]), tet_nodes=t(d["tet_nodes"]),
@@ -254,7 +254,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--spmv-reps", type=int, default=20)
-    ap.add_argument("--workload", default="config2", choices=["config1", "config2"])
+    ap.add_argument("--workload", default="box192", choices=["cube16", "box192"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-solve", action="store_true", help="CSR products only (profiling runs)")
@@ -274,7 +274,7 @@ def main():
     from synth import configs
 
     t0 = time.time()
-    c = configs.config2() if args.workload == "config2" else configs.config1()
+    c = configs.box192() if args.workload == "box192" else configs.cube16()
     n, nnz = int(c["n"]), int(c["col"].shape[0])
     log(f"inputs {args.workload}: n={n} nnz={nnz} ({time.time() - t0:.1f}s)")
     assert torch.cuda.is_available(), "no HIP device"
@@ -351,7 +351,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": ("helmholtz-p1-192x96x96-jittered (1,815,937 rows, 26,606,015 nnz, "
-                                "complex128 CSR, Jacobi BiCGStab to 1e-8)") if args.workload == "config2"
+                                "complex128 CSR, Jacobi BiCGStab to 1e-8)") if args.workload == "box192"
                    else "helmholtz-p1-16^3 (4,913 rows, 63,183 nnz)",
                    "n": n, "nnz": nnz, "spmv_plan": plan, "spmv_reps_per_step": args.spmv_reps},
         "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -73,7 +73,7 @@ def _pack(p, kappa2, g, extra=None):
     return out
 
 
-def config1():
+def cube16():
     """16^3 unit cube, constant c = 340, unjittered (4,913 nodes)."""
     def make():
         m, _ = cube(16)
@@ -81,7 +81,7 @@ def config1():
         k = 2 * math.pi / (10 * m.h)
         g = complex_rhs(np.random.default_rng(0), p.n, p.dirichlet)
         return _pack(p, complex(k * k, DAMP * k * k), g, {"k": np.float64(k)})
-    return _cached("config1", make)
+    return _cached("cube16", make)
 
 
 def _variable_speed(m, rng, bs):
@@ -91,7 +91,7 @@ def _variable_speed(m, rng, bs):
     return c, blk, omega
 
 
-def config2():
+def box192():
     """2:1:1 box, 192x96x96 cells, jittered, 8^3-cell speed blocks (1,815,937 nodes)."""
     def make():
         m, rng = cube(96, jitter=0.2, extent=(2.0, 1.0, 1.0), cells=(192, 96, 96))
@@ -100,10 +100,10 @@ def config2():
         g = complex_rhs(np.random.default_rng(0), p.n, p.dirichlet)
         return _pack(p, complex(omega ** 2, DAMP * omega ** 2), g,
                      {"c": c, "omega": np.float64(omega)})
-    return _cached("config2", make)
+    return _cached("box192", make)
 
 
-def config_hex(cells=86):
+def hex_box(cells=86):
     """Q1 hexahedra (27-point rows) on a jittered unit cube of ``cells``^3,
     c = 340, k = 2*pi/(10 h), 1% damping: the row structure of the paper's
     car-cavity matrices (86^3: 658,503 nodes, 17.2M nonzeros, up to 27 per
@@ -116,7 +116,7 @@ def config_hex(cells=86):
         k = 2 * math.pi / (10 * m.h)
         g = complex_rhs(np.random.default_rng(0), p.n, p.dirichlet)
         return _pack(p, complex(k * k, DAMP * k * k), g)
-    return _cached(f"config_hex{cells}", make)
+    return _cached(f"hex_box{cells}", make)
 
 
 def mesh48():
@@ -124,7 +124,7 @@ def mesh48():
     return m, rng
 
 
-def config4a(nfreq=64):
+def sweep48(nfreq=64):
     """Frequency sweep: 48^3 jittered mesh, c = 340, k_j over [0.5 k0, 1.5 k0]."""
     def make():
         m, _ = mesh48()
@@ -136,18 +136,18 @@ def config4a(nfreq=64):
                 "dirichlet": p.dirichlet, "ks": ks,
                 "kappa2": np.stack([ks ** 2, DAMP * ks ** 2], 1), "g": g,
                 "dims": np.array([48, 48, 48]), "h": np.float64(m.h)}
-    return _cached(f"config4a_{nfreq}", make)
+    return _cached(f"sweep48_{nfreq}", make)
 
 
-def config4b_sizes(nsys=32):
+def uneven_sizes(nsys=32):
     rng = np.random.default_rng(2)
     return rng.integers(8, 49, nsys), rng
 
 
-def config4b(nsys=32):
+def uneven(nsys=32):
     """Uneven batch: nsys unjittered cubes with n_s from default_rng(2)."""
     def make():
-        sizes, rng = config4b_sizes(nsys)
+        sizes, rng = uneven_sizes(nsys)
         out = {"sizes": sizes}
         for s, ns in enumerate(sizes):
             m, _ = cube(int(ns))
@@ -157,16 +157,16 @@ def config4b(nsys=32):
             for key, v in _pack(p, complex(k * k, DAMP * k * k), g).items():
                 out[f"s{s}_{key}"] = v
         return out
-    return _cached(f"config4b_{nsys}", make)
+    return _cached(f"uneven_{nsys}", make)
 
 
-def config4b_systems(nsys=32):
-    z = config4b(nsys)
+def uneven_systems(nsys=32):
+    z = uneven(nsys)
     return [{k[len(f"s{s}_"):]: v for k, v in z.items() if k.startswith(f"s{s}_")}
             for s in range(len(z["sizes"]))]
 
 
-def config5():
+def adjoint48():
     """Differentiable case: 48^3 jittered mesh, 216 speed blocks, 256 sample nodes."""
     def make():
         m, rng = mesh48()
@@ -184,4 +184,4 @@ def config5():
                      "tet_nodes": tnodes, "tet_block": tblk, "tet_vol": tvol,
                      "tet_ptr": tptr, "samples": S})
         return out
-    return _cached("config5", make)
+    return _cached("adjoint48", make)

@@ -6,7 +6,7 @@
   on the GPU) matches the oracle's adjoint gradient to 1e-8 relative and
   central finite differences (GPU solves, step 1e-6 relative) to 1e-5.
 * Full 48^3 / 216-block problem: grad_c and sampled grad_g match the stored
-  oracle gradient (tests/golden/config5_oracle_gradient.txt) to 1e-8.
+  oracle gradient (tests/golden/adjoint48_oracle_gradient.txt) to 1e-8.
 """
 import math
 import os
@@ -21,7 +21,7 @@ from synth import configs
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
-GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "config5_oracle_gradient.txt")
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "adjoint48_oracle_gradient.txt")
 
 
 def say(*a):
@@ -143,10 +143,10 @@ def read_golden():
 
 
 @pytest.mark.skipif(not os.path.exists(GOLDEN), reason="golden oracle gradient not generated")
-def test_adjoint_config5_full(hk):
-    d = configs.config5()
+def test_adjoint_adjoint48_full(hk):
+    d = configs.adjoint48()
     prob = make_problem(hk, d)
-    say("adjoint config5")
+    say("adjoint adjoint48")
     L, gg, gc = gpu_grad(hk, prob, d, 1e-12)
     Lo, gco, ggo = read_golden()
     assert abs(L - Lo) <= 1e-8 * Lo

@@ -74,7 +74,7 @@ def test_sweep_small_matches_oracle(hk, oracle, nc, nsys):
         assert infos[j]["status"] == 0, (j, infos[j])
         assert np.linalg.norm(Xh[:, j] - xo) <= 1e-7 * np.linalg.norm(xo), j
         # BiCGStab iteration counts at 1e-10 depend on the summation order of
-        # the dots (one 6^3 system: 100 here vs 135 in the oracle; config 1:
+        # the dots (one 6^3 system: 100 here vs 135 in the oracle; the 16^3 cube:
         # numpy 1,960 vs oracle 2,410), so the count is bounded loosely and
         # the solution and true residual carry the parity
         assert abs(infos[j]["iters"] - oi["iters"]) <= max(10, 0.4 * oi["iters"]), (j, infos[j], oi)
@@ -195,13 +195,13 @@ def test_blockdiag_rejects_coupled_systems(hk):
         hk.blockdiag_solve(A, [0, 30, int(offs[-1])], dev(b))
 
 
-def test_sweep_config4a_full(hk, oracle):
+def test_sweep_sweep48_full(hk, oracle):
     """64 frequencies on the 48^3 jittered mesh (117,649 nodes), tol 1e-8."""
-    c = configs.config4a()
+    c = configs.sweep48()
     n = int(c["n"])
     kap = [complex(a, b) for a, b in c["kappa2"]]
     B = np.repeat(c["g"][:, None], 64, axis=1)
-    say("sweep config4a")
+    say("sweep sweep48")
     X, infos = hk.sweep_solve(dev(c["rowptr"]), dev(c["col"]), dev(c["K"]), dev(c["M"]), kap, dev(B),
                               tol=1e-8)
     Xh = host(X)
@@ -216,9 +216,9 @@ def test_sweep_config4a_full(hk, oracle):
     assert n == 117649
 
 
-def test_blockdiag_config4b_full(hk, oracle):
+def test_blockdiag_uneven_full(hk, oracle):
     """32 unjittered cubes with 8..48 cells per side (1,073,278 rows), tol 1e-8."""
-    systems = configs.config4b_systems()
+    systems = configs.uneven_systems()
     offs = [0]
     rows, cols, vals, bs = [], [], [], []
     for s in systems:
@@ -233,7 +233,7 @@ def test_blockdiag_config4b_full(hk, oracle):
     val = np.concatenate(vals)
     b = np.concatenate(bs)
     A = hk.CSR(dev(rowptr), dev(col), dev(val), autotune=True)
-    say("blockdiag config4b", offs[-1])
+    say("blockdiag uneven", offs[-1])
     x, infos = hk.blockdiag_solve(A, offs, dev(b), tol=1e-8)
     xh = host(x)
     say("iters", [i["iters"] for i in infos])

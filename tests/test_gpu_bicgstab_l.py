@@ -70,10 +70,10 @@ def test_bicgstab_l_iterates(hk, oracle):
 
 
 @pytest.mark.parametrize("ell", [2, 8])
-def test_bicgstab_l_config1(hk, oracle, ell):
-    c = configs.config1()
+def test_bicgstab_l_cube16(hk, oracle, ell):
+    c = configs.cube16()
     A = make_csr(hk, c["rowptr"], c["col"], c["val"], autotune=True)
-    say("bicgstab_l config1 l", ell)
+    say("bicgstab_l cube16 l", ell)
     x, info, hist = hk.krylov_solve(A, dev(c["g"]), tol=1e-8, method="bicgstab_l", ell=ell, history=True)
     xo, oi = oracle.bicgstab_l(c["rowptr"], c["col"], c["val"], c["g"], ell=ell, tol=1e-8)
     say("gpu", info, "oracle", oi)
@@ -102,7 +102,7 @@ def test_bicgstab_l_edges_and_errors(hk, oracle):
     x, info = hk.krylov_solve(A2, dev(np.array([1.0, 2.0], dtype=np.complex128)), method="bicgstab_l", ell=4)
     assert info["status"] == hk.HK_BREAKDOWN and hk.BD_NAMES[info["breakdown"]] == "sigma"
     assert info["iters"] == 0 and np.all(host(x) == 0)
-    c = configs.config1()
+    c = configs.cube16()
     A = make_csr(hk, c["rowptr"], c["col"], c["val"])
     for bad in (0, 3, 16):
         with pytest.raises(hk.HKError):
@@ -117,12 +117,12 @@ def test_bicgstab_l_edges_and_errors(hk, oracle):
         hk.krylov_solve(A32, dev(c["g"].astype(np.complex64)), method="bicgstab_l")
 
 
-def test_bicgstab_l_config2(hk, oracle):
-    c = configs.config2()
+def test_bicgstab_l_box192(hk, oracle):
+    c = configs.box192()
     A = make_csr(hk, c["rowptr"], c["col"], c["val"], autotune=True)
-    say("bicgstab_l(8) config2 tol 1e-8")
+    say("bicgstab_l(8) box192 tol 1e-8")
     x, info = hk.krylov_solve(A, dev(c["g"]), tol=1e-8, method="bicgstab_l", ell=8)
-    say("config2", info)
+    say("box192", info)
     assert info["status"] == hk.HK_OK, info
     r = oracle.residual(c["rowptr"], c["col"], c["val"], c["g"], host(x))
     assert np.linalg.norm(r) / np.linalg.norm(c["g"]) <= 1.05e-8

@@ -213,26 +213,26 @@ def test_spmv_complex64(hk, oracle):
     assert np.all(np.abs(y - ref) <= bound)
 
 
-def test_spmv_config1_and_autotune(hk, oracle):
-    c = configs.config1()
+def test_spmv_cube16_and_autotune(hk, oracle):
+    c = configs.cube16()
     x = crandn(np.random.default_rng(5), int(c["n"]))
     ref = oracle.spmv(c["rowptr"], c["col"], c["val"], x)
     bound = 1e-12 * spmv_bound(c["rowptr"], c["col"], c["val"], x)
-    say("spmv config1 autotune")
+    say("spmv cube16 autotune")
     A = make_csr(hk, c["rowptr"], c["col"], c["val"], autotune=True)
     assert A.plan()["tuned"]
     y = host(A.spmv(dev(x)))
     assert np.all(np.abs(y - ref) <= bound)
 
 
-def test_spmv_config2_full(hk, oracle):
+def test_spmv_box192_full(hk, oracle):
     """The 1.8M-row / 26.6M-nnz matrix, every row, in the benchmark's launch shape."""
-    c = configs.config2()
+    c = configs.box192()
     n = int(c["n"])
     x = crandn(np.random.default_rng(6), n)
     ref = oracle.spmv(c["rowptr"], c["col"], c["val"], x)
     bound = 1e-12 * spmv_bound(c["rowptr"], c["col"], c["val"], x)
-    say("spmv config2 autotune", n)
+    say("spmv box192 autotune", n)
     A = make_csr(hk, c["rowptr"], c["col"], c["val"], autotune=True)
     say("plan", A.plan())
     y = host(A.spmv(dev(x)))
@@ -288,11 +288,11 @@ def test_elementwise_parity(hk, oracle):
 
 # ------------------------------------------------------------- BiCGStab
 
-def test_solve_config1(hk, oracle):
-    c = configs.config1()
+def test_solve_cube16(hk, oracle):
+    c = configs.cube16()
     A = make_csr(hk, c["rowptr"], c["col"], c["val"], autotune=True)
     b = dev(c["g"])
-    say("solve config1 tol 1e-8")
+    say("solve cube16 tol 1e-8")
     x8, info8 = hk.krylov_solve(A, b, tol=1e-8)
     assert info8["status"] == hk.HK_OK, info8
     xh = host(x8)
@@ -305,7 +305,7 @@ def test_solve_config1(hk, oracle):
     # oracle (2,410), a NumPy run of the same recurrences (1,960) and this
     # path all reach 1e-8, at counts up to ~20% apart.
     assert abs(info8["iters"] - oi8["iters"]) <= 0.25 * oi8["iters"]
-    say("solve config1 tol 1e-10")
+    say("solve cube16 tol 1e-10")
     x10, info10 = hk.krylov_solve(A, b, tol=1e-10)
     assert info10["status"] == hk.HK_OK
     xo, _ = oracle.bicgstab(c["rowptr"], c["col"], c["val"], c["g"], tol=1e-10)
@@ -404,7 +404,7 @@ def test_solve_breakdowns_and_errors(hk, oracle):
     with pytest.raises(hk.HKError):
         hk.krylov_solve(A, dev(np.ones(2, dtype=np.complex128)))
     say("nonfinite rhs")
-    c = configs.config1()
+    c = configs.cube16()
     A = make_csr(hk, c["rowptr"], c["col"], c["val"])
     g = c["g"].copy()
     g[7] = np.nan
@@ -428,17 +428,17 @@ def test_solve_breakdowns_and_errors(hk, oracle):
 
 def test_solve_history(hk):
     say("history")
-    c = configs.config1()
+    c = configs.cube16()
     A = make_csr(hk, c["rowptr"], c["col"], c["val"])
     x, info, hist = hk.krylov_solve(A, dev(c["g"]), tol=1e-6, history=True)
     h = host(hist)
     assert h[0] == pytest.approx(1.0) and h[-1] <= 1e-6 and h[-1] == pytest.approx(info["relres_rec"])
 
 
-def test_mixed_config1(hk, oracle):
-    c = configs.config1()
+def test_mixed_cube16(hk, oracle):
+    c = configs.cube16()
     A = make_csr(hk, c["rowptr"], c["col"], c["val"], autotune=True)
-    say("mixed config1", A.plan())
+    say("mixed cube16", A.plan())
     x, info = hk.krylov_solve_mixed(A, dev(c["g"]), inner_tol=1e-4, outer_tol=1e-10)
     assert info["status"] == hk.HK_OK, info
     xh = host(x)
@@ -450,18 +450,18 @@ def test_mixed_config1(hk, oracle):
     assert err <= 1e-7
 
 
-def test_solve_config2(hk, oracle):
-    c = configs.config2()
-    say("solve config2 tol 1e-8")
+def test_solve_box192(hk, oracle):
+    c = configs.box192()
+    say("solve box192 tol 1e-8")
     A = make_csr(hk, c["rowptr"], c["col"], c["val"], autotune=True)
     x, info = hk.krylov_solve(A, dev(c["g"]), tol=1e-8)
-    say("config2", info)
+    say("box192", info)
     assert info["status"] == hk.HK_OK, info
     r = oracle.residual(c["rowptr"], c["col"], c["val"], c["g"], host(x))
     assert np.linalg.norm(r) / np.linalg.norm(c["g"]) <= 1.05e-8
 
 
-def test_solve_config2_wide_workgroup_shapes(hk, oracle):
+def test_solve_box192_wide_workgroup_shapes(hk, oracle):
     """The fused products of the 1.8M-row solve in row-block shapes whose
     workgroups widen to stay under the workgroup cap (64-row blocks: 4 waves;
     16-row blocks: 8 waves and a grid-stride walk); 6 iterations each give
@@ -469,12 +469,12 @@ def test_solve_config2_wide_workgroup_shapes(hk, oracle):
     iterates from different summation orders separate quickly: numpy vs the
     oracle differ by 6e-14 after 6 iterations, 8e-13 after 8, 2e-9 after 10
     and 0.44 after 20.)"""
-    c = configs.config2()
+    c = configs.box192()
     A = make_csr(hk, c["rowptr"], c["col"], c["val"])
     g = dev(c["g"])
     xo, _ = oracle.bicgstab(c["rowptr"], c["col"], c["val"], c["g"], tol=1e-14, maxit=6)
     for plan in ((64, 32, 0), (64, 64, 0), (64, 16, 0), (16, 1, 0)):
-        say("config2 6 iterations, plan", plan)
+        say("box192 6 iterations, plan", plan)
         A.set_plan(*plan)
         x, info = hk.krylov_solve(A, g, tol=1e-14, max_iter=6)
         assert info["iters"] == 6 and info["status"] == hk.HK_NOT_CONVERGED, info

@@ -77,7 +77,7 @@ def test_hex_spmv_every_shape(hk, oracle):
 
 def test_hex86_spmv_full(hk, oracle):
     """The 658,503-row / 17.2M-nnz matrix, every row, in the tuned shape."""
-    c = configs.config_hex()
+    c = configs.hex_box()
     n = int(c["n"])
     x = crandn(np.random.default_rng(6), n)
     ref = oracle.spmv(c["rowptr"], c["col"], c["val"], x)

@@ -80,10 +80,10 @@ def test_tfqmr_iterates_every_launch_shape(hk, oracle):
             assert abs(info["relres_rec"] - oi["relres_rec"]) <= 10 * bound * oi["relres_rec"]
 
 
-def test_tfqmr_config1_full_solve(hk, oracle):
-    c = configs.config1()
+def test_tfqmr_cube16_full_solve(hk, oracle):
+    c = configs.cube16()
     A = make_csr(hk, c["rowptr"], c["col"], c["val"], autotune=True)
-    say("tfqmr config1 tol 1e-8")
+    say("tfqmr cube16 tol 1e-8")
     x, info, hist = hk.krylov_solve(A, dev(c["g"]), tol=1e-8, method="tfqmr", history=True)
     xo, oi = oracle.tfqmr(c["rowptr"], c["col"], c["val"], c["g"], tol=1e-8)
     say("gpu", info, "oracle", oi)
@@ -95,7 +95,7 @@ def test_tfqmr_config1_full_solve(hk, oracle):
     assert abs(info["iters"] - oi["iters"]) <= max(10, 0.25 * oi["iters"])
     h = host(hist)
     assert h.shape[0] == info["iters"] + 1 and abs(h[0] - 1.0) < 1e-12 and h[-1] <= 1e-8
-    say("tfqmr config1 tol 1e-11 vs the oracle solution")
+    say("tfqmr cube16 tol 1e-11 vs the oracle solution")
     x, info = hk.krylov_solve(A, dev(c["g"]), tol=1e-11, method="tfqmr")
     xo, _ = oracle.bicgstab(c["rowptr"], c["col"], c["val"], c["g"], tol=1e-12)
     assert info["status"] == hk.HK_OK
@@ -118,7 +118,7 @@ def test_tfqmr_breakdown_edges_and_errors(hk, oracle):
     x, info = hk.krylov_solve(A, dev(b), tol=1e-12, method="tfqmr")
     assert info["status"] == hk.HK_OK and info["iters"] == 1
     assert np.allclose(host(x), b / d, rtol=1e-14, atol=0)
-    c = configs.config1()
+    c = configs.cube16()
     A = make_csr(hk, c["rowptr"], c["col"], c["val"])
     say("tfqmr zero rhs, nonfinite rhs, cap, warm start")
     x, info = hk.krylov_solve(A, dev(np.zeros_like(c["g"])), method="tfqmr")
@@ -140,13 +140,13 @@ def test_tfqmr_breakdown_edges_and_errors(hk, oracle):
         hk.krylov_solve(A32, dev(c["g"].astype(np.complex64)), method="tfqmr")
 
 
-def test_tfqmr_config2(hk, oracle):
+def test_tfqmr_box192(hk, oracle):
     """The 1.8M-row system with the tuned fused-product shape, to 1e-8."""
-    c = configs.config2()
+    c = configs.box192()
     A = make_csr(hk, c["rowptr"], c["col"], c["val"], autotune=True)
-    say("tfqmr config2 tol 1e-8")
+    say("tfqmr box192 tol 1e-8")
     x, info = hk.krylov_solve(A, dev(c["g"]), tol=1e-8, method="tfqmr")
-    say("config2", info)
+    say("box192", info)
     assert info["status"] == hk.HK_OK, info
     r = oracle.residual(c["rowptr"], c["col"], c["val"], c["g"], host(x))
     assert np.linalg.norm(r) / np.linalg.norm(c["g"]) <= 1.05e-8

@@ -161,8 +161,8 @@ def test_bicgstab_diagonal_converges_in_one_iteration(oracle):
     assert np.allclose(x, b / d, rtol=1e-14, atol=0)
 
 
-def test_bicgstab_config1_true_residual_and_scipy(oracle):
-    c1 = configs.config1()
+def test_bicgstab_cube16_true_residual_and_scipy(oracle):
+    c1 = configs.cube16()
     x8, i8 = oracle.bicgstab(c1["rowptr"], c1["col"], c1["val"], c1["g"], tol=1e-8)
     assert i8["status"] == 0 and i8["relres_true"] <= 1.05e-8
     x10, i10 = oracle.bicgstab(c1["rowptr"], c1["col"], c1["val"], c1["g"], tol=1e-10)
@@ -200,7 +200,7 @@ def test_bicgstab_omega_breakdown(oracle):
 
 
 def test_bicgstab_error_paths(oracle):
-    c1 = configs.config1()
+    c1 = configs.cube16()
     g = c1["g"].copy()
     g[5] = np.nan
     _, info = oracle.bicgstab(c1["rowptr"], c1["col"], c1["val"], g)
@@ -243,8 +243,8 @@ def test_tfqmr_matches_scipy_steps_and_dense_lu(oracle, nc, seed):
     assert np.linalg.norm(x - xs) <= 1e-9 * np.linalg.norm(xs)
 
 
-def test_tfqmr_config1_diagonal_breakdown_and_errors(oracle):
-    c1 = configs.config1()
+def test_tfqmr_cube16_diagonal_breakdown_and_errors(oracle):
+    c1 = configs.cube16()
     x, info = oracle.tfqmr(c1["rowptr"], c1["col"], c1["val"], c1["g"], tol=1e-8)
     assert info["status"] == 0 and info["relres_true"] <= 1e-8 <= 1e-8 + info["relres_rec"]
     xb, _ = oracle.bicgstab(c1["rowptr"], c1["col"], c1["val"], c1["g"], tol=1e-12)
@@ -356,8 +356,8 @@ def test_bicgstab_l_pins(oracle, nc, seed):
         assert np.linalg.norm(x - xs) <= 1e-9 * np.linalg.norm(xs)
 
 
-def test_bicgstab_l_config1_edges_and_errors(oracle):
-    c1 = configs.config1()
+def test_bicgstab_l_cube16_edges_and_errors(oracle):
+    c1 = configs.cube16()
     x, info = oracle.bicgstab_l(c1["rowptr"], c1["col"], c1["val"], c1["g"], ell=8, tol=1e-8)
     assert info["status"] == 0 and info["relres_true"] <= 1e-8
     xb, _ = oracle.bicgstab(c1["rowptr"], c1["col"], c1["val"], c1["g"], tol=1e-12)
@@ -427,8 +427,8 @@ def test_bicgstab_c64_diagonal_and_sigma_breakdown(oracle):
     assert info["iters"] == 0 and np.all(x == 0)
 
 
-def test_mixed_refinement_config1(oracle):
-    c1 = configs.config1()
+def test_mixed_refinement_cube16(oracle):
+    c1 = configs.cube16()
     u, info = oracle.mixed_refine(c1["rowptr"], c1["col"], c1["val"], c1["g"])
     assert info["status"] == 0 and info["relres_true"] <= 1e-10
     x, _ = oracle.bicgstab(c1["rowptr"], c1["col"], c1["val"], c1["g"], tol=1e-12)

@@ -99,8 +99,8 @@ def test_interior_rows_closed_form_stencils():
             assert abs(p.M[q] / h ** 3 - em) <= 1e-14
 
 
-def test_config1_shape():
-    c1 = configs.config1()
+def test_cube16_shape():
+    c1 = configs.cube16()
     assert int(c1["n"]) == 4913 and c1["col"].shape[0] == 63183
     assert abs(c1["k"] - 2 * math.pi * 16 / 10) < 1e-12
     assert np.all(c1["g"][c1["dirichlet"]] == 0)
