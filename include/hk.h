@@ -133,13 +133,15 @@ int hk_residual(hk_csr A, const void* d_b, const void* d_x, void* d_r, void* str
 /* *d_res = x^H y = sum conj(x_i) y_i (Section 3, ZDOT: element-wise product,
  * then a two-stage sum: per-workgroup partials, then their sum).  d_res is
  * one complex128 in device memory.  Deterministic: the same bits on every
- * call for the same n and data. */
+ * call for the same n and data.  n = 0 gives 0 (x and y may then be NULL);
+ * n < 0 gives HK_EINVAL. */
 int hk_zdotc(int64_t n, const void* d_x, const void* d_y, void* d_res, void* stream);
 
 /* *d_res = x^T y = sum x_i y_i (unconjugated form of the same reduction). */
 int hk_zdotu(int64_t n, const void* d_x, const void* d_y, void* d_res, void* stream);
 
-/* *d_res = ||x||_2 = sqrt(sum re^2 + im^2) (Section 3, ZNORM); one double in device memory. */
+/* *d_res = ||x||_2 = sqrt(sum re^2 + im^2) (Section 3, ZNORM); one double in
+ * device memory; n = 0 gives 0. */
 int hk_dznrm2(int64_t n, const void* d_x, double* d_res, void* stream);
 
 /* y = alpha x + y (Section 3, ZAXPY listing); alpha is a host double[2]. */

@@ -99,10 +99,22 @@ __global__ void k_conj(int64_t n, const double2* x, double2* y) {
 
 static dim3 ew_grid(int64_t n) { return dim3((unsigned)((n + kBlock - 1) / kBlock)); }
 
+// res[0 .. count) = 0 (the value of an empty sum; a kernel rather than a
+// memset so the call stays capturable in a graph)
+__global__ void k_zero_res(double* res, int count) {
+  if ((int)threadIdx.x < count) res[threadIdx.x] = 0.0;
+}
+
 template <int KIND>
 static int reduce(int64_t n, const void* x, const void* y, void* res, void* stream, const char* who) {
-  if (n <= 0 || !x || !res || (KIND != 2 && !y)) HK_FAIL(HK_EINVAL, "%s: bad argument (n=%lld)", who, (long long)n);
+  if (n < 0 || !res || (n > 0 && (!x || (KIND != 2 && !y))))
+    HK_FAIL(HK_EINVAL, "%s: bad argument (n=%lld)", who, (long long)n);
   hipStream_t s = as_stream(stream);
+  if (n == 0) {
+    hipLaunchKernelGGL(k_zero_res, dim3(1), dim3(64), 0, s, (double*)res, KIND == 2 ? 1 : 2);
+    HK_CHECK_LAUNCH();
+    return HK_OK;
+  }
   const int nb = reduce_blocks(n);
   ReduceScratch* rs = nullptr;
   int rc = reduce_scratch(s, sizeof(double) * 2 * nb, &rs);

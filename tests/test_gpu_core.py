@@ -169,6 +169,8 @@ def test_spmv_edge_structures(hk, oracle):
     col = np.concatenate([np.sort(rng.choice(n, l, replace=False)) for l in lens]).astype(np.int32)
     cases.append(("ragged", rowptr, col))
     cases.append(("one", np.array([0, 1], dtype=np.int32), np.array([0], dtype=np.int32)))
+    # no entries at all: y = 0, and the residual is b
+    cases.append(("empty", np.zeros(40, dtype=np.int32), np.zeros(0, dtype=np.int32)))
     # 30 entries per row: a 64-row block spans several passes of the row-block scheme
     n2 = 200
     rowptr2 = np.arange(n2 + 1, dtype=np.int32) * 30
@@ -187,6 +189,26 @@ def test_spmv_edge_structures(hk, oracle):
             xd = dev(x)
             y = host(A.spmv(xd, torch.full_like(xd, complex("nan+nanj")), beta=0.0))
             assert np.all(np.abs(y - ref) <= bound), (name, L, U, g)
+        if name == "empty":
+            assert np.all(y == 0)
+            bb = crandn(rng, n)
+            assert np.array_equal(host(A.residual(dev(bb), xd)), bb)
+
+
+def test_reductions_of_length_zero_and_one(hk):
+    """An empty dot or norm is 0; a length-1 one is the single term."""
+    say("reductions n = 0, 1")
+    e = torch.zeros(0, dtype=torch.complex128, device=DEV)
+    out = torch.full((1,), complex(7, 7), dtype=torch.complex128, device=DEV)
+    assert host(hk.zdotc(e, e, out))[0] == 0 and host(hk.zdotu(e, e, out))[0] == 0
+    nrm = torch.full((1,), 7.0, dtype=torch.float64, device=DEV)
+    assert host(hk.dznrm2(e, nrm))[0] == 0
+    x, y = complex(3, -4), complex(0.5, 2)
+    xd = torch.tensor([x], dtype=torch.complex128, device=DEV)
+    yd = torch.tensor([y], dtype=torch.complex128, device=DEV)
+    assert host(hk.zdotc(xd, yd))[0] == x.conjugate() * y
+    assert host(hk.zdotu(xd, yd))[0] == x * y
+    assert host(hk.dznrm2(xd))[0] == 5.0
 
 
 def test_csr_create_rejects_bad_structure(hk):
