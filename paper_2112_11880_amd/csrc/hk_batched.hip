@@ -220,8 +220,16 @@ __device__ __forceinline__ void sweep_spmv(const SweepArgs& a, int r0, int r1, i
   if (!act) return;
   const cptr<int> rowptr = as_const(a.rowptr), col = as_const(a.col);
   const cptr<double> Kc = as_const(a.K), Mc = as_const(a.M);
-  for (int row = uni(r0); row < r1; row += rs) {
-    const int s = rowptr[row], e = rowptr[row + 1];
+  // the next row's extent is loaded while this row's gathers are in flight
+  int row = uni(r0);
+  int s = row < r1 ? rowptr[row] : 0, e = row < r1 ? rowptr[row + 1] : 0;
+  for (; row < r1; row += rs) {
+    const int nrow = row + rs;
+    const int ns = nrow < r1 ? rowptr[nrow] : 0, ne = nrow < r1 ? rowptr[nrow + 1] : 0;
+    // the epilogue's operand is loaded before the gathers as well
+    const size_t o = (size_t)row * kSys + j;
+    const double2 pre = EPI == 1 ? a.RH[o] : EPI == 2 ? a.SH[o] : a.B[o];
+    const double2 dg = EPI == 2 ? sweep_diag(a, row, kap) : make_double2(0, 0);
     double2 acc = make_double2(0, 0);
     // 8 entries at a time, all gathers in flight together; past the row's
     // end an entry re-reads the last column with a zero coefficient
@@ -242,19 +250,20 @@ __device__ __forceinline__ void sweep_spmv(const SweepArgs& a, int r0, int r1, i
 #pragma unroll
       for (int u = 0; u < 8; ++u) acc = cfma(make_double2(kv[u] - kap.x * mv[u], -kap.y * mv[u]), xv[u], acc);
     }
-    const size_t o = (size_t)row * kSys + j;
+    s = ns;
+    e = ne;
     if (EPI == 3) {
-      const double2 rt = csub(a.B[o], acc);
+      const double2 rt = csub(pre, acc);
       part[0] += cabs2(rt);
       continue;
     }
     dst[o] = acc;
     if (EPI == 1) {
-      const double2 h = a.RH[o];
+      const double2 h = pre;
       part[0] = fma(h.x, acc.x, fma(h.y, acc.y, part[0]));
       part[1] = fma(h.x, acc.y, fma(-h.y, acc.x, part[1]));
     } else if (EPI == 2) {
-      const double2 sv = cmul(sweep_diag(a, row, kap), a.SH[o]);
+      const double2 sv = cmul(dg, pre);
       part[0] = fma(acc.x, acc.x, fma(acc.y, acc.y, part[0]));
       part[1] = fma(acc.x, sv.x, fma(acc.y, sv.y, part[1]));
       part[2] = fma(acc.x, sv.y, fma(-acc.y, sv.x, part[2]));
