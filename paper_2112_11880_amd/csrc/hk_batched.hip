@@ -933,6 +933,7 @@ extern "C" int hk_sweep_solve(int64_t n, int64_t nnz, const int32_t* d_rowptr, c
   if (!d_rowptr || !d_col || !d_K || !d_M || !kappa || !d_B || !d_X || !opts || !infos)
     HK_FAIL(HK_EINVAL, "hk_sweep_solve: null argument");
   if (nsys < 1 || nsys > kSys) HK_FAIL(HK_EINVAL, "hk_sweep_solve: nsys must be in [1, 64]");
+  if (n < 1 || nnz < 1) HK_FAIL(HK_EINVAL, "hk_sweep_solve: empty matrix (n=%lld nnz=%lld)", (long long)n, (long long)nnz);
   if (!(opts->tol >= 0) || opts->max_iter < 0) HK_FAIL(HK_EINVAL, "hk_sweep_solve: bad options");
   hipStream_t s = as_stream(stream);
   // structure check through a temporary handle (real values are not read)
