@@ -26,6 +26,10 @@
  *     outcome of a solve.
  *   - Indices are int32 (rowptr has n+1 entries, col has nnz entries, column
  *     indices ascending within a row, 0 <= col < n).
+ *   - A matrix handle carries its solvers' workspace and tuned shapes: calls
+ *     on one handle must not overlap (from several threads, or on several
+ *     streams at once); use one handle per concurrent stream.  Distinct
+ *     handles, and the BLAS-1 calls on distinct streams, are independent.
  */
 #ifndef HK_H_
 #define HK_H_
