@@ -938,7 +938,7 @@ extern "C" int hk_sweep_solve(int64_t n, int64_t nnz, const int32_t* d_rowptr, c
   hipStream_t s = as_stream(stream);
   // structure check through a temporary handle (real values are not read)
   hk_csr A = nullptr;
-  int rc = hk_csr_create(&A, n, nnz, d_rowptr, d_col, d_K, HK_C128, 0, stream);
+  int rc = hk_csr_create(&A, n, nnz, d_rowptr, d_col, d_K, HK_C128, HK_INT32_COLS, stream);
   if (rc != HK_OK) return rc;
   (void)hk_csr_destroy(A);
   int grid = 0;
@@ -968,7 +968,9 @@ extern "C" int hk_sweep_solve(int64_t n, int64_t nnz, const int32_t* d_rowptr, c
   for (int j = 0; j < nsys; ++j) hk[j] = make_double2(kappa[2 * j], kappa[2 * j + 1]);
   int hflag = 0;
   hipError_t e = hipMemcpyAsync(kap, hk.data(), 16 * kSys, hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipMemsetAsync(a.bar, 0, sizeof(GridBar), s);
+  GridBar bar0{};
+  bar0.spin_limit = barrier_spin_limit();
+  if (e == hipSuccess) e = hipMemcpyAsync(a.bar, &bar0, sizeof(GridBar), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemsetAsync(flag, 0, 64, s);
   if (e == hipSuccess) e = hipMemsetAsync(a.st, 0, sizeof(BatchState), s);
   const dim3 ew((unsigned)((n + kBlock - 1) / kBlock));
@@ -1079,7 +1081,9 @@ extern "C" int hk_blockdiag_solve(hk_csr A, int32_t nsys, const int64_t* row_off
   if (e == hipSuccess) e = hipMemcpyAsync(d_send, sys_end.data(), 4 * kSys, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(d_sbeg, sys_begin.data(), 4 * kSys, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(d_t0, tile0.data(), 4 * (kSys + 1), hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipMemsetAsync(a.bar, 0, sizeof(GridBar), s);
+  GridBar bar0{};
+  bar0.spin_limit = barrier_spin_limit();
+  if (e == hipSuccess) e = hipMemcpyAsync(a.bar, &bar0, sizeof(GridBar), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemsetAsync(flag, 0, 64, s);
   if (e == hipSuccess) e = hipMemsetAsync(a.st, 0, sizeof(BatchState), s);
   BatchState init{};

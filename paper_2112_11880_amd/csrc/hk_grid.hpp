@@ -20,10 +20,13 @@
 // Two-sided fences at both points cost ~25 us more per solver iteration
 // (5 barriers) on MI355X.
 //
-// Every wait has a time limit: a workgroup that waits longer than
-// kSpinLimitTicks raises an abort flag and every workgroup leaves the kernel
-// at its next barrier, so a broken launch ends instead of hanging.
+// Every wait has a time limit: a workgroup that waits longer than the
+// barrier's spin_limit (kSpinLimitTicks unless the host sets another) raises
+// an abort flag and every workgroup leaves the kernel at its next barrier,
+// so a broken launch ends instead of hanging.
 #pragma once
+
+#include <cstdlib>
 
 #include "hk_common.hpp"
 
@@ -34,7 +37,8 @@ constexpr int kBarMaxBlocks = 1024;
 struct GridBar {
   unsigned release;      // last epoch released by workgroup 0
   int abort;
-  unsigned pad[62];      // keep release/abort on their own 256-byte line
+  unsigned long long spin_limit;  // wall-clock ticks a wait may take before it aborts
+  unsigned pad[60];      // keep release/abort on their own 256-byte line
   unsigned arrive[kBarMaxBlocks];  // last epoch each workgroup arrived at
 };
 
@@ -54,10 +58,11 @@ __device__ __forceinline__ void st_relaxed_u32(unsigned* p, unsigned v) {
 // Waits (one thread) until *p >= e; false on abort or time-out (which raises abort).
 __device__ __forceinline__ bool wait_epoch(const unsigned* p, unsigned e, GridBar* bar) {
   const unsigned long long t0 = wall_clock64();
+  const unsigned long long limit = bar->spin_limit;
   while (ld_relaxed_u32(p) < e) {
     __builtin_amdgcn_s_sleep(1);
     if (ld_relaxed_i32(&bar->abort)) return false;
-    if (wall_clock64() - t0 > kSpinLimitTicks) {
+    if (wall_clock64() - t0 > limit) {
       atomicExch(&bar->abort, 1);
       return false;
     }
@@ -104,6 +109,18 @@ __device__ __forceinline__ bool barrier_last(GridBar* bar, unsigned& epoch, F&& 
   }
   __syncthreads();
   return s_stop != 0;
+}
+
+// Host: the spin limit of a launch, kSpinLimitTicks unless the environment
+// variable HK_BARRIER_SPIN_TICKS holds a positive count (tests use a tiny
+// one to drive the abort path).
+inline unsigned long long barrier_spin_limit() {
+  const char* v = getenv("HK_BARRIER_SPIN_TICKS");
+  if (v) {
+    const unsigned long long t = strtoull(v, nullptr, 10);
+    if (t > 0) return t;
+  }
+  return kSpinLimitTicks;
 }
 
 }  // namespace hk

@@ -243,3 +243,32 @@ def test_blockdiag_uneven_full(hk, oracle):
         r = oracle.residual(s["rowptr"], s["col"], s["val"], s["g"], xh[lo:hi])
         assert np.linalg.norm(r) / np.linalg.norm(s["g"]) <= 1.05e-8, k
     assert offs[-1] == 1073278
+
+
+def test_batched_barrier_timeout_aborts_cleanly(hk, oracle, monkeypatch):
+    """With the grid barrier's wait limit set to one clock tick from the host,
+    the first wait of both persistent solvers times out: every workgroup
+    leaves through the abort path (no fault, no hang) and the call reports the
+    error; the next call, with the default limit, solves normally."""
+    p, kap, B = sweep_inputs(5, 3)
+    rowptr, col, val, b, offs = blockdiag_inputs([3, 4])
+    A = hk.CSR(dev(rowptr), dev(col), dev(val))
+    monkeypatch.setenv("HK_BARRIER_SPIN_TICKS", "1")
+    say("barrier time-out: sweep")
+    with pytest.raises(hk.HKError, match="timed out"):
+        hk.sweep_solve(dev(p.rowptr), dev(p.col), dev(p.K), dev(p.M), kap, dev(B), tol=1e-10)
+    say("barrier time-out: block-diagonal")
+    with pytest.raises(hk.HKError, match="timed out"):
+        hk.blockdiag_solve(A, offs, dev(b), tol=1e-10)
+    monkeypatch.delenv("HK_BARRIER_SPIN_TICKS")
+    say("after the time-outs")
+    X, infos = hk.sweep_solve(dev(p.rowptr), dev(p.col), dev(p.K), dev(p.M), kap, dev(B), tol=1e-10)
+    assert all(i["status"] == 0 for i in infos)
+    x, infos = hk.blockdiag_solve(A, offs, dev(b), tol=1e-10)
+    assert all(i["status"] == 0 for i in infos)
+    xh = host(x)
+    for k in range(2):
+        lo, hi = offs[k], offs[k + 1]
+        rp = rowptr[lo:hi + 1] - rowptr[lo]
+        xo, _ = oracle.bicgstab(rp, col[rowptr[lo]:rowptr[hi]] - lo, val[rowptr[lo]:rowptr[hi]], b[lo:hi], tol=1e-10)
+        assert np.linalg.norm(xh[lo:hi] - xo) <= 1e-7 * np.linalg.norm(xo)
