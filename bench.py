@@ -265,7 +265,7 @@ def main():
                     help="skip the batched sweep / uneven-batch extras")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(the row-slab design for several GPUs is described, not built).", file=sys.stderr)
         sys.exit(2)
 
