@@ -961,6 +961,10 @@ extern "C" int hk_sweep_solve(int64_t n, int64_t nnz, const int32_t* d_rowptr, c
   a.st = ar.take<BatchState>(1);
   a.bar = ar.take<GridBar>(1);
   int* flag = ar.take<int>(16);
+  if (ar.off > bytes) {
+    (void)hipFree(ar.base);
+    HK_FAIL(HK_EINVAL, "hk_sweep_solve: workspace layout exceeds its allocation");
+  }
   a.kd = kd; a.md = md; a.kap = kap;
   a.B = (const double2*)d_B; a.X = (double2*)d_X;
   a.tol = opts->tol; a.maxit = opts->max_iter;
@@ -1067,6 +1071,10 @@ extern "C" int hk_blockdiag_solve(hk_csr A, int32_t nsys, const int64_t* row_off
   a.st = ar.take<BatchState>(1);
   a.bar = ar.take<GridBar>(1);
   int* flag = ar.take<int>(16);
+  if (ar.off > bytes) {
+    (void)hipFree(ar.base);
+    HK_FAIL(HK_EINVAL, "hk_blockdiag_solve: workspace layout exceeds its allocation");
+  }
   a.d = d; a.dinv = dinv; a.sys_begin = d_sbeg; a.sys_end = d_send; a.sys_tile0 = d_t0;
   a.B = (const double2*)d_b; a.X = (double2*)d_x; a.tol = opts->tol; a.maxit = opts->max_iter;
   a.tile_rows = TR;

@@ -392,7 +392,18 @@ __global__ __launch_bounds__(kFinBlock) void k_fin(SolveState* st, const double*
   using V = double2;
   constexpr int NV = FinNV<F>::v;
   __shared__ double lds[NV * (kFinBlock / kWave)];
+  // The status and the fields the scalar update reads are loaded before the
+  // partials are summed, so their latency overlaps that of the sum's loads
+  // instead of following it.  The sum runs whatever the status: the partials
+  // are in bounds even when the producing kernel returned early, and are then
+  // ignored.
   const int status = st->status;
+  const V rho0 = st->rho, alpha0 = st->alpha, omega0 = st->omega;
+  const double theta2 = st->theta2, bb = st->bb;
+  const long long it0 = st->iter, maxit0 = st->maxit;
+  double* const history = st->history;
+  double tot[NV];
+  final_sum<NV>(partials, nb, tot, lds);
   if (F == F_XR) {
     if (status == S_HALF || status == S_TAUBD) {
       if (threadIdx.x == 0) {
@@ -411,8 +422,6 @@ __global__ __launch_bounds__(kFinBlock) void k_fin(SolveState* st, const double*
     }
   }
   if (F != F_INIT && F != F_TRUE && F != F_TUNE && status != S_RUN) return;
-  double tot[NV];
-  final_sum<NV>(partials, nb, tot, lds);
   if (threadIdx.x != 0) return;
   if (F == F_INIT) {
     st->bb = tot[0];
@@ -436,13 +445,13 @@ __global__ __launch_bounds__(kFinBlock) void k_fin(SolveState* st, const double*
     const V sigma = cmake<V>(tot[0], tot[1]);
     if (!cfinite(sigma)) {
       st->status = HK_NONFINITE;
-      st->iters_done = st->iter - 1;
+      st->iters_done = it0 - 1;
     } else if (sigma.x == 0 && sigma.y == 0) {
       st->status = HK_BREAKDOWN;
       st->bd = HK_BD_SIGMA;
-      st->iters_done = st->iter - 1;
+      st->iters_done = it0 - 1;
     } else {
-      st->alpha = cdiv(st->rho, sigma);
+      st->alpha = cdiv(rho0, sigma);
     }
   } else if (F == F_OMEGA) {
     const double tau = tot[0];
@@ -450,42 +459,41 @@ __global__ __launch_bounds__(kFinBlock) void k_fin(SolveState* st, const double*
     st->ss = tot[3];
     if (!isfinite(tot[3])) {
       st->status = HK_NONFINITE;
-      st->iters_done = st->iter - 1;
-    } else if (tot[3] <= st->theta2) {
+      st->iters_done = it0 - 1;
+    } else if (tot[3] <= theta2) {
       st->status = S_HALF;
     } else if (!isfinite(tau) || !cfinite(ts)) {
       st->status = HK_NONFINITE;
-      st->iters_done = st->iter - 1;
+      st->iters_done = it0 - 1;
     } else if (tau == 0) {
       st->status = S_TAUBD;
     } else {
       st->omega = cmake<V>(ts.x / tau, ts.y / tau);
     }
   } else if (F == F_XR) {
-    const long long it = st->iter;
+    const long long it = it0;
     const double rr = tot[0];
     const V rho = cmake<V>(tot[1], tot[2]);
-    const V alpha = st->alpha, omega = st->omega;
     st->rr = rr;
-    st->rho_old = st->rho;
+    st->rho_old = rho0;
     st->rho = rho;
     st->iters_done = it;
-    if (st->history) st->history[it] = st->bb > 0 ? sqrt((double)rr / (double)st->bb) : 0.0;
+    if (history) history[it] = bb > 0 ? sqrt((double)rr / (double)bb) : 0.0;
     if (!isfinite(rr) || !cfinite(rho)) {
       st->status = HK_NONFINITE;
-    } else if (rr <= st->theta2) {
+    } else if (rr <= theta2) {
       st->status = HK_OK;
-    } else if (omega.x == 0 && omega.y == 0) {
+    } else if (omega0.x == 0 && omega0.y == 0) {
       st->status = HK_BREAKDOWN;
       st->bd = HK_BD_OMEGA;
     } else if (rho.x == 0 && rho.y == 0) {
       st->status = HK_BREAKDOWN;
       st->bd = HK_BD_RHO;
-    } else if (it >= st->maxit) {
+    } else if (it >= maxit0) {
       st->status = HK_NOT_CONVERGED;
     } else {
       // beta = (rho / rho_old) (alpha / omega)
-      st->beta = cmul(cdiv(rho, st->rho_old), cdiv(alpha, omega));
+      st->beta = cmul(cdiv(rho, rho0), cdiv(alpha0, omega0));
       st->iter = it + 1;
     }
   } else if (F == F_TRUE) {
@@ -528,16 +536,11 @@ template <class R> struct Work {
 
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
-template <class R> static size_t work_bytes(int64_t n, int64_t nnz) {
+// The workspace layout is written once, as a sequence of take(bytes) calls;
+// work_bytes runs it with a counting take, carve with one that hands out
+// addresses, so the size and the layout cannot disagree.
+template <class R, class Take> static Work<R> layout(Take take, int64_t n, int64_t nnz) {
   using V = cplx<R>;
-  return 10 * align_up(sizeof(V) * n) + align_up(sizeof(V) * (nnz + 1)) +
-         align_up(sizeof(double) * 4 * partial_slots(n)) + align_up(sizeof(SolveState)) + align_up(64);
-}
-
-template <class R> static Work<R> carve(void* base, int64_t n, int64_t nnz) {
-  using V = cplx<R>;
-  char* q = static_cast<char*>(base);
-  auto take = [&](size_t bytes) { char* r = q; q += align_up(bytes); return r; };
   Work<R> w;
   w.y = (V*)take(sizeof(V) * n);
   w.r = (V*)take(sizeof(V) * n);
@@ -554,6 +557,17 @@ template <class R> static Work<R> carve(void* base, int64_t n, int64_t nnz) {
   w.st = (SolveState*)take(sizeof(SolveState));
   w.flag = (int*)take(64);
   return w;
+}
+
+template <class R> static size_t work_bytes(int64_t n, int64_t nnz) {
+  size_t q = 0;
+  (void)layout<R>([&](size_t bytes) { q += align_up(bytes); return (char*)nullptr; }, n, nnz);
+  return q;
+}
+
+template <class R> static Work<R> carve(void* base, int64_t n, int64_t nnz) {
+  char* q = static_cast<char*>(base);
+  return layout<R>([&](size_t bytes) { char* r = q; q += align_up(bytes); return r; }, n, nnz);
 }
 
 static int ensure_ws(void** ws, size_t* have, size_t need, hipStream_t s) {
@@ -1093,7 +1107,15 @@ __global__ __launch_bounds__(kFinBlock) void k_tq_fin(SolveState* st, const doub
   using V = double2;
   constexpr int NV = TqNV<F>::v;
   __shared__ double lds[NV * (kFinBlock / kWave)];
+  // As in k_fin: the status and the fields the update reads are loaded before
+  // the sum, which runs whatever the status.
   const int status = st->status;
+  const long long k = st->iter, maxit0 = st->maxit;
+  const V rho0 = st->rho, alpha0 = st->alpha, eta20 = st->tq_eta2;
+  const double theta0 = st->tq_theta, tau0 = st->tq_tau, theta2 = st->theta2, bb = st->bb;
+  double* const history = st->history;
+  double tot[NV];
+  final_sum<NV>(partials, nb, tot, lds);
   if (F == TQ_H1 && status != S_RUN) return;
   if (F == TQ_H2 && status != S_RUN) return;
   if (F == TQ_SIGMA0 && status != S_RUN) return;
@@ -1107,10 +1129,7 @@ __global__ __launch_bounds__(kFinBlock) void k_tq_fin(SolveState* st, const doub
     }
     if (status != S_RUN) return;
   }
-  double tot[NV];
-  final_sum<NV>(partials, nb, tot, lds);
   if (threadIdx.x != 0) return;
-  const long long k = st->iter;
   if (F == TQ_INIT) {
     st->bb = tot[0];
     st->rr = tot[1];
@@ -1130,37 +1149,38 @@ __global__ __launch_bounds__(kFinBlock) void k_tq_fin(SolveState* st, const doub
     else st->status = S_RUN;
     if (st->history) st->history[0] = tot[0] > 0 ? sqrt(tot[1] / tot[0]) : 0.0;
   } else if (F == TQ_SIGMA0 || F == TQ_SIGMA) {
+    long long it = k;
     if (F == TQ_SIGMA) {
       // the iteration ended without an exit
-      if (k >= st->maxit) { st->status = HK_NOT_CONVERGED; st->iters_done = k; return; }
-      st->iter = k + 1;
+      if (k >= maxit0) { st->status = HK_NOT_CONVERGED; st->iters_done = k; return; }
+      it = k + 1;
+      st->iter = it;
     }
     const V sigma = cmake<V>(tot[0], tot[1]);
     if (!cfinite(sigma)) {
       st->status = HK_NONFINITE;
-      st->iters_done = st->iter - 1;
+      st->iters_done = it - 1;
     } else if (sigma.x == 0 && sigma.y == 0) {
       st->status = HK_BREAKDOWN;
       st->bd = HK_BD_SIGMA;
-      st->iters_done = st->iter - 1;
+      st->iters_done = it - 1;
     } else {
-      const V alpha = cdiv(st->rho, sigma);
+      const V alpha = cdiv(rho0, sigma);
       st->alpha = alpha;
-      const double th = st->tq_theta;
-      st->tq_coef1 = cdiv(cmul(cmake<V>(th * th, 0), st->tq_eta2), alpha);
+      st->tq_coef1 = cdiv(cmul(cmake<V>(theta0 * theta0, 0), eta20), alpha);
     }
   } else {  // TQ_H1, TQ_H2: a half-step's theta, tau, eta and stop test
-    const double theta = sqrt(tot[0]) / st->tq_tau;
+    const double theta = sqrt(tot[0]) / tau0;
     const double c = 1.0 / sqrt(1.0 + theta * theta);
-    const double tau = st->tq_tau * theta * c;
-    const V alpha = st->alpha;
+    const double tau = tau0 * theta * c;
+    const V alpha = alpha0;
     const V eta = cmake<V>(c * c * alpha.x, c * c * alpha.y);
     st->tq_theta = theta;
     st->tq_tau = tau;
     const long long m = F == TQ_H1 ? 2 * k - 1 : 2 * k;  // half-step index, from 1
     const double bound = tau * sqrt((double)(m + 1));
     st->rr = bound * bound;
-    if (st->history) st->history[k] = st->bb > 0 ? bound / sqrt(st->bb) : 0.0;
+    if (history) history[k] = bb > 0 ? bound / sqrt(bb) : 0.0;
     if (F == TQ_H1) {
       st->tq_eta1 = eta;
       st->tq_coef2 = cdiv(cmul(cmake<V>(theta * theta, 0), eta), alpha);
@@ -1170,7 +1190,7 @@ __global__ __launch_bounds__(kFinBlock) void k_tq_fin(SolveState* st, const doub
     if (!isfinite(tau) || !cfinite(eta)) {
       st->status = HK_NONFINITE;
       st->iters_done = k;
-    } else if (bound * bound <= st->theta2) {
+    } else if (bound * bound <= theta2) {
       st->status = F == TQ_H1 ? S_HALF : S_HALF2;
       st->iters_done = k;
     } else if (F == TQ_H2) {
@@ -1181,7 +1201,7 @@ __global__ __launch_bounds__(kFinBlock) void k_tq_fin(SolveState* st, const doub
       } else if (rho.x == 0 && rho.y == 0) {
         st->status = S_RHOBD;
       } else {
-        st->beta = cdiv(rho, st->rho);
+        st->beta = cdiv(rho, rho0);
         st->rho = rho;
       }
     }
@@ -1338,16 +1358,9 @@ template <class R> static size_t bl_partial_doubles(int64_t n) {
   return (size_t)(a > b ? a : b);
 }
 
-template <class R> static size_t bl_work_bytes(int64_t n, int64_t nnz, int ell) {
+// One layout for sizing and carving, as for the BiCGStab/TFQMR workspace.
+template <class R, class Take> static BlWork<R> bl_layout(Take take, int64_t n, int64_t nnz, int ell) {
   using V = cplx<R>;
-  return (size_t)(3 + 2 * (ell + 1)) * align_up(sizeof(V) * n) + align_up(sizeof(V) * (nnz > 0 ? nnz : 1)) +
-         align_up(sizeof(double) * bl_partial_doubles<R>(n)) + align_up(sizeof(SolveState)) + align_up(64);
-}
-
-template <class R> static BlWork<R> bl_carve(void* base, int64_t n, int64_t nnz, int ell) {
-  using V = cplx<R>;
-  char* q = static_cast<char*>(base);
-  auto take = [&](size_t bytes) { char* r = q; q += align_up(bytes); return r; };
   BlWork<R> w{};
   w.y = (V*)take(sizeof(V) * n);
   w.rt = (V*)take(sizeof(V) * n);
@@ -1361,6 +1374,17 @@ template <class R> static BlWork<R> bl_carve(void* base, int64_t n, int64_t nnz,
   w.st = (SolveState*)take(sizeof(SolveState));
   w.flag = (int*)take(64);
   return w;
+}
+
+template <class R> static size_t bl_work_bytes(int64_t n, int64_t nnz, int ell) {
+  size_t q = 0;
+  (void)bl_layout<R>([&](size_t bytes) { q += align_up(bytes); return (char*)nullptr; }, n, nnz, ell);
+  return q;
+}
+
+template <class R> static BlWork<R> bl_carve(void* base, int64_t n, int64_t nnz, int ell) {
+  char* q = static_cast<char*>(base);
+  return bl_layout<R>([&](size_t bytes) { char* r = q; q += align_up(bytes); return r; }, n, nnz, ell);
 }
 
 // u_i = r_i - beta u_i, i = 0..j
@@ -1400,35 +1424,70 @@ __global__ __launch_bounds__(kBlock) void k_bl_r(int n, const SolveState* __rest
   store_block_partials<1>(acc, partials);
 }
 
-// Gram partials: z_i = r_i^H r_0 (i = 1..ELL), then Z_ij = r_i^H r_j
-// (1 <= i <= j <= ELL), as (re, im) pairs.
+// Products of the minimal-residual step, in partial-component order: first
+// z_i = r_i^H r_0 (i = 1..l), then Z_ij = r_i^H r_j (1 <= i <= j <= l).
+template <int ELL> struct BlProducts {
+  static constexpr int np = ELL + ELL * (ELL + 1) / 2;
+  int a[np], b[np];
+  constexpr BlProducts() : a(), b() {
+    int m = 0;
+    for (int i = 1; i <= ELL; ++i, ++m) { a[m] = i; b[m] = 0; }
+    for (int i = 1; i <= ELL; ++i)
+      for (int j = i; j <= ELL; ++j, ++m) { a[m] = i; b[m] = j; }
+  }
+};
+
+// Gram partials.  A workgroup stages kBlock elements of r_0..r_l in LDS per
+// round (kEw rounds), and wave w accumulates products m = w, w + NW, ...
+// over them, so a lane holds a quarter of the products instead of all of
+// them (88 doubles at l = 8, which left one wave per SIMD).  Each wave owns
+// its products, so its lane 0 stores their block partials directly.
 template <class R, int ELL>
 __global__ __launch_bounds__(kBlock) void k_bl_gram(int n, const SolveState* __restrict__ st, BlVecs<R> v,
                                                     double* partials) {
   using V = cplx<R>;
-  constexpr int NV = BlNV<ELL>::v;
-  __shared__ double lds[NV * (kBlock / kWave)];
+  constexpr BlProducts<ELL> P{};
+  constexpr int NW = kBlock / kWave;
+  constexpr int PW = (P.np + NW - 1) / NW;  // products per wave (at most)
+  __shared__ V tile[ELL + 1][kBlock];
   if (st->status != S_RUN) return;
-  double acc[NV];
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x % kWave;
+  double acc[2 * PW];
 #pragma unroll
-  for (int k = 0; k < NV; ++k) acc[k] = 0;
-  const int base = blockIdx.x * (kBlock * kEw) + threadIdx.x;
+  for (int k = 0; k < 2 * PW; ++k) acc[k] = 0;
+  const int base = blockIdx.x * (kBlock * kEw);
   for (int k = 0; k < kEw; ++k) {
-    const int q = base + k * kBlock;
-    if (q >= n) break;
-    V x[ELL + 1];
+    const int q = base + k * kBlock + threadIdx.x;
 #pragma unroll
-    for (int i = 0; i <= ELL; ++i) x[i] = v.r[i][q];
-    int m = 0;
+    for (int i = 0; i <= ELL; ++i) tile[i][threadIdx.x] = q < n ? v.r[i][q] : czero<V>();
+    __syncthreads();
 #pragma unroll
-    for (int i = 1; i <= ELL; ++i, m += 2) dotc_acc(x[i], x[0], acc[m], acc[m + 1]);
+    for (int e = lane; e < kBlock; e += kWave) {
+      V x[ELL + 1];
 #pragma unroll
-    for (int i = 1; i <= ELL; ++i)
+      for (int i = 0; i <= ELL; ++i) x[i] = tile[i][e];
+      // wave w's products; the branch is uniform over the wave
 #pragma unroll
-      for (int jj = i; jj <= ELL; ++jj, m += 2) dotc_acc(x[i], x[jj], acc[m], acc[m + 1]);
+      for (int ww = 0; ww < NW; ++ww) {
+        if (ww != w) continue;
+#pragma unroll
+        for (int p = 0; p < PW; ++p) {
+          const int m = ww + p * NW;
+          if (m < P.np) dotc_acc(x[P.a[m]], x[P.b[m]], acc[2 * p], acc[2 * p + 1]);
+        }
+      }
+    }
+    __syncthreads();
   }
-  block_sum<NV>(acc, lds);
-  store_block_partials<NV>(acc, partials);
+#pragma unroll
+  for (int p = 0; p < PW; ++p) {
+    const int m = w + p * NW;
+    const double re = wave_sum(acc[2 * p]), im = wave_sum(acc[2 * p + 1]);
+    if (lane == 0 && m < P.np) {
+      partials[(size_t)(2 * m) * gridDim.x + blockIdx.x] = re;
+      partials[(size_t)(2 * m + 1) * gridDim.x + blockIdx.x] = im;
+    }
+  }
 }
 
 // y += sum gamma_j r_{j-1}; r_0 -= sum gamma_j r_j; u_0 -= sum gamma_j u_j;
@@ -1514,11 +1573,17 @@ __global__ __launch_bounds__(kFinBlock) void k_bl_fin(SolveState* st, const doub
   using V = double2;
   constexpr int NV = BlFinNV<F, ELL>::v;
   __shared__ double lds[NV * (kFinBlock / kWave)];
-  if (F != BL_INIT && st->status != S_RUN) return;
+  // As in k_fin: the status and the fields the update reads are loaded before
+  // the sum, which runs whatever the status.
+  const int status = st->status;
+  const long long k = st->iter, maxit0 = st->maxit;
+  const V rho0 = st->rho, alpha0 = st->alpha, omega0 = st->omega;
+  const double theta2 = st->theta2, bb = st->bb;
+  double* const history = st->history;
   double tot[NV];
   final_sum<NV>(partials, nb, tot, lds);
+  if (F != BL_INIT && status != S_RUN) return;
   if (threadIdx.x != 0) return;
-  const long long k = st->iter;
   if (F == BL_INIT) {
     st->bb = tot[0];
     st->rr = tot[1];
@@ -1539,56 +1604,81 @@ __global__ __launch_bounds__(kFinBlock) void k_bl_fin(SolveState* st, const doub
     const V gam = cmake<V>(tot[0], tot[1]);
     if (!cfinite(gam)) { st->status = HK_NONFINITE; st->iters_done = k - 1; }
     else if (gam.x == 0 && gam.y == 0) { st->status = HK_BREAKDOWN; st->bd = HK_BD_SIGMA; st->iters_done = k - 1; }
-    else st->alpha = cdiv(st->rho, gam);
+    else st->alpha = cdiv(rho0, gam);
   } else if (F == BL_R) {
     st->rr = tot[0];
     if (!isfinite(tot[0])) { st->status = HK_NONFINITE; st->iters_done = k; }
-    else if (tot[0] <= st->theta2) {
+    else if (tot[0] <= theta2) {
       st->status = HK_OK;
       st->iters_done = k;
-      if (st->history) st->history[k] = st->bb > 0 ? sqrt(tot[0] / st->bb) : 0.0;
+      if (history) history[k] = bb > 0 ? sqrt(tot[0] / bb) : 0.0;
     }
   } else if (F == BL_RHO) {
     const V rho1 = cmake<V>(tot[0], tot[1]);
     if (!cfinite(rho1)) { st->status = HK_NONFINITE; st->iters_done = k - 1; }
     else if (rho1.x == 0 && rho1.y == 0) { st->status = HK_BREAKDOWN; st->bd = HK_BD_RHO; st->iters_done = k - 1; }
-    else { st->beta = cdiv(cmul(st->alpha, rho1), st->rho); st->rho = rho1; }
+    else { st->beta = cdiv(cmul(alpha0, rho1), rho0); st->rho = rho1; }
   } else {  // BL_MR: end of a cycle
     st->rr = tot[0];
     st->iters_done = k;
-    if (st->history) st->history[k] = st->bb > 0 ? sqrt(tot[0] / st->bb) : 0.0;
-    const V om = st->omega;
+    if (history) history[k] = bb > 0 ? sqrt(tot[0] / bb) : 0.0;
+    const V om = omega0;
     if (!isfinite(tot[0])) st->status = HK_NONFINITE;
-    else if (tot[0] <= st->theta2) st->status = HK_OK;
+    else if (tot[0] <= theta2) st->status = HK_OK;
     else if (om.x == 0 && om.y == 0) { st->status = HK_BREAKDOWN; st->bd = HK_BD_OMEGA; }
-    else if (k >= st->maxit) st->status = HK_NOT_CONVERGED;
+    else if (k >= maxit0) st->status = HK_NOT_CONVERGED;
     else { st->iter = k + 1; bl_cycle_start(st, cmake<V>(tot[1], tot[2])); }
   }
 }
 
 // Finalize of the Gram partials (NV = l(l+3) sums): wave w sums components
-// w, w+16, ... over the nb partials (lanes stride the partials, then a fixed
-// butterfly), into LDS; thread 0 then solves Z gamma = z by Cholesky.
+// w, w+16, ... over the nb partials (lane j takes partials j, j+64, ... in
+// order, then a fixed butterfly), into LDS; thread 0 then solves Z gamma = z
+// by Cholesky.  A lane issues the loads of U partials of each of its
+// components before adding them, so the latency is paid once per 64*U
+// partials rather than once per 64.
 template <int ELL>
 __global__ __launch_bounds__(kFinBlock) void k_bl_fin_gram(SolveState* st, const double* partials, int nb) {
   using V = double2;
   constexpr int NV = BlNV<ELL>::v;
   constexpr int W = kFinBlock / kWave;
+  constexpr int CW = (NV + W - 1) / W;  // components per wave (at most)
+  constexpr int U = 4;                  // CW*U loads in flight per lane, within 128 VGPRs
   __shared__ double tot[NV];
-  if (st->status != S_RUN) return;
+  // the status is checked after the sum, so the two loads overlap
+  const int status = st->status;
+  const long long k = st->iter;
   const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
-  for (int c = wv; c < NV; c += W) {
-    double sacc = 0;
-    for (int j = lane; j < nb; j += kWave) sacc += partials[(size_t)c * nb + j];
-    sacc = wave_sum(sacc);
-    if (lane == 0) tot[c] = sacc;
+  double sacc[CW];
+#pragma unroll
+  for (int q = 0; q < CW; ++q) sacc[q] = 0;
+  for (int j0 = lane; j0 < nb; j0 += kWave * U) {
+    double x[CW][U];
+#pragma unroll
+    for (int q = 0; q < CW; ++q)
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int c = wv + q * W, j = j0 + u * kWave;
+        x[q][u] = c < NV && j < nb ? partials[(size_t)c * nb + j] : 0.0;
+      }
+#pragma unroll
+    for (int q = 0; q < CW; ++q)
+#pragma unroll
+      for (int u = 0; u < U; ++u) sacc[q] += x[q][u];
+  }
+#pragma unroll
+  for (int q = 0; q < CW; ++q) {
+    const int c = wv + q * W;
+    const double t = wave_sum(sacc[q]);
+    if (lane == 0 && c < NV) tot[c] = t;
   }
   __syncthreads();
-  if (threadIdx.x != 0) return;
-  const long long k = st->iter;
+  if (status != S_RUN || threadIdx.x != 0) return;
   {
-    // Z gamma = z by Cholesky, Z = L L^H (Hermitian positive definite)
-    V z[ELL], Z[ELL][ELL], L[ELL][ELL], w[ELL], g[ELL];
+    // Z gamma = z by Cholesky, Z = L L^H (Hermitian positive definite).  The
+    // arrays are in LDS: as thread-private arrays they were placed in scratch
+    // memory, and the dependent scratch accesses made this kernel take ~90 us.
+    __shared__ V z[ELL], Z[ELL][ELL], L[ELL][ELL], w[ELL], g[ELL];
     int m = 0;
     for (int i = 0; i < ELL; ++i, m += 2) z[i] = cmake<V>(tot[m], tot[m + 1]);
     for (int i = 0; i < ELL; ++i)
@@ -1596,23 +1686,27 @@ __global__ __launch_bounds__(kFinBlock) void k_bl_fin_gram(SolveState* st, const
         Z[i][j] = cmake<V>(tot[m], tot[m + 1]);
         Z[j][i] = cconj(Z[i][j]);
       }
+#pragma unroll 1
     for (int j = 0; j < ELL; ++j) {
       double d = Z[j][j].x;
       for (int q = 0; q < j; ++q) d -= cabs2(L[j][q]);
       if (!(d > 0.0)) { st->status = HK_BREAKDOWN; st->bd = HK_BD_TAU; st->iters_done = k; return; }
       const double ljj = sqrt(d);
       L[j][j] = cmake<V>(ljj, 0);
+#pragma unroll 1
       for (int i = j + 1; i < ELL; ++i) {
         V sij = Z[i][j];
         for (int q = 0; q < j; ++q) sij = csub(sij, cmul(L[i][q], cconj(L[j][q])));
         L[i][j] = cmake<V>(sij.x / ljj, sij.y / ljj);
       }
     }
+#pragma unroll 1
     for (int i = 0; i < ELL; ++i) {
       V sum = z[i];
       for (int q = 0; q < i; ++q) sum = csub(sum, cmul(L[i][q], w[q]));
       w[i] = cmake<V>(sum.x / L[i][i].x, sum.y / L[i][i].x);
     }
+#pragma unroll 1
     for (int i = ELL - 1; i >= 0; --i) {
       V sum = w[i];
       for (int q = i + 1; q < ELL; ++q) sum = csub(sum, cmul(cconj(L[q][i]), g[q]));
