@@ -217,7 +217,10 @@ int hk_krylov_solve(hk_csr A, const void* d_b, void* d_x, const hk_solve_opts* o
  * norm, the stopping test ||r|| <= outer_tol ||b|| and the update u += d run
  * in complex128; d solves A d = r with Jacobi BiCGStab in complex64 (values
  * of A rounded to nearest per component; complex64 vectors and products,
- * dots and scalars in double) to inner_tol relative to ||r||.  At most
+ * dots and scalars in double) to a tolerance relative to ||r|| of
+ * max(inner_tol, outer_tol ||b|| / (2 ||r||)): inner_tol, except in a cycle
+ * that needs less than that to reach outer_tol, which stops at half the
+ * reduction it needs.  At most
  * max_outer cycles; a cycle that does not lower ||r|| ends the loop
  * (HK_NOT_CONVERGED).  opts->max_iter caps each inner solve; opts->method
  * must be HK_BICGSTAB.  The complex64 copy of A is kept in the handle.

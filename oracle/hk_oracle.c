@@ -633,8 +633,10 @@ done:
  * the test ||r|| <= outer_tol ||b|| and the update u += d are double; the
  * correction d solves A d = r approximately with the complex-float BiCGStab
  * above on the complex-float rounding of A (each component rounded to
- * nearest) to a tolerance inner_tol relative to ||r||.  u holds the initial
- * guess on entry.  info->iters counts outer cycles, *inner_total the inner
+ * nearest) to a tolerance relative to ||r|| of
+ * max(inner_tol, outer_tol ||b|| / (2 ||r||)): inner_tol, except in a cycle
+ * that needs a smaller reduction to reach outer_tol, which stops at half of
+ * that reduction.  u holds the initial guess on entry.  info->iters counts outer cycles, *inner_total the inner
  * iterations.  A cycle that does not lower ||r|| counts as stagnation and
  * ends the loop with OR_NOT_CONVERGED.
  */
@@ -661,8 +663,10 @@ int orc_mixed_refine(int64_t n, const int32_t *rowptr, const int32_t *col, const
         if (rn >= prev || k == max_outer) { status = OR_NOT_CONVERGED; break; }
         prev = rn;
         for (int64_t i = 0; i < n; ++i) r32[i] = (float)creal(r[i]) + I * (float)cimag(r[i]);
+        double itol = 0.5 * outer_tol / rel;
+        if (itol < inner_tol) itol = inner_tol;
         or_info in;
-        int st = orc_bicgstab_c64(n, rowptr, col, val32, r32, d32, (float)inner_tol, max_inner, &in);
+        int st = orc_bicgstab_c64(n, rowptr, col, val32, r32, d32, (float)itol, max_inner, &in);
         *inner_total += in.iters;
         if (st == OR_EINVAL || st == OR_NONFINITE) { status = st; break; }
         for (int64_t i = 0; i < n; ++i) u[i] += (double)crealf(d32[i]) + I * (double)cimagf(d32[i]);

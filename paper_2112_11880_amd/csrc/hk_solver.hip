@@ -1437,11 +1437,12 @@ template <int ELL> struct BlProducts {
   }
 };
 
-// Gram partials.  A workgroup stages kBlock elements of r_0..r_l in LDS per
-// round (kEw rounds), and wave w accumulates products m = w, w + NW, ...
-// over them, so a lane holds a quarter of the products instead of all of
-// them (88 doubles at l = 8, which left one wave per SIMD).  Each wave owns
-// its products, so its lane 0 stores their block partials directly.
+// Gram partials.  Wave w of a workgroup accumulates products m = w, w + NW,
+// ... over the workgroup's kBlock*kEw elements, so a lane holds a quarter of
+// the products instead of all of them (88 doubles at l = 8, which left one
+// wave per SIMD).  The waves of a workgroup load the same elements at about
+// the same time, so HBM sees each once and the repeats hit the caches.  Each
+// wave owns its products: its lane 0 stores their block partials directly.
 template <class R, int ELL>
 __global__ __launch_bounds__(kBlock) void k_bl_gram(int n, const SolveState* __restrict__ st, BlVecs<R> v,
                                                     double* partials) {
@@ -1449,35 +1450,28 @@ __global__ __launch_bounds__(kBlock) void k_bl_gram(int n, const SolveState* __r
   constexpr BlProducts<ELL> P{};
   constexpr int NW = kBlock / kWave;
   constexpr int PW = (P.np + NW - 1) / NW;  // products per wave (at most)
-  __shared__ V tile[ELL + 1][kBlock];
   if (st->status != S_RUN) return;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x % kWave;
   double acc[2 * PW];
 #pragma unroll
   for (int k = 0; k < 2 * PW; ++k) acc[k] = 0;
   const int base = blockIdx.x * (kBlock * kEw);
-  for (int k = 0; k < kEw; ++k) {
-    const int q = base + k * kBlock + threadIdx.x;
+  for (int e = lane; e < kBlock * kEw; e += kWave) {
+    const int q = base + e;
+    if (q >= n) break;
+    V x[ELL + 1];
 #pragma unroll
-    for (int i = 0; i <= ELL; ++i) tile[i][threadIdx.x] = q < n ? v.r[i][q] : czero<V>();
-    __syncthreads();
+    for (int i = 0; i <= ELL; ++i) x[i] = v.r[i][q];
+    // wave w's products; the branch is uniform over the wave
 #pragma unroll
-    for (int e = lane; e < kBlock; e += kWave) {
-      V x[ELL + 1];
+    for (int ww = 0; ww < NW; ++ww) {
+      if (ww != w) continue;
 #pragma unroll
-      for (int i = 0; i <= ELL; ++i) x[i] = tile[i][e];
-      // wave w's products; the branch is uniform over the wave
-#pragma unroll
-      for (int ww = 0; ww < NW; ++ww) {
-        if (ww != w) continue;
-#pragma unroll
-        for (int p = 0; p < PW; ++p) {
-          const int m = ww + p * NW;
-          if (m < P.np) dotc_acc(x[P.a[m]], x[P.b[m]], acc[2 * p], acc[2 * p + 1]);
-        }
+      for (int p = 0; p < PW; ++p) {
+        const int m = ww + p * NW;
+        if (m < P.np) dotc_acc(x[P.a[m]], x[P.b[m]], acc[2 * p], acc[2 * p + 1]);
       }
     }
-    __syncthreads();
   }
 #pragma unroll
   for (int p = 0; p < PW; ++p) {
@@ -1679,6 +1673,7 @@ __global__ __launch_bounds__(kFinBlock) void k_bl_fin_gram(SolveState* st, const
     // arrays are in LDS: as thread-private arrays they were placed in scratch
     // memory, and the dependent scratch accesses made this kernel take ~90 us.
     __shared__ V z[ELL], Z[ELL][ELL], L[ELL][ELL], w[ELL], g[ELL];
+    __shared__ double rl[ELL];  // 1 / L_jj: one division per column
     int m = 0;
     for (int i = 0; i < ELL; ++i, m += 2) z[i] = cmake<V>(tot[m], tot[m + 1]);
     for (int i = 0; i < ELL; ++i)
@@ -1691,26 +1686,27 @@ __global__ __launch_bounds__(kFinBlock) void k_bl_fin_gram(SolveState* st, const
       double d = Z[j][j].x;
       for (int q = 0; q < j; ++q) d -= cabs2(L[j][q]);
       if (!(d > 0.0)) { st->status = HK_BREAKDOWN; st->bd = HK_BD_TAU; st->iters_done = k; return; }
-      const double ljj = sqrt(d);
+      const double ljj = sqrt(d), rj = 1.0 / ljj;
       L[j][j] = cmake<V>(ljj, 0);
+      rl[j] = rj;
 #pragma unroll 1
       for (int i = j + 1; i < ELL; ++i) {
         V sij = Z[i][j];
         for (int q = 0; q < j; ++q) sij = csub(sij, cmul(L[i][q], cconj(L[j][q])));
-        L[i][j] = cmake<V>(sij.x / ljj, sij.y / ljj);
+        L[i][j] = cmake<V>(sij.x * rj, sij.y * rj);
       }
     }
 #pragma unroll 1
     for (int i = 0; i < ELL; ++i) {
       V sum = z[i];
       for (int q = 0; q < i; ++q) sum = csub(sum, cmul(L[i][q], w[q]));
-      w[i] = cmake<V>(sum.x / L[i][i].x, sum.y / L[i][i].x);
+      w[i] = cmake<V>(sum.x * rl[i], sum.y * rl[i]);
     }
 #pragma unroll 1
     for (int i = ELL - 1; i >= 0; --i) {
       V sum = w[i];
       for (int q = i + 1; q < ELL; ++q) sum = csub(sum, cmul(cconj(L[q][i]), g[q]));
-      g[i] = cmake<V>(sum.x / L[i][i].x, sum.y / L[i][i].x);
+      g[i] = cmake<V>(sum.x * rl[i], sum.y * rl[i]);
     }
     for (int i = 0; i < ELL; ++i) st->bl_gamma[i] = g[i];
     st->omega = g[ELL - 1];
@@ -1998,6 +1994,9 @@ extern "C" int hk_krylov_solve_mixed(hk_csr A, const void* d_b, void* d_x, doubl
     const double scale = std::ldexp(1.0, -std::ilogb(rn));
     hipLaunchKernelGGL(k_round_c64, ew, dim3(kBlock), 0, s, n, (const double2*)r, r32, scale);
     HK_CHECK_LAUNCH();
+    // inner tolerance: inner_tol, or, where a smaller reduction reaches
+    // outer_tol, half of that reduction (the last cycle stops early)
+    io.tol = std::max(inner_tol, 0.5 * outer_tol / rel);
     hk_solve_info ii{};
     rc = bicgstab<float>(&A32, (const float2*)A->val32, r32, d32, io, A->ws32, &ii, s);
     A->dot_plan[1] = A32.dot_plan[1];  // the inner solve's tuned fused shape
