@@ -46,11 +46,26 @@ class HelmholtzProblem:
         return self.tet_ptr.numel() - 1
 
 
+def _check_problem(prob: HelmholtzProblem, c: torch.Tensor):
+    """Dtypes and lengths of the problem arrays and the speeds: the library
+    takes raw pointers and cannot check them."""
+    nnz, cv = prob.col.numel(), _hk._cvec
+    cv(prob.rowptr, torch.int32, "rowptr"), cv(prob.col, torch.int32, "col")
+    cv(prob.K, torch.float64, "K", nnz), cv(prob.bm_ptr, torch.int32, "bm_ptr", nnz + 1)
+    cv(prob.bm_blk, torch.int32, "bm_blk"), cv(prob.bm_val, torch.float64, "bm_val", prob.bm_blk.numel())
+    cv(prob.tet_ptr, torch.int32, "tet_ptr"), cv(prob.tet_vol, torch.float64, "tet_vol", prob.tet_nodes.shape[0])
+    cv(prob.tet_nodes, torch.int32, "tet_nodes", 4 * prob.tet_nodes.shape[0])
+    cv(prob.dirichlet, torch.uint8, "dirichlet", prob.n)
+    cv(c, torch.float64, "c", prob.nblocks)
+
+
 def assemble(prob: HelmholtzProblem, c: torch.Tensor, out=None):
     """Complex128 CSR values of A(c) (library kernel)."""
     lib = _declare()
-    val = torch.empty(prob.col.numel(), dtype=torch.complex128, device=prob.col.device) if out is None else out
     c = c.detach().contiguous()
+    _check_problem(prob, c)
+    val = (torch.empty(prob.col.numel(), dtype=torch.complex128, device=prob.col.device) if out is None
+           else _hk._cvec(out, name="out", n=prob.col.numel()))
     _hk._check(lib.hk_assemble_helmholtz(prob.col.numel(), _hk._ptr(prob.K), _hk._ptr(prob.bm_ptr),
                                          _hk._ptr(prob.bm_blk), _hk._ptr(prob.bm_val),
                                          prob.bm_blk.numel(), prob.nblocks, _hk._ptr(c),
@@ -63,6 +78,8 @@ def elem_sens(prob: HelmholtzProblem, lam, u, c):
     """dL/dc_b from the adjoint state (library kernel)."""
     lib = _declare()
     c = c.detach().contiguous()
+    _check_problem(prob, c)
+    _hk._cvec(lam, name="lambda", n=prob.n), _hk._cvec(u, name="u", n=prob.n)
     out = torch.empty(prob.nblocks, dtype=torch.float64, device=c.device)
     _hk._check(lib.hk_elem_sens(prob.n, prob.tet_nodes.shape[0], prob.nblocks, _hk._ptr(prob.tet_nodes),
                                 _hk._ptr(prob.tet_ptr), _hk._ptr(prob.tet_vol), _hk._ptr(prob.dirichlet),

@@ -105,11 +105,15 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr()) if t is not None else None
 
 
-def _cvec(t, dtype=torch.complex128, name="vector"):
+def _cvec(t, dtype=torch.complex128, name="vector", n=None):
+    """Checks that t is a contiguous device tensor of dtype (and, given n, of
+    n elements): the library takes raw pointers and cannot check lengths."""
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
         raise HKError(HK_EINVAL, f"{name} must be a CUDA (HIP) tensor")
     if t.dtype != dtype or not t.is_contiguous():
         raise HKError(HK_EINVAL, f"{name} must be a contiguous {dtype} tensor")
+    if n is not None and t.numel() != n:
+        raise HKError(HK_EINVAL, f"{name} has {t.numel()} elements, expected {n}")
     return t
 
 
@@ -135,6 +139,8 @@ class CSR:
         for t in (self.rowptr, self.col, self.val):
             if not t.is_cuda:
                 raise HKError(HK_EINVAL, "CSR arrays must be device tensors")
+        if self.rowptr.numel() < 1 or self.val.numel() != self.col.numel():
+            raise HKError(HK_EINVAL, "rowptr needs n + 1 entries and val as many as col")
         self.n = self.rowptr.numel() - 1
         self.nnz = self.col.numel()
         self.dtype = self.val.dtype
@@ -175,48 +181,49 @@ class CSR:
 
     def spmv(self, x, y=None, alpha=1.0, beta=0.0):
         """y = alpha A x + beta y (y allocated when None)."""
-        _cvec(x, self.dtype, "x")
+        _cvec(x, self.dtype, "x", self.n)
         if y is None:
             y = torch.empty_like(x)
             beta = 0.0
-        _cvec(y, self.dtype, "y")
+        _cvec(y, self.dtype, "y", self.n)
         _check(load().hk_spmv(self.h, _scalar(alpha, self.dtype), _ptr(x), _scalar(beta, self.dtype),
                               _ptr(y), _stream()))
         return y
 
     def residual(self, b, x, r=None):
         """r = b - A x."""
-        _cvec(b, self.dtype, "b")
-        _cvec(x, self.dtype, "x")
-        r = torch.empty_like(b) if r is None else _cvec(r, self.dtype, "r")
+        _cvec(b, self.dtype, "b", self.n)
+        _cvec(x, self.dtype, "x", self.n)
+        r = torch.empty_like(b) if r is None else _cvec(r, self.dtype, "r", self.n)
         _check(load().hk_residual(self.h, _ptr(b), _ptr(x), _ptr(r), _stream()))
         return r
 
 
 def zdotc(x, y, out=None):
-    _cvec(x, name="x"), _cvec(y, name="y")
-    out = torch.empty(1, dtype=torch.complex128, device=x.device) if out is None else out
+    _cvec(x, name="x"), _cvec(y, name="y", n=x.numel())
+    out = torch.empty(1, dtype=torch.complex128, device=x.device) if out is None else _cvec(out, name="out", n=1)
     _check(load().hk_zdotc(x.numel(), _ptr(x), _ptr(y), _ptr(out), _stream()))
     return out
 
 
 def zdotu(x, y, out=None):
-    _cvec(x, name="x"), _cvec(y, name="y")
-    out = torch.empty(1, dtype=torch.complex128, device=x.device) if out is None else out
+    _cvec(x, name="x"), _cvec(y, name="y", n=x.numel())
+    out = torch.empty(1, dtype=torch.complex128, device=x.device) if out is None else _cvec(out, name="out", n=1)
     _check(load().hk_zdotu(x.numel(), _ptr(x), _ptr(y), _ptr(out), _stream()))
     return out
 
 
 def dznrm2(x, out=None):
     _cvec(x, name="x")
-    out = torch.empty(1, dtype=torch.float64, device=x.device) if out is None else out
+    out = (torch.empty(1, dtype=torch.float64, device=x.device) if out is None
+           else _cvec(out, torch.float64, name="out", n=1))
     _check(load().hk_dznrm2(x.numel(), _ptr(x), _ptr(out), _stream()))
     return out
 
 
 def zaxpy(alpha, x, y):
     """y = alpha x + y (in place)."""
-    _cvec(x, name="x"), _cvec(y, name="y")
+    _cvec(x, name="x"), _cvec(y, name="y", n=x.numel())
     _check(load().hk_zaxpy(x.numel(), _scalar(alpha), _ptr(x), _ptr(y), _stream()))
     return y
 
@@ -230,20 +237,20 @@ def zscal(alpha, x):
 
 def zaxmy(x, y):
     """y = x .* y (in place)."""
-    _cvec(x, name="x"), _cvec(y, name="y")
+    _cvec(x, name="x"), _cvec(y, name="y", n=x.numel())
     _check(load().hk_zaxmy(x.numel(), _ptr(x), _ptr(y), _stream()))
     return y
 
 
 def zcopy(x, y):
-    _cvec(x, name="x"), _cvec(y, name="y")
+    _cvec(x, name="x"), _cvec(y, name="y", n=x.numel())
     _check(load().hk_zcopy(x.numel(), _ptr(x), _ptr(y), _stream()))
     return y
 
 
 def zconj(x, y=None):
     _cvec(x, name="x")
-    y = torch.empty_like(x) if y is None else _cvec(y, name="y")
+    y = torch.empty_like(x) if y is None else _cvec(y, name="y", n=x.numel())
     _check(load().hk_zconj(x.numel(), _ptr(x), _ptr(y), _stream()))
     return y
 
@@ -271,9 +278,9 @@ def krylov_solve(A: CSR, b, x=None, tol=1e-8, max_iter=400000, precond=True, che
     """Jacobi right-preconditioned BiCGStab, TFQMR or BiCGStab(ell) (the last two
     complex128) in A's precision; returns (x, info dict[, history]).  For
     BiCGStab(ell), iters counts cycles of ell BiCG steps."""
-    _cvec(b, A.dtype, name="b")
+    _cvec(b, A.dtype, name="b", n=A.n)
     use_x0 = x is not None
-    x = torch.zeros_like(b) if x is None else _cvec(x, A.dtype, name="x")
+    x = torch.zeros_like(b) if x is None else _cvec(x, A.dtype, name="x", n=A.n)
     hist = torch.zeros(int(max_iter) + 1, dtype=torch.float64, device=b.device) if history else None
     info = SolveInfo()
     o = _opts(tol, max_iter, precond, check_every, use_x0, hist, method, ell)
@@ -288,9 +295,9 @@ def krylov_solve(A: CSR, b, x=None, tol=1e-8, max_iter=400000, precond=True, che
 def krylov_solve_mixed(A: CSR, b, x=None, inner_tol=1e-4, outer_tol=1e-10, max_outer=50,
                        max_inner=400000, check_every=0):
     """complex64-inner / complex128-outer refinement; returns (x, info dict)."""
-    _cvec(b, name="b")
+    _cvec(b, name="b", n=A.n)
     use_x0 = x is not None
-    x = torch.zeros_like(b) if x is None else _cvec(x, name="x")
+    x = torch.zeros_like(b) if x is None else _cvec(x, name="x", n=A.n)
     info = SolveInfo()
     o = _opts(0.0, max_inner, True, check_every, use_x0, None)
     _check(load().hk_krylov_solve_mixed(A.h, _ptr(b), _ptr(x), float(inner_tol), float(outer_tol),
@@ -310,13 +317,14 @@ def sweep_solve(rowptr, col, K, M, kappa, B, tol=1e-8, max_iter=400000):
     (columns >= len(kappa) ignored).  Returns (X, list of info dicts).
     """
     nsys = len(kappa)
+    _cvec(rowptr, torch.int32, name="rowptr")
+    _cvec(col, torch.int32, name="col")
     n = rowptr.numel() - 1
     if B.shape != (n, SWEEP_LANES):
         raise HKError(HK_EINVAL, "B must have shape (n, 64)")
     _cvec(B, name="B")
     for t, nm in ((K, "K"), (M, "M")):
-        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
-            raise HKError(HK_EINVAL, f"{nm} must be a contiguous float64 device tensor")
+        _cvec(t, torch.float64, name=nm, n=col.numel())
     X = torch.zeros_like(B)
     kap = (C.c_double * (2 * nsys))(*[v for z in kappa for v in (complex(z).real, complex(z).imag)])
     infos = (SolveInfo * nsys)()
@@ -328,7 +336,7 @@ def sweep_solve(rowptr, col, K, M, kappa, B, tol=1e-8, max_iter=400000):
 
 def blockdiag_solve(A: CSR, row_off, b, tol=1e-8, max_iter=400000):
     """Uneven batch: A block-diagonal with systems [row_off[k], row_off[k+1])."""
-    _cvec(b, name="b")
+    _cvec(b, name="b", n=A.n)
     nsys = len(row_off) - 1
     offs = (C.c_int64 * (nsys + 1))(*[int(v) for v in row_off])
     x = torch.zeros_like(b)

@@ -211,6 +211,35 @@ def test_reductions_of_length_zero_and_one(hk):
     assert host(hk.dznrm2(xd))[0] == 5.0
 
 
+def test_binding_rejects_wrong_lengths(hk):
+    """The library takes raw pointers, so the binding checks every vector's
+    length against the matrix (or its partner) before any launch."""
+    say("binding length checks")
+    rowptr = np.array([0, 1, 2, 3], dtype=np.int32)
+    col = np.array([0, 1, 2], dtype=np.int32)
+    A = make_csr(hk, rowptr, col, np.ones(3, dtype=np.complex128))
+    x3, x2 = dev(np.ones(3, dtype=np.complex128)), dev(np.ones(2, dtype=np.complex128))
+    with pytest.raises(hk.HKError, match="elements"):
+        A.spmv(x2)
+    with pytest.raises(hk.HKError, match="elements"):
+        A.spmv(x3, x2)
+    with pytest.raises(hk.HKError, match="elements"):
+        A.residual(x3, x2)
+    with pytest.raises(hk.HKError, match="elements"):
+        hk.krylov_solve(A, x2)
+    with pytest.raises(hk.HKError, match="elements"):
+        hk.krylov_solve(A, x3, x=x2)
+    for f in (hk.zdotc, hk.zdotu, hk.zcopy, hk.zaxmy):
+        with pytest.raises(hk.HKError, match="elements"):
+            f(x3, x2)
+    with pytest.raises(hk.HKError, match="elements"):
+        hk.zaxpy(1.0, x3, x2)
+    with pytest.raises(hk.HKError):
+        hk.CSR(dev(rowptr), dev(col), dev(np.ones(2, dtype=np.complex128)))
+    # the checks pass matching lengths through
+    assert np.allclose(host(A.spmv(x3)), np.ones(3))
+
+
 def test_csr_create_rejects_bad_structure(hk):
     say("csr validation")
     rowptr = np.array([0, 2, 3], dtype=np.int32)
