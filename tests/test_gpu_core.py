@@ -277,17 +277,26 @@ def test_spmv_cube16_and_autotune(hk, oracle):
 
 
 def test_spmv_box192_full(hk, oracle):
-    """The 1.8M-row / 26.6M-nnz matrix, every row, in the benchmark's launch shape."""
+    """The 1.8M-row / 26.6M-nnz matrix, every row, in the benchmark's launch
+    shapes: the autotuned handle on the arrays as given (int32 columns, the
+    benchmark's headline product) and on the 16-bit column stream (the
+    solvers' handle), each launched as the benchmark does (back to back, then
+    checked)."""
     c = configs.box192()
     n = int(c["n"])
     x = crandn(np.random.default_rng(6), n)
     ref = oracle.spmv(c["rowptr"], c["col"], c["val"], x)
     bound = 1e-12 * spmv_bound(c["rowptr"], c["col"], c["val"], x)
-    say("spmv box192 autotune", n)
-    A = make_csr(hk, c["rowptr"], c["col"], c["val"], autotune=True)
-    say("plan", A.plan())
-    y = host(A.spmv(dev(x)))
-    assert np.all(np.abs(y - ref) <= bound)
+    xd = dev(x)
+    for compact in (False, True):
+        say("spmv box192 autotune, 16-bit columns" if compact else "spmv box192 autotune, int32 columns", n)
+        A = hk.CSR(dev(c["rowptr"]), dev(c["col"]), dev(c["val"]), autotune=True, compact_cols=compact)
+        say("plan", A.plan(), A.info())
+        assert A.info()["col_bytes"] == (2 if compact else 4)
+        y = torch.full_like(xd, complex("nan+nanj"))
+        for _ in range(4):
+            A.spmv(xd, y)
+        assert np.all(np.abs(host(y) - ref) <= bound), compact
 
 
 # -------------------------------------------------------------- BLAS-1
