@@ -41,14 +41,30 @@ def build(force=True):
     return LIB
 
 
+def build_sanitized(path):
+    """Compile the same source with AddressSanitizer and UndefinedBehaviorSanitizer
+    (host code; any report aborts) into path, for a run of the oracle's checks
+    with HK_ORACLE_LIB=path and the sanitizer runtimes preloaded."""
+    cmd = ["gcc", "-O1", "-g", "-std=gnu99", "-fPIC", "-shared", "-fopenmp", "-fcx-fortran-rules",
+           "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer",
+           "-o", path, SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    return path
+
+
 _lib = None
 
 
 def lib():
     global _lib
     if _lib is None:
-        build(force=False)
-        L = C.CDLL(LIB)
+        # HK_ORACLE_LIB names another build of the same source (the sanitized
+        # build of the oracle's own checks); by default the library is built here
+        path = os.environ.get("HK_ORACLE_LIB")
+        if not path:
+            build(force=False)
+            path = LIB
+        L = C.CDLL(path)
         P = C.c_void_p
         i64, dbl, i32 = C.c_int64, C.c_double, C.c_int
         L.orc_spmv.argtypes = [i64, P, P, P, P, P]
