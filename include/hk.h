@@ -232,6 +232,15 @@ int hk_krylov_solve_mixed(hk_csr A, const void* d_b, void* d_x, double inner_tol
 /* ------------------------------------------------------ batched solves */
 
 /*
+ * Both batched solves run one cooperative launch whose workgroups meet at
+ * grid barriers.  Every barrier wait is bounded: a workgroup that waits
+ * longer than the limit (default 4 s; the environment variable
+ * HK_BARRIER_SPIN_TICKS, read at each call, sets it in 100 MHz ticks) raises
+ * an abort flag, every workgroup leaves at its next barrier, and the call
+ * frees its workspace and returns HK_EHIP with "grid barrier timed out".
+ */
+
+/*
  * Frequency sweep in one persistent launch (not in the paper; it batches the
  * paper's P-BiCGSTAB over systems that share a sparsity pattern): for
  * j < nsys (nsys <= 64), solve (K - kappa_j M) x_j = b_j with Jacobi
