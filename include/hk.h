@@ -224,6 +224,8 @@ int hk_krylov_solve(hk_csr A, const void* d_b, void* d_x, const hk_solve_opts* o
  * max_outer cycles; a cycle that does not lower ||r|| ends the loop
  * (HK_NOT_CONVERGED).  opts->max_iter caps each inner solve; opts->method
  * must be HK_BICGSTAB.  The complex64 copy of A is kept in the handle.
+ * With the environment variable HK_TRACE set, each cycle's relative
+ * residual and inner iteration count are printed to stderr.
  */
 int hk_krylov_solve_mixed(hk_csr A, const void* d_b, void* d_x, double inner_tol,
                           double outer_tol, int32_t max_outer, const hk_solve_opts* opts,
