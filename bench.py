@@ -488,6 +488,27 @@ def main():
                                "cores": cores, "kind": "oracle",
                                "sample": f"{reps} oracle CSR products (plain C, OpenMP over rows) "
                                          f"on the same matrix, {tc:.1f} s"}
+        model = ""
+        try:
+            with open("/proc/cpuinfo") as fh:
+                model = next((l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")), "")
+        except OSError:
+            pass
+        out["cpu_baseline"]["host"] = model
+        if not args.no_solve:
+            # the oracle's Jacobi BiCGStab on the same system for a fixed 40
+            # iterations (a few seconds); its time to 1e-8 is extrapolated
+            # with the GPU's iteration count
+            ts = time.perf_counter()
+            _, io = oracle.bicgstab(c["rowptr"], c["col"], c["val"], c["g"], tol=1e-8, maxit=40)
+            tso = time.perf_counter() - ts
+            sp = {"iters": io["iters"], "time_s": round(tso, 3),
+                  "s_per_iter": round(tso / max(io["iters"], 1), 5)}
+            if "solve_plain" in out:
+                gi = out["solve_plain"]["iters"]
+                sp["extrapolated_time_to_1e-8_s"] = round(sp["s_per_iter"] * gi, 1)
+                sp["gpu_speedup_per_iter"] = round(sp["s_per_iter"] / (out["solve_plain"]["us_per_iter"] * 1e-6), 1)
+            out["cpu_baseline"]["bicgstab_sample"] = sp
         log("cpu", out["cpu_baseline"])
     print(json.dumps(out), flush=True)
 
