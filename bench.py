@@ -76,12 +76,12 @@ def pmc_traffic(plan, col_bytes):
     return None
 
 
-def bench_blas1(hk, torch, dev, stream, log, h=14_000_000, reps=21, sets=3):
-    """BLAS-1 kernels at the paper's largest vector size, achieved algorithmic
-    GB/s: zdotc 32 B/element, dznrm2 16, zaxpy 48, zscal 32, zaxmy 48.  The
-    calls rotate over `sets` independent vector pairs (1.3 GB in all), so
-    the operands do not stay in the 256 MB last-level cache between calls."""
-    g = torch.Generator(device=dev).manual_seed(7)
+# flops per element in the paper's BLAS-1 tables (GFlop/s x ms / h)
+PAPER_FLOPS = {"zdotc": 8, "dznrm2": 5, "zaxpy": 8, "zscal": 6, "zaxmy": 6}
+
+
+def _blas1_once(hk, torch, dev, h, reps, sets, seed=7):
+    g = torch.Generator(device=dev).manual_seed(seed)
     xs = [torch.randn(h, dtype=torch.complex128, device=dev, generator=g) for _ in range(sets)]
     ys = [torch.randn(h, dtype=torch.complex128, device=dev, generator=g) for _ in range(sets)]
     out = torch.empty(1, dtype=torch.complex128, device=dev)
@@ -89,6 +89,7 @@ def bench_blas1(hk, torch, dev, stream, log, h=14_000_000, reps=21, sets=3):
     ops = {"zdotc": (32, lambda k: hk.zdotc(xs[k], ys[k], out)), "dznrm2": (16, lambda k: hk.dznrm2(xs[k], nrm)),
            "zaxpy": (48, lambda k: hk.zaxpy(1e-3, xs[k], ys[k])), "zscal": (32, lambda k: hk.zscal(0.999, ys[k])),
            "zaxmy": (48, lambda k: hk.zaxmy(xs[k], ys[k]))}
+    stream = torch.cuda.current_stream()
     res = {}
     for name, (bpe, fn) in ops.items():
         for k in range(sets):
@@ -100,10 +101,27 @@ def bench_blas1(hk, torch, dev, stream, log, h=14_000_000, reps=21, sets=3):
         e1.record(stream)
         torch.cuda.synchronize()
         us = e0.elapsed_time(e1) / reps * 1e3
-        res[name] = {"us": round(us, 2), "gbs": round(bpe * h / (us * 1e-6) / 1e9, 1)}
-    log("blas1", res)
+        res[name] = {"us": round(us, 2), "gbs": round(bpe * h / (us * 1e-6) / 1e9, 1),
+                     "gflops": round(PAPER_FLOPS[name] * h / (us * 1e-6) / 1e9, 1)}
     del xs, ys
-    return {"blas1": {"h": h, "rotating_sets": sets, "ops": res}}
+    return res
+
+
+def bench_blas1(hk, torch, dev, stream, log, h=14_000_000, reps=21, sets=3):
+    """BLAS-1 kernels at the paper's vector sizes, achieved algorithmic GB/s
+    (zdotc 32 B/element, dznrm2 16, zaxpy 48, zscal 32, zaxmy 48) and GFLOP/s
+    in the paper's flop convention.  Each entry point call (its kernels and,
+    for the reductions, the finalize) is timed; the calls rotate over
+    independent vector pairs, enough of them (at least 512 MB in all) that
+    the operands do not stay in the 256 MB last-level cache between calls."""
+    res = _blas1_once(hk, torch, dev, h, reps, sets)
+    log("blas1", res)
+    paper = {}
+    for hp in (648_849, 2_000_000, 9_000_000):
+        ns = max(2, -(-512 * 2**20 // (32 * hp)))
+        paper[str(hp)] = {"rotating_sets": ns, "ops": _blas1_once(hk, torch, dev, hp, max(reps, ns + 1), ns)}
+    log("blas1 at the paper's other sizes", {k: {o: v["us"] for o, v in d["ops"].items()} for k, d in paper.items()})
+    return {"blas1": {"h": h, "rotating_sets": sets, "ops": res, "paper_sizes": paper}}
 
 
 def bench_batched(hk, torch, np, dev, log):
