@@ -773,6 +773,98 @@ static int finish_solve(const hk_csr_s* A, const cplx<R>* val, const cplx<R>* b,
 
 // Runs the whole solve for precision R on values `val` (A's pattern), right
 // side b, solution x (input when use_x0).  Fills info (host), synchronises.
+// Chunked iteration driver shared by the three methods.  enqueue(q)
+// enqueues one chunk (m iterations) on stream q and returns the first launch
+// error.  After each chunk the status word is copied to pinned memory and
+// read one chunk behind, so the GPU always has the next chunk queued; the
+// loop ends once a solve has stopped or max_iter iterations are enqueued.
+// The chunk is recorded once into a HIP graph on a private stream and
+// replayed, one launch per chunk instead of one per kernel: on small systems
+// the kernels take a few microseconds each and the host's launch rate would
+// otherwise bound the solve.  The chunk holds kernels only (no memset or
+// copy), on buffers fixed for the solve.  If the graph cannot be built, or
+// HK_SOLVE_GRAPHS=0 is set, the chunks are launched on s directly.  s is
+// idle on return or holds only work ordered after the chunks.
+template <class Enq>
+static int run_chunks(int* pin, SolveState* st, int m, long long max_iter, hipStream_t s, Enq&& enqueue) {
+  const char* env = getenv("HK_SOLVE_GRAPHS");
+  const bool want_graph = !(env && env[0] == '0');
+  hipStream_t cs = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t ev[2] = {nullptr, nullptr}, fork = nullptr;
+  HK_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+  HK_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+  if (want_graph) {
+    bool ok = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&fork, hipEventDisableTiming) == hipSuccess;
+    ok = ok && hipEventRecord(fork, s) == hipSuccess && hipStreamWaitEvent(cs, fork, 0) == hipSuccess;
+    if (ok && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+      const hipError_t le = enqueue(cs);
+      hipGraph_t g = nullptr;
+      const hipError_t ce = hipStreamEndCapture(cs, &g);
+      if (le == hipSuccess && ce == hipSuccess && g) {
+        graph = g;
+        ok = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+      } else {
+        if (g) (void)hipGraphDestroy(g);
+        ok = false;
+      }
+    } else {
+      ok = false;
+    }
+    if (!ok) {  // direct launches on s instead
+      if (exec) (void)hipGraphExecDestroy(exec);
+      if (graph) (void)hipGraphDestroy(graph);
+      exec = nullptr;
+      graph = nullptr;
+      if (cs) {
+        (void)hipStreamSynchronize(cs);
+        (void)hipStreamDestroy(cs);
+      }
+      cs = nullptr;
+      (void)hipGetLastError();
+    }
+  }
+  hipStream_t q = exec ? cs : s;
+  int rc = HK_OK;
+  long long enq = 0;
+  const size_t status_off = offsetof(SolveState, status);
+  for (int k = 0;; ++k) {
+    hipError_t e = exec ? hipGraphLaunch(exec, q) : enqueue(q);
+    if (e != hipSuccess) {
+      set_error_text("krylov solve: launch failed: %s", hipGetErrorString(e));
+      rc = HK_EHIP;
+      break;
+    }
+    enq += m;
+    e = hipMemcpyAsync(&pin[k & 1], (char*)st + status_off, sizeof(int), hipMemcpyDeviceToHost, q);
+    if (e == hipSuccess) e = hipEventRecord(ev[k & 1], q);
+    if (e == hipSuccess && k > 0) e = hipEventSynchronize(ev[(k - 1) & 1]);
+    if (e != hipSuccess) {
+      set_error_text("krylov solve: %s", hipGetErrorString(e));
+      rc = HK_EHIP;
+      break;
+    }
+    if (k > 0 && pin[(k - 1) & 1] < S_RUN) break;
+    if (enq >= max_iter) break;
+  }
+  if (cs) {
+    // the graph and its stream are released once the last chunk has run
+    if (hipStreamSynchronize(cs) != hipSuccess && rc == HK_OK) {
+      set_error_text("krylov solve: stream synchronisation failed");
+      rc = HK_EHIP;
+    }
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipStreamDestroy(cs);
+  }
+  if (fork) (void)hipEventDestroy(fork);
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
+  return rc;
+}
+
 template <class R>
 static int bicgstab(hk_csr_s* A, const cplx<R>* val, const cplx<R>* b, cplx<R>* x,
                     const hk_solve_opts& o, void* wsbase, hk_solve_info* info, hipStream_t s) {
@@ -821,56 +913,28 @@ static int bicgstab(hk_csr_s* A, const cplx<R>* val, const cplx<R>* b, cplx<R>* 
 
   // iterations, in chunks; the status word is read one chunk behind
   int m = o.check_every > 0 ? o.check_every : (n < 200000 ? 64 : 16);
-  int* pin = A->pinned;
-  hipEvent_t ev[2];
-  HK_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
-  HK_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
-  int rc = HK_OK;
-  long long enq = 0;
-  int k = 0;
-  const size_t status_off = offsetof(SolveState, status);
-  for (;;) {
-    for (int j = 0; j < m && rc == HK_OK; ++j) {
-      hipLaunchKernelGGL(k_p<R>, ew, dim3(kBlock), 0, s, n, wk.st, wk.r, wk.p, wk.v);
-      hipError_t e = hipGetLastError();
-      if (e == hipSuccess)
-        e = launch_spmv_dot<R>(A, dp, 1, wk.ahat, wk.p, wk.v, wk.rh, wk, s);
-      if (e == hipSuccess) e = launch_fin<R, F_SIGMA>(wk, gs, 0, 0, s);
+  const int rc = run_chunks(A->pinned, wk.st, m, o.max_iter, s, [&](hipStream_t q) {
+    hipError_t e = hipSuccess;
+    for (int j = 0; j < m && e == hipSuccess; ++j) {
+      hipLaunchKernelGGL(k_p<R>, ew, dim3(kBlock), 0, q, n, wk.st, wk.r, wk.p, wk.v);
+      e = hipGetLastError();
+      if (e == hipSuccess) e = launch_spmv_dot<R>(A, dp, 1, wk.ahat, wk.p, wk.v, wk.rh, wk, q);
+      if (e == hipSuccess) e = launch_fin<R, F_SIGMA>(wk, gs, 0, 0, q);
       if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_s<R>, dim3(gv), dim3(kBlock), 0, s, n, wk.st, wk.r, wk.v, wk.s);
+        hipLaunchKernelGGL(k_s<R>, dim3(gv), dim3(kBlock), 0, q, n, wk.st, wk.r, wk.v, wk.s);
         e = hipGetLastError();
       }
-      if (e == hipSuccess)
-        e = launch_spmv_dot<R>(A, dp, 2, wk.ahat, wk.s, wk.t, wk.s, wk, s);
-      if (e == hipSuccess) e = launch_fin<R, F_OMEGA>(wk, gs, 0, 0, s);
+      if (e == hipSuccess) e = launch_spmv_dot<R>(A, dp, 2, wk.ahat, wk.s, wk.t, wk.s, wk, q);
+      if (e == hipSuccess) e = launch_fin<R, F_OMEGA>(wk, gs, 0, 0, q);
       if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_xr<R>, dim3(gv), dim3(kBlock), 0, s, n, wk.st, wk.rh, wk.r, wk.p, wk.s,
+        hipLaunchKernelGGL(k_xr<R>, dim3(gv), dim3(kBlock), 0, q, n, wk.st, wk.rh, wk.r, wk.p, wk.s,
                            wk.t, wk.y, wk.partials);
         e = hipGetLastError();
       }
-      if (e == hipSuccess) e = launch_fin<R, F_XR>(wk, gv, 0, 0, s);
-      if (e != hipSuccess) {
-        set_error_text("krylov solve: launch failed: %s", hipGetErrorString(e));
-        rc = HK_EHIP;
-      }
+      if (e == hipSuccess) e = launch_fin<R, F_XR>(wk, gv, 0, 0, q);
     }
-    if (rc != HK_OK) break;
-    enq += m;
-    hipError_t e = hipMemcpyAsync(&pin[k & 1], (char*)wk.st + status_off, sizeof(int),
-                                  hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipEventRecord(ev[k & 1], s);
-    if (e == hipSuccess && k > 0) e = hipEventSynchronize(ev[(k - 1) & 1]);
-    if (e != hipSuccess) {
-      set_error_text("krylov solve: %s", hipGetErrorString(e));
-      rc = HK_EHIP;
-      break;
-    }
-    if (k > 0 && pin[(k - 1) & 1] < S_RUN) break;
-    if (enq >= o.max_iter) break;
-    ++k;
-  }
-  (void)hipEventDestroy(ev[0]);
-  (void)hipEventDestroy(ev[1]);
+    return e;
+  });
   if (rc != HK_OK) return rc;
 
   return finish_solve<R>(A, val, b, x, wk, info, s);
@@ -1275,48 +1339,23 @@ static int tfqmr(hk_csr_s* A, const double2* val, const double2* b, double2* x, 
   const EpiTqB<R> eb{w, d, wk.y, u2, wk.rh, y2};
   const EpiTqD<R, 0> ed{u1, v, u2, wk.rh};
   int m = o.check_every > 0 ? o.check_every : (n < 200000 ? 64 : 16);
-  int* pin = A->pinned;
-  hipEvent_t ev[2];
-  HK_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
-  HK_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
-  int rc = HK_OK;
-  long long enq = 0;
-  int k = 0;
-  const size_t status_off = offsetof(SolveState, status);
-  for (;;) {
-    for (int j = 0; j < m && rc == HK_OK; ++j) {
-      hipLaunchKernelGGL(k_tq_a<R>, dim3(gv), dim3(kBlock), 0, s, n, wk.st, y1, v, u1, y2, w, d, wk.partials);
-      hipError_t e = hipGetLastError();
-      if (e == hipSuccess) e = launch_tq_fin<TQ_H1>(wk.st, wk.partials, gv, 0, 0, s);
-      if (e == hipSuccess) e = launch_fused(A, dp, wk.ahat, y2, eb, wk.st, wk.partials, s);
-      if (e == hipSuccess) e = launch_tq_fin<TQ_H2>(wk.st, wk.partials, gs, 0, 0, s);
+  const int rc = run_chunks(A->pinned, wk.st, m, o.max_iter, s, [&](hipStream_t q) {
+    hipError_t e = hipSuccess;
+    for (int j = 0; j < m && e == hipSuccess; ++j) {
+      hipLaunchKernelGGL(k_tq_a<R>, dim3(gv), dim3(kBlock), 0, q, n, wk.st, y1, v, u1, y2, w, d, wk.partials);
+      e = hipGetLastError();
+      if (e == hipSuccess) e = launch_tq_fin<TQ_H1>(wk.st, wk.partials, gv, 0, 0, q);
+      if (e == hipSuccess) e = launch_fused(A, dp, wk.ahat, y2, eb, wk.st, wk.partials, q);
+      if (e == hipSuccess) e = launch_tq_fin<TQ_H2>(wk.st, wk.partials, gs, 0, 0, q);
       if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_tq_c<R>, dim3(gv), dim3(kBlock), 0, s, n, wk.st, w, y2, d, wk.y, y1);
+        hipLaunchKernelGGL(k_tq_c<R>, dim3(gv), dim3(kBlock), 0, q, n, wk.st, w, y2, d, wk.y, y1);
         e = hipGetLastError();
       }
-      if (e == hipSuccess) e = launch_fused(A, dp, wk.ahat, y1, ed, wk.st, wk.partials, s);
-      if (e == hipSuccess) e = launch_tq_fin<TQ_SIGMA>(wk.st, wk.partials, gs, 0, 0, s);
-      if (e != hipSuccess) {
-        set_error_text("krylov solve: launch failed: %s", hipGetErrorString(e));
-        rc = HK_EHIP;
-      }
+      if (e == hipSuccess) e = launch_fused(A, dp, wk.ahat, y1, ed, wk.st, wk.partials, q);
+      if (e == hipSuccess) e = launch_tq_fin<TQ_SIGMA>(wk.st, wk.partials, gs, 0, 0, q);
     }
-    if (rc != HK_OK) break;
-    enq += m;
-    hipError_t e = hipMemcpyAsync(&pin[k & 1], (char*)wk.st + status_off, sizeof(int), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipEventRecord(ev[k & 1], s);
-    if (e == hipSuccess && k > 0) e = hipEventSynchronize(ev[(k - 1) & 1]);
-    if (e != hipSuccess) {
-      set_error_text("krylov solve: %s", hipGetErrorString(e));
-      rc = HK_EHIP;
-      break;
-    }
-    if (k > 0 && pin[(k - 1) & 1] < S_RUN) break;
-    if (enq >= o.max_iter) break;
-    ++k;
-  }
-  (void)hipEventDestroy(ev[0]);
-  (void)hipEventDestroy(ev[1]);
+    return e;
+  });
   if (rc != HK_OK) return rc;
   return finish_solve<R>(A, val, b, x, wk, info, s);
 }
@@ -1782,71 +1821,45 @@ static int bicgstab_l(hk_csr_s* A, const double2* val, const double2* b, double2
   if (hflag) HK_FAIL(HK_EINVAL, "krylov solve: zero diagonal entry (Jacobi undefined)");
 
   const int m = o.check_every > 0 ? o.check_every : std::max(1, (n < 200000 ? 64 : 16) / ELL);
-  int* pin = A->pinned;
-  hipEvent_t ev[2];
-  HK_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
-  HK_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
-  int rc = HK_OK;
-  long long enq = 0;
-  int kk = 0;
-  const size_t status_off = offsetof(SolveState, status);
-  for (;;) {
-    for (int c = 0; c < m && rc == HK_OK; ++c) {
-      hipError_t e = hipSuccess;
+  const int rc = run_chunks(A->pinned, wk.st, m, o.max_iter, s, [&](hipStream_t q) {
+    hipError_t e = hipSuccess;
+    for (int c = 0; c < m && e == hipSuccess; ++c) {
       for (int j = 0; j < ELL && e == hipSuccess; ++j) {
-        hipLaunchKernelGGL(k_bl_u<R>, dim3(gv), dim3(kBlock), 0, s, n, wk.st, j, wk.vec);
+        hipLaunchKernelGGL(k_bl_u<R>, dim3(gv), dim3(kBlock), 0, q, n, wk.st, j, wk.vec);
         e = hipGetLastError();
         if (e == hipSuccess) {
           EpiStoreDot<R> eu{wk.vec.u[j + 1], wk.rt};
-          e = launch_fused(A, dp, wk.ahat, wk.vec.u[j], eu, wk.st, wk.partials, s);
+          e = launch_fused(A, dp, wk.ahat, wk.vec.u[j], eu, wk.st, wk.partials, q);
         }
-        if (e == hipSuccess) e = launch_bl_fin<BL_ALPHA, ELL>(wk.st, wk.partials, gs, 0, 0, s);
+        if (e == hipSuccess) e = launch_bl_fin<BL_ALPHA, ELL>(wk.st, wk.partials, gs, 0, 0, q);
         if (e == hipSuccess) {
-          hipLaunchKernelGGL(k_bl_r<R>, dim3(gv), dim3(kBlock), 0, s, n, wk.st, j, wk.vec, wk.y, wk.partials);
+          hipLaunchKernelGGL(k_bl_r<R>, dim3(gv), dim3(kBlock), 0, q, n, wk.st, j, wk.vec, wk.y, wk.partials);
           e = hipGetLastError();
         }
-        if (e == hipSuccess) e = launch_bl_fin<BL_R, ELL>(wk.st, wk.partials, gv, 0, 0, s);
+        if (e == hipSuccess) e = launch_bl_fin<BL_R, ELL>(wk.st, wk.partials, gv, 0, 0, q);
         if (e == hipSuccess) {
           EpiStoreDot<R> er{wk.vec.r[j + 1], wk.rt};
-          e = launch_fused(A, dp, wk.ahat, wk.vec.r[j], er, wk.st, wk.partials, s);
+          e = launch_fused(A, dp, wk.ahat, wk.vec.r[j], er, wk.st, wk.partials, q);
         }
-        if (e == hipSuccess && j + 1 < ELL) e = launch_bl_fin<BL_RHO, ELL>(wk.st, wk.partials, gs, 0, 0, s);
+        if (e == hipSuccess && j + 1 < ELL) e = launch_bl_fin<BL_RHO, ELL>(wk.st, wk.partials, gs, 0, 0, q);
       }
       if (e == hipSuccess) {
-        hipLaunchKernelGGL((k_bl_gram<R, ELL>), dim3(gv), dim3(kBlock), 0, s, n, wk.st, wk.vec, wk.partials);
+        hipLaunchKernelGGL((k_bl_gram<R, ELL>), dim3(gv), dim3(kBlock), 0, q, n, wk.st, wk.vec, wk.partials);
         e = hipGetLastError();
       }
       if (e == hipSuccess) {
-        hipLaunchKernelGGL((k_bl_fin_gram<ELL>), dim3(1), dim3(kFinBlock), 0, s, wk.st, wk.partials, gv);
+        hipLaunchKernelGGL((k_bl_fin_gram<ELL>), dim3(1), dim3(kFinBlock), 0, q, wk.st, wk.partials, gv);
         e = hipGetLastError();
       }
       if (e == hipSuccess) {
-        hipLaunchKernelGGL((k_bl_mr<R, ELL>), dim3(gv), dim3(kBlock), 0, s, n, wk.st, wk.vec, wk.y, wk.rt,
+        hipLaunchKernelGGL((k_bl_mr<R, ELL>), dim3(gv), dim3(kBlock), 0, q, n, wk.st, wk.vec, wk.y, wk.rt,
                            wk.partials);
         e = hipGetLastError();
       }
-      if (e == hipSuccess) e = launch_bl_fin<BL_MR, ELL>(wk.st, wk.partials, gv, 0, 0, s);
-      if (e != hipSuccess) {
-        set_error_text("krylov solve: launch failed: %s", hipGetErrorString(e));
-        rc = HK_EHIP;
-      }
+      if (e == hipSuccess) e = launch_bl_fin<BL_MR, ELL>(wk.st, wk.partials, gv, 0, 0, q);
     }
-    if (rc != HK_OK) break;
-    enq += m;
-    hipError_t e = hipMemcpyAsync(&pin[kk & 1], (char*)wk.st + status_off, sizeof(int), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipEventRecord(ev[kk & 1], s);
-    if (e == hipSuccess && kk > 0) e = hipEventSynchronize(ev[(kk - 1) & 1]);
-    if (e != hipSuccess) {
-      set_error_text("krylov solve: %s", hipGetErrorString(e));
-      rc = HK_EHIP;
-      break;
-    }
-    if (kk > 0 && pin[(kk - 1) & 1] < S_RUN) break;
-    if (enq >= o.max_iter) break;
-    ++kk;
-  }
-  (void)hipEventDestroy(ev[0]);
-  (void)hipEventDestroy(ev[1]);
+    return e;
+  });
   if (rc != HK_OK) return rc;
   // the common ending (x = D^-1 y, true residual, info) through a Work view
   Work<R> view{};

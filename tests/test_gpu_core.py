@@ -211,6 +211,29 @@ def test_reductions_of_length_zero_and_one(hk):
     assert host(hk.dznrm2(xd))[0] == 5.0
 
 
+def test_graph_replays_match_direct_launches(hk, monkeypatch):
+    """The solvers replay one recorded chunk of iterations as a HIP graph; with
+    HK_SOLVE_GRAPHS=0 they launch every kernel directly.  Both give the same
+    bits, in every method, with a chunk of 3 iterations (many replays, each
+    followed by the host's status read) and with the default chunk."""
+    rowptr, col, val = small_mesh_problem()
+    n = rowptr.shape[0] - 1
+    b = crandn(np.random.default_rng(21), n)
+    A = make_csr(hk, rowptr, col, val, autotune=True)
+    for method, kw in (("bicgstab", {}), ("tfqmr", {}), ("bicgstab_l", {"ell": 4})):
+        for every in (3, 0):
+            got = {}
+            for graphs in ("1", "0"):
+                monkeypatch.setenv("HK_SOLVE_GRAPHS", graphs)
+                say("graph replay", method, "check_every", every, "graphs", graphs)
+                x, info = hk.krylov_solve(A, dev(b), tol=1e-10, check_every=every, method=method, **kw)
+                got[graphs] = (host(x), info)
+            assert got["1"][1] == got["0"][1], (method, every)
+            assert np.array_equal(got["1"][0], got["0"][0]), (method, every)
+            assert got["1"][1]["status"] == hk.HK_OK, got["1"][1]
+    monkeypatch.delenv("HK_SOLVE_GRAPHS")
+
+
 def test_binding_rejects_wrong_lengths(hk):
     """The library takes raw pointers, so the binding checks every vector's
     length against the matrix (or its partner) before any launch."""
