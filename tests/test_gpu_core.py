@@ -105,6 +105,40 @@ def test_spmv_all_shapes_ragged(hk, oracle):
             assert np.array_equal(outs[(L, U, g, True)], outs[(L, U, g, False)]), (U, g)
 
 
+def random_structure(rng, n, max_row):
+    """CSR with row lengths drawn from [0, max_row] (a quarter of the rows
+    empty), sorted distinct columns anywhere in [0, n), random values."""
+    lens = rng.integers(0, max_row + 1, n)
+    lens[rng.random(n) < 0.25] = 0
+    lens = np.minimum(lens, n)
+    rowptr = np.zeros(n + 1, dtype=np.int32)
+    rowptr[1:] = np.cumsum(lens)
+    col = np.concatenate([np.sort(rng.choice(n, size=k, replace=False)) for k in lens]
+                         + [np.zeros(0, dtype=np.int64)]).astype(np.int32)
+    val = crandn(rng, int(rowptr[-1]))
+    return rowptr, col, val
+
+
+def test_spmv_random_structures(hk, oracle):
+    """Unstructured matrices: rows of 0 to 700 entries (longer than one pass
+    of a row-block wave, 512 entries), columns anywhere, n not a multiple of
+    64; every launch shape on both column streams against the oracle."""
+    for seed, n, max_row in ((31, 1001, 40), (32, 2500, 700), (33, 77, 77)):
+        rng = np.random.default_rng(seed)
+        rowptr, col, val = random_structure(rng, n, max_row)
+        x = crandn(rng, n)
+        ref = oracle.spmv(rowptr, col, val, x)
+        bound = 1e-12 * spmv_bound(rowptr, col, val, x)
+        xd = dev(x)
+        for compact in (True, False):
+            A = hk.CSR(dev(rowptr), dev(col), dev(val), compact_cols=compact)
+            for L, U, g in SHAPES:
+                say("spmv random", seed, n, max_row, "shape", L, U, g, "compact", compact)
+                A.set_plan(L, U, g)
+                y = host(A.spmv(xd, torch.full_like(xd, complex("nan+nanj")), beta=0.0))
+                assert np.all(np.abs(y - ref) <= bound), (seed, L, U, g, compact)
+
+
 def test_spmv_column_stream_limits(hk, oracle):
     """The 16-bit column stream is built exactly when every |col - (row &
     ~63)| <= 32767; at the limit, one past it and with offsets of both signs
