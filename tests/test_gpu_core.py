@@ -616,6 +616,46 @@ def test_solvers_same_bits_from_either_column_stream(hk):
         assert xs[0][1:] == xs[1][1:] and np.array_equal(xs[0][0], xs[1][0]), method
 
 
+def test_solver_plans_random_structure(hk, oracle):
+    """The solvers' fused products on an unstructured, diagonally dominant
+    matrix whose rows hold 1 to 301 entries (a 64-row block spans many passes,
+    rows and blocks start at odd entries), in a spread of fixed shapes and
+    both entry layouts: two BiCGStab and two TFQMR steps and one BiCGStab(2)
+    cycle give the oracle's iterate."""
+    rng = np.random.default_rng(42)
+    n = 1500
+    cols, vals = [], []
+    rowptr = np.zeros(n + 1, dtype=np.int32)
+    for i in range(n):
+        k = int(rng.integers(0, 301))
+        off = rng.choice(np.delete(np.arange(n), i), size=k, replace=False)
+        c = np.sort(np.append(off, i))
+        v = crandn(rng, k + 1) * 0.1
+        v[c == i] = (np.abs(v).sum() + 1.0) * (1 + 0.1j)
+        cols.append(c)
+        vals.append(v)
+        rowptr[i + 1] = rowptr[i] + k + 1
+    col = np.concatenate(cols).astype(np.int32)
+    val = np.concatenate(vals)
+    assert col.shape[0] % 2 == 1  # the paired layout's last pass reads the padding entry
+    b = crandn(rng, n)
+    ref = {"bicgstab": oracle.bicgstab(rowptr, col, val, b, tol=1e-14, maxit=2)[0],
+           "tfqmr": oracle.tfqmr(rowptr, col, val, b, tol=1e-14, maxit=2)[0],
+           "bicgstab_l": oracle.bicgstab_l(rowptr, col, val, b, ell=2, tol=1e-14, maxit=1)[0]}
+    A = make_csr(hk, rowptr, col, val)
+    assert A.info()["col_bytes"] == 2
+    for rw, nw in ((16, 8), (32, 2), (64, 2), (64, 8)):
+        for paired in (False, True):
+            for grid in (0, 3):
+                say("solver plan random", rw, nw, "paired" if paired else "lanes", grid)
+                A.set_solver_plan(rw, nw, grid, paired)
+                for method, its in (("bicgstab", 2), ("tfqmr", 2), ("bicgstab_l", 1)):
+                    x, info = hk.krylov_solve(A, dev(b), tol=1e-14, max_iter=its, method=method, ell=2)
+                    assert info["iters"] == its, (method, info)
+                    xo = ref[method]
+                    assert np.linalg.norm(host(x) - xo) <= 1e-10 * np.linalg.norm(xo), (method, rw, nw, paired, grid)
+
+
 def test_solver_plans_every_shape(hk, oracle):
     """Every fixed shape of the solvers' fused products (16/32/64 rows per
     wave, 2/4/8 waves, lane-per-entry and paired layouts, one workgroup per
