@@ -621,7 +621,8 @@ def test_solver_plans_random_structure(hk, oracle):
     matrix whose rows hold 1 to 301 entries (a 64-row block spans many passes,
     rows and blocks start at odd entries), in a spread of fixed shapes and
     both entry layouts: two BiCGStab and two TFQMR steps and one BiCGStab(2)
-    cycle give the oracle's iterate."""
+    cycle in complex128, one BiCGStab step in complex64, give the oracle's
+    iterate."""
     rng = np.random.default_rng(42)
     n = 1500
     cols, vals = [], []
@@ -642,7 +643,10 @@ def test_solver_plans_random_structure(hk, oracle):
     ref = {"bicgstab": oracle.bicgstab(rowptr, col, val, b, tol=1e-14, maxit=2)[0],
            "tfqmr": oracle.tfqmr(rowptr, col, val, b, tol=1e-14, maxit=2)[0],
            "bicgstab_l": oracle.bicgstab_l(rowptr, col, val, b, ell=2, tol=1e-14, maxit=1)[0]}
+    b32, v32 = b.astype(np.complex64), val.astype(np.complex64)
+    ref64 = oracle.bicgstab_c64(rowptr, col, v32, b32, tol=1e-9, maxit=1)[0]
     A = make_csr(hk, rowptr, col, val)
+    A32 = make_csr(hk, rowptr, col, v32)
     assert A.info()["col_bytes"] == 2
     for rw, nw in ((16, 8), (32, 2), (64, 2), (64, 8)):
         for paired in (False, True):
@@ -654,6 +658,10 @@ def test_solver_plans_random_structure(hk, oracle):
                     assert info["iters"] == its, (method, info)
                     xo = ref[method]
                     assert np.linalg.norm(host(x) - xo) <= 1e-10 * np.linalg.norm(xo), (method, rw, nw, paired, grid)
+                A32.set_solver_plan(rw, nw, grid, paired)
+                x, info = hk.krylov_solve(A32, dev(b32), tol=1e-9, max_iter=1)
+                assert info["iters"] == 1
+                assert np.linalg.norm(host(x) - ref64) <= 1e-6 * np.linalg.norm(ref64), (rw, nw, paired, grid)
 
 
 def test_solver_plans_every_shape(hk, oracle):
