@@ -279,9 +279,14 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-solve", action="store_true", help="CSR products only (profiling runs)")
     ap.add_argument("--plan", default="", help="force the CSR launch shape 'L,U,grid' instead of tuning")
+    ap.add_argument("--solve-max-iter", type=int, default=0,
+                    help="counter runs: cap the plain solve at this many iterations and skip the other solves")
     ap.add_argument("--no-batched", dest="batched", action="store_false",
                     help="skip the batched sweep / uneven-batch extras")
     args = ap.parse_args()
+    if args.solve_max_iter:
+        # a counter run: the capped plain solve only
+        args.no_mixed, args.batched, args.no_cpu = True, False, True
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(the row-slab design for several GPUs is described, not built).", file=sys.stderr)
@@ -335,7 +340,7 @@ def main():
         hk.dznrm2(y)
         info = None
         if not args.no_solve:
-            _, info = hk.krylov_solve(A, g, tol=1e-8)
+            _, info = hk.krylov_solve(A, g, tol=1e-8, max_iter=args.solve_max_iter or 400000)
         torch.cuda.synchronize()
         timed_spmv.append(ev0.elapsed_time(ev1) / args.spmv_reps)
         return info
@@ -423,7 +428,7 @@ def main():
                               "time_s_mean": round(float(np.mean(solve_s)) - (args.spmv_reps + 3) * ms_spmv * 1e-3, 4),
                               "us_per_iter": round((float(np.mean(solve_s)) - (args.spmv_reps + 3) * ms_spmv * 1e-3)
                                                    / max(st["iters"], 1) * 1e6, 2)}
-    if not args.no_solve:
+    if not args.no_solve and not args.solve_max_iter:
         # P-TFQMR (the paper's third method) on the same system and tolerance
         torch.cuda.synchronize()
         ts = time.perf_counter()
@@ -484,7 +489,7 @@ def main():
             if "solve_plain" in out:
                 sweep[f"{itol:g}"]["speedup_vs_plain"] = round(out["solve_plain"]["time_s_mean"] / ti, 3)
         out["solve_mixed_1e-8"]["inner_tol_sweep"] = sweep
-    if not args.no_solve:
+    if not args.no_solve and not args.solve_max_iter:
         out.update(bench_blas1(hk, torch, dev, stream, log))
     if args.batched and not args.no_solve:
         out.update(bench_hex(hk, torch, np, dev, stream, log))
