@@ -782,13 +782,15 @@ static int finish_solve(const hk_csr_s* A, const cplx<R>* val, const cplx<R>* b,
 // replayed, one launch per chunk instead of one per kernel: on small systems
 // the kernels take a few microseconds each and the host's launch rate would
 // otherwise bound the solve.  The chunk holds kernels only (no memset or
-// copy), on buffers fixed for the solve.  If the graph cannot be built, or
-// HK_SOLVE_GRAPHS=0 is set, the chunks are launched on s directly.  s is
+// copy), on buffers fixed for the solve.  If the graph cannot be built, the
+// chunk is longer than 256 iterations, or HK_SOLVE_GRAPHS=0 is set, the
+// chunks are launched on s directly.  s is
 // idle on return or holds only work ordered after the chunks.
 template <class Enq>
 static int run_chunks(int* pin, SolveState* st, int m, long long max_iter, hipStream_t s, Enq&& enqueue) {
   const char* env = getenv("HK_SOLVE_GRAPHS");
-  const bool want_graph = !(env && env[0] == '0');
+  // a chunk of at most 256 iterations is recorded (a few thousand graph nodes)
+  const bool want_graph = !(env && env[0] == '0') && m <= 256;
   hipStream_t cs = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
