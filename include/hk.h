@@ -205,7 +205,11 @@ typedef struct {
  * only) a complex64 solve whose vectors and products are complex64 and whose
  * dots and scalars are double (b and x then complex64).  Scalars stay in
  * device memory; the host reads a status word every check_every iterations
- * and synchronises the stream once at the end to fill *info.  A zero
+ * and synchronises the stream once at the end to fill *info.  A chunk of
+ * check_every iterations (up to 256) is recorded once into a HIP graph on a
+ * private stream that waits for `stream`, and replayed; the environment
+ * variable HK_SOLVE_GRAPHS=0 launches every kernel on `stream` instead (same
+ * results, bit for bit).  A zero
  * diagonal entry with precond = 1, or an unknown method, gives HK_EINVAL.
  * Returns info->status (>= 0) or an error.  x always holds the last iterate.
  */
