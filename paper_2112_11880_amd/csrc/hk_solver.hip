@@ -393,12 +393,12 @@ template <> struct FinNV<F_XR> { static constexpr int v = 3; };
 
 // One workgroup: sums the nb partials of the preceding kernel and applies
 // the scalar update of step F.
-template <class R, int F>
-__global__ __launch_bounds__(kFinBlock) void k_fin(SolveState* st, const double* partials, int nb, double tol,
-                                                   long long maxit) {
+template <class R, int F, int BS>
+__global__ __launch_bounds__(BS) void k_fin(SolveState* st, const double* partials, int nb, double tol,
+                                            long long maxit) {
   using V = double2;
   constexpr int NV = FinNV<F>::v;
-  __shared__ double lds[NV * (kFinBlock / kWave)];
+  __shared__ double lds[NV * (BS / kWave)];
   // The status and the fields the scalar update reads are loaded before the
   // partials are summed, so their latency overlaps that of the sum's loads
   // instead of following it.  The sum runs whatever the status: the partials
@@ -410,7 +410,7 @@ __global__ __launch_bounds__(kFinBlock) void k_fin(SolveState* st, const double*
   const long long it0 = st->iter, maxit0 = st->maxit;
   double* const history = st->history;
   double tot[NV];
-  final_sum<NV>(partials, nb, tot, lds);
+  final_sum<NV, double, BS>(partials, nb, tot, lds);
   if (F == F_XR) {
     if (status == S_HALF || status == S_TAUBD) {
       if (threadIdx.x == 0) {
@@ -668,7 +668,11 @@ static hipError_t launch_spmv_dot(const hk_csr_s* A, const SpmvPlan& p, int dot,
 
 template <class R, int F>
 static hipError_t launch_fin(const Work<R>& wk, int nb, double tol, long long maxit, hipStream_t s) {
-  hipLaunchKernelGGL((k_fin<R, F>), dim3(1), dim3(kFinBlock), 0, s, wk.st, wk.partials, nb, tol, maxit);
+  if (nb <= kFinSmallNb)
+    hipLaunchKernelGGL((k_fin<R, F, kFinBlockSmall>), dim3(1), dim3(kFinBlockSmall), 0, s, wk.st, wk.partials, nb,
+                       tol, maxit);
+  else
+    hipLaunchKernelGGL((k_fin<R, F, kFinBlock>), dim3(1), dim3(kFinBlock), 0, s, wk.st, wk.partials, nb, tol, maxit);
   return hipGetLastError();
 }
 
@@ -1173,12 +1177,12 @@ template <> struct TqNV<TQ_H2> { static constexpr int v = 3; };
 
 // One workgroup: sums the partials of the preceding kernel and applies the
 // TFQMR scalar step F.
-template <int F>
-__global__ __launch_bounds__(kFinBlock) void k_tq_fin(SolveState* st, const double* partials, int nb, double tol,
+template <int F, int BS>
+__global__ __launch_bounds__(BS) void k_tq_fin(SolveState* st, const double* partials, int nb, double tol,
                                                       long long maxit) {
   using V = double2;
   constexpr int NV = TqNV<F>::v;
-  __shared__ double lds[NV * (kFinBlock / kWave)];
+  __shared__ double lds[NV * (BS / kWave)];
   // As in k_fin: the status and the fields the update reads are loaded before
   // the sum, which runs whatever the status.
   const int status = st->status;
@@ -1187,7 +1191,7 @@ __global__ __launch_bounds__(kFinBlock) void k_tq_fin(SolveState* st, const doub
   const double theta0 = st->tq_theta, tau0 = st->tq_tau, theta2 = st->theta2, bb = st->bb;
   double* const history = st->history;
   double tot[NV];
-  final_sum<NV>(partials, nb, tot, lds);
+  final_sum<NV, double, BS>(partials, nb, tot, lds);
   if (F == TQ_H1 && status != S_RUN) return;
   if (F == TQ_H2 && status != S_RUN) return;
   if (F == TQ_SIGMA0 && status != S_RUN) return;
@@ -1283,7 +1287,11 @@ __global__ __launch_bounds__(kFinBlock) void k_tq_fin(SolveState* st, const doub
 template <int F>
 static hipError_t launch_tq_fin(SolveState* st, const double* partials, int nb, double tol, long long maxit,
                                 hipStream_t s) {
-  hipLaunchKernelGGL((k_tq_fin<F>), dim3(1), dim3(kFinBlock), 0, s, st, partials, nb, tol, maxit);
+  if (nb <= kFinSmallNb)
+    hipLaunchKernelGGL((k_tq_fin<F, kFinBlockSmall>), dim3(1), dim3(kFinBlockSmall), 0, s, st, partials, nb, tol,
+                       maxit);
+  else
+    hipLaunchKernelGGL((k_tq_fin<F, kFinBlock>), dim3(1), dim3(kFinBlock), 0, s, st, partials, nb, tol, maxit);
   return hipGetLastError();
 }
 
@@ -1608,12 +1616,12 @@ __device__ __forceinline__ void bl_cycle_start(SolveState* st, double2 rho1) {
   }
 }
 
-template <int F, int ELL>
-__global__ __launch_bounds__(kFinBlock) void k_bl_fin(SolveState* st, const double* partials, int nb, double tol,
+template <int F, int ELL, int BS>
+__global__ __launch_bounds__(BS) void k_bl_fin(SolveState* st, const double* partials, int nb, double tol,
                                                       long long maxit) {
   using V = double2;
   constexpr int NV = BlFinNV<F, ELL>::v;
-  __shared__ double lds[NV * (kFinBlock / kWave)];
+  __shared__ double lds[NV * (BS / kWave)];
   // As in k_fin: the status and the fields the update reads are loaded before
   // the sum, which runs whatever the status.
   const int status = st->status;
@@ -1622,7 +1630,7 @@ __global__ __launch_bounds__(kFinBlock) void k_bl_fin(SolveState* st, const doub
   const double theta2 = st->theta2, bb = st->bb;
   double* const history = st->history;
   double tot[NV];
-  final_sum<NV>(partials, nb, tot, lds);
+  final_sum<NV, double, BS>(partials, nb, tot, lds);
   if (F != BL_INIT && status != S_RUN) return;
   if (threadIdx.x != 0) return;
   if (F == BL_INIT) {
@@ -1764,7 +1772,11 @@ __global__ __launch_bounds__(kFinBlock) void k_bl_fin_gram(SolveState* st, const
 template <int F, int ELL>
 static hipError_t launch_bl_fin(SolveState* st, const double* partials, int nb, double tol, long long maxit,
                                 hipStream_t s) {
-  hipLaunchKernelGGL((k_bl_fin<F, ELL>), dim3(1), dim3(kFinBlock), 0, s, st, partials, nb, tol, maxit);
+  if (nb <= kFinSmallNb)
+    hipLaunchKernelGGL((k_bl_fin<F, ELL, kFinBlockSmall>), dim3(1), dim3(kFinBlockSmall), 0, s, st, partials, nb,
+                       tol, maxit);
+  else
+    hipLaunchKernelGGL((k_bl_fin<F, ELL, kFinBlock>), dim3(1), dim3(kFinBlock), 0, s, st, partials, nb, tol, maxit);
   return hipGetLastError();
 }
 
