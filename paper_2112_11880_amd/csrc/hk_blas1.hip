@@ -63,13 +63,14 @@ __global__ __launch_bounds__(kBlock) void k_reduce(int64_t n, const double2* __r
   store_block_partials<NV>(v, partials);
 }
 
-// Second stage (one workgroup): the result, written to device memory.
-template <int KIND>
-__global__ __launch_bounds__(kFinBlock) void k_reduce_fin(const double* partials, int nb, double* out) {
+// Second stage (one workgroup of BS threads): the result, written to device
+// memory.
+template <int KIND, int BS>
+__global__ __launch_bounds__(BS) void k_reduce_fin(const double* partials, int nb, double* out) {
   constexpr int NV = KIND == 2 ? 1 : 2;
-  __shared__ double lds[NV * (kFinBlock / kWave)];
+  __shared__ double lds[NV * (BS / kWave)];
   double tot[NV];
-  final_sum<NV>(partials, nb, tot, lds);
+  final_sum<NV, double, BS>(partials, nb, tot, lds);
   if (threadIdx.x == 0) {
     if (KIND == 2) out[0] = sqrt(tot[0]);
     else { out[0] = tot[0]; out[NV - 1] = tot[NV - 1]; }
@@ -122,8 +123,12 @@ static int reduce(int64_t n, const void* x, const void* y, void* res, void* stre
   hipLaunchKernelGGL(k_reduce<KIND>, dim3(nb), dim3(kBlock), 0, s, n, (const double2*)x,
                      (const double2*)y, (double*)rs->partials);
   HK_CHECK_LAUNCH();
-  hipLaunchKernelGGL(k_reduce_fin<KIND>, dim3(1), dim3(kFinBlock), 0, s, (const double*)rs->partials, nb,
-                     (double*)res);
+  if (nb <= kFinSmallNb)
+    hipLaunchKernelGGL((k_reduce_fin<KIND, kFinBlockSmall>), dim3(1), dim3(kFinBlockSmall), 0, s,
+                       (const double*)rs->partials, nb, (double*)res);
+  else
+    hipLaunchKernelGGL((k_reduce_fin<KIND, kFinBlock>), dim3(1), dim3(kFinBlock), 0, s,
+                       (const double*)rs->partials, nb, (double*)res);
   HK_CHECK_LAUNCH();
   return HK_OK;
 }
