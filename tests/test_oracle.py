@@ -435,6 +435,22 @@ def test_mixed_refinement_cube16(oracle):
     assert np.linalg.norm(u - x) <= 1e-8 * np.linalg.norm(x)
 
 
+def test_mixed_refinement_last_cycle_stops_near_the_tolerance(oracle):
+    """A cycle's inner tolerance is max(inner_tol, outer_tol ||b|| / (2 ||r||)):
+    the last cycle stops once it has halved the remaining distance to the
+    outer tolerance, so the final residual lands within a small factor below
+    it instead of orders of magnitude below (a cycle run to inner_tol = 1e-4
+    from just above 1e-8 would end near 1e-12)."""
+    c1 = configs.cube16()
+    for outer in (1e-8, 1e-10):
+        u, info = oracle.mixed_refine(c1["rowptr"], c1["col"], c1["val"], c1["g"], inner_tol=1e-4,
+                                      outer_tol=outer)
+        assert info["status"] == 0, info
+        assert 0.02 * outer < info["relres_true"] <= outer, (outer, info)
+        r = oracle.residual(c1["rowptr"], c1["col"], c1["val"], c1["g"], u)
+        assert np.linalg.norm(r) / np.linalg.norm(c1["g"]) == pytest.approx(info["relres_true"], rel=1e-6)
+
+
 # ------------------------------------------------------------- adjoint
 
 def _block_problem(nc=4, bs=2, seed=1):
