@@ -15,10 +15,13 @@ CSR arrays as given (int32 column indices), over the step's timed launches
 (after three untimed ones).  The solves run on the library's
 default handle, whose row-block products stream 16-bit column offsets (18 B
 per nonzero); that product is timed beside it (`roofline.compact_cols`).
-After the timed steps (untimed for ms_per_step): the mixed-precision
-refinement on the same matrix (complex64 inner to 1e-4, complex128 outer to
-1e-10) and, unless --no-cpu, the CPU oracle's CSR product on the same matrix
-on the host cores (a bounded sample).
+After the timed steps (outside ms_per_step): the TFQMR and BiCGStab(8)
+solves of the same system, the mixed-precision refinement (complex64 inner
+to 1e-4, complex128 outer to 1e-10 and 1e-8, and an inner-tolerance sweep),
+BLAS-1 at the paper's vector sizes, and, unless --no-batched, the Q1-hex
+system, the 64-frequency sweep, the uneven batch and the adjoint; then,
+unless --no-cpu, the CPU oracle on the host cores (bounded samples of its
+CSR product and of its BiCGStab).
 """
 import argparse
 import hashlib
