@@ -321,6 +321,50 @@ def test_spmv_complex64(hk, oracle):
     assert np.all(np.abs(y - ref) <= bound)
 
 
+def c64_row_bound(rowptr, col, v32, x32, b32=None):
+    """Rounding bound of a complex64 CSR row (float32 products summed in
+    float32, any order): (len + 4) * 2u * (sum |a||x| (+ |b|)), u = 2^-24."""
+    lens = np.diff(rowptr).astype(np.float64)
+    s = spmv_bound(rowptr, col, v32.astype(np.complex128), x32.astype(np.complex128))
+    if b32 is not None:
+        s = s + np.abs(b32.astype(np.complex128))
+    return (lens + 5) * 2.0 ** -23 * s
+
+
+def test_spmv_complex64_all_shapes(hk, oracle):
+    """complex64 CSR product and residual in every launch shape, on both
+    column streams, for a mesh matrix and a random structure with rows of 0 to
+    700 entries: within the float32 rounding bound of each row of the oracle's
+    exact (FP64) product of the same float32 values; the row-block shapes
+    give the same bits from either stream."""
+    rng = np.random.default_rng(41)
+    cases = [("mesh", *small_mesh_problem((6, 7, 5), 11)),
+             ("random", *random_structure(np.random.default_rng(42), 2500, 700))]
+    for name, rowptr, col, val in cases:
+        n = rowptr.shape[0] - 1
+        v32 = val.astype(np.complex64)
+        x32 = crandn(rng, n).astype(np.complex64)
+        b32 = crandn(rng, n).astype(np.complex64)
+        ref = oracle.spmv(rowptr, col, v32.astype(np.complex128), x32.astype(np.complex128))
+        bound = c64_row_bound(rowptr, col, v32, x32)
+        rbound = c64_row_bound(rowptr, col, v32, x32, b32)
+        xd, bd = dev(x32), dev(b32)
+        outs = {}
+        for compact in (True, False):
+            A = hk.CSR(dev(rowptr), dev(col), dev(v32), compact_cols=compact)
+            for L, U, g in SHAPES:
+                say("spmv complex64", name, "n", n, "shape", L, U, g, "compact", compact)
+                A.set_plan(L, U, g)
+                y = host(A.spmv(xd, torch.full_like(xd, complex("nan+nanj")), beta=0.0))
+                assert np.all(np.abs(y - ref) <= bound), (name, L, U, g, compact)
+                outs[(L, U, g, compact)] = y
+                r = host(A.residual(bd, xd))
+                assert np.all(np.abs(r - (b32.astype(np.complex128) - ref)) <= rbound), (name, L, U, g)
+        for L, U, g in SHAPES:
+            if L == 64:
+                assert np.array_equal(outs[(L, U, g, True)], outs[(L, U, g, False)]), (name, U, g)
+
+
 def test_spmv_cube16_and_autotune(hk, oracle):
     c = configs.cube16()
     x = crandn(np.random.default_rng(5), int(c["n"]))
@@ -373,6 +417,40 @@ def test_dots_and_norm_parity(hk, oracle):
             assert abs(d - g(x, y)) <= 1e-12 * scale, (n, f.__name__)
         nr = host(hk.dznrm2(xd))[0]
         assert abs(nr - oracle.dznrm2(x)) <= 1e-12 * oracle.dznrm2(x)
+
+
+def test_dots_and_norm_parity_large(hk, oracle):
+    """Sizes that take the reductions' other paths: 2,097,153 elements (1,025
+    partials, the first size whose finalize runs 1,024 threads) and the
+    paper's 9M and 14M (the 4,096-workgroup cap, each workgroup walking a
+    longer chunk, with a ragged last chunk)."""
+    rng = np.random.default_rng(17)
+    for n in (2097153, 9000000, 14000000):
+        say("dots large n", n)
+        x, y = crandn(rng, n), crandn(rng, n)
+        xd, yd = dev(x), dev(y)
+        scale = np.sum(np.abs(x) * np.abs(y))
+        for f, g in ((hk.zdotc, oracle.zdotc), (hk.zdotu, oracle.zdotu)):
+            d = host(f(xd, yd))[0]
+            assert abs(d - g(x, y)) <= 1e-12 * scale, (n, f.__name__)
+        nr = host(hk.dznrm2(xd))[0]
+        assert abs(nr - oracle.dznrm2(x)) <= 1e-12 * oracle.dznrm2(x), n
+        del xd, yd
+        torch.cuda.empty_cache()
+
+
+def test_dot_deterministic_14m(hk):
+    """Bitwise the same result on every call at the paper's largest size
+    (4,096 workgroups, the 1,024-thread finalize)."""
+    say("dot determinism 14M")
+    rng = np.random.default_rng(18)
+    n = 14000000
+    x, y = dev(crandn(rng, n)), dev(crandn(rng, n))
+    ref_c, ref_u, ref_n = host(hk.zdotc(x, y)), host(hk.zdotu(x, y)), host(hk.dznrm2(x))
+    for _ in range(5):
+        assert np.array_equal(host(hk.zdotc(x, y)), ref_c)
+        assert np.array_equal(host(hk.zdotu(x, y)), ref_u)
+        assert np.array_equal(host(hk.dznrm2(x)), ref_n)
 
 
 def test_dot_deterministic(hk):
