@@ -356,6 +356,53 @@ def test_bicgstab_l_pins(oracle, nc, seed):
         assert np.linalg.norm(x - xs) <= 1e-9 * np.linalg.norm(xs)
 
 
+def _cyclic_shift_system(n, seed):
+    """Dense complex n x n: diagonal 2 e^{i phi}, cyclic super-diagonal
+    e^{i psi}, one small random entry per row (phases and values from
+    default_rng(seed)).  After Jacobi scaling the operator is I plus a shift
+    of modulus 1/2 (eigenvalues near a circle of radius 1/2 about 1), so the
+    power basis of an 8-step cycle stays well conditioned and BiCGStab(8)
+    converges in a few cycles."""
+    rng = np.random.default_rng(seed)
+    A = np.zeros((n, n), dtype=complex)
+    for i in range(n):
+        A[i, i] = 2.0 * np.exp(1j * rng.uniform(0, 2 * np.pi))
+        A[i, (i + 1) % n] = np.exp(1j * rng.uniform(0, 2 * np.pi))
+        j = int(rng.integers(n))
+        if j not in (i, (i + 1) % n):
+            A[i, j] = 0.005 * complex(rng.standard_normal(), rng.standard_normal())
+    rowptr = np.zeros(n + 1, dtype=np.int32)
+    cols, vals = [], []
+    for i in range(n):
+        nz = np.flatnonzero(A[i])
+        cols.extend(nz)
+        vals.extend(A[i, nz])
+        rowptr[i + 1] = len(cols)
+    return A, rowptr, np.array(cols, dtype=np.int32), np.array(vals)
+
+
+@pytest.mark.parametrize("n,seed", [(40, 1), (57, 2), (64, 3), (71, 4)])
+def test_bicgstab_l8_pin(oracle, n, seed):
+    """l = 8, the paper's P-BiCGSTAB(8): the oracle's iterates after one and
+    two cycles (16 and 32 products) are those of the Gram-Schmidt form of the
+    method to 1e-9.  The two forms of the minimal-residual step differ in
+    rounding by about the square of the condition number of the cycle's
+    Krylov basis times the unit roundoff; on these systems they agree to
+    4e-11, while a wrong term would move the iterate by the size of the
+    residual (3e-5 after one cycle, 5e-10 after two)."""
+    A, rowptr, col, val = _cyclic_shift_system(n, seed)
+    b = crandn(np.random.default_rng(seed + 10), n)
+    dinv = 1.0 / np.diag(A)
+    for k in (1, 2):
+        xo, io = oracle.bicgstab_l(rowptr, col, val, b, ell=8, tol=1e-15, maxit=k)
+        assert io["iters"] == k and io["status"] == oracle.NOT_CONVERGED, io
+        xm = _bicgstab_l_mgs(A, dinv, b, 8, k)
+        assert np.linalg.norm(xo - xm) <= 1e-9 * np.linalg.norm(xm), k
+    x, info = oracle.bicgstab_l(rowptr, col, val, b, ell=8, tol=1e-12)
+    assert info["status"] == 0 and info["iters"] <= 4, info
+    assert np.linalg.norm(x - np.linalg.solve(A, b)) <= 1e-10 * np.linalg.norm(x)
+
+
 def test_bicgstab_l_cube16_edges_and_errors(oracle):
     c1 = configs.cube16()
     x, info = oracle.bicgstab_l(c1["rowptr"], c1["col"], c1["val"], c1["g"], ell=8, tol=1e-8)
