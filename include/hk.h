@@ -175,8 +175,18 @@ typedef struct {
   double* d_history;     /* optional device buffer of max_iter+1 doubles: ||r_k||/||b||
                             (TFQMR: the quasi-residual bound sqrt(m+1) tau / ||b||) */
   int32_t ell;           /* HK_BICGSTAB_L: BiCG steps per cycle, 1, 2, 4 or 8 (the paper: 8) */
-  int32_t reserved;      /* must be 0 */
+  int32_t flags;         /* hk_solve_flags bits (0: none) */
+  int32_t shape[4];      /* batched solves: a launch shape to use instead of the tuned one
+                            (all 0: autotune; see hk_sweep_solve / hk_blockdiag_solve);
+                            other solves: must be all 0 */
 } hk_solve_opts;
+
+/* Bits of hk_solve_opts.flags. */
+enum hk_solve_flags {
+  /* hk_krylov_solve_mixed: solve every cycle to inner_tol, without the
+   * last cycle's clamp to half the reduction still needed */
+  HK_MIXED_LITERAL_INNER = 1
+};
 
 /* Krylov method of hk_krylov_solve (Section 4 implements all three). */
 typedef enum { HK_BICGSTAB = 0, HK_TFQMR = 1, HK_BICGSTAB_L = 2 } hk_method;
@@ -188,6 +198,9 @@ typedef struct {
   int32_t status;        /* HK_OK / HK_NOT_CONVERGED / HK_BREAKDOWN / HK_NONFINITE */
   int32_t breakdown;     /* hk_breakdown: which scalar vanished */
   int64_t inner_iters;   /* mixed precision: total inner iterations; else 0 */
+  int32_t shape[4];      /* launch shape of the solve's products (see each solve) */
+  int32_t shape_tuned;   /* 1 if that shape was chosen by timing on the device */
+  int32_t pad;
 } hk_solve_info;
 
 /*
@@ -211,6 +224,9 @@ typedef struct {
  * variable HK_SOLVE_GRAPHS=0 launches every kernel on `stream` instead (same
  * results, bit for bit).  A zero
  * diagonal entry with precond = 1, or an unknown method, gives HK_EINVAL.
+ * info->shape reports the fused products' launch shape {lanes per row (64:
+ * row blocks), rows per lane group or per wave, waves per workgroup, paired
+ * layout}, and info->shape_tuned whether the solver timed it.
  * Returns info->status (>= 0) or an error.  x always holds the last iterate.
  */
 int hk_krylov_solve(hk_csr A, const void* d_b, void* d_x, const hk_solve_opts* opts,
@@ -224,12 +240,15 @@ int hk_krylov_solve(hk_csr A, const void* d_b, void* d_x, const hk_solve_opts* o
  * dots and scalars in double) to a tolerance relative to ||r|| of
  * max(inner_tol, outer_tol ||b|| / (2 ||r||)): inner_tol, except in a cycle
  * that needs less than that to reach outer_tol, which stops at half the
- * reduction it needs.  At most
+ * reduction it needs (with HK_MIXED_LITERAL_INNER in opts->flags: inner_tol
+ * in every cycle).  At most
  * max_outer cycles; a cycle that does not lower ||r|| ends the loop
  * (HK_NOT_CONVERGED).  opts->max_iter caps each inner solve; opts->method
  * must be HK_BICGSTAB.  The complex64 copy of A is kept in the handle.
  * With the environment variable HK_TRACE set, each cycle's relative
- * residual and inner iteration count are printed to stderr.
+ * residual and inner iteration count are printed to stderr.  info->iters
+ * counts cycles, info->inner_iters the inner iterations; info->shape is
+ * the complex64 fused products' shape, as for hk_krylov_solve.
  */
 int hk_krylov_solve_mixed(hk_csr A, const void* d_b, void* d_x, double inner_tol,
                           double outer_tol, int32_t max_outer, const hk_solve_opts* opts,
@@ -256,6 +275,19 @@ int hk_krylov_solve_mixed(hk_csr A, const void* d_b, void* d_x, double inner_tol
  * (entry (i, j) at index i*64 + j; columns j >= nsys are ignored).  x starts
  * at 0.  opts->tol, max_iter apply to every system; infos receives nsys
  * records.  Synchronises `stream`.  Returns the largest per-system status.
+ * Launch shape {product form, row mapping, 0, 0}: product form 1 walks a
+ * wave's rows one at a time, 2 streams the entries of a wave's contiguous
+ * rows across row boundaries; row mapping 1 deals each XCD's eighth of the
+ * rows round-robin to its waves, 2 deals all rows round-robin to all waves,
+ * 3 gives each wave a contiguous range of its XCD's eighth (form 2 needs
+ * mapping 3).  The candidates are {1,1}, {1,2}, {1,3} and {2,3}.  With
+ * opts->shape all 0, the first call for a given (device, n, nnz, longest
+ * row, nsys) runs every candidate for 4 iterations, timed with HIP events,
+ * and keeps the fastest for this and later calls (the batch-plan analogue
+ * of the paper's per-matrix tuning of the GPU grid, Section 3); the trial
+ * launches write only the call's workspace and X.  A nonzero opts->shape
+ * must be a candidate (HK_EINVAL otherwise) and is used as is.  Every
+ * infos[j].shape holds the shape used, shape_tuned whether it was timed.
  */
 int hk_sweep_solve(int64_t n, int64_t nnz, const int32_t* d_rowptr, const int32_t* d_col,
                    const double* d_K, const double* d_M, int32_t nsys, const double* kappa,
@@ -269,7 +301,15 @@ int hk_sweep_solve(int64_t n, int64_t nnz, const int32_t* d_rowptr, const int32_
  * n).  Each system is solved with Jacobi BiCGStab from x = 0 to its own
  * relative tolerance; systems that finish drop out of the work list.
  * d_b, d_x: n complex128 (systems concatenated).  A column outside its
- * row's system gives HK_EINVAL.  Synchronises `stream`.
+ * row's system gives HK_EINVAL.  Synchronises `stream`.  Rows are dealt in
+ * tiles that never straddle systems.  Launch shape {lanes per row, rows
+ * per block, entries per lane per pass, tile rows}: {64, R, CH, TR} cuts a
+ * tile of TR rows (512 or 1024) into blocks of R rows (16, 32 or 64), each
+ * streamed by one wave with CH entries (2 or 4) per lane per pass;
+ * {32, 0, 0, TR} gives each row 32 lanes.  With opts->shape all 0 the
+ * shape is tuned and cached as for hk_sweep_solve (key: device, n, nnz,
+ * longest row, nsys) over all 14 candidates; a nonzero opts->shape must be
+ * one of them.  infos[k].shape holds the shape used.
  */
 int hk_blockdiag_solve(hk_csr A, int32_t nsys, const int64_t* row_off, const void* d_b, void* d_x,
                        const hk_solve_opts* opts, hk_solve_info* infos, void* stream);

@@ -20,6 +20,10 @@
 // counts live in device memory; at each grid barrier workgroup 0 finishes
 // the reductions (fixed order) and updates them.
 #include <algorithm>
+#include <array>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "hk_grid.hpp"
@@ -271,30 +275,179 @@ __device__ __forceinline__ void sweep_spmv(const SweepArgs& a, int r0, int r1, i
   }
 }
 
-// Rows r0, r0 + rs, ... < r1 of the calling wave.  XCD x (the workgroups b
-// with b % 8 == x) owns a contiguous eighth of the rows and its waves take
-// them round-robin, so each XCD advances through its eighth as one front and
-// the x[col] gathers of neighbouring rows meet in its L2.  On the 48^3 sweep
-// this measured 902 us per iteration against 948 us for one contiguous row
-// range per wave and 906 us for waves round-robin over all rows.
+// Rows of the calling wave: r0, r0 + rs, ... < r1.  Three mappings, chosen
+// per matrix by timing (hk_sweep_solve):
+//  MAP 1: XCD x (the workgroups b with b % 8 == x) owns a contiguous eighth
+//         of the rows and its waves take them round-robin, so each XCD
+//         advances through its eighth as one front and the x[col] gathers of
+//         neighbouring rows meet in its L2 (902 us per iteration on the 48^3
+//         sweep with the per-row product);
+//  MAP 2: every wave of the grid round-robin over all rows (906 us);
+//  MAP 3: each XCD's eighth split into one contiguous range per wave (the
+//         entry-stream product needs contiguous rows; 948 us per-row).
+template <int MAP>
 __device__ __forceinline__ void sweep_rows(int n, int G, int& r0, int& r1, int& rs) {
   const int w = threadIdx.x >> 6;
+  if (MAP == 2) {
+    r0 = blockIdx.x * kPW + w;
+    r1 = n;
+    rs = G * kPW;
+    return;
+  }
   const int x = blockIdx.x % kXcds, i = blockIdx.x / kXcds;
-  const int nbx = (G - x + kXcds - 1) / kXcds;  // workgroups on XCD x
+  const int nbx = (G - x + kXcds - 1) / kXcds;  // workgroups on XCD x (G >= kXcds)
   const int X0 = (int)(((long long)x * n) / kXcds), X1 = (int)(((long long)(x + 1) * n) / kXcds);
-  r0 = X0 + i * kPW + w;
-  r1 = X1;
-  rs = nbx * kPW;
+  if (MAP == 1) {
+    r0 = X0 + i * kPW + w;
+    r1 = X1;
+    rs = nbx * kPW;
+    return;
+  }
+  const int nw = nbx * kPW, wi = i * kPW + w;
+  r0 = X0 + (int)(((long long)(X1 - X0) * wi) / nw);
+  r1 = X0 + (int)(((long long)(X1 - X0) * (wi + 1)) / nw);
+  rs = 1;
 }
 
+// Value of `v` in lane l (wave-uniform), in every lane.
+__device__ __forceinline__ int bcast(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ __forceinline__ double bcast(double v, int l) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Entry-stream form of sweep_spmv for the wave's contiguous rows [ra, rb)
+// (MAP 3): the entries [rowptr[ra], rowptr[rb]) are one contiguous run,
+// loaded 64 at a time with one vector load each of col, K and M (lane u
+// holds entry c0 + u), the next 64 loaded while the current ones are used.
+// Entry p's column and coefficients reach every lane (= system) by
+// readlane.  The x gathers go out NG entries at a time regardless of row
+// boundaries, each round's gathers issued before the previous round's
+// multiply-adds, so 2 NG gathers of 1 KB are in flight; a row's sum is
+// finished when the walk passes its last entry.  The product is formed as
+// K x - kappa_j (M x), two real-coefficient sums per lane.  Every row must
+// have an entry (the sweep's nonzero-diagonal check guarantees it).  Lanes
+// of finished systems load from the addresses of a running system's lane
+// (same lines, no extra traffic) so every load runs with all lanes on --
+// the broadcasts read lanes that must all have loaded -- and they neither
+// store nor add to the sums.
+template <int EPI, int NV, int NG>
+__device__ __forceinline__ void sweep_spmv_stream(const SweepArgs& a, int ra, int rb, const double2* src,
+                                                  double2* dst, bool act, double2 kap, double (&part)[NV]) {
+  static_assert(64 % NG == 0, "rounds tile a chunk");
+  const int j = threadIdx.x & 63;
+  const unsigned long long live = __ballot(act);
+  if (live == 0 || ra >= rb) return;  // uniform
+  const int jl = act ? j : __ffsll((long long)live) - 1;
+  const cptr<int> rowptr = as_const(a.rowptr);
+  ra = uni(ra);
+  rb = uni(rb);
+  const int pa = rowptr[ra], pb = rowptr[rb];
+  // lane i holds the end of row rbase + i
+  int rbase = ra;
+  int rpv = a.rowptr[min(rbase + 1 + j, rb)];
+  int row = ra;
+  int rend = bcast(rpv, 0);
+  auto operand = [&](int r) -> double2 {
+    const size_t o = (size_t)r * kSys + jl;
+    return EPI == 1 ? a.RH[o] : EPI == 2 ? a.SH[o] : a.B[o];
+  };
+  double2 pre = operand(row);
+  double2 dg = EPI == 2 ? sweep_diag(a, row, kap) : make_double2(0, 0);
+  auto chunk = [&](int c0, int& cv, double& kv, double& mv) {
+    const int q = min(c0 + j, pb - 1);
+    cv = ldnt(a.col + q);
+    kv = __builtin_nontemporal_load(a.K + q);
+    mv = __builtin_nontemporal_load(a.M + q);
+  };
+  int cv0, cv1;
+  double kv0, kv1, mv0, mv1;
+  chunk(pa, cv0, kv0, mv0);
+  chunk(pa + 64, cv1, kv1, mv1);
+  double2 acK = make_double2(0, 0), acM = make_double2(0, 0);
+  double2 xv[NG], xn[NG];
+#pragma unroll
+  for (int g = 0; g < NG; ++g) xv[g] = src[(size_t)bcast(cv0, g) * kSys + jl];
+  const int nr = (pb - pa + NG - 1) / NG;
+  for (int r = 0; r < nr; ++r) {
+    const int u = (r * NG) & 63, un = ((r + 1) * NG) & 63;
+    const bool next_chunk = un == 0;
+    if (r + 1 < nr) {
+      const int cvs = next_chunk ? cv1 : cv0;
+#pragma unroll
+      for (int g = 0; g < NG; ++g) xn[g] = src[(size_t)bcast(cvs, un + g) * kSys + jl];
+    }
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+      const int p = pa + r * NG + g;
+      if (p < pb) {
+        const double k = bcast(kv0, u + g), m = bcast(mv0, u + g);
+        acK.x = fma(k, xv[g].x, acK.x);
+        acK.y = fma(k, xv[g].y, acK.y);
+        acM.x = fma(m, xv[g].x, acM.x);
+        acM.y = fma(m, xv[g].y, acM.y);
+        while (p + 1 == rend) {
+          const double2 y = csub(acK, cmul(kap, acM));
+          acK = make_double2(0, 0);
+          acM = make_double2(0, 0);
+          const size_t o = (size_t)row * kSys + j;
+          if (act) {
+            if constexpr (EPI == 3) {
+              part[0] += cabs2(csub(pre, y));
+            } else if constexpr (EPI == 1) {
+              dst[o] = y;
+              part[0] = fma(pre.x, y.x, fma(pre.y, y.y, part[0]));
+              part[1] = fma(pre.x, y.y, fma(-pre.y, y.x, part[1]));
+            } else {
+              dst[o] = y;
+              const double2 sv = cmul(dg, pre);
+              part[0] = fma(y.x, y.x, fma(y.y, y.y, part[0]));
+              part[1] = fma(y.x, sv.x, fma(y.y, sv.y, part[1]));
+              part[2] = fma(y.x, sv.y, fma(-y.y, sv.x, part[2]));
+            }
+          }
+          if (++row >= rb) break;
+          pre = operand(row);
+          if constexpr (EPI == 2) dg = sweep_diag(a, row, kap);
+          if (row - rbase == 64) {
+            rbase = row;
+            rpv = a.rowptr[min(rbase + 1 + j, rb)];
+          }
+          rend = bcast(rpv, row - rbase);
+        }
+      }
+    }
+    if (next_chunk) {
+      cv0 = cv1; kv0 = kv1; mv0 = mv1;
+      chunk(pa + (r + 1) * NG + 64, cv1, kv1, mv1);
+    }
+#pragma unroll
+    for (int g = 0; g < NG; ++g) xv[g] = xn[g];
+  }
+}
+
+// The product of a phase in the shape PF of the kernel: 1 the per-row form
+// (rows r0, r0 + rs, ...), 2 the entry stream over [r0, r1) (rs == 1).
+template <int PF, int EPI, int NV>
+__device__ __forceinline__ void sweep_product(const SweepArgs& a, int r0, int r1, int rs, const double2* src,
+                                              double2* dst, bool act, double2 kap, double (&part)[NV]) {
+  if constexpr (PF == 1) sweep_spmv<EPI, NV>(a, r0, r1, rs, src, dst, act, kap, part);
+  else sweep_spmv_stream<EPI, NV, 4>(a, r0, r1, src, dst, act, kap, part);
+}
+
+// PF: product form (1 per row, 2 entry stream); MAP: row mapping (sweep_rows).
+template <int PF, int MAP>
 __global__ __launch_bounds__(kPB) void k_sweep(SweepArgs a) {
+  static_assert(PF == 1 || MAP == 3, "the entry stream walks contiguous rows");
   __shared__ double lds[4 * kPW * kSys];
   unsigned epoch = 0;
   BatchState* st = a.st;
   const int j = threadIdx.x & 63;
   const int G = gridDim.x;
   int r0, r1, rs;
-  sweep_rows(a.n, G, r0, r1, rs);
+  sweep_rows<MAP>(a.n, G, r0, r1, rs);
   const bool lane_ok = j < a.nsys;
   const double2 kap = lane_ok ? a.kap[j] : make_double2(0, 0);
 
@@ -359,7 +512,7 @@ __global__ __launch_bounds__(kPB) void k_sweep(SweepArgs a) {
     // ---- v = A phat ; sigma = rhat^H v
     {
       double part[2] = {0, 0};
-      sweep_spmv<1, 2>(a, r0, r1, rs, a.PH, a.V, act, kap, part);
+      sweep_product<PF, 1, 2>(a, r0, r1, rs, a.PH, a.V, act, kap, part);
       store_partials64<2>(part, a.partials, lds);
       if (barrier_last(a.bar, epoch, [&] {
             double tot[2];
@@ -408,7 +561,7 @@ __global__ __launch_bounds__(kPB) void k_sweep(SweepArgs a) {
     // ---- t = A shat ; tau = t^H t ; t^H s
     {
       double part[3] = {0, 0, 0};
-      sweep_spmv<2, 3>(a, r0, r1, rs, a.SH, a.T, act, kap, part);
+      sweep_product<PF, 2, 3>(a, r0, r1, rs, a.SH, a.T, act, kap, part);
       store_partials64<3>(part, a.partials, lds);
       if (barrier_last(a.bar, epoch, [&] {
             double tot[3];
@@ -477,7 +630,7 @@ __global__ __launch_bounds__(kPB) void k_sweep(SweepArgs a) {
   // ---- true residual ||b - A x||^2 per system
   {
     double part[1] = {0};
-    sweep_spmv<3, 1>(a, r0, r1, rs, a.X, nullptr, lane_ok, kap, part);
+    sweep_product<PF, 3, 1>(a, r0, r1, rs, a.X, nullptr, lane_ok, kap, part);
     store_partials64<1>(part, a.partials, lds);
     barrier_last(a.bar, epoch, [&] {
       double tot[1];
@@ -503,7 +656,7 @@ struct BdArgs {
   const int* sys_end;    // system -> one past its last row
   const int* sys_tile0;  // system -> first static tile (nsys+1 entries)
   // active tile list: tile t (of ntiles_active) covers rows act_row0[t] ..
-  // min(act_row0[t] + kPB, act_end[t]) - 1 of system act_sys[t]
+  // act_end[t] - 1 (at most tile_rows rows) of system act_sys[t]
   int* act_sys;
   int* act_row0;
   int* act_end;
@@ -621,32 +774,35 @@ __device__ __forceinline__ void bd_tile_spmv(const BdArgs& a, const BdTile& tile
   }
 }
 
-// Row-block variant: wave w of the workgroup owns rows trow + 64 w ..
-// trow + 64 w + 63 of the tile (kPW waves x 64 rows = one tile) and streams
-// their entries with all its lanes (csr_block_rows); each row's sum goes to
-// callback g(row, acc) in the lane that owns the row.  `stage` is the
-// workgroup's staging area (kPW slices of kBdCh * 64 products).
-constexpr int kBdCh = 4;  // entries per lane per pass: 8 needs more than the 128 VGPRs of a 1024-thread workgroup
-template <class G2>
+// Row-block variant: the tile's rows are cut into blocks of R consecutive
+// rows (R in {16, 32, 64}); wave w of the workgroup takes blocks w, w + kPW,
+// ... and streams each block's entries with all its lanes, CH entries per
+// lane per pass (csr_block_rows); each row's sum goes to callback g(row,
+// acc) in the lane that owns the row.  `stage` is the workgroup's staging
+// area (kPW slices of CH * 64 products).
+template <int R, int CH, class G2>
 __device__ __forceinline__ void bd_tile_spmv_rb(const BdArgs& a, const BdTile& tile, const double2* src,
                                                 double2* stage, G2&& g) {
   const int end = tile.end;
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const int r0 = tile.row0 + w * 64;
-  if (r0 >= end) return;  // uniform across the wave
-  const double2 acc = csr_block_rows<64, kBdCh, double2, int>(r0, end, a.rowptr, a.col, a.val, src,
-                                                              stage + w * kBdCh * kWave);
-  if (r0 + l < end) g(r0 + l, acc);
+  for (int r0 = tile.row0 + w * R; r0 < end; r0 += kPW * R) {  // uniform across the wave
+    const double2 acc = csr_block_rows<R, CH, double2, int>(r0, end, a.rowptr, a.col, a.val, src,
+                                                            stage + w * CH * kWave);
+    if (l < R && r0 + l < end) g(r0 + l, acc);
+  }
 }
 
-// L in {4, 8, 16, 32}: lane-group tile products; L == kRowBlockL: row blocks.
-template <int L>
+// Tile products: L in {4, 8, 16, 32} lane groups (R, CH unused), or
+// L == kRowBlockL row blocks of R rows, CH entries per lane per pass (CH = 8
+// needs more than the 128 VGPRs a 1024-thread workgroup allows).  Tiles are
+// a.tile_rows <= kPB rows (chosen at run time with the tile shape).
+template <int L, int R, int CH>
 __global__ __launch_bounds__(kPB) void k_blockdiag(BdArgs a) {
   // [4 kPW] wave sums | [4 kSys] per-system sums | scratch shared by the
   // barrier callbacks (4 kPW kSys doubles) and the row-block staging area,
   // which are never live at the same time
   constexpr int kFin = 4 * kPW * kSys;
-  constexpr int kStage = L == kRowBlockL ? kPW * kBdCh * kWave * 2 : 0;
+  constexpr int kStage = L == kRowBlockL ? kPW * CH * kWave * 2 : 0;
   __shared__ __align__(16) double lds[4 * kPW + 4 * kSys + (kFin > kStage ? kFin : kStage)];
   unsigned epoch = 0;
   double* fin = lds + 4 * kPW + 4 * kSys;
@@ -654,7 +810,7 @@ __global__ __launch_bounds__(kPB) void k_blockdiag(BdArgs a) {
   __shared__ BdShared sh;
   BatchState* st = a.st;
   auto tile_spmv = [&](const BdTile& tile, const double2* src, auto&& g) {
-    if constexpr (L == kRowBlockL) bd_tile_spmv_rb(a, tile, src, stage, g);
+    if constexpr (L == kRowBlockL) bd_tile_spmv_rb<R, CH>(a, tile, src, stage, g);
     else bd_tile_spmv<L>(a, tile, src, g);
   };
   // the row of the calling thread in an element-wise phase (one per thread), or -1
@@ -681,11 +837,11 @@ __global__ __launch_bounds__(kPB) void k_blockdiag(BdArgs a) {
     for (int q = 0; q < a.nsys; ++q) {
       if (!all && st->status[q] != B_RUN) continue;
       const int base = s_off[q], cnt = a.sys_tile0[q + 1] - a.sys_tile0[q];
-      const int r0 = a.sys_begin[q], end = a.sys_end[q];
+      const int r0 = a.sys_begin[q], end = a.sys_end[q], tr = a.tile_rows;
       for (int k = threadIdx.x; k < cnt; k += kPB) {
         a.act_sys[base + k] = q;
-        a.act_row0[base + k] = r0 + k * kPB;
-        a.act_end[base + k] = end;
+        a.act_row0[base + k] = r0 + k * tr;
+        a.act_end[base + k] = min(r0 + (k + 1) * tr, end);
       }
     }
   };
@@ -899,6 +1055,8 @@ static int coop_grid(const void* kernel, int* grid) {
   HK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, kPB, 0));
   if (per < 1) HK_FAIL(HK_EHIP, "persistent kernel does not fit on a CU");
   *grid = std::min(cus * std::min(per, kCoopPerCu), kBarMaxBlocks);
+  // the sweep's row mappings deal rows per XCD: every XCD needs a workgroup
+  if (*grid < kXcds) HK_FAIL(HK_EHIP, "persistent grid of %d workgroups is below %d", *grid, kXcds);
   return HK_OK;
 }
 
@@ -922,6 +1080,103 @@ static int worst_status(const hk_solve_info* infos, int nsys) {
   return w;
 }
 
+// ---------------------------------------------------- batch-plan autotuner
+//
+// The counterpart of the paper's per-matrix tuning of the GPU grid
+// (Section 3, Table 8) for the persistent solvers: on the first solve of a
+// batch shape, each candidate launch shape runs the whole persistent kernel
+// for kTuneIters iterations (tolerance 0, so every system keeps iterating)
+// on the call's own data, timed with HIP events; the fastest is cached by
+// (device, n, nnz, longest row, number of systems) and used for the solve
+// and for later calls with the same key.  A shape given in opts->shape is
+// used as is.  The trial launches write only the call's workspace and x,
+// which the solve then starts over.
+constexpr int kTuneIters = 4;
+
+using PlanKey = std::tuple<int, int64_t, int64_t, int, int>;
+struct PlanCache {
+  std::mutex mu;
+  std::map<PlanKey, std::array<int, 4>> shapes;
+  bool get(const PlanKey& k, std::array<int, 4>* out) {
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = shapes.find(k);
+    if (it == shapes.end()) return false;
+    *out = it->second;
+    return true;
+  }
+  void put(const PlanKey& k, const std::array<int, 4>& v) {
+    std::lock_guard<std::mutex> lock(mu);
+    shapes[k] = v;
+  }
+};
+static PlanCache g_sweep_plans, g_bd_plans;
+
+static void set_shape(hk_solve_info* infos, int nsys, const std::array<int, 4>& sh, int tuned) {
+  for (int j = 0; j < nsys; ++j) {
+    for (int k = 0; k < 4; ++k) infos[j].shape[k] = sh[k];
+    infos[j].shape_tuned = tuned;
+    infos[j].pad = 0;
+  }
+}
+
+// A pair of HIP events around one persistent launch (the trial timings).
+struct EventPair {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  ~EventPair() {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  }
+  hipError_t create() {
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    return e;
+  }
+};
+
+// Sweep shapes: {product form, row mapping, 0, 0} (k_sweep<PF, MAP>).
+static const std::array<int, 4> kSweepShapes[] = {{1, 1, 0, 0}, {1, 2, 0, 0}, {1, 3, 0, 0}, {2, 3, 0, 0}};
+
+static const void* sweep_kernel(const std::array<int, 4>& sh) {
+  if (sh[2] != 0 || sh[3] != 0) return nullptr;
+  if (sh[0] == 1 && sh[1] == 1) return (const void*)k_sweep<1, 1>;
+  if (sh[0] == 1 && sh[1] == 2) return (const void*)k_sweep<1, 2>;
+  if (sh[0] == 1 && sh[1] == 3) return (const void*)k_sweep<1, 3>;
+  if (sh[0] == 2 && sh[1] == 3) return (const void*)k_sweep<2, 3>;
+  return nullptr;
+}
+
+// Block-diagonal shapes: {lanes per row (64: row blocks), rows per block,
+// entries per lane per pass, tile rows} (k_blockdiag<L, R, CH>).
+static std::vector<std::array<int, 4>> bd_shapes() {
+  std::vector<std::array<int, 4>> v;
+  for (int tr : {1024, 512}) {
+    for (int r : {64, 32, 16})
+      for (int ch : {4, 2}) v.push_back({kRowBlockL, r, ch, tr});
+    v.push_back({32, 0, 0, tr});
+  }
+  return v;
+}
+
+static const void* bd_kernel(const std::array<int, 4>& sh) {
+  if (sh[3] != 512 && sh[3] != 1024) return nullptr;
+  if (sh[0] == 32) return sh[1] == 0 && sh[2] == 0 ? (const void*)k_blockdiag<32, 0, 0> : nullptr;
+  if (sh[0] != kRowBlockL) return nullptr;
+  if (sh[2] == 4) {
+    if (sh[1] == 64) return (const void*)k_blockdiag<kRowBlockL, 64, 4>;
+    if (sh[1] == 32) return (const void*)k_blockdiag<kRowBlockL, 32, 4>;
+    if (sh[1] == 16) return (const void*)k_blockdiag<kRowBlockL, 16, 4>;
+  } else if (sh[2] == 2) {
+    if (sh[1] == 64) return (const void*)k_blockdiag<kRowBlockL, 64, 2>;
+    if (sh[1] == 32) return (const void*)k_blockdiag<kRowBlockL, 32, 2>;
+    if (sh[1] == 16) return (const void*)k_blockdiag<kRowBlockL, 16, 2>;
+  }
+  return nullptr;
+}
+
+static bool shape_given(const hk_solve_opts* o) {
+  return o->shape[0] || o->shape[1] || o->shape[2] || o->shape[3];
+}
+
 }  // namespace hk
 
 using namespace hk;
@@ -935,19 +1190,32 @@ extern "C" int hk_sweep_solve(int64_t n, int64_t nnz, const int32_t* d_rowptr, c
   if (nsys < 1 || nsys > kSys) HK_FAIL(HK_EINVAL, "hk_sweep_solve: nsys must be in [1, 64]");
   if (n < 1 || nnz < 1) HK_FAIL(HK_EINVAL, "hk_sweep_solve: empty matrix (n=%lld nnz=%lld)", (long long)n, (long long)nnz);
   if (!(opts->tol >= 0) || opts->max_iter < 0) HK_FAIL(HK_EINVAL, "hk_sweep_solve: bad options");
+  if (opts->flags) HK_FAIL(HK_EINVAL, "hk_sweep_solve: no flags apply");
+  std::array<int, 4> forced{opts->shape[0], opts->shape[1], opts->shape[2], opts->shape[3]};
+  if (shape_given(opts) && !sweep_kernel(forced))
+    HK_FAIL(HK_EINVAL, "hk_sweep_solve: unknown shape {%d, %d, %d, %d}", forced[0], forced[1], forced[2], forced[3]);
   hipStream_t s = as_stream(stream);
-  // structure check through a temporary handle (real values are not read)
+  // structure check through a temporary handle (real values are not read),
+  // which also finds the longest row (part of the plan key)
   hk_csr A = nullptr;
   int rc = hk_csr_create(&A, n, nnz, d_rowptr, d_col, d_K, HK_C128, HK_INT32_COLS, stream);
   if (rc != HK_OK) return rc;
+  const int max_row = A->max_row;
   (void)hk_csr_destroy(A);
-  int grid = 0;
-  rc = coop_grid((const void*)k_sweep, &grid);
-  if (rc != HK_OK) return rc;
+  int dev = 0;
+  HK_HIP(hipGetDevice(&dev));
+  // the largest grid of any candidate sizes the partials
+  int gmax = 0;
+  for (const auto& sh : kSweepShapes) {
+    int g = 0;
+    rc = coop_grid(sweep_kernel(sh), &g);
+    if (rc != HK_OK) return rc;
+    gmax = std::max(gmax, g);
+  }
   const size_t vec = (size_t)n * kSys;
   Arena ar;
   const size_t bytes = 6 * a256(16 * vec) + 2 * a256(8 * n) + a256(16 * kSys) +
-                       a256(8 * 4 * (size_t)grid * kSys) + a256(sizeof(BatchState)) + a256(sizeof(GridBar)) +
+                       a256(8 * 4 * (size_t)gmax * kSys) + a256(sizeof(BatchState)) + a256(sizeof(GridBar)) +
                        a256(64);
   if (hipMalloc((void**)&ar.base, bytes) != hipSuccess) HK_FAIL(HK_ENOMEM, "hk_sweep_solve: hipMalloc(%zu)", bytes);
   SweepArgs a{};
@@ -957,7 +1225,7 @@ extern "C" int hk_sweep_solve(int64_t n, int64_t nnz, const int32_t* d_rowptr, c
   double* kd = ar.take<double>(n);
   double* md = ar.take<double>(n);
   double2* kap = ar.take<double2>(kSys);
-  a.partials = ar.take<double>(4 * (size_t)grid * kSys);
+  a.partials = ar.take<double>(4 * (size_t)gmax * kSys);
   a.st = ar.take<BatchState>(1);
   a.bar = ar.take<GridBar>(1);
   int* flag = ar.take<int>(16);
@@ -967,16 +1235,11 @@ extern "C" int hk_sweep_solve(int64_t n, int64_t nnz, const int32_t* d_rowptr, c
   }
   a.kd = kd; a.md = md; a.kap = kap;
   a.B = (const double2*)d_B; a.X = (double2*)d_X;
-  a.tol = opts->tol; a.maxit = opts->max_iter;
   std::vector<double2> hk(kSys, make_double2(0, 0));
   for (int j = 0; j < nsys; ++j) hk[j] = make_double2(kappa[2 * j], kappa[2 * j + 1]);
   int hflag = 0;
   hipError_t e = hipMemcpyAsync(kap, hk.data(), 16 * kSys, hipMemcpyHostToDevice, s);
-  GridBar bar0{};
-  bar0.spin_limit = barrier_spin_limit();
-  if (e == hipSuccess) e = hipMemcpyAsync(a.bar, &bar0, sizeof(GridBar), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemsetAsync(flag, 0, 64, s);
-  if (e == hipSuccess) e = hipMemsetAsync(a.st, 0, sizeof(BatchState), s);
   const dim3 ew((unsigned)((n + kBlock - 1) / kBlock));
   if (e == hipSuccess) {
     hipLaunchKernelGGL(k_real_diag, ew, dim3(kBlock), 0, s, (int)n, d_rowptr, d_col, d_K, d_M, kd, md);
@@ -988,14 +1251,75 @@ extern "C" int hk_sweep_solve(int64_t n, int64_t nnz, const int32_t* d_rowptr, c
   }
   if (e == hipSuccess) e = hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (e == hipSuccess && hflag) {
+  if (e != hipSuccess) {
+    (void)hipFree(ar.base);
+    HK_FAIL(HK_EHIP, "hk_sweep_solve: %s", hipGetErrorString(e));
+  }
+  if (hflag) {
     (void)hipFree(ar.base);
     HK_FAIL(HK_EINVAL, "hk_sweep_solve: zero diagonal entry for some system (Jacobi undefined)");
   }
-  if (e == hipSuccess) {
+  const unsigned long long spin = barrier_spin_limit();
+  // one persistent launch of shape sh: fresh state and barrier, then the kernel
+  // (with events: recorded around the kernel alone)
+  auto launch = [&](const std::array<int, 4>& sh, double tol, long long maxit, EventPair* ev) -> hipError_t {
+    const void* kern = sweep_kernel(sh);
+    int grid = 0;
+    if (coop_grid(kern, &grid) != HK_OK) return hipErrorInvalidConfiguration;
+    a.tol = tol;
+    a.maxit = maxit;
+    GridBar bar0{};
+    bar0.spin_limit = spin;
+    hipError_t e2 = hipMemcpyAsync(a.bar, &bar0, sizeof(GridBar), hipMemcpyHostToDevice, s);
+    if (e2 == hipSuccess) e2 = hipMemsetAsync(a.st, 0, sizeof(BatchState), s);
+    if (e2 == hipSuccess && ev) e2 = hipEventRecord(ev->e0, s);
     void* args[] = {&a};
-    e = hipLaunchCooperativeKernel((const void*)k_sweep, dim3(grid), dim3(kPB), args, 0, s);
+    if (e2 == hipSuccess) e2 = hipLaunchCooperativeKernel(kern, dim3(grid), dim3(kPB), args, 0, s);
+    if (e2 == hipSuccess && ev) e2 = hipEventRecord(ev->e1, s);
+    // bar0 lives on this frame: the copy must be done before it goes
+    if (e2 == hipSuccess) e2 = hipStreamSynchronize(s);
+    return e2;
+  };
+  auto aborted = [&](bool* ab) -> hipError_t {
+    GridBar hb{};
+    hipError_t e2 = hipMemcpyAsync(&hb, a.bar, sizeof(hb), hipMemcpyDeviceToHost, s);
+    if (e2 == hipSuccess) e2 = hipStreamSynchronize(s);
+    *ab = hb.abort != 0;
+    return e2;
+  };
+  std::array<int, 4> shape = forced;
+  int tuned = 0;
+  const PlanKey key{dev, n, nnz, max_row, nsys};
+  if (!shape_given(opts)) {
+    tuned = 1;
+    if (!g_sweep_plans.get(key, &shape)) {
+      float best = -1;
+      EventPair ev;
+      e = ev.create();
+      for (const auto& sh : kSweepShapes) {
+        float ms = -1;
+        for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
+          float t = 0;
+          e = launch(sh, 0.0, kTuneIters, &ev);
+          if (e == hipSuccess) e = hipEventElapsedTime(&t, ev.e0, ev.e1);
+          ms = rep == 0 ? t : std::min(ms, t);
+        }
+        bool ab = false;
+        if (e == hipSuccess) e = aborted(&ab);
+        if (e != hipSuccess || ab) {
+          (void)hipFree(ar.base);
+          if (ab) HK_FAIL(HK_EHIP, "hk_sweep_solve: grid barrier timed out");
+          HK_FAIL(HK_EHIP, "hk_sweep_solve: trial launch: %s", hipGetErrorString(e));
+        }
+        if (best < 0 || ms < best) {
+          best = ms;
+          shape = sh;
+        }
+      }
+      g_sweep_plans.put(key, shape);
+    }
   }
+  e = launch(shape, opts->tol, opts->max_iter, nullptr);
   BatchState hs{};
   GridBar hb{};
   if (e == hipSuccess) e = hipMemcpyAsync(&hs, a.st, sizeof(hs), hipMemcpyDeviceToHost, s);
@@ -1005,6 +1329,7 @@ extern "C" int hk_sweep_solve(int64_t n, int64_t nnz, const int32_t* d_rowptr, c
   if (e != hipSuccess) HK_FAIL(HK_EHIP, "hk_sweep_solve: %s", hipGetErrorString(e));
   if (hb.abort) HK_FAIL(HK_EHIP, "hk_sweep_solve: grid barrier timed out");
   fill_infos(hs, nsys, infos);
+  set_shape(infos, nsys, shape, tuned);
   return worst_status(infos, nsys);
 }
 
@@ -1015,59 +1340,57 @@ extern "C" int hk_blockdiag_solve(hk_csr A, int32_t nsys, const int64_t* row_off
   if (A->dtype != HK_C128) HK_FAIL(HK_EINVAL, "hk_blockdiag_solve: matrix must be complex128");
   if (nsys < 1 || nsys > kSys) HK_FAIL(HK_EINVAL, "hk_blockdiag_solve: nsys must be in [1, 64]");
   if (!(opts->tol >= 0) || opts->max_iter < 0) HK_FAIL(HK_EINVAL, "hk_blockdiag_solve: bad options");
+  if (opts->flags) HK_FAIL(HK_EINVAL, "hk_blockdiag_solve: no flags apply");
   if (row_off[0] != 0 || row_off[nsys] != A->n) HK_FAIL(HK_EINVAL, "hk_blockdiag_solve: row offsets must span [0, n]");
   for (int k = 0; k < nsys; ++k)
     if (row_off[k + 1] <= row_off[k]) HK_FAIL(HK_EINVAL, "hk_blockdiag_solve: empty or decreasing system %d", k);
+  std::array<int, 4> forced{opts->shape[0], opts->shape[1], opts->shape[2], opts->shape[3]};
+  if (shape_given(opts) && !bd_kernel(forced))
+    HK_FAIL(HK_EINVAL, "hk_blockdiag_solve: unknown shape {%d, %d, %d, %d}", forced[0], forced[1], forced[2], forced[3]);
   hipStream_t s = as_stream(stream);
-  // tile products: row blocks (one wave per 64 rows) unless the rows are
-  // long (mean above 32 entries), then 32-lane groups per row
-  const double mean_row = (double)A->nnz / (double)A->n;
-  const int L = mean_row > 32 ? 32 : kRowBlockL;
-  const int TR = kPB;
-  // static tiles
-  std::vector<int> tsys, trow, sys_end(kSys, 0), sys_begin(kSys, 0), tile0(kSys + 1, 0);
+  const std::vector<std::array<int, 4>> cands = bd_shapes();
+  int dev = 0;
+  HK_HIP(hipGetDevice(&dev));
+  int gmax = 0;
+  for (const auto& sh : cands) {
+    int g = 0;
+    int rc = coop_grid(bd_kernel(sh), &g);
+    if (rc != HK_OK) return rc;
+    gmax = std::max(gmax, g);
+  }
+  std::vector<int> sys_end(kSys, 0), sys_begin(kSys, 0);
   std::vector<int> sys_of_row((size_t)A->n);
   for (int k = 0; k < nsys; ++k) {
-    tile0[k] = (int)tsys.size();
     sys_begin[k] = (int)row_off[k];
     sys_end[k] = (int)row_off[k + 1];
-    for (int64_t r = row_off[k]; r < row_off[k + 1]; r += TR) {
-      tsys.push_back(k);
-      trow.push_back((int)r);
-    }
     for (int64_t r = row_off[k]; r < row_off[k + 1]; ++r) sys_of_row[r] = k;
   }
-  tile0[nsys] = (int)tsys.size();
-  for (int k = nsys + 1; k <= kSys; ++k) tile0[k] = tile0[nsys];
-  const int nt = (int)tsys.size();
-  const void* kern = nullptr;
-  if (L == kRowBlockL) kern = (const void*)k_blockdiag<kRowBlockL>;
-  else kern = (const void*)k_blockdiag<32>;
-  int grid = 0;
-  int rc = coop_grid(kern, &grid);
-  if (rc != HK_OK) return rc;
+  // static tiles of tile_rows rows that never straddle systems; the arrays
+  // are sized for the smallest tiles
+  int nt_max = 0;
+  for (int k = 0; k < nsys; ++k) nt_max += (int)((row_off[k + 1] - row_off[k] + 511) / 512);
   const int64_t n = A->n;
   Arena ar;
-  const size_t bytes = 8 * a256(16 * (size_t)n) + 3 * a256(4 * (size_t)nt) +
-                       a256(4 * (size_t)n) + 4 * a256(4 * (kSys + 1)) + a256(8 * 4 * (size_t)grid * kSys) +
+  const size_t bytes = 8 * a256(16 * (size_t)n) + 3 * a256(4 * (size_t)nt_max) +
+                       a256(4 * (size_t)n) + 4 * a256(4 * (kSys + 1)) + a256(8 * 4 * (size_t)gmax * kSys) +
                        a256(sizeof(BatchState)) + a256(sizeof(GridBar)) + a256(64);
   if (hipMalloc((void**)&ar.base, bytes) != hipSuccess) HK_FAIL(HK_ENOMEM, "hk_blockdiag_solve: hipMalloc(%zu)", bytes);
   BdArgs a{};
-  a.n = (int)n; a.nsys = nsys; a.L = L; a.rowptr = A->rowptr; a.col = A->col;
+  a.n = (int)n; a.nsys = nsys; a.rowptr = A->rowptr; a.col = A->col;
   a.val = (const double2*)A->val;
   a.R = ar.take<double2>(n); a.RH = ar.take<double2>(n); a.PH = ar.take<double2>(n);
   a.V = ar.take<double2>(n); a.SH = ar.take<double2>(n); a.T = ar.take<double2>(n);
   double2* d = ar.take<double2>(n);
   double2* dinv = ar.take<double2>(n);
-  a.act_sys = ar.take<int>(nt);
-  a.act_row0 = ar.take<int>(nt);
-  a.act_end = ar.take<int>(nt);
+  a.act_sys = ar.take<int>(nt_max);
+  a.act_row0 = ar.take<int>(nt_max);
+  a.act_end = ar.take<int>(nt_max);
   int* d_sor = ar.take<int>(n);
   int* d_send = ar.take<int>(kSys + 1);
   int* d_sbeg = ar.take<int>(kSys + 1);
   int* d_t0 = ar.take<int>(kSys + 1);
   (void)ar.take<int>(kSys + 1);
-  a.partials = ar.take<double>(4 * (size_t)grid * kSys);
+  a.partials = ar.take<double>(4 * (size_t)gmax * kSys);
   a.st = ar.take<BatchState>(1);
   a.bar = ar.take<GridBar>(1);
   int* flag = ar.take<int>(16);
@@ -1076,44 +1399,109 @@ extern "C" int hk_blockdiag_solve(hk_csr A, int32_t nsys, const int64_t* row_off
     HK_FAIL(HK_EINVAL, "hk_blockdiag_solve: workspace layout exceeds its allocation");
   }
   a.d = d; a.dinv = dinv; a.sys_begin = d_sbeg; a.sys_end = d_send; a.sys_tile0 = d_t0;
-  a.B = (const double2*)d_b; a.X = (double2*)d_x; a.tol = opts->tol; a.maxit = opts->max_iter;
-  a.tile_rows = TR;
+  a.B = (const double2*)d_b; a.X = (double2*)d_x;
   int hflag = 0;
-  // the start phase walks every tile
-  std::vector<int> tend(nt);
-  for (int k = 0; k < nt; ++k) tend[k] = sys_end[tsys[k]];
-  hipError_t e = hipMemcpyAsync(a.act_sys, tsys.data(), 4 * (size_t)nt, hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(a.act_row0, trow.data(), 4 * (size_t)nt, hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(a.act_end, tend.data(), 4 * (size_t)nt, hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(d_sor, sys_of_row.data(), 4 * (size_t)n, hipMemcpyHostToDevice, s);
+  hipError_t e = hipMemcpyAsync(d_sor, sys_of_row.data(), 4 * (size_t)n, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(d_send, sys_end.data(), 4 * kSys, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(d_sbeg, sys_begin.data(), 4 * kSys, hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(d_t0, tile0.data(), 4 * (kSys + 1), hipMemcpyHostToDevice, s);
-  GridBar bar0{};
-  bar0.spin_limit = barrier_spin_limit();
-  if (e == hipSuccess) e = hipMemcpyAsync(a.bar, &bar0, sizeof(GridBar), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemsetAsync(flag, 0, 64, s);
-  if (e == hipSuccess) e = hipMemsetAsync(a.st, 0, sizeof(BatchState), s);
-  BatchState init{};
-  init.ntiles_active = nt;
-  if (e == hipSuccess) e = hipMemcpyAsync(a.st, &init, sizeof(init), hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);  // host vectors above go out of scope
   if (e == hipSuccess) {
     hipLaunchKernelGGL(k_bd_diag, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, (int)n,
                        A->rowptr, A->col, (const double2*)A->val, d_sor, d_sbeg, d_send, d, dinv, flag);
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (e == hipSuccess && hflag) {
+  if (e == hipSuccess) e = hipStreamSynchronize(s);  // the host vectors above go out of scope
+  if (e != hipSuccess) {
+    (void)hipFree(ar.base);
+    HK_FAIL(HK_EHIP, "hk_blockdiag_solve: %s", hipGetErrorString(e));
+  }
+  if (hflag) {
     (void)hipFree(ar.base);
     if (hflag & 2) HK_FAIL(HK_EINVAL, "hk_blockdiag_solve: matrix is not block-diagonal for the given offsets");
     HK_FAIL(HK_EINVAL, "hk_blockdiag_solve: zero diagonal entry (Jacobi undefined)");
   }
-  if (e == hipSuccess) {
+  const unsigned long long spin = barrier_spin_limit();
+  // one persistent launch of shape sh: its static tile table (the start
+  // phase walks every tile), fresh state and barrier, then the kernel
+  auto launch = [&](const std::array<int, 4>& sh, double tol, long long maxit, EventPair* ev) -> hipError_t {
+    const void* kern = bd_kernel(sh);
+    int grid = 0;
+    if (coop_grid(kern, &grid) != HK_OK) return hipErrorInvalidConfiguration;
+    const int tr = sh[3];
+    std::vector<int> tsys, trow, tend, tile0(kSys + 1, 0);
+    for (int k = 0; k < nsys; ++k) {
+      tile0[k] = (int)tsys.size();
+      for (int64_t r = row_off[k]; r < row_off[k + 1]; r += tr) {
+        tsys.push_back(k);
+        trow.push_back((int)r);
+        tend.push_back((int)std::min<int64_t>(r + tr, row_off[k + 1]));
+      }
+    }
+    const int nt = (int)tsys.size();
+    for (int k = nsys; k <= kSys; ++k) tile0[k] = nt;
+    a.L = sh[0];
+    a.tile_rows = tr;
+    a.tol = tol;
+    a.maxit = maxit;
+    BatchState init{};
+    init.ntiles_active = nt;
+    GridBar bar0{};
+    bar0.spin_limit = spin;
+    hipError_t e2 = hipMemcpyAsync(a.act_sys, tsys.data(), 4 * (size_t)nt, hipMemcpyHostToDevice, s);
+    if (e2 == hipSuccess) e2 = hipMemcpyAsync(a.act_row0, trow.data(), 4 * (size_t)nt, hipMemcpyHostToDevice, s);
+    if (e2 == hipSuccess) e2 = hipMemcpyAsync(a.act_end, tend.data(), 4 * (size_t)nt, hipMemcpyHostToDevice, s);
+    if (e2 == hipSuccess) e2 = hipMemcpyAsync(d_t0, tile0.data(), 4 * (kSys + 1), hipMemcpyHostToDevice, s);
+    if (e2 == hipSuccess) e2 = hipMemcpyAsync(a.bar, &bar0, sizeof(GridBar), hipMemcpyHostToDevice, s);
+    if (e2 == hipSuccess) e2 = hipMemcpyAsync(a.st, &init, sizeof(init), hipMemcpyHostToDevice, s);
+    if (e2 == hipSuccess && ev) e2 = hipEventRecord(ev->e0, s);
     void* args[] = {&a};
-    e = hipLaunchCooperativeKernel(kern, dim3(grid), dim3(kPB), args, 0, s);
+    if (e2 == hipSuccess) e2 = hipLaunchCooperativeKernel(kern, dim3(grid), dim3(kPB), args, 0, s);
+    if (e2 == hipSuccess && ev) e2 = hipEventRecord(ev->e1, s);
+    // the host tables live on this frame: the copies must be done before they go
+    if (e2 == hipSuccess) e2 = hipStreamSynchronize(s);
+    return e2;
+  };
+  auto aborted = [&](bool* ab) -> hipError_t {
+    GridBar hb{};
+    hipError_t e2 = hipMemcpyAsync(&hb, a.bar, sizeof(hb), hipMemcpyDeviceToHost, s);
+    if (e2 == hipSuccess) e2 = hipStreamSynchronize(s);
+    *ab = hb.abort != 0;
+    return e2;
+  };
+  std::array<int, 4> shape = forced;
+  int tuned = 0;
+  const PlanKey key{dev, n, A->nnz, A->max_row, nsys};
+  if (!shape_given(opts)) {
+    tuned = 1;
+    if (!g_bd_plans.get(key, &shape)) {
+      float best = -1;
+      EventPair ev;
+      e = ev.create();
+      for (const auto& sh : cands) {
+        float ms = -1;
+        for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
+          float t = 0;
+          e = launch(sh, 0.0, kTuneIters, &ev);
+          if (e == hipSuccess) e = hipEventElapsedTime(&t, ev.e0, ev.e1);
+          ms = rep == 0 ? t : std::min(ms, t);
+        }
+        bool ab = false;
+        if (e == hipSuccess) e = aborted(&ab);
+        if (e != hipSuccess || ab) {
+          (void)hipFree(ar.base);
+          if (ab) HK_FAIL(HK_EHIP, "hk_blockdiag_solve: grid barrier timed out");
+          HK_FAIL(HK_EHIP, "hk_blockdiag_solve: trial launch: %s", hipGetErrorString(e));
+        }
+        if (best < 0 || ms < best) {
+          best = ms;
+          shape = sh;
+        }
+      }
+      g_bd_plans.put(key, shape);
+    }
   }
+  e = launch(shape, opts->tol, opts->max_iter, nullptr);
   BatchState hs{};
   GridBar hb{};
   if (e == hipSuccess) e = hipMemcpyAsync(&hs, a.st, sizeof(hs), hipMemcpyDeviceToHost, s);
@@ -1123,5 +1511,6 @@ extern "C" int hk_blockdiag_solve(hk_csr A, int32_t nsys, const int64_t* row_off
   if (e != hipSuccess) HK_FAIL(HK_EHIP, "hk_blockdiag_solve: %s", hipGetErrorString(e));
   if (hb.abort) HK_FAIL(HK_EHIP, "hk_blockdiag_solve: grid barrier timed out");
   fill_infos(hs, nsys, infos);
+  set_shape(infos, nsys, shape, tuned);
   return worst_status(infos, nsys);
 }

@@ -1902,8 +1902,25 @@ static int ensure_pinned(hk_csr_s* A) {
   return HK_OK;
 }
 
+// info->shape of the plain and mixed solves: the fused products' shape
+// {lanes per row (64: row blocks), rows per group or wave, waves per
+// workgroup, paired layout} of precision slot prec (0 complex128, 1
+// complex64), or the handle's CSR shape when none was fixed or tuned.
+static void report_shape(const hk_csr_s* A, int prec, hk_solve_info* info) {
+  const SpmvPlan& d = A->dot_plan[prec].tuned ? A->dot_plan[prec] : A->plan;
+  info->shape[0] = d.L;
+  info->shape[1] = d.U;
+  info->shape[2] = d.nw;
+  info->shape[3] = d.pairs;
+  info->shape_tuned = d.tuned == 1 ? 1 : 0;
+  info->pad = 0;
+}
+
 static int check_opts(const hk_solve_opts* o, const char* who) {
   if (!o) HK_FAIL(HK_EINVAL, "%s: opts is NULL", who);
+  if (o->shape[0] || o->shape[1] || o->shape[2] || o->shape[3])
+    HK_FAIL(HK_EINVAL, "%s: opts->shape applies to the batched solves only", who);
+  if (o->flags & ~HK_MIXED_LITERAL_INNER) HK_FAIL(HK_EINVAL, "%s: unknown flags 0x%x", who, (unsigned)o->flags);
   if (!(o->tol >= 0) || o->max_iter < 0 || o->check_every < 0)
     HK_FAIL(HK_EINVAL, "%s: bad options (tol=%g max_iter=%lld)", who, o->tol, (long long)o->max_iter);
   if (o->method != HK_BICGSTAB && o->method != HK_TFQMR && o->method != HK_BICGSTAB_L)
@@ -1946,6 +1963,7 @@ extern "C" int hk_krylov_solve(hk_csr A, const void* d_b, void* d_x, const hk_so
                             info, s);
   }
   if (rc != HK_OK) return rc;
+  report_shape(A, A->dtype == HK_C64 ? 1 : 0, info);
   return info->status;
 }
 
@@ -2009,6 +2027,8 @@ extern "C" int hk_krylov_solve_mixed(hk_csr A, const void* d_b, void* d_x, doubl
     A32.plan = A->plan32;
   }
   const bool trace = getenv("HK_TRACE") != nullptr;
+  const bool literal = (opts->flags & HK_MIXED_LITERAL_INNER) != 0;
+  io.flags = 0;
   for (k = 0; k <= max_outer; ++k) {
     rc = spmv_dispatch(A, d_x, r, d_b, nullptr, nullptr, 1, s);   // r = b - A u (complex128)
     if (rc != HK_OK) return rc;
@@ -2028,8 +2048,9 @@ extern "C" int hk_krylov_solve_mixed(hk_csr A, const void* d_b, void* d_x, doubl
     hipLaunchKernelGGL(k_round_c64, ew, dim3(kBlock), 0, s, n, (const double2*)r, r32, scale);
     HK_CHECK_LAUNCH();
     // inner tolerance: inner_tol, or, where a smaller reduction reaches
-    // outer_tol, half of that reduction (the last cycle stops early)
-    io.tol = std::max(inner_tol, 0.5 * outer_tol / rel);
+    // outer_tol, half of that reduction (the last cycle stops early);
+    // HK_MIXED_LITERAL_INNER keeps inner_tol in every cycle
+    io.tol = literal ? inner_tol : std::max(inner_tol, 0.5 * outer_tol / rel);
     hk_solve_info ii{};
     rc = bicgstab<float>(&A32, (const float2*)A->val32, r32, d32, io, A->ws32, &ii, s);
     A->dot_plan[1] = A32.dot_plan[1];  // the inner solve's tuned fused shape
@@ -2049,5 +2070,6 @@ extern "C" int hk_krylov_solve_mixed(hk_csr A, const void* d_b, void* d_x, doubl
   info->relres_rec = rel;
   info->relres_true = rel;
   info->inner_iters = inner_total;
+  report_shape(A, 1, info);
   return status;
 }

@@ -32,15 +32,23 @@ class HKError(RuntimeError):
 class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int64), ("precond", C.c_int32),
                 ("check_every", C.c_int32), ("use_x0", C.c_int32), ("method", C.c_int32),
-                ("d_history", C.c_void_p), ("ell", C.c_int32), ("reserved", C.c_int32)]
+                ("d_history", C.c_void_p), ("ell", C.c_int32), ("flags", C.c_int32),
+                ("shape", C.c_int32 * 4)]
+
+
+HK_MIXED_LITERAL_INNER = 1
 
 
 class SolveInfo(C.Structure):
     _fields_ = [("iters", C.c_int64), ("relres_rec", C.c_double), ("relres_true", C.c_double),
-                ("status", C.c_int32), ("breakdown", C.c_int32), ("inner_iters", C.c_int64)]
+                ("status", C.c_int32), ("breakdown", C.c_int32), ("inner_iters", C.c_int64),
+                ("shape", C.c_int32 * 4), ("shape_tuned", C.c_int32), ("pad", C.c_int32)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+        d["shape"] = list(self.shape)
+        d["shape_tuned"] = bool(self.shape_tuned)
+        return d
 
 
 # Exported entry points and their ctypes signatures (restype int unless noted).
@@ -258,10 +266,17 @@ def zconj(x, y=None):
 METHODS = {"bicgstab": 0, "tfqmr": 1, "bicgstab_l": 2}
 
 
-def _opts(tol, max_iter, precond, check_every, use_x0, history, method="bicgstab", ell=8):
+def _opts(tol, max_iter, precond, check_every, use_x0, history, method="bicgstab", ell=8, flags=0,
+          shape=None):
     if method not in METHODS:
         raise HKError(HK_EINVAL, f"unknown method {method!r}; one of {sorted(METHODS)}")
     o = SolveOpts()
+    o.flags = int(flags)
+    if shape is not None:
+        if len(shape) != 4:
+            raise HKError(HK_EINVAL, "shape has 4 entries")
+        for k, v in enumerate(shape):
+            o.shape[k] = int(v)
     o.method = METHODS[method]
     o.ell = int(ell)
     o.tol = float(tol)
@@ -293,13 +308,15 @@ def krylov_solve(A: CSR, b, x=None, tol=1e-8, max_iter=400000, precond=True, che
 
 
 def krylov_solve_mixed(A: CSR, b, x=None, inner_tol=1e-4, outer_tol=1e-10, max_outer=50,
-                       max_inner=400000, check_every=0):
-    """complex64-inner / complex128-outer refinement; returns (x, info dict)."""
+                       max_inner=400000, check_every=0, literal_inner=False):
+    """complex64-inner / complex128-outer refinement; returns (x, info dict).
+    literal_inner: every cycle to inner_tol (no clamp of the last cycle)."""
     _cvec(b, name="b", n=A.n)
     use_x0 = x is not None
     x = torch.zeros_like(b) if x is None else _cvec(x, name="x", n=A.n)
     info = SolveInfo()
-    o = _opts(0.0, max_inner, True, check_every, use_x0, None)
+    o = _opts(0.0, max_inner, True, check_every, use_x0, None,
+              flags=HK_MIXED_LITERAL_INNER if literal_inner else 0)
     _check(load().hk_krylov_solve_mixed(A.h, _ptr(b), _ptr(x), float(inner_tol), float(outer_tol),
                                         int(max_outer), C.byref(o), C.byref(info), _stream()),
            allow_positive=True)
@@ -307,14 +324,20 @@ def krylov_solve_mixed(A: CSR, b, x=None, inner_tol=1e-4, outer_tol=1e-10, max_o
 
 
 SWEEP_LANES = 64
+# launch shapes the batched solvers time (and accept as `shape`)
+SWEEP_SHAPES = [(1, 1, 0, 0), (1, 2, 0, 0), (1, 3, 0, 0), (2, 3, 0, 0)]
+BLOCKDIAG_SHAPES = ([(64, r, ch, tr) for tr in (1024, 512) for r in (64, 32, 16) for ch in (4, 2)]
+                    + [(32, 0, 0, tr) for tr in (1024, 512)])
 
 
-def sweep_solve(rowptr, col, K, M, kappa, B, tol=1e-8, max_iter=400000):
+def sweep_solve(rowptr, col, K, M, kappa, B, tol=1e-8, max_iter=400000, shape=None):
     """Frequency sweep: solve (K - kappa_j M) X[:, j] = B[:, j] for j < len(kappa).
 
     rowptr/col int32, K/M float64 device tensors on one pattern; kappa a
     sequence of complex numbers (<= 64); B an (n, 64) complex128 device tensor
-    (columns >= len(kappa) ignored).  Returns (X, list of info dicts).
+    (columns >= len(kappa) ignored).  shape: a launch shape (product form, row
+    mapping, 0, 0) to use instead of the tuned one.  Returns (X, list of info
+    dicts).
     """
     nsys = len(kappa)
     _cvec(rowptr, torch.int32, name="rowptr")
@@ -328,20 +351,22 @@ def sweep_solve(rowptr, col, K, M, kappa, B, tol=1e-8, max_iter=400000):
     X = torch.zeros_like(B)
     kap = (C.c_double * (2 * nsys))(*[v for z in kappa for v in (complex(z).real, complex(z).imag)])
     infos = (SolveInfo * nsys)()
-    o = _opts(tol, max_iter, True, 0, False, None)
+    o = _opts(tol, max_iter, True, 0, False, None, shape=shape)
     _check(load().hk_sweep_solve(n, col.numel(), _ptr(rowptr), _ptr(col), _ptr(K), _ptr(M), nsys, kap,
                                  _ptr(B), _ptr(X), C.byref(o), infos, _stream()), allow_positive=True)
     return X, [i.as_dict() for i in infos]
 
 
-def blockdiag_solve(A: CSR, row_off, b, tol=1e-8, max_iter=400000):
-    """Uneven batch: A block-diagonal with systems [row_off[k], row_off[k+1])."""
+def blockdiag_solve(A: CSR, row_off, b, tol=1e-8, max_iter=400000, shape=None):
+    """Uneven batch: A block-diagonal with systems [row_off[k], row_off[k+1]).
+    shape: a tile shape (lanes per row, rows per block, entries per lane,
+    tile rows) to use instead of the tuned one."""
     _cvec(b, name="b", n=A.n)
     nsys = len(row_off) - 1
     offs = (C.c_int64 * (nsys + 1))(*[int(v) for v in row_off])
     x = torch.zeros_like(b)
     infos = (SolveInfo * max(nsys, 1))()
-    o = _opts(tol, max_iter, True, 0, False, None)
+    o = _opts(tol, max_iter, True, 0, False, None, shape=shape)
     _check(load().hk_blockdiag_solve(A.h, nsys, offs, _ptr(b), _ptr(x), C.byref(o), infos, _stream()),
            allow_positive=True)
     return x, [infos[k].as_dict() for k in range(nsys)]

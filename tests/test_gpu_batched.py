@@ -97,6 +97,49 @@ def test_sweep_iteration_cap_and_zero_rhs(hk, oracle):
         assert np.linalg.norm(host(X)[:, j] - xo) <= 1e-12 * np.linalg.norm(xo)
 
 
+def sweep_iterates_every_shape(hk, oracle, p, kap, B, tag):
+    """Every sweep launch shape: each system's iterate after 4 iterations is
+    the oracle's to 1e-12 (a system with a zero right-hand side stops at 0
+    and drops out of the products from the start)."""
+    nsys = len(kap)
+    ref = []
+    for j in range(nsys):
+        val = H.helmholtz_values(p, kap[j])
+        ref.append(oracle.bicgstab(p.rowptr, p.col, val, B[:, j], tol=1e-14, maxit=4))
+    args = (dev(p.rowptr), dev(p.col), dev(p.K), dev(p.M), kap, dev(B))
+    for sh in hk.SWEEP_SHAPES:
+        say("sweep iterates", tag, "n", p.n, "nsys", nsys, "shape", sh)
+        X, infos = hk.sweep_solve(*args, tol=1e-14, max_iter=4, shape=sh)
+        Xh = host(X)
+        for j in range(nsys):
+            xo, oi = ref[j]
+            assert infos[j]["shape"] == list(sh) and not infos[j]["shape_tuned"], infos[j]
+            assert infos[j]["iters"] == oi["iters"] and infos[j]["status"] == oi["status"], (sh, j, infos[j], oi)
+            assert np.linalg.norm(Xh[:, j] - xo) <= 1e-12 * max(np.linalg.norm(xo), 1e-300), (sh, j)
+        assert np.all(Xh[:, nsys:] == 0), sh
+    say("sweep iterates", tag, "tuned")
+    X, infos = hk.sweep_solve(*args, tol=1e-14, max_iter=4)
+    assert infos[0]["shape_tuned"] and tuple(infos[0]["shape"]) in hk.SWEEP_SHAPES, infos[0]
+    say("tuned shape", infos[0]["shape"])
+    Xh = host(X)
+    for j in range(nsys):
+        assert np.linalg.norm(Xh[:, j] - ref[j][0]) <= 1e-12 * max(np.linalg.norm(ref[j][0]), 1e-300), j
+
+
+def test_sweep_every_shape_small(hk, oracle):
+    p, kap, B = sweep_inputs(6, 64)
+    B[:, 1] = 0
+    sweep_iterates_every_shape(hk, oracle, p, kap, B, "6^3")
+
+
+def test_sweep_every_shape_large(hk, oracle):
+    """614,125 rows: more than 64 rows (and many 64-entry chunks) per wave in
+    the entry-stream product; 7 systems (lanes 7..63 idle), one with b = 0."""
+    p, kap, B = sweep_inputs(84, 7, seed=3)
+    B[:, 2] = 0
+    sweep_iterates_every_shape(hk, oracle, p, kap, B, "84^3")
+
+
 def blockdiag_inputs(sizes, seed=2):
     rng = np.random.default_rng(seed)
     rows, cols, vals, bs, offs = [], [], [], [], [0]
@@ -185,6 +228,64 @@ def test_blockdiag_long_rows_matches_oracle(hk, oracle):
         xo, oi = oracle.bicgstab(rp, cc, vv, b[lo:hi], tol=1e-10)
         assert infos[k]["status"] == 0, (k, infos[k])
         assert np.linalg.norm(xh[lo:hi] - xo) <= 1e-9 * np.linalg.norm(xo), k
+    # 41-entry rows: several passes per row block in every tile shape
+    blockdiag_iterates_every_shape(hk, oracle, rowptr, col, val, b, np.array(offs, dtype=np.int64), "long rows")
+
+
+def blockdiag_iterates_every_shape(hk, oracle, rowptr, col, val, b, offs, tag):
+    """Every block-diagonal tile shape: each system's iterate after 4
+    iterations is the oracle's to 1e-11."""
+    A = hk.CSR(dev(rowptr), dev(col), dev(val))
+    ref = []
+    for k in range(len(offs) - 1):
+        lo, hi = int(offs[k]), int(offs[k + 1])
+        rp = rowptr[lo:hi + 1] - rowptr[lo]
+        ref.append(oracle.bicgstab(rp, col[rowptr[lo]:rowptr[hi]] - lo, val[rowptr[lo]:rowptr[hi]], b[lo:hi],
+                                   tol=1e-14, maxit=4))
+    bd = dev(b)
+    for sh in hk.BLOCKDIAG_SHAPES:
+        say("blockdiag iterates", tag, "shape", sh)
+        x, infos = hk.blockdiag_solve(A, offs, bd, tol=1e-14, max_iter=4, shape=sh)
+        xh = host(x)
+        for k in range(len(offs) - 1):
+            lo, hi = int(offs[k]), int(offs[k + 1])
+            xo, oi = ref[k]
+            assert infos[k]["shape"] == list(sh) and not infos[k]["shape_tuned"], infos[k]
+            assert infos[k]["iters"] == oi["iters"] and infos[k]["status"] == oi["status"], (sh, k, infos[k], oi)
+            assert np.linalg.norm(xh[lo:hi] - xo) <= 1e-11 * np.linalg.norm(xo), (sh, k)
+    say("blockdiag iterates", tag, "tuned")
+    x, infos = hk.blockdiag_solve(A, offs, bd, tol=1e-14, max_iter=4)
+    assert infos[0]["shape_tuned"] and tuple(infos[0]["shape"]) in hk.BLOCKDIAG_SHAPES, infos[0]
+    say("tuned shape", infos[0]["shape"])
+    xh = host(x)
+    for k in range(len(offs) - 1):
+        lo, hi = int(offs[k]), int(offs[k + 1])
+        assert np.linalg.norm(xh[lo:hi] - ref[k][0]) <= 1e-11 * np.linalg.norm(ref[k][0]), k
+    with pytest.raises(hk.HKError):
+        hk.blockdiag_solve(A, offs, bd, tol=1e-14, max_iter=4, shape=(64, 48, 4, 1024))
+
+
+def test_blockdiag_every_shape_small(hk, oracle):
+    rowptr, col, val, b, offs = blockdiag_inputs([5, 3, 8, 4, 6, 2, 7])
+    blockdiag_iterates_every_shape(hk, oracle, rowptr, col, val, b, offs, "7 cubes")
+
+
+def test_blockdiag_every_shape_uneven(hk, oracle):
+    """The 32-system uneven batch (1,073,278 rows) at 4 iterations."""
+    systems = configs.uneven_systems()
+    offs = [0]
+    rows, cols, vals, bs = [], [], [], []
+    for s_ in systems:
+        rows.append(s_["rowptr"][:-1] + sum(c.shape[0] for c in cols))
+        cols.append(s_["col"] + offs[-1])
+        vals.append(s_["val"])
+        bs.append(s_["g"])
+        offs.append(offs[-1] + int(s_["n"]))
+    nnz = sum(c.shape[0] for c in cols)
+    rowptr = np.concatenate(rows + [np.array([nnz])]).astype(np.int32)
+    blockdiag_iterates_every_shape(hk, oracle, rowptr, np.concatenate(cols).astype(np.int32),
+                                   np.concatenate(vals), np.concatenate(bs), np.array(offs, dtype=np.int64),
+                                   "uneven32")
 
 
 def test_blockdiag_rejects_coupled_systems(hk):
