@@ -26,6 +26,7 @@
 #include <complex.h>
 #include <float.h>
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -48,6 +49,12 @@ typedef struct {
     int32_t status;
     int32_t breakdown;   /* OR_BD_* */
 } or_info;
+
+/* Thread count of the OpenMP loops, for the host-baseline timings.  Every
+ * parallel loop writes independent rows or elements and every sum runs on
+ * one thread in index order, so results do not depend on it. */
+void orc_set_threads(int t) { omp_set_num_threads(t > 0 ? t : 1); }
+int orc_max_threads(void) { return omp_get_max_threads(); }
 
 /* ---------------------------------------------------------------- kernels */
 

@@ -86,8 +86,19 @@ def lib():
         L.orc_assemble_helmholtz.argtypes = [i64, P, P, P, P, i64, P, P, P, P, dbl, dbl, P]
         L.orc_assemble_helmholtz.restype = i32
         L.orc_elem_sens.argtypes = [i64, P, P, P, P, P, P, P, i64, dbl, dbl, P]
+        L.orc_set_threads.argtypes = [i32]
+        L.orc_max_threads.restype = i32
         _lib = L
     return _lib
+
+
+def set_threads(t):
+    """Thread count of the oracle's OpenMP loops (results do not depend on it)."""
+    lib().orc_set_threads(int(t))
+
+
+def max_threads():
+    return int(lib().orc_max_threads())
 
 
 def _p(a):
