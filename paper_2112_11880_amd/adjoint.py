@@ -10,7 +10,8 @@ gradients follow torch's convention for complex tensors
 """
 from __future__ import annotations
 
-from dataclasses import dataclass
+import itertools
+from dataclasses import dataclass, field
 
 import torch
 
@@ -36,6 +37,15 @@ class HelmholtzProblem:
     dirichlet: torch.Tensor   # uint8 (n)
     omega: float
     damp: float = 0.01
+    # the assembled operator: one value buffer and one CSR handle on it, made
+    # on the first solve and reused (the pattern never changes), and the
+    # forward solve whose speeds the buffer holds
+    _val: torch.Tensor = field(default=None, repr=False, compare=False)
+    _A: object = field(default=None, repr=False, compare=False)
+    _owner: int = field(default=-1, repr=False, compare=False)
+    # records of the last forward and adjoint solves (iterations, residuals)
+    last_forward_info: dict = field(default=None, repr=False, compare=False)
+    last_adjoint_info: dict = field(default=None, repr=False, compare=False)
 
     @property
     def n(self):
@@ -88,17 +98,33 @@ def elem_sens(prob: HelmholtzProblem, lam, u, c):
     return out
 
 
+_tokens = itertools.count()
+
+
+def _operator(prob: HelmholtzProblem, c: torch.Tensor, owner: int):
+    """A(c) assembled into the problem's value buffer, and the CSR handle on
+    it (created once per problem), marked as holding the speeds of `owner`."""
+    if prob._val is None:
+        prob._val = torch.empty(prob.col.numel(), dtype=torch.complex128, device=prob.col.device)
+    assemble(prob, c, out=prob._val)
+    if prob._A is None:
+        prob._A = _hk.CSR(prob.rowptr, prob.col, prob._val)
+    prob._owner = owner
+    return prob._A
+
+
 class HelmholtzSolve(torch.autograd.Function):
     """u = A(c)^-1 g (Jacobi BiCGStab) with the adjoint backward pass."""
 
     @staticmethod
     def forward(ctx, g, c, prob: HelmholtzProblem, tol: float, max_iter: int):
-        val = assemble(prob, c)
-        A = _hk.CSR(prob.rowptr, prob.col, val)
+        ctx.token = next(_tokens)
+        A = _operator(prob, c, ctx.token)
         u, info = _hk.krylov_solve(A, g.detach().contiguous(), tol=tol, max_iter=max_iter)
+        prob.last_forward_info = info
         if info["status"] != _hk.HK_OK:
             raise _hk.HKError(info["status"], f"forward solve did not converge: {info}")
-        ctx.A, ctx.prob, ctx.tol, ctx.max_iter = A, prob, tol, max_iter
+        ctx.prob, ctx.tol, ctx.max_iter = prob, tol, max_iter
         ctx.info_forward = info
         ctx.save_for_backward(c, u)
         return u
@@ -106,8 +132,12 @@ class HelmholtzSolve(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_u):
         c, u = ctx.saved_tensors
+        prob = ctx.prob
+        # another forward on the same problem may have reassembled the buffer
+        A = prob._A if prob._owner == ctx.token else _operator(prob, c, ctx.token)
         rhs = _hk.zconj(grad_u.contiguous())
-        lam, info = _hk.krylov_solve(ctx.A, rhs, tol=ctx.tol, max_iter=ctx.max_iter)
+        lam, info = _hk.krylov_solve(A, rhs, tol=ctx.tol, max_iter=ctx.max_iter)
+        prob.last_adjoint_info = info
         if info["status"] != _hk.HK_OK:
             raise _hk.HKError(info["status"], f"adjoint solve did not converge: {info}")
         grad_g = _hk.zconj(lam) if ctx.needs_input_grad[0] else None

@@ -98,8 +98,11 @@ extern "C" int hk_assemble_helmholtz(int64_t nnz, const double* d_K, const int32
       !d_bm_val || !d_c || !d_val)
     HK_FAIL(HK_EINVAL, "hk_assemble_helmholtz: bad argument");
   hipStream_t s = as_stream(stream);
-  int* flag = nullptr;
-  HK_HIP(hipMalloc(&flag, sizeof(int)));
+  // the error word lives in the stream's reduction scratch (allocated once)
+  ReduceScratch* scr = nullptr;
+  const int rc = reduce_scratch(s, sizeof(int), &scr);
+  if (rc != HK_OK) return rc;
+  int* flag = static_cast<int*>(scr->partials);
   int h = 0;
   hipError_t e = hipMemsetAsync(flag, 0, sizeof(int), s);
   if (e == hipSuccess) {
@@ -111,7 +114,6 @@ extern "C" int hk_assemble_helmholtz(int64_t nnz, const double* d_K, const int32
   }
   if (e == hipSuccess) e = hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  (void)hipFree(flag);
   if (e != hipSuccess) HK_FAIL(HK_EHIP, "hk_assemble_helmholtz: %s", hipGetErrorString(e));
   if (h) HK_FAIL(HK_EINVAL, "hk_assemble_helmholtz: malformed block-mass lists");
   return HK_OK;
@@ -127,8 +129,11 @@ extern "C" int hk_elem_sens(int64_t n, int64_t ntet, int32_t nblocks, const int3
       !d_grad_c)
     HK_FAIL(HK_EINVAL, "hk_elem_sens: bad argument");
   hipStream_t s = as_stream(stream);
-  int* flag = nullptr;
-  HK_HIP(hipMalloc(&flag, sizeof(int)));
+  // the error word lives in the stream's reduction scratch (allocated once)
+  ReduceScratch* scr = nullptr;
+  const int rc = reduce_scratch(s, sizeof(int), &scr);
+  if (rc != HK_OK) return rc;
+  int* flag = static_cast<int*>(scr->partials);
   int h = 0;
   hipError_t e = hipMemsetAsync(flag, 0, sizeof(int), s);
   if (e == hipSuccess) {
@@ -138,10 +143,7 @@ extern "C" int hk_elem_sens(int64_t n, int64_t ntet, int32_t nblocks, const int3
   }
   if (e == hipSuccess) e = hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (e == hipSuccess && h) {
-    (void)hipFree(flag);
-    HK_FAIL(HK_EINVAL, "hk_elem_sens: element block offsets are not a partition of [0, ntet]");
-  }
+  if (e == hipSuccess && h) HK_FAIL(HK_EINVAL, "hk_elem_sens: element block offsets are not a partition of [0, ntet]");
   if (e == hipSuccess) {
     const double w2 = omega * omega;
     hipLaunchKernelGGL(k_elem_sens, dim3((unsigned)nblocks), dim3(kBlock), 0, s, (int)n, (int)nblocks,
@@ -151,7 +153,6 @@ extern "C" int hk_elem_sens(int64_t n, int64_t ntet, int32_t nblocks, const int3
   }
   if (e == hipSuccess) e = hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  (void)hipFree(flag);
   if (e != hipSuccess) HK_FAIL(HK_EHIP, "hk_elem_sens: %s", hipGetErrorString(e));
   if (h) HK_FAIL(HK_EINVAL, "hk_elem_sens: element node index out of range");
   return HK_OK;
