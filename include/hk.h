@@ -141,6 +141,19 @@ int hk_residual(hk_csr A, const void* d_b, const void* d_x, void* d_r, void* str
  * n < 0 gives HK_EINVAL. */
 int hk_zdotc(int64_t n, const void* d_x, const void* d_y, void* d_res, void* stream);
 
+/* The same *d_res = x^H y as hk_zdotc, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): no hipMalloc, hipFree or allocating
+ * library call is made.  The per-workgroup partials go to a static 64 KiB
+ * device array of the library (one per GPU, held until the process ends,
+ * its address looked up on the first call on each device), enough for the
+ * reduction's at most 4096 workgroups; nothing in it needs clearing.  Same
+ * kernels, so the same bits as hk_zdotc.  n up to 2^40 (HK_EINVAL above);
+ * n = 0 gives 0.  Calls that overlap on one GPU (several streams or host
+ * threads at once) race on the shared array and must be serialised by the
+ * caller. */
+int hk_zdotc_noalloc(int64_t n, const void* d_x, const void* d_y, void* d_res, void* stream);
+
 /* *d_res = x^T y = sum x_i y_i (unconjugated form of the same reduction). */
 int hk_zdotu(int64_t n, const void* d_x, const void* d_y, void* d_res, void* stream);
 

@@ -7,12 +7,17 @@
 // one partial, and a one-workgroup kernel sums the partials in a fixed order
 // and writes the result to device memory, so no host copy is needed and the
 // result is bitwise reproducible.
+#include <mutex>
+
 #include "hk_common.hpp"
 #include "hk_internal.hpp"
 
 namespace hk {
 
 constexpr int kRedMaxBlocks = 4096;
+// largest n of the allocation-free dot (the index arithmetic is int64; this
+// bound keeps chunk * workgroups far from overflow)
+constexpr int64_t kNoAllocMaxN = int64_t(1) << 40;
 
 // workgroups of a reduction over n elements: at least 8 elements per thread,
 // at most kRedMaxBlocks workgroups (each then walks a longer chunk)
@@ -106,6 +111,24 @@ __global__ void k_zero_res(double* res, int count) {
   if ((int)threadIdx.x < count) res[threadIdx.x] = 0.0;
 }
 
+// The two stages of a reduction over n > 0 elements, partials in `partials`
+// (room for 2 reduce_blocks(n) doubles).
+template <int KIND>
+static int launch_reduce(int64_t n, const void* x, const void* y, void* res, hipStream_t s, double* partials) {
+  const int nb = reduce_blocks(n);
+  hipLaunchKernelGGL(k_reduce<KIND>, dim3(nb), dim3(kBlock), 0, s, n, (const double2*)x,
+                     (const double2*)y, partials);
+  HK_CHECK_LAUNCH();
+  if (nb <= kFinSmallNb)
+    hipLaunchKernelGGL((k_reduce_fin<KIND, kFinBlockSmall>), dim3(1), dim3(kFinBlockSmall), 0, s,
+                       (const double*)partials, nb, (double*)res);
+  else
+    hipLaunchKernelGGL((k_reduce_fin<KIND, kFinBlock>), dim3(1), dim3(kFinBlock), 0, s,
+                       (const double*)partials, nb, (double*)res);
+  HK_CHECK_LAUNCH();
+  return HK_OK;
+}
+
 template <int KIND>
 static int reduce(int64_t n, const void* x, const void* y, void* res, void* stream, const char* who) {
   if (n < 0 || !res || (n > 0 && (!x || (KIND != 2 && !y))))
@@ -116,20 +139,42 @@ static int reduce(int64_t n, const void* x, const void* y, void* res, void* stre
     HK_CHECK_LAUNCH();
     return HK_OK;
   }
-  const int nb = reduce_blocks(n);
   ReduceScratch* rs = nullptr;
-  int rc = reduce_scratch(s, sizeof(double) * 2 * nb, &rs);
+  int rc = reduce_scratch(s, sizeof(double) * 2 * reduce_blocks(n), &rs);
   if (rc != HK_OK) return rc;
-  hipLaunchKernelGGL(k_reduce<KIND>, dim3(nb), dim3(kBlock), 0, s, n, (const double2*)x,
-                     (const double2*)y, (double*)rs->partials);
-  HK_CHECK_LAUNCH();
-  if (nb <= kFinSmallNb)
-    hipLaunchKernelGGL((k_reduce_fin<KIND, kFinBlockSmall>), dim3(1), dim3(kFinBlockSmall), 0, s,
-                       (const double*)rs->partials, nb, (double*)res);
-  else
-    hipLaunchKernelGGL((k_reduce_fin<KIND, kFinBlock>), dim3(1), dim3(kFinBlock), 0, s,
-                       (const double*)rs->partials, nb, (double*)res);
-  HK_CHECK_LAUNCH();
+  return launch_reduce<KIND>(n, x, y, res, s, (double*)rs->partials);
+}
+
+// ------------------------------------------- allocation-free zdotc scratch
+//
+// The partials of hk_zdotc_noalloc live in this file-scope device array (one
+// copy per GPU, held until the process ends): two doubles for each of at
+// most kRedMaxBlocks workgroups, 64 KiB.  Every first-stage workgroup writes
+// its partial before the finalize reads it, so nothing needs clearing
+// between calls.  The array's name is only a host-side stand-in; kernels get
+// its device address, looked up once per device.
+constexpr int kNoAllocPartials = 2 * kRedMaxBlocks;
+static __device__ __align__(256) double scratch[kNoAllocPartials];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on first use).
+static int noalloc_scratch(double** out) {
+  int dev = 0;
+  HK_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) HK_FAIL(HK_EINVAL, "hk_zdotc_noalloc: device %d beyond %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      HK_FAIL(HK_EHIP, "hk_zdotc_noalloc: hipGetSymbolAddress(scratch) on device %d: %s", dev,
+              hipGetErrorString(e));
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
   return HK_OK;
 }
 
@@ -139,6 +184,25 @@ using namespace hk;
 
 extern "C" int hk_zdotc(int64_t n, const void* x, const void* y, void* res, void* stream) {
   return reduce<0>(n, x, y, res, stream, "hk_zdotc");
+}
+extern "C" int hk_zdotc_noalloc(int64_t n, const void* x, const void* y, void* res, void* stream) {
+  if (n < 0 || !res || (n > 0 && (!x || !y)))
+    HK_FAIL(HK_EINVAL, "hk_zdotc_noalloc: bad argument (n=%lld)", (long long)n);
+  if (n > kNoAllocMaxN)
+    HK_FAIL(HK_EINVAL, "hk_zdotc_noalloc: n=%lld above the limit %lld", (long long)n, (long long)kNoAllocMaxN);
+  hipStream_t s = as_stream(stream);
+  if (n == 0) {
+    hipLaunchKernelGGL(k_zero_res, dim3(1), dim3(64), 0, s, (double*)res, 2);
+    HK_CHECK_LAUNCH();
+    return HK_OK;
+  }
+  if (2 * reduce_blocks(n) > kNoAllocPartials)
+    HK_FAIL(HK_EINVAL, "hk_zdotc_noalloc: %d partials exceed the scratch of %d", 2 * reduce_blocks(n),
+            kNoAllocPartials);
+  double* partials = nullptr;
+  const int rc = noalloc_scratch(&partials);
+  if (rc != HK_OK) return rc;
+  return launch_reduce<0>(n, x, y, res, s, partials);
 }
 extern "C" int hk_zdotu(int64_t n, const void* x, const void* y, void* res, void* stream) {
   return reduce<1>(n, x, y, res, stream, "hk_zdotu");

@@ -64,6 +64,7 @@ SIGNATURES = {
     "hk_spmv": ([P, P, P, P, P, P], C.c_int),
     "hk_residual": ([P, P, P, P, P], C.c_int),
     "hk_zdotc": ([I64, P, P, P, P], C.c_int),
+    "hk_zdotc_noalloc": ([I64, P, P, P, P], C.c_int),
     "hk_zdotu": ([I64, P, P, P, P], C.c_int),
     "hk_dznrm2": ([I64, P, P, P], C.c_int),
     "hk_zaxpy": ([I64, P, P, P, P], C.c_int),
@@ -211,6 +212,15 @@ def zdotc(x, y, out=None):
     _cvec(x, name="x"), _cvec(y, name="y", n=x.numel())
     out = torch.empty(1, dtype=torch.complex128, device=x.device) if out is None else _cvec(out, name="out", n=1)
     _check(load().hk_zdotc(x.numel(), _ptr(x), _ptr(y), _ptr(out), _stream()))
+    return out
+
+
+def zdotc_noalloc(x, y, out):
+    """x^H y into out (one complex128 on the device) without any allocation:
+    partials in the library's static per-GPU scratch (calls on one GPU must
+    not overlap)."""
+    _cvec(x, name="x"), _cvec(y, name="y", n=x.numel()), _cvec(out, name="out", n=1)
+    _check(load().hk_zdotc_noalloc(x.numel(), _ptr(x), _ptr(y), _ptr(out), _stream()))
     return out
 
 
