@@ -7,6 +7,7 @@ Every case prints its name before launching anything.  Bounds:
   * solves at tol 1e-8: the oracle recomputes ||b - A x|| / ||b|| <= 1.05e-8;
     at tol 1e-10 the solution is within 1e-7 of the oracle's solution.
 """
+import os
 import sys
 
 import numpy as np
@@ -654,6 +655,45 @@ def test_solve_box192(hk, oracle):
     assert info["status"] == hk.HK_OK, info
     r = oracle.residual(c["rowptr"], c["col"], c["val"], c["g"], host(x))
     assert np.linalg.norm(r) / np.linalg.norm(c["g"]) <= 1.05e-8
+
+
+GOLDEN_BOX192 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "box192_oracle_solution.txt")
+
+
+def box192_golden():
+    """Sampled rows of the oracle's FP64 solution of the 192x96x96 system
+    (tests/golden/make_box192_solution.py: oracle BiCGStab to 1e-12)."""
+    idx, ref = [], []
+    with open(GOLDEN_BOX192) as fh:
+        for line in fh:
+            t = line.split()
+            if t and t[0] == "x":
+                idx.append(int(t[1]))
+                ref.append(complex(float(t[2]), float(t[3])))
+    return np.array(idx), np.array(ref)
+
+
+@pytest.mark.parametrize("literal", [False, True], ids=["clamped", "literal"])
+def test_mixed_box192(hk, oracle, literal):
+    """The mixed-precision workload at its own size: 192x96x96 system, complex64
+    inner BiCGStab to 1e-4 (with and without the last cycle's clamp), complex128
+    outer loop to 1e-10.  The oracle recomputes the true residual (<= 1.05e-10),
+    and the solution is within 1e-7 of the oracle's FP64 solution on its 4,098
+    sampled rows."""
+    c = configs.box192()
+    idx, ref = box192_golden()
+    A = make_csr(hk, c["rowptr"], c["col"], c["val"], autotune=True)
+    say("mixed box192 inner 1e-4 outer 1e-10", "literal" if literal else "clamped")
+    x, info = hk.krylov_solve_mixed(A, dev(c["g"]), inner_tol=1e-4, outer_tol=1e-10, literal_inner=literal)
+    say("mixed box192", info)
+    assert info["status"] == hk.HK_OK, info
+    xh = host(x)
+    r = oracle.residual(c["rowptr"], c["col"], c["val"], c["g"], xh)
+    rel = np.linalg.norm(r) / np.linalg.norm(c["g"])
+    err = np.linalg.norm(xh[idx] - ref) / np.linalg.norm(ref)
+    say("mixed box192 true relres", rel, "err vs fp64 oracle", err)
+    assert rel <= 1.05e-10
+    assert err <= 1e-7
 
 
 def test_solve_box192_wide_workgroup_shapes(hk, oracle):
