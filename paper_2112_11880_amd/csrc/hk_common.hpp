@@ -61,6 +61,34 @@ template <class V> __device__ __forceinline__ bool cfinite(V a) {
   return isfinite(a.x) && isfinite(a.y);
 }
 
+// ------------------------------------------------- non-temporal access
+// Loads and stores that hint the caches not to keep the line: for streams
+// read or written once (matrix entries, results, vectors larger than the
+// last-level cache).
+typedef double nd2 __attribute__((ext_vector_type(2)));
+typedef float nf2 __attribute__((ext_vector_type(2)));
+
+template <class V> struct native;
+template <> struct native<double2> { using type = nd2; };
+template <> struct native<float2> { using type = nf2; };
+
+template <class V> __device__ __forceinline__ V ldnt(const V* p) {
+  using N = typename native<V>::type;
+  N v = __builtin_nontemporal_load(reinterpret_cast<const N*>(p));
+  return cmake<V>(v.x, v.y);
+}
+// Non-temporal store of one complex value (a result written once and not
+// read again by the same kernel).
+template <class V> __device__ __forceinline__ void stnt(V* p, V v) {
+  using N = typename native<V>::type;
+  N o;
+  o.x = v.x;
+  o.y = v.y;
+  __builtin_nontemporal_store(o, reinterpret_cast<N*>(p));
+}
+__device__ __forceinline__ int ldnt(const int* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ int ldnt(const short* p) { return (int)__builtin_nontemporal_load(p); }
+
 __device__ __forceinline__ double2 to_c128(float2 a) { return make_double2(a.x, a.y); }
 __device__ __forceinline__ float2 to_c64(double2 a) { return make_float2((float)a.x, (float)a.y); }
 

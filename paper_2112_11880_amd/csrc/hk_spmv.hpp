@@ -20,20 +20,6 @@
 
 namespace hk {
 
-typedef double nd2 __attribute__((ext_vector_type(2)));
-typedef float nf2 __attribute__((ext_vector_type(2)));
-
-template <class V> struct native;
-template <> struct native<double2> { using type = nd2; };
-template <> struct native<float2> { using type = nf2; };
-
-template <class V> __device__ __forceinline__ V ldnt(const V* p) {
-  using N = typename native<V>::type;
-  N v = __builtin_nontemporal_load(reinterpret_cast<const N*>(p));
-  return cmake<V>(v.x, v.y);
-}
-__device__ __forceinline__ int ldnt(const int* p) { return __builtin_nontemporal_load(p); }
-__device__ __forceinline__ int ldnt(const short* p) { return (int)__builtin_nontemporal_load(p); }
 
 // Column stream of the row-block products.  A matrix whose every entry lies
 // within 32767 columns of its row's 64-aligned base (row & ~63) -- a banded
