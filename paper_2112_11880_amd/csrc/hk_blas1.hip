@@ -15,6 +15,18 @@
 namespace hk {
 
 constexpr int kRedMaxBlocks = 4096;
+// Vectors of at least this many elements (64 MiB of complex128) are streamed
+// with non-temporal loads and stores: they do not fit the last-level cache
+// with their operands, and the hint measured 80.1 -> 74.0 us for zdotc and
+// 114.9 -> 102.6 us for zaxpy at 14M elements.  Smaller vectors keep plain
+// accesses (at 648,849 elements zaxpy took 8.1 us plain, 9.7 us
+// non-temporal).
+constexpr int64_t kNtMinElems = int64_t(1) << 22;
+template <bool NT> __device__ __forceinline__ double2 ld(const double2* p) { return NT ? ldnt(p) : *p; }
+template <bool NT> __device__ __forceinline__ void st(double2* p, double2 v) {
+  if (NT) stnt(p, v);
+  else *p = v;
+}
 // largest n of the allocation-free dot (the index arithmetic is int64; this
 // bound keeps chunk * workgroups far from overflow)
 constexpr int64_t kNoAllocMaxN = int64_t(1) << 40;
@@ -29,7 +41,7 @@ static int reduce_blocks(int64_t n) {
 
 // First stage. KIND 0: x^H y, 1: x^T y, 2: ||x||^2.  Each workgroup reduces
 // a contiguous chunk, 4 independent loads per vector in flight per thread.
-template <int KIND>
+template <int KIND, bool NT>
 __global__ __launch_bounds__(kBlock) void k_reduce(int64_t n, const double2* __restrict__ x,
                                                    const double2* __restrict__ y, double* partials) {
   __shared__ double lds[2 * (kBlock / kWave)];
@@ -44,8 +56,8 @@ __global__ __launch_bounds__(kBlock) void k_reduce(int64_t n, const double2* __r
     double2 a[4], b[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      a[u] = x[i + u * kBlock];
-      if (KIND != 2) b[u] = y[i + u * kBlock];
+      a[u] = ld<NT>(x + i + u * kBlock);
+      if (KIND != 2) b[u] = ld<NT>(y + i + u * kBlock);
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -55,9 +67,9 @@ __global__ __launch_bounds__(kBlock) void k_reduce(int64_t n, const double2* __r
     }
   }
   for (; i < i1; i += kBlock) {
-    const double2 a = x[i];
-    if (KIND == 0) acc = cfmac(a, y[i], acc);
-    else if (KIND == 1) acc = cfma(a, y[i], acc);
+    const double2 a = ld<NT>(x + i);
+    if (KIND == 0) acc = cfmac(a, ld<NT>(y + i), acc);
+    else if (KIND == 1) acc = cfma(a, ld<NT>(y + i), acc);
     else acc.x = fma(a.x, a.x, fma(a.y, a.y, acc.x));
   }
   constexpr int NV = KIND == 2 ? 1 : 2;
@@ -82,21 +94,25 @@ __global__ __launch_bounds__(BS) void k_reduce_fin(const double* partials, int n
   }
 }
 
+template <bool NT>
 __global__ void k_axpy(int64_t n, double2 a, const double2* __restrict__ x, double2* __restrict__ y) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i < n) y[i] = cfma(a, x[i], y[i]);
+  if (i < n) st<NT>(y + i, cfma(a, ld<NT>(x + i), ld<NT>(y + i)));
 }
+template <bool NT>
 __global__ void k_scal(int64_t n, double2 a, double2* __restrict__ x) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i < n) x[i] = cmul(a, x[i]);
+  if (i < n) st<NT>(x + i, cmul(a, ld<NT>(x + i)));
 }
+template <bool NT>
 __global__ void k_axmy(int64_t n, const double2* __restrict__ x, double2* __restrict__ y) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i < n) y[i] = cmul(x[i], y[i]);
+  if (i < n) st<NT>(y + i, cmul(ld<NT>(x + i), ld<NT>(y + i)));
 }
+template <bool NT>
 __global__ void k_copy(int64_t n, const double2* __restrict__ x, double2* __restrict__ y) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i < n) y[i] = x[i];
+  if (i < n) st<NT>(y + i, ld<NT>(x + i));
 }
 __global__ void k_conj(int64_t n, const double2* x, double2* y) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -116,8 +132,12 @@ __global__ void k_zero_res(double* res, int count) {
 template <int KIND>
 static int launch_reduce(int64_t n, const void* x, const void* y, void* res, hipStream_t s, double* partials) {
   const int nb = reduce_blocks(n);
-  hipLaunchKernelGGL(k_reduce<KIND>, dim3(nb), dim3(kBlock), 0, s, n, (const double2*)x,
-                     (const double2*)y, partials);
+  if (n >= kNtMinElems)
+    hipLaunchKernelGGL((k_reduce<KIND, true>), dim3(nb), dim3(kBlock), 0, s, n, (const double2*)x,
+                       (const double2*)y, partials);
+  else
+    hipLaunchKernelGGL((k_reduce<KIND, false>), dim3(nb), dim3(kBlock), 0, s, n, (const double2*)x,
+                       (const double2*)y, partials);
   HK_CHECK_LAUNCH();
   if (nb <= kFinSmallNb)
     hipLaunchKernelGGL((k_reduce_fin<KIND, kFinBlockSmall>), dim3(1), dim3(kFinBlockSmall), 0, s,
@@ -214,32 +234,32 @@ extern "C" int hk_dznrm2(int64_t n, const void* x, double* res, void* stream) {
 extern "C" int hk_zaxpy(int64_t n, const double* alpha, const void* x, void* y, void* stream) {
   if (n < 0 || !alpha || (n > 0 && (!x || !y))) HK_FAIL(HK_EINVAL, "hk_zaxpy: bad argument");
   if (n == 0) return HK_OK;
-  hipLaunchKernelGGL(k_axpy, ew_grid(n), dim3(kBlock), 0, as_stream(stream), n,
-                     make_double2(alpha[0], alpha[1]), (const double2*)x, (double2*)y);
+  hipLaunchKernelGGL(n >= kNtMinElems ? k_axpy<true> : k_axpy<false>, ew_grid(n), dim3(kBlock), 0,
+                     as_stream(stream), n, make_double2(alpha[0], alpha[1]), (const double2*)x, (double2*)y);
   HK_CHECK_LAUNCH();
   return HK_OK;
 }
 extern "C" int hk_zscal(int64_t n, const double* alpha, void* x, void* stream) {
   if (n < 0 || !alpha || (n > 0 && !x)) HK_FAIL(HK_EINVAL, "hk_zscal: bad argument");
   if (n == 0) return HK_OK;
-  hipLaunchKernelGGL(k_scal, ew_grid(n), dim3(kBlock), 0, as_stream(stream), n,
-                     make_double2(alpha[0], alpha[1]), (double2*)x);
+  hipLaunchKernelGGL(n >= kNtMinElems ? k_scal<true> : k_scal<false>, ew_grid(n), dim3(kBlock), 0,
+                     as_stream(stream), n, make_double2(alpha[0], alpha[1]), (double2*)x);
   HK_CHECK_LAUNCH();
   return HK_OK;
 }
 extern "C" int hk_zaxmy(int64_t n, const void* x, void* y, void* stream) {
   if (n < 0 || (n > 0 && (!x || !y))) HK_FAIL(HK_EINVAL, "hk_zaxmy: bad argument");
   if (n == 0) return HK_OK;
-  hipLaunchKernelGGL(k_axmy, ew_grid(n), dim3(kBlock), 0, as_stream(stream), n, (const double2*)x,
-                     (double2*)y);
+  hipLaunchKernelGGL(n >= kNtMinElems ? k_axmy<true> : k_axmy<false>, ew_grid(n), dim3(kBlock), 0,
+                     as_stream(stream), n, (const double2*)x, (double2*)y);
   HK_CHECK_LAUNCH();
   return HK_OK;
 }
 extern "C" int hk_zcopy(int64_t n, const void* x, void* y, void* stream) {
   if (n < 0 || (n > 0 && (!x || !y))) HK_FAIL(HK_EINVAL, "hk_zcopy: bad argument");
   if (n == 0) return HK_OK;
-  hipLaunchKernelGGL(k_copy, ew_grid(n), dim3(kBlock), 0, as_stream(stream), n, (const double2*)x,
-                     (double2*)y);
+  hipLaunchKernelGGL(n >= kNtMinElems ? k_copy<true> : k_copy<false>, ew_grid(n), dim3(kBlock), 0,
+                     as_stream(stream), n, (const double2*)x, (double2*)y);
   HK_CHECK_LAUNCH();
   return HK_OK;
 }
