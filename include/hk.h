@@ -290,10 +290,12 @@ int hk_krylov_solve_mixed(hk_csr A, const void* d_b, void* d_x, double inner_tol
  * records.  Synchronises `stream`.  Returns the largest per-system status.
  * Launch shape {product form, row mapping, 0, 0}: product form 1 walks a
  * wave's rows one at a time, 2 streams the entries of a wave's contiguous
- * rows across row boundaries; row mapping 1 deals each XCD's eighth of the
- * rows round-robin to its waves, 2 deals all rows round-robin to all waves,
- * 3 gives each wave a contiguous range of its XCD's eighth (form 2 needs
- * mapping 3).  The candidates are {1,1}, {1,2}, {1,3} and {2,3}.  With
+ * rows across row boundaries, 3 walks rows one at a time with the next
+ * row's first 16 entries loaded while the current row's gathers are in
+ * flight; row mapping 1 deals each XCD's eighth of the rows round-robin to
+ * its waves, 2 deals all rows round-robin to all waves, 3 gives each wave a
+ * contiguous range of its XCD's eighth (form 2 needs mapping 3).  The
+ * candidates are {1,1}, {1,2}, {1,3}, {2,3}, {3,1} and {3,2}.  With
  * opts->shape all 0, the first call for a given (device, n, nnz, longest
  * row, nsys) runs every candidate for 4 iterations, timed with HIP events,
  * and keeps the fastest for this and later calls (the batch-plan analogue

@@ -261,7 +261,7 @@ __device__ __forceinline__ void sweep_spmv(const SweepArgs& a, int r0, int r1, i
       part[0] += cabs2(rt);
       continue;
     }
-    dst[o] = acc;
+    stnt(dst + o, acc);
     if (EPI == 1) {
       const double2 h = pre;
       part[0] = fma(h.x, acc.x, fma(h.y, acc.y, part[0]));
@@ -397,11 +397,11 @@ __device__ __forceinline__ void sweep_spmv_stream(const SweepArgs& a, int ra, in
             if constexpr (EPI == 3) {
               part[0] += cabs2(csub(pre, y));
             } else if constexpr (EPI == 1) {
-              dst[o] = y;
+              stnt(dst + o, y);
               part[0] = fma(pre.x, y.x, fma(pre.y, y.y, part[0]));
               part[1] = fma(pre.x, y.y, fma(-pre.y, y.x, part[1]));
             } else {
-              dst[o] = y;
+              stnt(dst + o, y);
               const double2 sv = cmul(dg, pre);
               part[0] = fma(y.x, y.x, fma(y.y, y.y, part[0]));
               part[1] = fma(y.x, sv.x, fma(y.y, sv.y, part[1]));
@@ -428,19 +428,149 @@ __device__ __forceinline__ void sweep_spmv_stream(const SweepArgs& a, int ra, in
   }
 }
 
+// Per-row form with the next row prefetched: lanes 0..15 of the wave hold
+// the column, K and M of the current row's first 16 entries (one vector load
+// each, issued while the previous row was in flight), so a row's gathers
+// need not wait for its matrix entries.  The next row's extent, entries and
+// epilogue operand are loaded behind the first gathers; then the
+// multiply-adds, with each
+// entry's column and coefficients broadcast by readlane.  The gathers go
+// in two rounds of 8, the second issued before the first round's sums (16
+// gathers at once spill registers).  Entries past the
+// 16th (longer rows) go in rounds of 8 through scalar loads as in
+// sweep_spmv.  The matrix loads run in every lane whatever its system's
+// state (the broadcasts read lanes 0..15); gathers, sums and stores only in
+// the lanes of running systems.  Every row has an entry (nonzero diagonal).
+template <int EPI, int NV>
+__device__ __forceinline__ void sweep_spmv_pf(const SweepArgs& a, int r0, int r1, int rs, const double2* src,
+                                              double2* dst, bool act, double2 kap, double (&part)[NV]) {
+  constexpr int W = 16, G = 8;  // entries prefetched per row; gathers per round
+  const int j = threadIdx.x & 63;
+  if (__ballot(act) == 0) return;  // uniform: no running system
+  const cptr<int> rowptr = as_const(a.rowptr), col = as_const(a.col);
+  const cptr<double> Kc = as_const(a.K), Mc = as_const(a.M);
+  int row = uni(r0);
+  if (row >= r1) return;
+  int s = rowptr[row], e = rowptr[row + 1];
+  auto fetch = [&](int s_, int e_, int& cv, double& kv, double& mv) {
+    const int q = min(s_ + (j & (W - 1)), e_ - 1);
+    cv = ldnt(a.col + q);
+    kv = __builtin_nontemporal_load(a.K + q);
+    mv = __builtin_nontemporal_load(a.M + q);
+  };
+  int cv, cvn = 0;
+  double kv, mv, kvn = 0, mvn = 0;
+  fetch(s, e, cv, kv, mv);
+  for (; row < r1; row += rs) {
+    const int len = e - s;
+    const size_t o = (size_t)row * kSys + j;
+    double2 acK = make_double2(0, 0), acM = make_double2(0, 0);
+    double2 xv[G];
+    // the first G gathers, then the next row and this row's epilogue
+    // operand behind them, then the next G gathers and the sums
+#pragma unroll
+    for (int u = 0; u < G; ++u)
+      if (u < len && act) xv[u] = src[(size_t)bcast(cv, u) * kSys + j];
+    const int nrow = row + rs;
+    int ns = 0, ne = 0;
+    if (nrow < r1) {
+      ns = rowptr[nrow];
+      ne = rowptr[nrow + 1];
+      fetch(ns, ne, cvn, kvn, mvn);
+    }
+    double2 pre = make_double2(0, 0), dg = make_double2(0, 0);
+    if (act) pre = EPI == 1 ? a.RH[o] : EPI == 2 ? a.SH[o] : a.B[o];
+    if (EPI == 2) dg = sweep_diag(a, row, kap);
+#pragma unroll
+    for (int h = 0; h < W / G; ++h) {
+      double2 xn[G];
+      if (h + 1 < W / G) {
+#pragma unroll
+        for (int u = 0; u < G; ++u)
+          if ((h + 1) * G + u < len && act) xn[u] = src[(size_t)bcast(cv, (h + 1) * G + u) * kSys + j];
+      }
+#pragma unroll
+      for (int u = 0; u < G; ++u) {
+        if (h * G + u < len) {
+          const double k = bcast(kv, h * G + u), m = bcast(mv, h * G + u);
+          if (act) {
+            acK.x = fma(k, xv[u].x, acK.x);
+            acK.y = fma(k, xv[u].y, acK.y);
+            acM.x = fma(m, xv[u].x, acM.x);
+            acM.y = fma(m, xv[u].y, acM.y);
+          }
+        }
+      }
+      if (h + 1 < W / G) {
+#pragma unroll
+        for (int u = 0; u < G; ++u) xv[u] = xn[u];
+      }
+    }
+    // entries past the 16th, 8 at a time
+    for (int q0 = s + W; q0 < e; q0 += 8) {
+      int c[8];
+      double k8[8], m8[8];
+      double2 x8[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const bool in = q0 + u < e;
+        const int q = in ? q0 + u : e - 1;
+        c[u] = col[q];
+        k8[u] = in ? Kc[q] : 0.0;
+        m8[u] = in ? Mc[q] : 0.0;
+      }
+      if (act) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) x8[u] = src[(size_t)c[u] * kSys + j];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          acK.x = fma(k8[u], x8[u].x, acK.x);
+          acK.y = fma(k8[u], x8[u].y, acK.y);
+          acM.x = fma(m8[u], x8[u].x, acM.x);
+          acM.y = fma(m8[u], x8[u].y, acM.y);
+        }
+      }
+    }
+    if (act) {
+      const double2 y = csub(acK, cmul(kap, acM));
+      if constexpr (EPI == 3) {
+        part[0] += cabs2(csub(pre, y));
+      } else if constexpr (EPI == 1) {
+        stnt(dst + o, y);
+        part[0] = fma(pre.x, y.x, fma(pre.y, y.y, part[0]));
+        part[1] = fma(pre.x, y.y, fma(-pre.y, y.x, part[1]));
+      } else {
+        stnt(dst + o, y);
+        const double2 sv = cmul(dg, pre);
+        part[0] = fma(y.x, y.x, fma(y.y, y.y, part[0]));
+        part[1] = fma(y.x, sv.x, fma(y.y, sv.y, part[1]));
+        part[2] = fma(y.x, sv.y, fma(-y.y, sv.x, part[2]));
+      }
+    }
+    s = ns;
+    e = ne;
+    cv = cvn;
+    kv = kvn;
+    mv = mvn;
+  }
+}
+
 // The product of a phase in the shape PF of the kernel: 1 the per-row form
-// (rows r0, r0 + rs, ...), 2 the entry stream over [r0, r1) (rs == 1).
+// (rows r0, r0 + rs, ...), 2 the entry stream over [r0, r1) (rs == 1), 3 the
+// per-row form with the next row prefetched.
 template <int PF, int EPI, int NV>
 __device__ __forceinline__ void sweep_product(const SweepArgs& a, int r0, int r1, int rs, const double2* src,
                                               double2* dst, bool act, double2 kap, double (&part)[NV]) {
   if constexpr (PF == 1) sweep_spmv<EPI, NV>(a, r0, r1, rs, src, dst, act, kap, part);
+  else if constexpr (PF == 3) sweep_spmv_pf<EPI, NV>(a, r0, r1, rs, src, dst, act, kap, part);
   else sweep_spmv_stream<EPI, NV, 4>(a, r0, r1, src, dst, act, kap, part);
 }
 
-// PF: product form (1 per row, 2 entry stream); MAP: row mapping (sweep_rows).
+// PF: product form (1 per row, 2 entry stream, 3 per row with the next row
+// prefetched); MAP: row mapping (sweep_rows).
 template <int PF, int MAP>
 __global__ __launch_bounds__(kPB) void k_sweep(SweepArgs a) {
-  static_assert(PF == 1 || MAP == 3, "the entry stream walks contiguous rows");
+  static_assert(PF != 2 || MAP == 3, "the entry stream walks contiguous rows");
   __shared__ double lds[4 * kPW * kSys];
   unsigned epoch = 0;
   BatchState* st = a.st;
@@ -499,7 +629,7 @@ __global__ __launch_bounds__(kPB) void k_sweep(SweepArgs a) {
           }
 #pragma unroll
           for (int u = 0; u < 4; ++u)
-            a.PH[(size_t)(row + u * rs) * kSys + j] = cfma(beta, pv[u], cmul(crecip(dv[u]), csub(rv[u], cmul(bo, vv[u]))));
+            stnt(a.PH + (size_t)(row + u * rs) * kSys + j, cfma(beta, pv[u], cmul(crecip(dv[u]), csub(rv[u], cmul(bo, vv[u])))));
         }
         for (; row < r1; row += rs) {
           const size_t o = (size_t)row * kSys + j;
@@ -538,7 +668,7 @@ __global__ __launch_bounds__(kPB) void k_sweep(SweepArgs a) {
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
             const double2 s = csub(rv[u], cmul(alpha, vv[u]));
-            a.SH[(size_t)(row + u * rs) * kSys + j] = cmul(crecip(dv[u]), s);
+            stnt(a.SH + (size_t)(row + u * rs) * kSys + j, cmul(crecip(dv[u]), s));
             part[0] += cabs2(s);
           }
         }
@@ -578,9 +708,9 @@ __global__ __launch_bounds__(kPB) void k_sweep(SweepArgs a) {
       if (sj == B_RUN) {
         auto upd = [&](int row, double2 sh, double2 ph, double2 xv, double2 tv, double2 h, double2 d) {
           const size_t o = (size_t)row * kSys + j;
-          a.X[o] = cfma(omega, sh, cfma(alpha, ph, xv));
+          stnt(a.X + o, cfma(omega, sh, cfma(alpha, ph, xv)));
           const double2 r = csub(cmul(d, sh), cmul(omega, tv));
-          a.R[o] = r;
+          stnt(a.R + o, r);
           part[0] += cabs2(r);
           part[1] = fma(h.x, r.x, fma(h.y, r.y, part[1]));
           part[2] = fma(h.x, r.y, fma(-h.y, r.x, part[2]));
@@ -1134,7 +1264,8 @@ struct EventPair {
 };
 
 // Sweep shapes: {product form, row mapping, 0, 0} (k_sweep<PF, MAP>).
-static const std::array<int, 4> kSweepShapes[] = {{1, 1, 0, 0}, {1, 2, 0, 0}, {1, 3, 0, 0}, {2, 3, 0, 0}};
+static const std::array<int, 4> kSweepShapes[] = {{1, 1, 0, 0}, {1, 2, 0, 0}, {1, 3, 0, 0}, {2, 3, 0, 0},
+                                                   {3, 1, 0, 0}, {3, 2, 0, 0}};
 
 static const void* sweep_kernel(const std::array<int, 4>& sh) {
   if (sh[2] != 0 || sh[3] != 0) return nullptr;
@@ -1142,6 +1273,8 @@ static const void* sweep_kernel(const std::array<int, 4>& sh) {
   if (sh[0] == 1 && sh[1] == 2) return (const void*)k_sweep<1, 2>;
   if (sh[0] == 1 && sh[1] == 3) return (const void*)k_sweep<1, 3>;
   if (sh[0] == 2 && sh[1] == 3) return (const void*)k_sweep<2, 3>;
+  if (sh[0] == 3 && sh[1] == 1) return (const void*)k_sweep<3, 1>;
+  if (sh[0] == 3 && sh[1] == 2) return (const void*)k_sweep<3, 2>;
   return nullptr;
 }
 

@@ -335,7 +335,7 @@ def krylov_solve_mixed(A: CSR, b, x=None, inner_tol=1e-4, outer_tol=1e-10, max_o
 
 SWEEP_LANES = 64
 # launch shapes the batched solvers time (and accept as `shape`)
-SWEEP_SHAPES = [(1, 1, 0, 0), (1, 2, 0, 0), (1, 3, 0, 0), (2, 3, 0, 0)]
+SWEEP_SHAPES = [(1, 1, 0, 0), (1, 2, 0, 0), (1, 3, 0, 0), (2, 3, 0, 0), (3, 1, 0, 0), (3, 2, 0, 0)]
 BLOCKDIAG_SHAPES = ([(64, r, ch, tr) for tr in (1024, 512) for r in (64, 32, 16) for ch in (4, 2)]
                     + [(32, 0, 0, tr) for tr in (1024, 512)])
 
