@@ -153,7 +153,7 @@ def bench_blas1(hk, torch, dev, stream, log, h=14_000_000, reps=21, sets=3):
     return {"blas1": {"h": h, "rotating_sets": sets, "ops": res, "paper_sizes": paper}}
 
 
-def bench_batched(hk, torch, np, dev, log, legs=("sweep", "uneven"), plain=True):
+def bench_batched(hk, torch, np, dev, log, legs=("sweep", "uneven"), plain=True, max_iter=400000):
     """Batched persistent solves vs the plain solver on the same systems
     (`legs` picks the batches; plain=False skips the plain-solver references).
 
@@ -168,13 +168,13 @@ def bench_batched(hk, torch, np, dev, log, legs=("sweep", "uneven"), plain=True)
     from synth import configs
     res = {}
     if "sweep" in legs:
-        res.update(_bench_sweep(hk, torch, np, dev, log, plain))
+        res.update(_bench_sweep(hk, torch, np, dev, log, plain, max_iter))
     if "uneven" in legs:
-        res.update(_bench_uneven(hk, torch, np, dev, log, plain))
+        res.update(_bench_uneven(hk, torch, np, dev, log, plain, max_iter))
     return res
 
 
-def _bench_sweep(hk, torch, np, dev, log, plain):
+def _bench_sweep(hk, torch, np, dev, log, plain, max_iter):
     from synth import configs
     res = {}
     c = configs.sweep48()
@@ -188,7 +188,7 @@ def _bench_sweep(hk, torch, np, dev, log, plain):
     torch.cuda.synchronize()
     tune_sweep = time.perf_counter() - ts
     ts = time.perf_counter()
-    X, infos = hk.sweep_solve(rp, cl, Kd, Md, kap, B, tol=1e-8)
+    X, infos = hk.sweep_solve(rp, cl, Kd, Md, kap, B, tol=1e-8, max_iter=max_iter)
     torch.cuda.synchronize()
     t_sweep = time.perf_counter() - ts
     its = [i["iters"] for i in infos]
@@ -221,7 +221,7 @@ def _bench_sweep(hk, torch, np, dev, log, plain):
     return res
 
 
-def _bench_uneven(hk, torch, np, dev, log, plain):
+def _bench_uneven(hk, torch, np, dev, log, plain, max_iter):
     from synth import configs
     res = {}
     systems = configs.uneven_systems()
@@ -243,7 +243,7 @@ def _bench_uneven(hk, torch, np, dev, log, plain):
     torch.cuda.synchronize()
     tune_bd = time.perf_counter() - ts
     ts = time.perf_counter()
-    _, infos = hk.blockdiag_solve(A, offs, b, tol=1e-8)
+    _, infos = hk.blockdiag_solve(A, offs, b, tol=1e-8, max_iter=max_iter)
     torch.cuda.synchronize()
     t_bd = time.perf_counter() - ts
     its = [i["iters"] for i in infos]
@@ -272,7 +272,7 @@ def _bench_uneven(hk, torch, np, dev, log, plain):
     return res
 
 
-def bench_hex(hk, torch, np, dev, stream, log, reps=20):
+def bench_hex(hk, torch, np, dev, stream, log, reps=20, max_iter=400000):
     """Q1 hexahedra on an 86^3 jittered cube (658,503 rows, 17.2M nonzeros, up
     to 27 per row -- the row length of the paper's car-cavity matrices): CSR
     product in the tuned shape, and BiCGStab / TFQMR to 1e-8."""
@@ -299,7 +299,7 @@ def bench_hex(hk, torch, np, dev, stream, log, reps=20):
     for method in ("bicgstab", "tfqmr", "bicgstab_l"):
         torch.cuda.synchronize()
         ts = time.perf_counter()
-        _, info = hk.krylov_solve(A, g, tol=1e-8, method=method, ell=8)
+        _, info = hk.krylov_solve(A, g, tol=1e-8, method=method, ell=8, max_iter=max_iter)
         torch.cuda.synchronize()
         res[method] = {"iters": info["iters"], "status": info["status"], "relres_true": info["relres_true"],
                        "time_s": round(time.perf_counter() - ts, 4)}
@@ -427,6 +427,25 @@ def bench_cpu(c, xh, nbytes, out, args, np, log):
     return res
 
 
+def copy_ceiling(hk, torch, dev):
+    """Practical streaming ceiling: 11 copies of 64 Mi complex128 elements
+    (1 GiB read and 1 GiB written each; also the calibration kernel of the
+    counter runs); returns GB/s over the last 10."""
+    ncp = 1 << 26
+    src = torch.zeros(ncp, dtype=torch.complex128, device=dev)
+    dst = torch.empty_like(src)
+    hk.zcopy(src, dst)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(10):
+        hk.zcopy(src, dst)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    del src, dst
+    return 32 * ncp / (e0.elapsed_time(e1) / 10 * 1e-3) / 1e9
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -442,9 +461,11 @@ def main():
     ap.add_argument("--plan", default="", help="force the CSR launch shape 'L,U,grid' instead of tuning")
     ap.add_argument("--solve-max-iter", type=int, default=0,
                     help="counter runs: cap the plain solve at this many iterations and skip the other solves")
-    ap.add_argument("--only", choices=["hex", "sweep", "uneven", "adjoint"], default="",
-                    help="profiling runs: this leg alone (batched legs without their plain references), "
-                         "its record printed as one JSON line")
+    ap.add_argument("--only", choices=["hex", "sweep", "uneven", "adjoint", "tfqmr", "bicgstab_l", "mixed"],
+                    default="",
+                    help="profiling runs: this leg alone (batched legs without their plain references; "
+                         "tfqmr, bicgstab_l and mixed on the 192x96x96 system), capped at --solve-max-iter "
+                         "iterations (cycles, inner iterations) when given; its record printed as one JSON line")
     ap.add_argument("--no-batched", dest="batched", action="store_false",
                     help="skip the batched sweep / uneven-batch extras")
     args = ap.parse_args()
@@ -466,13 +487,28 @@ def main():
         assert torch.cuda.is_available(), "no HIP device"
         hk.load()
         dev = "cuda:0"
+        cap = args.solve_max_iter or 400000
+        copy_gbs = copy_ceiling(hk, torch, dev)
         if args.only == "hex":
-            rec = bench_hex(hk, torch, np, dev, torch.cuda.current_stream(), log)
+            rec = bench_hex(hk, torch, np, dev, torch.cuda.current_stream(), log, max_iter=cap)
         elif args.only == "adjoint":
             rec = bench_adjoint(hk, torch, np, dev, log)
+        elif args.only in ("sweep", "uneven"):
+            rec = bench_batched(hk, torch, np, dev, log, legs=(args.only,), plain=False, max_iter=cap)
         else:
-            rec = bench_batched(hk, torch, np, dev, log, legs=(args.only,), plain=False)
-        print(json.dumps({"only": args.only, **rec}), flush=True)
+            c = configs.box192()
+            t = lambda a: torch.from_numpy(a).to(dev)
+            A = hk.CSR(t(c["rowptr"]), t(c["col"]), t(c["val"]), autotune=True)
+            g = t(c["g"])
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            if args.only == "mixed":
+                _, info = hk.krylov_solve_mixed(A, g, inner_tol=1e-4, outer_tol=1e-10, max_inner=cap)
+            else:
+                _, info = hk.krylov_solve(A, g, tol=1e-8, method=args.only, ell=8, max_iter=cap)
+            torch.cuda.synchronize()
+            rec = {args.only: {**info, "time_s": round(time.perf_counter() - ts, 4)}}
+        print(json.dumps({"only": args.only, "copy_kernel_gbs": round(copy_gbs, 1), **rec}), flush=True)
         return
 
     t0 = time.time()
@@ -528,20 +564,8 @@ def main():
 
     last_x = [None]
 
-    # practical streaming ceiling: complex128 copy of 64 Mi elements (2 GiB moved)
-    ncp = 1 << 26
-    src = torch.zeros(ncp, dtype=torch.complex128, device=dev)
-    dst = torch.empty_like(src)
-    hk.zcopy(src, dst)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(10):
-        hk.zcopy(src, dst)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    copy_gbs = 32 * ncp / (e0.elapsed_time(e1) / 10 * 1e-3) / 1e9
+    copy_gbs = copy_ceiling(hk, torch, dev)
     log(f"copy ceiling {copy_gbs:.0f} GB/s")
-    del src, dst
 
     spmv_ms = []
     for _ in range(args.warmup):
