@@ -482,6 +482,30 @@ def test_mixed_refinement_cube16(oracle):
     assert np.linalg.norm(u - x) <= 1e-8 * np.linalg.norm(x)
 
 
+def test_mixed_refinement_diagonal_closed_form(oracle):
+    """Iterative refinement with an inner solver exact to float rounding: on a
+    diagonal system Jacobi BiCGStab converges in one iteration (d = r / diag
+    rounded to complex64), so each cycle shrinks the FP64 residual by about
+    2^-24: two cycles of one inner iteration each reach 1e-10, and the result
+    is b / diag to double rounding.  A residual formed in complex64, an update
+    that replaces u instead of adding to it, or an unscaled rounding of tiny
+    residuals would stall near 1e-7 or lose the second cycle's gain."""
+    n = 64
+    rng = np.random.default_rng(12)
+    d = crandn(rng, n) + 3.0
+    b = crandn(rng, n)
+    rowptr = np.arange(n + 1, dtype=np.int32)
+    col = np.arange(n, dtype=np.int32)
+    u, info = oracle.mixed_refine(rowptr, col, d, b, inner_tol=1e-4, outer_tol=1e-10)
+    assert info["status"] == 0 and info["iters"] == 2 and info["inner_iters"] == 2, info
+    assert info["relres_true"] <= 1e-13, info
+    assert np.linalg.norm(u - b / d) <= 1e-14 * np.linalg.norm(b / d)
+    # one cycle alone stops at complex64 rounding of the solution
+    u1, i1 = oracle.mixed_refine(rowptr, col, d, b, inner_tol=1e-4, outer_tol=1e-10, max_outer=1)
+    assert i1["iters"] == 1 and i1["status"] == oracle.NOT_CONVERGED, i1
+    assert 1e-9 < i1["relres_true"] < 2 ** -22, i1
+
+
 def test_mixed_refinement_last_cycle_stops_near_the_tolerance(oracle):
     """A cycle's inner tolerance is max(inner_tol, outer_tol ||b|| / (2 ||r||)):
     the last cycle stops once it has halved the remaining distance to the
