@@ -153,7 +153,7 @@ def bench_blas1(hk, torch, dev, stream, log, h=14_000_000, reps=21, sets=3):
     return {"blas1": {"h": h, "rotating_sets": sets, "ops": res, "paper_sizes": paper}}
 
 
-def bench_batched(hk, torch, np, dev, log, legs=("sweep", "uneven"), plain=True, max_iter=400000):
+def bench_batched(hk, torch, np, dev, log, legs=("sweep", "uneven"), plain=True, max_iter=400000, shape=None):
     """Batched persistent solves vs the plain solver on the same systems
     (`legs` picks the batches; plain=False skips the plain-solver references).
 
@@ -168,13 +168,40 @@ def bench_batched(hk, torch, np, dev, log, legs=("sweep", "uneven"), plain=True,
     from synth import configs
     res = {}
     if "sweep" in legs:
-        res.update(_bench_sweep(hk, torch, np, dev, log, plain, max_iter))
+        res.update(_bench_sweep(hk, torch, np, dev, log, plain, max_iter, shape))
     if "uneven" in legs:
-        res.update(_bench_uneven(hk, torch, np, dev, log, plain, max_iter))
+        res.update(_bench_uneven(hk, torch, np, dev, log, plain, max_iter, shape))
     return res
 
 
-def _bench_sweep(hk, torch, np, dev, log, plain, max_iter):
+def sweep_phases(stamps, iters_all, n, nnz, np):
+    """Per-phase time of the sweep's iterations while every system runs
+    (iterations 2 .. the smallest iteration count), from the barrier stamps
+    (100 MHz clock): each phase's mean time, barrier included, its
+    algorithmic bytes with all 64 systems running, and those bytes' share of
+    the 8 TB/s peak over that time."""
+    V = 64 * 16 * n                  # one [node][64] complex128 vector pass
+    mat = 4 * (n + 1) + 20 * nnz     # rowptr, col, K, M of one product
+    dg = 16 * n                      # the diagonals of K and M
+    names = ("p_update", "v_product", "s_update", "t_product", "xr_update")
+    nbytes = (4 * V + dg, mat + 3 * V, 3 * V + dg, mat + 2 * V + dg, 7 * V + dg)
+    k = np.arange(2, max(iters_all, 3))
+    if len(k) < 2 or 5 * k[-1] >= stamps.shape[0] or not np.all(stamps[1:5 * k[-1] + 1] > 0):
+        return None
+    out = {"iterations": int(len(k))}
+    total = 0.0
+    for ph in range(5):
+        e = 5 * k - 4 + ph   # barrier after phase ph of iteration k (k >= 2)
+        us = float(np.mean(stamps[e] - stamps[e - 1])) * 1e-2
+        total += us
+        out[names[ph]] = {"us": round(us, 1), "bytes": nbytes[ph],
+                          "hbm_frac": round(nbytes[ph] / (us * 1e-6) / 8e12, 3)}
+    out["iteration_us"] = round(total, 1)
+    out["iteration_hbm_frac"] = round(sum(nbytes) / (total * 1e-6) / 8e12, 3)
+    return out
+
+
+def _bench_sweep(hk, torch, np, dev, log, plain, max_iter, shape):
     from synth import configs
     res = {}
     c = configs.sweep48()
@@ -184,14 +211,17 @@ def _bench_sweep(hk, torch, np, dev, log, plain, max_iter):
     Kd, Md = torch.from_numpy(c["K"]).to(dev), torch.from_numpy(c["M"]).to(dev)
     torch.cuda.synchronize()
     ts = time.perf_counter()
-    hk.sweep_solve(rp, cl, Kd, Md, kap, B, tol=1e-8, max_iter=4)
+    hk.sweep_solve(rp, cl, Kd, Md, kap, B, tol=1e-8, max_iter=4, shape=shape)
     torch.cuda.synchronize()
     tune_sweep = time.perf_counter() - ts
+    stamps = torch.zeros(8 * (max_iter + 1), dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
     ts = time.perf_counter()
-    X, infos = hk.sweep_solve(rp, cl, Kd, Md, kap, B, tol=1e-8, max_iter=max_iter)
+    X, infos = hk.sweep_solve(rp, cl, Kd, Md, kap, B, tol=1e-8, max_iter=max_iter, shape=shape, stamps=stamps)
     torch.cuda.synchronize()
     t_sweep = time.perf_counter() - ts
     its = [i["iters"] for i in infos]
+    phases = sweep_phases(stamps.cpu().numpy(), min(its), int(c["n"]), int(c["col"].shape[0]), np)
     log(f"sweep 64 systems: {t_sweep:.3f} s, iters {min(its)}..{max(its)}, "
         f"worst relres {max(i['relres_true'] for i in infos):.2e}")
     g = torch.from_numpy(c["g"]).to(dev)
@@ -210,7 +240,8 @@ def _bench_sweep(hk, torch, np, dev, log, plain, max_iter):
         it_plain.append(inf["iters"])
     if plain:
         log(f"plain every 8th frequency: {t_plain:.3f} s x 8 (iters {it_plain})")
-    res["solve_sweep"] = {"systems": 64, "n": int(c["n"]), "time_s": round(t_sweep, 4),
+    log("sweep phases", phases)
+    res["solve_sweep"] = {"systems": 64, "n": int(c["n"]), "time_s": round(t_sweep, 4), "phases": phases,
                           "shape": infos[0]["shape"], "shape_tuned": infos[0]["shape_tuned"],
                           "tune_s": round(tune_sweep, 4), "iters_min": min(its), "iters_max": max(its),
                           "us_per_iter_max": round(t_sweep / max(its) * 1e6, 2),
@@ -221,7 +252,7 @@ def _bench_sweep(hk, torch, np, dev, log, plain, max_iter):
     return res
 
 
-def _bench_uneven(hk, torch, np, dev, log, plain, max_iter):
+def _bench_uneven(hk, torch, np, dev, log, plain, max_iter, shape):
     from synth import configs
     res = {}
     systems = configs.uneven_systems()
@@ -239,11 +270,11 @@ def _bench_uneven(hk, torch, np, dev, log, plain, max_iter):
     b = torch.from_numpy(np.concatenate(bs)).to(dev)
     torch.cuda.synchronize()
     ts = time.perf_counter()
-    hk.blockdiag_solve(A, offs, b, tol=1e-8, max_iter=4)
+    hk.blockdiag_solve(A, offs, b, tol=1e-8, max_iter=4, shape=shape)
     torch.cuda.synchronize()
     tune_bd = time.perf_counter() - ts
     ts = time.perf_counter()
-    _, infos = hk.blockdiag_solve(A, offs, b, tol=1e-8, max_iter=max_iter)
+    _, infos = hk.blockdiag_solve(A, offs, b, tol=1e-8, max_iter=max_iter, shape=shape)
     torch.cuda.synchronize()
     t_bd = time.perf_counter() - ts
     its = [i["iters"] for i in infos]
@@ -272,7 +303,7 @@ def _bench_uneven(hk, torch, np, dev, log, plain, max_iter):
     return res
 
 
-def bench_hex(hk, torch, np, dev, stream, log, reps=20, max_iter=400000):
+def bench_hex(hk, torch, np, dev, stream, log, reps=20, max_iter=400000, plan=None, solver_plan=None):
     """Q1 hexahedra on an 86^3 jittered cube (658,503 rows, 17.2M nonzeros, up
     to 27 per row -- the row length of the paper's car-cavity matrices): CSR
     product in the tuned shape, and BiCGStab / TFQMR to 1e-8."""
@@ -280,7 +311,8 @@ def bench_hex(hk, torch, np, dev, stream, log, reps=20, max_iter=400000):
     c = configs.hex_box()
     n, nnz = int(c["n"]), int(c["col"].shape[0])
     t = lambda a: torch.from_numpy(a).to(dev)
-    A = hk.CSR(t(c["rowptr"]), t(c["col"]), t(c["val"]), autotune=True)
+    A = hk.CSR(t(c["rowptr"]), t(c["col"]), t(c["val"]), autotune=plan is None)
+    pin(A, plan, solver_plan)
     x = t(np.random.default_rng(3).standard_normal(n) + 0j)
     y = torch.empty_like(x)
     A.spmv(x, y)
@@ -427,6 +459,19 @@ def bench_cpu(c, xh, nbytes, out, args, np, log):
     return res
 
 
+def ints(text):
+    return tuple(int(v) for v in text.split(",")) if text else None
+
+
+def pin(A, plan, solver_plan):
+    """Counter runs: fix the CSR shape and the solvers' fused-product shape
+    instead of timing candidates under the profiler."""
+    if plan:
+        A.set_plan(*plan)
+    if solver_plan:
+        A.set_solver_plan(*solver_plan)
+
+
 def copy_ceiling(hk, torch, dev):
     """Practical streaming ceiling: 11 copies of 64 Mi complex128 elements
     (1 GiB read and 1 GiB written each; also the calibration kernel of the
@@ -459,6 +504,10 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-solve", action="store_true", help="CSR products only (profiling runs)")
     ap.add_argument("--plan", default="", help="force the CSR launch shape 'L,U,grid' instead of tuning")
+    ap.add_argument("--solver-plan", default="",
+                    help="force the solvers' fused-product shape 'rows_per_wave,waves,grid,paired' (counter runs)")
+    ap.add_argument("--batch-shape", default="",
+                    help="force the batched solvers' launch shape 'a,b,c,d' (counter runs)")
     ap.add_argument("--solve-max-iter", type=int, default=0,
                     help="counter runs: cap the plain solve at this many iterations and skip the other solves")
     ap.add_argument("--only", choices=["hex", "sweep", "uneven", "adjoint", "tfqmr", "bicgstab_l", "mixed"],
@@ -490,15 +539,18 @@ def main():
         cap = args.solve_max_iter or 400000
         copy_gbs = copy_ceiling(hk, torch, dev)
         if args.only == "hex":
-            rec = bench_hex(hk, torch, np, dev, torch.cuda.current_stream(), log, max_iter=cap)
+            rec = bench_hex(hk, torch, np, dev, torch.cuda.current_stream(), log, max_iter=cap,
+                            plan=ints(args.plan), solver_plan=ints(args.solver_plan))
         elif args.only == "adjoint":
             rec = bench_adjoint(hk, torch, np, dev, log)
         elif args.only in ("sweep", "uneven"):
-            rec = bench_batched(hk, torch, np, dev, log, legs=(args.only,), plain=False, max_iter=cap)
+            rec = bench_batched(hk, torch, np, dev, log, legs=(args.only,), plain=False, max_iter=cap,
+                                shape=ints(args.batch_shape))
         else:
             c = configs.box192()
             t = lambda a: torch.from_numpy(a).to(dev)
-            A = hk.CSR(t(c["rowptr"]), t(c["col"]), t(c["val"]), autotune=True)
+            A = hk.CSR(t(c["rowptr"]), t(c["col"]), t(c["val"]), autotune=not args.plan)
+            pin(A, ints(args.plan), ints(args.solver_plan))
             g = t(c["g"])
             torch.cuda.synchronize()
             ts = time.perf_counter()
@@ -534,8 +586,8 @@ def main():
     Acsr = hk.CSR(rowptr, col, val, autotune=not args.plan, compact_cols=False)
     A = hk.CSR(rowptr, col, val, autotune=not args.plan)
     if args.plan:
-        Acsr.set_plan(*[int(v) for v in args.plan.split(",")])
-        A.set_plan(*[int(v) for v in args.plan.split(",")])
+        Acsr.set_plan(*ints(args.plan))
+    pin(A, ints(args.plan), ints(args.solver_plan))
     plan = Acsr.plan()
     col_bytes = Acsr.info()["col_bytes"]
     log("plan", plan, "column bytes", col_bytes, "| solver handle plan", A.plan(), "column bytes", A.info()["col_bytes"])

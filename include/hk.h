@@ -276,6 +276,15 @@ int hk_krylov_solve_mixed(hk_csr A, const void* d_b, void* d_x, double inner_tol
  * HK_BARRIER_SPIN_TICKS, read at each call, sets it in 100 MHz ticks) raises
  * an abort flag, every workgroup leaves at its next barrier, and the call
  * frees its workspace and returns HK_EHIP with "grid barrier timed out".
+ * With opts->d_history non-null (device, 8 (max_iter + 1) doubles, caller
+ * owned) the solve records barrier times in it: entry e (e >= 1, the e-th
+ * barrier of the launch) = the device's 100 MHz wall clock when the last
+ * workgroup arrived; entries of barriers that did not happen are left
+ * untouched.  The sweep's barriers are: 1 after the start phase; then per
+ * iteration (4 in the first, which has no p update) after the p update, the
+ * v product, the s update, the t product and the x/r update; then one
+ * after the true-residual product.  The time between two entries is the
+ * phase between those barriers, the barrier included.
  */
 
 /*

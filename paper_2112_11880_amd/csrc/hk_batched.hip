@@ -435,8 +435,9 @@ __device__ __forceinline__ void sweep_spmv_stream(const SweepArgs& a, int ra, in
 // epilogue operand are loaded behind the first gathers; then the
 // multiply-adds, with each
 // entry's column and coefficients broadcast by readlane.  The gathers go
-// in two rounds of 8, the second issued before the first round's sums (16
-// gathers at once spill registers).  Entries past the
+// in rounds of 4, each issued before the previous round's sums (16 gathers
+// at once spill registers; rounds of 8 spilled 25 VGPRs and ran 667 against
+// 663 us per 64-system iteration).  Entries past the
 // 16th (longer rows) go in rounds of 8 through scalar loads as in
 // sweep_spmv.  The matrix loads run in every lane whatever its system's
 // state (the broadcasts read lanes 0..15); gathers, sums and stores only in
@@ -444,7 +445,7 @@ __device__ __forceinline__ void sweep_spmv_stream(const SweepArgs& a, int ra, in
 template <int EPI, int NV>
 __device__ __forceinline__ void sweep_spmv_pf(const SweepArgs& a, int r0, int r1, int rs, const double2* src,
                                               double2* dst, bool act, double2 kap, double (&part)[NV]) {
-  constexpr int W = 16, G = 8;  // entries prefetched per row; gathers per round
+  constexpr int W = 16, G = 4;  // entries prefetched per row; gathers per round
   const int j = threadIdx.x & 63;
   if (__ballot(act) == 0) return;  // uniform: no running system
   const cptr<int> rowptr = as_const(a.rowptr), col = as_const(a.col);
@@ -1403,6 +1404,9 @@ extern "C" int hk_sweep_solve(int64_t n, int64_t nnz, const int32_t* d_rowptr, c
     a.maxit = maxit;
     GridBar bar0{};
     bar0.spin_limit = spin;
+    // barrier stamps for the solve itself, not for the tuner's trials
+    bar0.stamps = ev ? nullptr : opts->d_history;
+    bar0.nstamps = bar0.stamps ? 8ull * ((unsigned long long)maxit + 1) : 0;
     hipError_t e2 = hipMemcpyAsync(a.bar, &bar0, sizeof(GridBar), hipMemcpyHostToDevice, s);
     if (e2 == hipSuccess) e2 = hipMemsetAsync(a.st, 0, sizeof(BatchState), s);
     if (e2 == hipSuccess && ev) e2 = hipEventRecord(ev->e0, s);
@@ -1581,6 +1585,9 @@ extern "C" int hk_blockdiag_solve(hk_csr A, int32_t nsys, const int64_t* row_off
     init.ntiles_active = nt;
     GridBar bar0{};
     bar0.spin_limit = spin;
+    // barrier stamps for the solve itself, not for the tuner's trials
+    bar0.stamps = ev ? nullptr : opts->d_history;
+    bar0.nstamps = bar0.stamps ? 8ull * ((unsigned long long)maxit + 1) : 0;
     hipError_t e2 = hipMemcpyAsync(a.act_sys, tsys.data(), 4 * (size_t)nt, hipMemcpyHostToDevice, s);
     if (e2 == hipSuccess) e2 = hipMemcpyAsync(a.act_row0, trow.data(), 4 * (size_t)nt, hipMemcpyHostToDevice, s);
     if (e2 == hipSuccess) e2 = hipMemcpyAsync(a.act_end, tend.data(), 4 * (size_t)nt, hipMemcpyHostToDevice, s);

@@ -38,7 +38,11 @@ struct GridBar {
   unsigned release;      // last epoch released by workgroup 0
   int abort;
   unsigned long long spin_limit;  // wall-clock ticks a wait may take before it aborts
-  unsigned pad[60];      // keep release/abort on their own 256-byte line
+  // optional: stamps[e] = wall clock (100 MHz ticks) when every workgroup had
+  // arrived at barrier e, for e < nstamps (null: none)
+  double* stamps;
+  unsigned long long nstamps;
+  unsigned pad[56];      // keep release/abort on their own 256-byte line
   unsigned arrive[kBarMaxBlocks];  // last epoch each workgroup arrived at
 };
 
@@ -92,6 +96,7 @@ __device__ __forceinline__ bool barrier_last(GridBar* bar, unsigned& epoch, F&& 
     if (threadIdx.x == 0) {
       s_stop = ld_relaxed_i32(&bar->abort);
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // every workgroup's writes
+      if (bar->stamps && e < bar->nstamps) bar->stamps[e] = (double)wall_clock64();
     }
     __syncthreads();
     if (!s_stop) on_last();

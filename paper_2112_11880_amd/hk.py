@@ -340,14 +340,15 @@ BLOCKDIAG_SHAPES = ([(64, r, ch, tr) for tr in (1024, 512) for r in (64, 32, 16)
                     + [(32, 0, 0, tr) for tr in (1024, 512)])
 
 
-def sweep_solve(rowptr, col, K, M, kappa, B, tol=1e-8, max_iter=400000, shape=None):
+def sweep_solve(rowptr, col, K, M, kappa, B, tol=1e-8, max_iter=400000, shape=None, stamps=None):
     """Frequency sweep: solve (K - kappa_j M) X[:, j] = B[:, j] for j < len(kappa).
 
     rowptr/col int32, K/M float64 device tensors on one pattern; kappa a
     sequence of complex numbers (<= 64); B an (n, 64) complex128 device tensor
     (columns >= len(kappa) ignored).  shape: a launch shape (product form, row
-    mapping, 0, 0) to use instead of the tuned one.  Returns (X, list of info
-    dicts).
+    mapping, 0, 0) to use instead of the tuned one.  stamps: a float64 device tensor
+    of 8 (max_iter + 1) entries that receives the barrier times (100 MHz
+    clock ticks, see hk.h).  Returns (X, list of info dicts).
     """
     nsys = len(kappa)
     _cvec(rowptr, torch.int32, name="rowptr")
@@ -362,6 +363,8 @@ def sweep_solve(rowptr, col, K, M, kappa, B, tol=1e-8, max_iter=400000, shape=No
     kap = (C.c_double * (2 * nsys))(*[v for z in kappa for v in (complex(z).real, complex(z).imag)])
     infos = (SolveInfo * nsys)()
     o = _opts(tol, max_iter, True, 0, False, None, shape=shape)
+    if stamps is not None:
+        o.d_history = _ptr(_cvec(stamps, torch.float64, name="stamps", n=8 * (int(max_iter) + 1)))
     _check(load().hk_sweep_solve(n, col.numel(), _ptr(rowptr), _ptr(col), _ptr(K), _ptr(M), nsys, kap,
                                  _ptr(B), _ptr(X), C.byref(o), infos, _stream()), allow_positive=True)
     return X, [i.as_dict() for i in infos]

@@ -140,6 +140,27 @@ def test_sweep_every_shape_large(hk, oracle):
     sweep_iterates_every_shape(hk, oracle, p, kap, B, "84^3")
 
 
+def test_sweep_barrier_stamps(hk, oracle):
+    """The barrier-time record: one entry per grid barrier of the solve (the
+    start phase, 4 in the first iteration, 5 in each later one, the final
+    residual), non-decreasing, the rest untouched; the solution is the same
+    as without the record."""
+    p, kap, B = sweep_inputs(6, 5)
+    args = (dev(p.rowptr), dev(p.col), dev(p.K), dev(p.M), kap, dev(B))
+    say("sweep stamps")
+    X0, i0 = hk.sweep_solve(*args, tol=1e-10, max_iter=500)
+    stamps = torch.zeros(8 * 501, dtype=torch.float64, device=DEV)
+    X1, i1 = hk.sweep_solve(*args, tol=1e-10, max_iter=500, stamps=stamps)
+    assert np.array_equal(host(X0), host(X1)) and [i["iters"] for i in i0] == [i["iters"] for i in i1]
+    st = host(stamps)
+    loops = max(i["iters"] for i in i1)
+    nbar = 5 * loops + 1
+    assert st[0] == 0 and np.all(st[1:nbar + 1] > 0) and np.all(st[nbar + 1:] == 0), (loops, np.count_nonzero(st))
+    assert np.all(np.diff(st[1:nbar + 1]) >= 0)
+    with pytest.raises(hk.HKError):
+        hk.sweep_solve(*args, tol=1e-10, max_iter=500, stamps=torch.zeros(10, dtype=torch.float64, device=DEV))
+
+
 def blockdiag_inputs(sizes, seed=2):
     rng = np.random.default_rng(seed)
     rows, cols, vals, bs, offs = [], [], [], [], [0]
