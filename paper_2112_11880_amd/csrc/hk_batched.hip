@@ -115,6 +115,32 @@ __device__ __forceinline__ void final_partials64(const double* partials, double 
 
 __device__ __forceinline__ double2 crecip(double2 d) { return cdiv(make_double2(1.0, 0.0), d); }
 
+// Copies of a workgroup's LDS copy of the state to memory, by wave 0 (the
+// wave whose thread 0 fences before a barrier's release): the fields the
+// phases read, or all of it.  Called by every thread of the workgroup.
+__device__ __forceinline__ void publish_phase_state(BatchState* g, const BatchState& l) {
+  __syncthreads();
+  const int j = threadIdx.x;
+  if (j < kSys) {
+    g->status[j] = l.status[j];
+    g->alpha[j] = l.alpha[j];
+    g->omega[j] = l.omega[j];
+    g->beta[j] = l.beta[j];
+    if (j == 0) {
+      g->running = l.running;
+      g->iter = l.iter;
+    }
+  }
+}
+__device__ __forceinline__ void publish_state(BatchState* g, const BatchState& l) {
+  __syncthreads();
+  if (threadIdx.x < kWave) {
+    const unsigned* src = reinterpret_cast<const unsigned*>(&l);
+    unsigned* dst = reinterpret_cast<unsigned*>(g);
+    for (int i = threadIdx.x; i < (int)(sizeof(BatchState) / 4); i += kWave) dst[i] = src[i];
+  }
+}
+
 // Scalar updates shared by both batch shapes (thread j = system j).
 __device__ __forceinline__ void upd_sigma(BatchState* st, int j, double2 sigma) {
   if (st->status[j] != B_RUN) return;
@@ -307,6 +333,163 @@ __device__ __forceinline__ void sweep_rows(int n, int G, int& r0, int& r1, int& 
   r0 = X0 + (int)(((long long)(X1 - X0) * wi) / nw);
   r1 = X0 + (int)(((long long)(X1 - X0) * (wi + 1)) / nw);
   rs = 1;
+}
+
+// ------------------------------------------------ claimed rows (vector phases)
+//
+// The element-wise phases (p, s and x/r updates) stream their rows with no
+// reuse, and the memory system serves the 16 waves of a workgroup unevenly:
+// with a fixed share of rows per wave, the first waves of a workgroup were
+// done after ~40% of the phase and the last ones set the workgroup's time
+// (e.g. 46 to 161 us for the x/r update).  So the waves claim the
+// workgroup's rows in units of kUnitRows through an LDS counter.  The rows
+// of a workgroup are the rows its waves own in the product phases (sweep_rows),
+// taken in the order row(q) = base + q % kPW + (q / kPW) step, q < nrows.
+//
+// A reduction over claimed rows stays bitwise reproducible: each unit's sum
+// is formed in row order and parked in an LDS ring (kUnitRing units), and
+// the units are added in unit order, a batch of kUnitBatch at a time, by the
+// wave that completes the batch, once every earlier batch is added.  A unit
+// waits for its ring slot only if the batch kUnitRing / kUnitBatch before it
+// is not added yet.  Every wait ends: the batches before any waiting unit
+// hold only units that are claimed already (claims go in order) and need
+// no slot; the waits also carry the grid barrier's time limit.
+constexpr int kUnitRows = 4;
+constexpr int kUnitBatch = 16;
+constexpr int kUnitRing = 64;
+constexpr int kUnitNV = 3;  // at most this many sums per lane
+
+struct WgRows {
+  int base, step, nrows;
+};
+
+template <int MAP>
+__device__ __forceinline__ WgRows sweep_wg_rows(int n, int G) {
+  int base, step, end;
+  if (MAP == 2) {
+    base = blockIdx.x * kPW;
+    step = G * kPW;
+    end = n;
+  } else {
+    const int x = blockIdx.x % kXcds, i = blockIdx.x / kXcds;
+    const int nbx = (G - x + kXcds - 1) / kXcds;
+    const int X0 = (int)(((long long)x * n) / kXcds), X1 = (int)(((long long)(x + 1) * n) / kXcds);
+    if (MAP == 1) {
+      base = X0 + i * kPW;
+      step = nbx * kPW;
+      end = X1;
+    } else {
+      const int nw = nbx * kPW;
+      base = X0 + (int)(((long long)(X1 - X0) * (i * kPW)) / nw);
+      end = X0 + (int)(((long long)(X1 - X0) * (i * kPW + kPW)) / nw);
+      step = kPW;
+    }
+  }
+  // full groups of kPW rows, then a partial one
+  const int L = end - base;
+  const int full = L >= kPW ? (L - kPW) / step + 1 : 0;
+  const int rest = min(max(L - full * step, 0), kPW);
+  return WgRows{base, step, full * kPW + rest};
+}
+
+struct UnitSync {
+  int claim;             // 64 x the next unit to hand out
+  int added;             // batches added to acc so far
+  int count[kUnitRing / kUnitBatch];  // 64 x the units finished per batch in the ring
+};
+
+__device__ __forceinline__ int lds_load_acq(const int* p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Waits until *p >= v (p in LDS) within the grid barrier's time limit; past
+// it the wave raises the abort flag and goes on, and the kernel stops at its
+// next grid barrier.
+__device__ __forceinline__ void lds_wait_ge(const int* p, int v, GridBar* bar) {
+  if (lds_load_acq(p) >= v) return;
+  const unsigned long long t0 = wall_clock64();
+  while (lds_load_acq(p) < v) {
+    __builtin_amdgcn_s_sleep(1);
+    if (wall_clock64() - t0 > bar->spin_limit) {
+      atomicExch(&bar->abort, 1);
+      return;
+    }
+  }
+}
+
+// Resets the claim state (all threads; ends with a workgroup barrier).
+__device__ __forceinline__ void units_reset(UnitSync& us, double* acc) {
+  if (threadIdx.x == 0) {
+    us.claim = 0;
+    us.added = 0;
+    for (int b = 0; b < kUnitRing / kUnitBatch; ++b) us.count[b] = 0;
+  }
+  if (threadIdx.x < kUnitNV * kSys) acc[threadIdx.x] = 0;
+  __syncthreads();
+}
+
+// Runs body(row0, cnt, part) for every unit of the workgroup's rows, claimed
+// by the calling waves; part[NV] (zeroed per unit) takes the unit's sums.
+// With NV > 0, acc[k * 64 + lane] ends as the workgroup's sums in unit order
+// (after the closing workgroup barrier).  Wave-uniform; all threads call it.
+template <int NV, class F>
+__device__ __forceinline__ void claim_units(const WgRows& wr, UnitSync& us, double* ring, double* acc, GridBar* bar,
+                                            F&& body) {
+  static_assert(NV <= kUnitNV, "too many sums");
+  static_assert(kPW % kUnitRows == 0, "a unit stays within a group of rows");
+  const int j = threadIdx.x & 63;
+  const int nunits = (wr.nrows + kUnitRows - 1) / kUnitRows;
+  // Counters are advanced by every lane of the wave (one LDS instruction, so
+  // the wave's results are consecutive and / 64 names the unit), not by lane 0
+  // alone: the compiler may restructure a loop around a lane-0 branch so that
+  // lane 0 leaves it apart from the other lanes, and a broadcast of a value
+  // only lane 0 holds then reads another lane's.
+  for (;;) {
+    const int u = __builtin_amdgcn_readfirstlane(atomicAdd(&us.claim, 1)) / kWave;
+    if (u >= nunits) break;
+    const int q = u * kUnitRows;
+    const int row0 = wr.base + q % kPW + (q / kPW) * wr.step;
+    const int cnt = min(kUnitRows, wr.nrows - q);
+    double part[NV > 0 ? NV : 1];
+#pragma unroll
+    for (int k = 0; k < (NV > 0 ? NV : 1); ++k) part[k] = 0;
+    body(row0, cnt, part);
+    if constexpr (NV > 0) {
+      const int b = u / kUnitBatch, slot = u % kUnitRing;
+      // the ring slot is free once the batch kUnitRing / kUnitBatch earlier is added
+      lds_wait_ge(&us.added, b - (kUnitRing / kUnitBatch - 1), bar);
+#pragma unroll
+      for (int k = 0; k < NV; ++k) ring[(slot * kUnitNV + k) * kSys + j] = part[k];
+      const int done = __builtin_amdgcn_readfirstlane(__hip_atomic_fetch_add(
+                           &us.count[b % (kUnitRing / kUnitBatch)], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP)) /
+                           kWave + 1;
+      if (done == min(kUnitBatch, nunits - b * kUnitBatch)) {
+        // this wave completed batch b: add it once batches 0 .. b-1 are in
+        lds_wait_ge(&us.added, b, bar);
+        const int s0 = (b * kUnitBatch) % kUnitRing;
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+          double t = ring[(s0 * kUnitNV + k) * kSys + j];
+          for (int m = 1; m < done; ++m) t += ring[((s0 + m) * kUnitNV + k) * kSys + j];
+          acc[k * kSys + j] += t;
+        }
+        // every lane stores the same values
+        us.count[b % (kUnitRing / kUnitBatch)] = 0;
+        __hip_atomic_store(&us.added, b + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// The workgroup's sums from claim_units to partials[(k*G + block)*64 + lane].
+template <int NV>
+__device__ __forceinline__ void store_unit_partials(const double* acc, double* partials) {
+  const int j = threadIdx.x & 63, G = gridDim.x;
+  if (threadIdx.x < kSys) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) partials[((size_t)k * G + blockIdx.x) * kSys + j] = acc[k * kSys + j];
+  }
 }
 
 // Value of `v` in lane l (wave-uniform), in every lane.
@@ -572,13 +755,23 @@ __device__ __forceinline__ void sweep_product(const SweepArgs& a, int r0, int r1
 template <int PF, int MAP>
 __global__ __launch_bounds__(kPB) void k_sweep(SweepArgs a) {
   static_assert(PF != 2 || MAP == 3, "the entry stream walks contiguous rows");
-  __shared__ double lds[4 * kPW * kSys];
+  static_assert(kUnitRing * kUnitNV >= 4 * kPW, "lds holds the unit ring and the per-wave sums");
+  __shared__ double lds[kUnitRing * kUnitNV * kSys];
+  __shared__ double uacc[kUnitNV * kSys];
+  __shared__ UnitSync us;
+  // Workgroup 0 keeps every system's scalars in LDS, so that its updates at
+  // the barriers do not wait on memory (a chain of dependent loads after the
+  // barrier's cache invalidate cost several us per barrier); after each
+  // update it copies the fields the phases read to a.st, and all of the state
+  // at the end.  The phases read a.st.
+  __shared__ BatchState ls;
   unsigned epoch = 0;
   BatchState* st = a.st;
   const int j = threadIdx.x & 63;
   const int G = gridDim.x;
   int r0, r1, rs;
   sweep_rows<MAP>(a.n, G, r0, r1, rs);
+  const WgRows wr = sweep_wg_rows<MAP>(a.n, G);
   const bool lane_ok = j < a.nsys;
   const double2 kap = lane_ok ? a.kap[j] : make_double2(0, 0);
 
@@ -598,17 +791,21 @@ __global__ __launch_bounds__(kPB) void k_sweep(SweepArgs a) {
     if (barrier_last(a.bar, epoch, [&] {
           double tot[1];
           final_partials64<1>(a.partials, tot, lds);
+          for (int i = threadIdx.x; i < (int)(sizeof(BatchState) / 4); i += blockDim.x)
+            reinterpret_cast<unsigned*>(&ls)[i] = 0;
+          __syncthreads();
           if (threadIdx.x < kSys) {
-            if (threadIdx.x < a.nsys) init_sys(st, threadIdx.x, tot[0], a.tol, a.maxit);
-            else st->status[threadIdx.x] = HK_OK;
+            if (threadIdx.x < a.nsys) init_sys(&ls, threadIdx.x, tot[0], a.tol, a.maxit);
+            else ls.status[threadIdx.x] = HK_OK;
           }
-          if (threadIdx.x == 0) { st->iter = 1; st->maxit = a.maxit; st->changed = 0; }
+          if (threadIdx.x == 0) { ls.iter = 1; ls.maxit = a.maxit; ls.changed = 0; }
           __syncthreads();
           if (threadIdx.x == 0) {
             int run = 0;
-            for (int u = 0; u < a.nsys; ++u) run += st->status[u] == B_RUN;
-            st->running = run;
+            for (int u = 0; u < a.nsys; ++u) run += ls.status[u] == B_RUN;
+            ls.running = run;
           }
+          publish_state(st, ls);
         }))
       return;
   }
@@ -619,25 +816,23 @@ __global__ __launch_bounds__(kPB) void k_sweep(SweepArgs a) {
     // ---- phat = D^-1 (r - beta omega v) + beta phat
     if (it > 1) {
       const double2 beta = st->beta[j], bo = cmul(st->beta[j], st->omega[j]);
-      if (act) {
-        int row = r0;
-        for (; row + 3 * rs < r1; row += 4 * rs) {
-          double2 rv[4], vv[4], pv[4], dv[4];
+      units_reset(us, uacc);
+      claim_units<0>(wr, us, lds, uacc, a.bar, [&](int row0, int cnt, auto&) {
+        double2 rv[kUnitRows] = {}, vv[kUnitRows] = {}, pv[kUnitRows] = {}, dv[kUnitRows];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const size_t o = (size_t)(row + u * rs) * kSys + j;
-            rv[u] = a.R[o]; vv[u] = a.V[o]; pv[u] = a.PH[o]; dv[u] = sweep_diag(a, row + u * rs, kap);
+        for (int u = 0; u < kUnitRows; ++u) {
+          const int r = row0 + min(u, cnt - 1);
+          const size_t o = (size_t)r * kSys + j;
+          if (act) {
+            rv[u] = a.R[o]; vv[u] = a.V[o]; pv[u] = a.PH[o];
           }
+          dv[u] = sweep_diag(a, r, kap);
+        }
 #pragma unroll
-          for (int u = 0; u < 4; ++u)
-            stnt(a.PH + (size_t)(row + u * rs) * kSys + j, cfma(beta, pv[u], cmul(crecip(dv[u]), csub(rv[u], cmul(bo, vv[u])))));
-        }
-        for (; row < r1; row += rs) {
-          const size_t o = (size_t)row * kSys + j;
-          const double2 w = csub(a.R[o], cmul(bo, a.V[o]));
-          a.PH[o] = cfma(beta, a.PH[o], cmul(crecip(sweep_diag(a, row, kap)), w));
-        }
-      }
+        for (int u = 0; u < kUnitRows; ++u)
+          if (act && u < cnt)
+            stnt(a.PH + (size_t)(row0 + u) * kSys + j, cfma(beta, pv[u], cmul(crecip(dv[u]), csub(rv[u], cmul(bo, vv[u])))));
+      });
       if (barrier_last(a.bar, epoch, [] {})) return;
     }
     // ---- v = A phat ; sigma = rhat^H v
@@ -648,43 +843,42 @@ __global__ __launch_bounds__(kPB) void k_sweep(SweepArgs a) {
       if (barrier_last(a.bar, epoch, [&] {
             double tot[2];
             final_partials64<2>(a.partials, tot, lds);
-            if (threadIdx.x < a.nsys) upd_sigma(st, threadIdx.x, make_double2(tot[0], tot[1]));
+            if (threadIdx.x < a.nsys) upd_sigma(&ls, threadIdx.x, make_double2(tot[0], tot[1]));
+            publish_phase_state(st, ls);
           }))
         return;
     }
     act = lane_ok && st->status[j] == B_RUN;
     // ---- s = r - alpha v ; shat = D^-1 s ; ||s||^2
     {
-      double part[1] = {0};
       const double2 alpha = st->alpha[j];
-      if (act) {
-        int row = r0;
-        for (; row + 3 * rs < r1; row += 4 * rs) {
-          double2 rv[4], vv[4], dv[4];
+      units_reset(us, uacc);
+      claim_units<1>(wr, us, lds, uacc, a.bar, [&](int row0, int cnt, auto& part) {
+        double2 rv[kUnitRows] = {}, vv[kUnitRows] = {}, dv[kUnitRows];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const size_t o = (size_t)(row + u * rs) * kSys + j;
-            rv[u] = a.R[o]; vv[u] = a.V[o]; dv[u] = sweep_diag(a, row + u * rs, kap);
+        for (int u = 0; u < kUnitRows; ++u) {
+          const int r = row0 + min(u, cnt - 1);
+          const size_t o = (size_t)r * kSys + j;
+          if (act) {
+            rv[u] = a.R[o]; vv[u] = a.V[o];
           }
+          dv[u] = sweep_diag(a, r, kap);
+        }
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < kUnitRows; ++u) {
+          if (act && u < cnt) {
             const double2 s = csub(rv[u], cmul(alpha, vv[u]));
-            stnt(a.SH + (size_t)(row + u * rs) * kSys + j, cmul(crecip(dv[u]), s));
+            stnt(a.SH + (size_t)(row0 + u) * kSys + j, cmul(crecip(dv[u]), s));
             part[0] += cabs2(s);
           }
         }
-        for (; row < r1; row += rs) {
-          const size_t o = (size_t)row * kSys + j;
-          const double2 s = csub(a.R[o], cmul(alpha, a.V[o]));
-          a.SH[o] = cmul(crecip(sweep_diag(a, row, kap)), s);
-          part[0] += cabs2(s);
-        }
-      }
-      store_partials64<1>(part, a.partials, lds);
+      });
+      store_unit_partials<1>(uacc, a.partials);
       if (barrier_last(a.bar, epoch, [&] {
             double tot[1];
             final_partials64<1>(a.partials, tot, lds);
-            if (threadIdx.x < a.nsys) upd_s(st, threadIdx.x, tot[0]);
+            if (threadIdx.x < a.nsys) upd_s(&ls, threadIdx.x, tot[0]);
+            publish_phase_state(st, ls);
           }))
         return;
     }
@@ -697,63 +891,67 @@ __global__ __launch_bounds__(kPB) void k_sweep(SweepArgs a) {
       if (barrier_last(a.bar, epoch, [&] {
             double tot[3];
             final_partials64<3>(a.partials, tot, lds);
-            if (threadIdx.x < a.nsys) upd_omega(st, threadIdx.x, tot[0], make_double2(tot[1], tot[2]));
+            if (threadIdx.x < a.nsys) upd_omega(&ls, threadIdx.x, tot[0], make_double2(tot[1], tot[2]));
+            publish_phase_state(st, ls);
           }))
         return;
     }
     // ---- x += alpha phat + omega shat ; r = s - omega t ; ||r||^2 ; rhat^H r
     {
       const int sj = lane_ok ? st->status[j] : HK_OK;
-      double part[3] = {0, 0, 0};
+      const bool run = sj == B_RUN, half = sj == B_HALF || sj == B_TAUBD;
       const double2 alpha = st->alpha[j], omega = st->omega[j];
-      if (sj == B_RUN) {
-        auto upd = [&](int row, double2 sh, double2 ph, double2 xv, double2 tv, double2 h, double2 d) {
-          const size_t o = (size_t)row * kSys + j;
-          stnt(a.X + o, cfma(omega, sh, cfma(alpha, ph, xv)));
-          const double2 r = csub(cmul(d, sh), cmul(omega, tv));
-          stnt(a.R + o, r);
-          part[0] += cabs2(r);
-          part[1] = fma(h.x, r.x, fma(h.y, r.y, part[1]));
-          part[2] = fma(h.x, r.y, fma(-h.y, r.x, part[2]));
-        };
-        int row = r0;
-        for (; row + rs < r1; row += 2 * rs) {
-          double2 sh[2], ph[2], xv[2], tv[2], hv[2], dv[2];
+      units_reset(us, uacc);
+      claim_units<3>(wr, us, lds, uacc, a.bar, [&](int row0, int cnt, auto& part) {
+        // two rows at a time (five loads each)
+#pragma unroll
+        for (int h = 0; h < kUnitRows; h += 2) {
+          double2 sh[2] = {}, ph[2] = {}, xv[2] = {}, tv[2] = {}, hv[2] = {}, dv[2];
 #pragma unroll
           for (int u = 0; u < 2; ++u) {
-            const size_t o = (size_t)(row + u * rs) * kSys + j;
-            sh[u] = a.SH[o]; ph[u] = a.PH[o]; xv[u] = a.X[o]; tv[u] = a.T[o]; hv[u] = a.RH[o];
-            dv[u] = sweep_diag(a, row + u * rs, kap);
+            const int r = row0 + min(h + u, cnt - 1);
+            const size_t o = (size_t)r * kSys + j;
+            if (run) {
+              sh[u] = a.SH[o]; ph[u] = a.PH[o]; xv[u] = a.X[o]; tv[u] = a.T[o]; hv[u] = a.RH[o];
+            } else if (half) {
+              ph[u] = a.PH[o]; xv[u] = a.X[o];
+            }
+            dv[u] = sweep_diag(a, r, kap);
           }
 #pragma unroll
-          for (int u = 0; u < 2; ++u) upd(row + u * rs, sh[u], ph[u], xv[u], tv[u], hv[u], dv[u]);
+          for (int u = 0; u < 2; ++u) {
+            if (h + u >= cnt) continue;
+            const size_t o = (size_t)(row0 + h + u) * kSys + j;
+            if (run) {
+              stnt(a.X + o, cfma(omega, sh[u], cfma(alpha, ph[u], xv[u])));
+              const double2 r = csub(cmul(dv[u], sh[u]), cmul(omega, tv[u]));
+              stnt(a.R + o, r);
+              part[0] += cabs2(r);
+              part[1] = fma(hv[u].x, r.x, fma(hv[u].y, r.y, part[1]));
+              part[2] = fma(hv[u].x, r.y, fma(-hv[u].y, r.x, part[2]));
+            } else if (half) {
+              a.X[o] = cfma(alpha, ph[u], xv[u]);
+            }
+          }
         }
-        for (; row < r1; row += rs) {
-          const size_t o = (size_t)row * kSys + j;
-          upd(row, a.SH[o], a.PH[o], a.X[o], a.T[o], a.RH[o], sweep_diag(a, row, kap));
-        }
-      } else if (sj == B_HALF || sj == B_TAUBD) {
-        for (int row = r0; row < r1; row += rs) {
-          const size_t o = (size_t)row * kSys + j;
-          a.X[o] = cfma(alpha, a.PH[o], a.X[o]);
-        }
-      }
-      store_partials64<3>(part, a.partials, lds);
+      });
+      store_unit_partials<3>(uacc, a.partials);
       if (barrier_last(a.bar, epoch, [&] {
             double tot[3];
             final_partials64<3>(a.partials, tot, lds);
             __shared__ int s_run[kSys];
             if (threadIdx.x < kSys)
               s_run[threadIdx.x] = threadIdx.x < a.nsys
-                                       ? upd_xr(st, threadIdx.x, tot[0], make_double2(tot[1], tot[2]))
+                                       ? upd_xr(&ls, threadIdx.x, tot[0], make_double2(tot[1], tot[2]))
                                        : 0;
             __syncthreads();
             if (threadIdx.x == 0) {
               int run = 0;
               for (int u = 0; u < kSys; ++u) run += s_run[u];
-              st->running = run;
-              st->iter = st->iter + 1;
+              ls.running = run;
+              ls.iter = ls.iter + 1;
             }
+            publish_phase_state(st, ls);
           }))
         return;
     }
@@ -766,7 +964,8 @@ __global__ __launch_bounds__(kPB) void k_sweep(SweepArgs a) {
     barrier_last(a.bar, epoch, [&] {
       double tot[1];
       final_partials64<1>(a.partials, tot, lds);
-      if (threadIdx.x < a.nsys) st->rr_true[threadIdx.x] = tot[0];
+      if (threadIdx.x < a.nsys) ls.rr_true[threadIdx.x] = tot[0];
+      publish_state(st, ls);
     });
   }
 }

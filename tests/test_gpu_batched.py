@@ -97,14 +97,39 @@ def test_sweep_iteration_cap_and_zero_rhs(hk, oracle):
         assert np.linalg.norm(host(X)[:, j] - xo) <= 1e-12 * np.linalg.norm(xo)
 
 
+def iterate_close(oracle, p, val, b, x, xo, maxit=4, base=1e-12):
+    """x (the solver's iterate after maxit steps) against the oracle's xo: the
+    two sum their dot products in different orders, so they differ by
+    rounding amplified as the iteration amplifies it.  The bar is base (relative)
+    times that amplification where it exceeds 1, measured on the oracle: the
+    largest relative change of its iterate under three random perturbations
+    of b of relative size 1e-13, per unit of perturbation.  (On the 6^3 sweep
+    the highest-frequency systems amplify 2-9x, the others about 1x.)"""
+    nx = max(np.linalg.norm(xo), 1e-300)
+    err = np.linalg.norm(x - xo)
+    if err <= base * nx:
+        return True
+    rng = np.random.default_rng(11)
+    amp = 1.0
+    for _ in range(3):
+        d = crandn(rng, p.n)
+        d[p.dirichlet] = 0
+        d *= 1e-13 * np.linalg.norm(b) / np.linalg.norm(d)
+        x1, _ = oracle.bicgstab(p.rowptr, p.col, val, b + d, tol=1e-14, maxit=maxit)
+        amp = max(amp, np.linalg.norm(x1 - xo) / nx / 1e-13)
+    return err <= base * amp * nx
+
+
 def sweep_iterates_every_shape(hk, oracle, p, kap, B, tag):
     """Every sweep launch shape: each system's iterate after 4 iterations is
-    the oracle's to 1e-12 (a system with a zero right-hand side stops at 0
+    the oracle's to 1e-12, times the system's amplification of rounding where
+    it exceeds 1 (iterate_close; a system with a zero right-hand side stops at 0
     and drops out of the products from the start)."""
     nsys = len(kap)
-    ref = []
+    ref, vals = [], []
     for j in range(nsys):
         val = H.helmholtz_values(p, kap[j])
+        vals.append(val)
         ref.append(oracle.bicgstab(p.rowptr, p.col, val, B[:, j], tol=1e-14, maxit=4))
     args = (dev(p.rowptr), dev(p.col), dev(p.K), dev(p.M), kap, dev(B))
     for sh in hk.SWEEP_SHAPES:
@@ -115,7 +140,7 @@ def sweep_iterates_every_shape(hk, oracle, p, kap, B, tag):
             xo, oi = ref[j]
             assert infos[j]["shape"] == list(sh) and not infos[j]["shape_tuned"], infos[j]
             assert infos[j]["iters"] == oi["iters"] and infos[j]["status"] == oi["status"], (sh, j, infos[j], oi)
-            assert np.linalg.norm(Xh[:, j] - xo) <= 1e-12 * max(np.linalg.norm(xo), 1e-300), (sh, j)
+            assert iterate_close(oracle, p, vals[j], B[:, j], Xh[:, j], xo), (sh, j)
         assert np.all(Xh[:, nsys:] == 0), sh
     say("sweep iterates", tag, "tuned")
     X, infos = hk.sweep_solve(*args, tol=1e-14, max_iter=4)
@@ -123,7 +148,7 @@ def sweep_iterates_every_shape(hk, oracle, p, kap, B, tag):
     say("tuned shape", infos[0]["shape"])
     Xh = host(X)
     for j in range(nsys):
-        assert np.linalg.norm(Xh[:, j] - ref[j][0]) <= 1e-12 * max(np.linalg.norm(ref[j][0]), 1e-300), j
+        assert iterate_close(oracle, p, vals[j], B[:, j], Xh[:, j], ref[j][0]), j
 
 
 def test_sweep_every_shape_small(hk, oracle):
