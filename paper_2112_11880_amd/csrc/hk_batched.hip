@@ -74,26 +74,28 @@ __device__ __forceinline__ void store_partials64(const double (&v)[NV], double* 
 // Second stage: out[k] (valid in threads 0..63, thread j = system j) = sum
 // over workgroups in a fixed order.  Thread (g, j) sums workgroups g, g +
 // kPW, g + 2 kPW, ... in that order; the loads of kFinBatch of them (for all
-// NV sums) are issued before any is added, since the partials come from
-// memory after the barrier's acquire and a load-add chain would wait out
-// every load in turn.
+// NV sums; twice as many for one sum) are issued before any is added, since
+// the partials come from memory after the barrier's acquire and a load-add
+// chain would wait out every load in turn.
 constexpr int kFinBatch = 8;
 template <int NV>
 __device__ __forceinline__ void final_partials64(const double* partials, double (&out)[NV], double* lds) {
   const int j = threadIdx.x & 63, g = threadIdx.x >> 6, G = gridDim.x;
+  // one sum: twice the loads in flight in the same registers
+  constexpr int FB = NV == 1 ? 2 * kFinBatch : kFinBatch;
   double s[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) s[k] = 0;
-  for (int b0 = g; b0 < G; b0 += kFinBatch * kPW) {
-    double v[NV][kFinBatch];
+  for (int b0 = g; b0 < G; b0 += FB * kPW) {
+    double v[NV][FB];
 #pragma unroll
-    for (int u = 0; u < kFinBatch; ++u) {
+    for (int u = 0; u < FB; ++u) {
       const int b = b0 + u * kPW < G ? b0 + u * kPW : b0;
 #pragma unroll
       for (int k = 0; k < NV; ++k) v[k][u] = partials[((size_t)k * G + b) * kSys + j];
     }
 #pragma unroll
-    for (int u = 0; u < kFinBatch; ++u)
+    for (int u = 0; u < FB; ++u)
       if (b0 + u * kPW < G) {
 #pragma unroll
         for (int k = 0; k < NV; ++k) s[k] += v[k][u];
@@ -342,9 +344,8 @@ __device__ __forceinline__ void sweep_rows(int n, int G, int& r0, int& r1, int& 
 // with a fixed share of rows per wave, the first waves of a workgroup were
 // done after ~40% of the phase and the last ones set the workgroup's time
 // (e.g. 46 to 161 us for the x/r update).  So the waves claim the
-// workgroup's rows in units of kUnitRows through an LDS counter.  The rows
-// of a workgroup are the rows its waves own in the product phases (sweep_rows),
-// taken in the order row(q) = base + q % kPW + (q / kPW) step, q < nrows.
+// workgroup's rows in units of kUnitRows through an LDS counter, in the
+// order row(q) = base + q % kPW + (q / kPW) step, q < nrows (sweep_wg_rows).
 //
 // A reduction over claimed rows stays bitwise reproducible: each unit's sum
 // is formed in row order and parked in an LDS ring (kUnitRing units), and
@@ -363,30 +364,15 @@ struct WgRows {
   int base, step, nrows;
 };
 
-template <int MAP>
+// The element-wise phases have no reuse to keep local; what pays is one
+// front: workgroup b takes the groups of kPW rows b kPW + k G kPW (k >= 0), so
+// the whole grid streams each vector as a single window of G kPW rows (on the
+// 48^3 sweep 642 us per iteration, against 656 with the product phases' XCD
+// eighths and 669 with one contiguous range per workgroup).
 __device__ __forceinline__ WgRows sweep_wg_rows(int n, int G) {
-  int base, step, end;
-  if (MAP == 2) {
-    base = blockIdx.x * kPW;
-    step = G * kPW;
-    end = n;
-  } else {
-    const int x = blockIdx.x % kXcds, i = blockIdx.x / kXcds;
-    const int nbx = (G - x + kXcds - 1) / kXcds;
-    const int X0 = (int)(((long long)x * n) / kXcds), X1 = (int)(((long long)(x + 1) * n) / kXcds);
-    if (MAP == 1) {
-      base = X0 + i * kPW;
-      step = nbx * kPW;
-      end = X1;
-    } else {
-      const int nw = nbx * kPW;
-      base = X0 + (int)(((long long)(X1 - X0) * (i * kPW)) / nw);
-      end = X0 + (int)(((long long)(X1 - X0) * (i * kPW + kPW)) / nw);
-      step = kPW;
-    }
-  }
+  const int base = blockIdx.x * kPW, step = G * kPW;
   // full groups of kPW rows, then a partial one
-  const int L = end - base;
+  const int L = n - base;
   const int full = L >= kPW ? (L - kPW) / step + 1 : 0;
   const int rest = min(max(L - full * step, 0), kPW);
   return WgRows{base, step, full * kPW + rest};
@@ -771,7 +757,7 @@ __global__ __launch_bounds__(kPB) void k_sweep(SweepArgs a) {
   const int G = gridDim.x;
   int r0, r1, rs;
   sweep_rows<MAP>(a.n, G, r0, r1, rs);
-  const WgRows wr = sweep_wg_rows<MAP>(a.n, G);
+  const WgRows wr = sweep_wg_rows(a.n, G);
   const bool lane_ok = j < a.nsys;
   const double2 kap = lane_ok ? a.kap[j] : make_double2(0, 0);
 
@@ -939,17 +925,15 @@ __global__ __launch_bounds__(kPB) void k_sweep(SweepArgs a) {
       if (barrier_last(a.bar, epoch, [&] {
             double tot[3];
             final_partials64<3>(a.partials, tot, lds);
-            __shared__ int s_run[kSys];
-            if (threadIdx.x < kSys)
-              s_run[threadIdx.x] = threadIdx.x < a.nsys
-                                       ? upd_xr(&ls, threadIdx.x, tot[0], make_double2(tot[1], tot[2]))
-                                       : 0;
-            __syncthreads();
-            if (threadIdx.x == 0) {
-              int run = 0;
-              for (int u = 0; u < kSys; ++u) run += s_run[u];
-              ls.running = run;
-              ls.iter = ls.iter + 1;
+            // wave 0 (thread j = system j) updates and counts the running
+            // systems with one ballot
+            if (threadIdx.x < kWave) {
+              const int r = threadIdx.x < a.nsys ? upd_xr(&ls, threadIdx.x, tot[0], make_double2(tot[1], tot[2])) : 0;
+              const int run = __popcll(__ballot(r != 0));
+              if (threadIdx.x == 0) {
+                ls.running = run;
+                ls.iter = ls.iter + 1;
+              }
             }
             publish_phase_state(st, ls);
           }))
