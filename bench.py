@@ -174,17 +174,15 @@ def bench_batched(hk, torch, np, dev, log, legs=("sweep", "uneven"), plain=True,
     return res
 
 
-def sweep_phases(stamps, iters_all, n, nnz, np):
-    """Per-phase time of the sweep's iterations while every system runs
-    (iterations 2 .. the smallest iteration count), from the barrier stamps
-    (100 MHz clock): each phase's mean time, barrier included, its
-    algorithmic bytes with all 64 systems running, and those bytes' share of
-    the 8 TB/s peak over that time."""
-    V = 64 * 16 * n                  # one [node][64] complex128 vector pass
-    mat = 4 * (n + 1) + 20 * nnz     # rowptr, col, K, M of one product
-    dg = 16 * n                      # the diagonals of K and M
-    names = ("p_update", "v_product", "s_update", "t_product", "xr_update")
-    nbytes = (4 * V + dg, mat + 3 * V, 3 * V + dg, mat + 2 * V + dg, 7 * V + dg)
+PHASES = ("p_update", "v_product", "s_update", "t_product", "xr_update")
+
+
+def barrier_phases(stamps, iters_all, nbytes, np):
+    """Per-phase time of a batched solve's iterations while every system
+    runs (iterations 2 .. the smallest iteration count), from the barrier
+    stamps (100 MHz clock): each phase's mean time, barrier included, its
+    algorithmic bytes with every system running (nbytes, in PHASES order),
+    and those bytes' share of the 8 TB/s peak over that time."""
     k = np.arange(2, max(iters_all, 3))
     if len(k) < 2 or 5 * k[-1] >= stamps.shape[0] or not np.all(stamps[1:5 * k[-1] + 1] > 0):
         return None
@@ -194,11 +192,29 @@ def sweep_phases(stamps, iters_all, n, nnz, np):
         e = 5 * k - 4 + ph   # barrier after phase ph of iteration k (k >= 2)
         us = float(np.mean(stamps[e] - stamps[e - 1])) * 1e-2
         total += us
-        out[names[ph]] = {"us": round(us, 1), "bytes": nbytes[ph],
-                          "hbm_frac": round(nbytes[ph] / (us * 1e-6) / 8e12, 3)}
+        out[PHASES[ph]] = {"us": round(us, 1), "bytes": nbytes[ph],
+                           "hbm_frac": round(nbytes[ph] / (us * 1e-6) / 8e12, 3)}
     out["iteration_us"] = round(total, 1)
     out["iteration_hbm_frac"] = round(sum(nbytes) / (total * 1e-6) / 8e12, 3)
     return out
+
+
+def sweep_phases(stamps, iters_all, n, nnz, np):
+    """barrier_phases of the sweep: a [node][64] complex128 vector pass is
+    64 x 16 B per row; a product reads rowptr, col, K and M."""
+    V = 64 * 16 * n
+    mat = 4 * (n + 1) + 20 * nnz
+    dg = 16 * n                      # the diagonals of K and M
+    return barrier_phases(stamps, iters_all, (4 * V + dg, mat + 3 * V, 3 * V + dg, mat + 2 * V + dg, 7 * V + dg), np)
+
+
+def uneven_phases(stamps, iters_all, n, nnz, np):
+    """barrier_phases of the block-diagonal batch: a vector pass is 16 B per
+    row (the diagonal and its inverse count as vectors); a product reads
+    rowptr, int32 columns and complex128 values."""
+    V = 16 * n
+    mat = 4 * (n + 1) + 20 * nnz
+    return barrier_phases(stamps, iters_all, (5 * V, mat + 3 * V, 4 * V, mat + 3 * V, 8 * V), np)
 
 
 def _bench_sweep(hk, torch, np, dev, log, plain, max_iter, shape):
@@ -273,8 +289,9 @@ def _bench_uneven(hk, torch, np, dev, log, plain, max_iter, shape):
     hk.blockdiag_solve(A, offs, b, tol=1e-8, max_iter=4, shape=shape)
     torch.cuda.synchronize()
     tune_bd = time.perf_counter() - ts
+    stamps = torch.zeros(8 * (max_iter + 1), dtype=torch.float64, device=dev)
     ts = time.perf_counter()
-    _, infos = hk.blockdiag_solve(A, offs, b, tol=1e-8, max_iter=max_iter, shape=shape)
+    _, infos = hk.blockdiag_solve(A, offs, b, tol=1e-8, max_iter=max_iter, shape=shape, stamps=stamps)
     torch.cuda.synchronize()
     t_bd = time.perf_counter() - ts
     its = [i["iters"] for i in infos]
@@ -293,7 +310,8 @@ def _bench_uneven(hk, torch, np, dev, log, plain, max_iter, shape):
         it_seq.append(inf["iters"])
     if plain:
         log(f"32 plain solves: {t_seq:.3f} s")
-    res["solve_uneven"] = {"systems": 32, "rows": offs[-1], "time_s": round(t_bd, 4),
+    phases = uneven_phases(stamps.cpu().numpy(), min(its), offs[-1], nnz, np)
+    res["solve_uneven"] = {"systems": 32, "rows": offs[-1], "time_s": round(t_bd, 4), "phases": phases,
                            "shape": infos[0]["shape"], "shape_tuned": infos[0]["shape_tuned"],
                            "tune_s": round(tune_bd, 4), "iters_min": min(its), "iters_max": max(its),
                            "status_all_ok": all(i["status"] == 0 for i in infos),

@@ -280,11 +280,12 @@ int hk_krylov_solve_mixed(hk_csr A, const void* d_b, void* d_x, double inner_tol
  * owned) the solve records barrier times in it: entry e (e >= 1, the e-th
  * barrier of the launch) = the device's 100 MHz wall clock when the last
  * workgroup arrived; entries of barriers that did not happen are left
- * untouched.  The sweep's barriers are: 1 after the start phase; then per
- * iteration (4 in the first, which has no p update) after the p update, the
- * v product, the s update, the t product and the x/r update; then one
- * after the true-residual product.  The time between two entries is the
- * phase between those barriers, the barrier included.
+ * untouched.  The barriers of both solves are: 1 after the start phase;
+ * then per iteration (4 in the first, which has no p update) after the p
+ * update, the v product, the s update, the t product and the x/r update;
+ * then the sweep has one after its true-residual product, the uneven batch
+ * one before (the full tile list rebuilt) and one after it.  The time between
+ * two entries is the phase between those barriers, the barrier included.
  */
 
 /*

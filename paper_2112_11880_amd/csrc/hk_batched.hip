@@ -982,56 +982,46 @@ struct BdArgs {
   int tile_rows;
 };
 
-// Flush the workgroup's running sums of the current system into the LDS
-// per-system accumulators (thread 0 adds; uniform call).
-template <int NV>
-__device__ __forceinline__ void bd_flush(double (&acc)[NV], int sys, double* red, double* sysacc) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-#pragma unroll
-  for (int k = 0; k < NV; ++k) acc[k] = wave_sum(acc[k]);
-  __syncthreads();
-  if (lane == 0) {
-#pragma unroll
-    for (int k = 0; k < NV; ++k) red[k * kPW + w] = acc[k];
-  }
-  __syncthreads();
-  if (threadIdx.x == 0 && sys >= 0) {
-#pragma unroll
-    for (int k = 0; k < NV; ++k) {
-      double s = 0;
-      for (int u = 0; u < kPW; ++u) s += red[k * kPW + u];
-      sysacc[k * kSys + sys] += s;
-    }
-  }
-#pragma unroll
-  for (int k = 0; k < NV; ++k) acc[k] = 0;
-}
-
 // A tile of the active list as the phases see it, and the per-system
-// scalars the phases read, both staged in LDS at the start of a phase.
+// scalars the phases read, staged in LDS at the start of a phase.
 struct BdTile {
   int row0, end, sys;
 };
-constexpr int kBdTileBatch = 64;  // active tiles staged in LDS at a time
 struct BdShared {
-  int tsys[kBdTileBatch], trow0[kBdTileBatch], tend[kBdTileBatch];
   double2 alpha[kSys], omega[kSys], beta[kSys];
   int status[kSys];
 };
 
-// Walk this workgroup's share of the active tiles: f(tile, acc) for each,
-// with the metadata of up to kBdTileBatch tiles and every system's scalars
-// loaded into LDS together (one round of loads instead of a dependent chain
-// per tile); per-system sums end in partials[(k*G + block)*64 + sys].
-template <int NV, class F>
-__device__ __forceinline__ void bd_phase(const BdArgs& a, double* lds, BdShared& sh, F&& f) {
-  double* red = lds;                    // NV * kPW
-  double* sysacc = lds + 4 * kPW;       // NV * 64
+// The phases cut the active tiles into units of UR rows: tile t holds units
+// t P .. t P + P - 1, P = tile_rows / UR, unit p covering rows row0 + p UR ..
+// (a unit past its tile's end is empty).  Workgroup lb (xcd_block order)
+// takes the units [S lb / G, S (lb + 1) / G) of the S = na P, so every
+// workgroup gets the same number of units: with whole tiles per workgroup
+// (8 or 9 of the 2,112 tiles of the 32-system batch) a workgroup's product
+// time followed its row count (correlation 0.84) and spread over 45%.  Its
+// waves claim the units in order through an LDS counter, as the sweep's
+// element-wise phases do, since the memory system serves a workgroup's
+// waves unevenly.  f(tile, r0, acc) runs one unit in one wave; the unit's
+// sums (acc, reduced over the wave) are added in unit order into the
+// workgroup's per-system sums through an LDS ring, so they stay bitwise
+// reproducible whichever wave ran which unit; they end in
+// partials[(k*G + block)*64 + sys].  All threads call it.
+struct BdRing {
+  double v[kUnitRing][4];
+  int sys[kUnitRing];
+};
+template <int NV, int UR, class F>
+__device__ __forceinline__ void bd_units(const BdArgs& a, double* lds, BdShared& sh, UnitSync& us, BdRing& ring,
+                                         F&& f) {
+  static_assert(NV <= 3, "at most three sums");
+  double* sysacc = lds;  // NV * 64
   const int G = gridDim.x;
   const int lb = xcd_block(blockIdx.x, G);
   const BatchState* st = a.st;
   const int na = st->ntiles_active;
-  const int t0 = (int)(((long long)lb * na) / G), t1 = (int)(((long long)(lb + 1) * na) / G);
+  const int P = a.tile_rows / UR;
+  const long long S = (long long)na * P;
+  const int u0 = (int)((S * lb) / G), nunits = (int)((S * (lb + 1)) / G) - u0;
   for (int k = threadIdx.x; k < NV * kSys; k += kPB) sysacc[k] = 0;
   if (threadIdx.x < a.nsys) {
     const int j = threadIdx.x;
@@ -1040,96 +1030,109 @@ __device__ __forceinline__ void bd_phase(const BdArgs& a, double* lds, BdShared&
     sh.beta[j] = st->beta[j];
     sh.status[j] = st->status[j];
   }
-  double acc[NV];
-#pragma unroll
-  for (int k = 0; k < NV; ++k) acc[k] = 0;
-  int cur = -1;
-  for (int c = t0; c < t1; c += kBdTileBatch) {
-    const int cnt = t1 - c < kBdTileBatch ? t1 - c : kBdTileBatch;
-    __syncthreads();  // the previous batch is done with the staged tiles
-    if (threadIdx.x >= kSys && threadIdx.x < kSys + cnt) {
-      const int t = c + threadIdx.x - kSys;
-      sh.tsys[t - c] = a.act_sys[t];
-      sh.trow0[t - c] = a.act_row0[t];
-      sh.tend[t - c] = a.act_end[t];
-    }
-    __syncthreads();
-    for (int k = 0; k < cnt; ++k) {
-      const BdTile tile{sh.trow0[k], sh.tend[k], sh.tsys[k]};
-      if (tile.sys != cur) {
-        if (cur >= 0) bd_flush<NV>(acc, cur, red, sysacc);
-        cur = tile.sys;
-      }
-      f(tile, acc);
-    }
+  if (threadIdx.x == 0) {
+    us.claim = 0;
+    us.added = 0;
+    for (int b = 0; b < kUnitRing / kUnitBatch; ++b) us.count[b] = 0;
   }
-  bd_flush<NV>(acc, cur, red, sysacc);
   __syncthreads();
-  for (int k = threadIdx.x; k < NV * kSys; k += kPB) {
-    const int kk = k / kSys, s = k % kSys;
-    a.partials[((size_t)kk * G + blockIdx.x) * kSys + s] = sysacc[k];
+  const int lane = threadIdx.x & 63;
+  // counters advanced by every lane of the wave, as in claim_units
+  for (;;) {
+    const int u = __builtin_amdgcn_readfirstlane(atomicAdd(&us.claim, 1)) / kWave;
+    if (u >= nunits) break;
+    const int t = (u0 + u) / P, p = (u0 + u) % P;
+    const BdTile tile{__builtin_amdgcn_readfirstlane(a.act_row0[t]), __builtin_amdgcn_readfirstlane(a.act_end[t]),
+                      __builtin_amdgcn_readfirstlane(a.act_sys[t])};
+    const int r0 = tile.row0 + p * UR;
+    double acc[NV > 0 ? NV : 1];
+#pragma unroll
+    for (int k = 0; k < (NV > 0 ? NV : 1); ++k) acc[k] = 0;
+    if (r0 < tile.end) f(tile, r0, acc);
+    if constexpr (NV > 0) {
+#pragma unroll
+      for (int k = 0; k < NV; ++k) acc[k] = wave_sum(acc[k]);
+      const int b = u / kUnitBatch, slot = u % kUnitRing;
+      lds_wait_ge(&us.added, b - (kUnitRing / kUnitBatch - 1), a.bar);
+      // every lane stores the same values
+#pragma unroll
+      for (int k = 0; k < NV; ++k) ring.v[slot][k] = acc[k];
+      ring.sys[slot] = tile.sys;
+      const int done = __builtin_amdgcn_readfirstlane(__hip_atomic_fetch_add(
+                           &us.count[b % (kUnitRing / kUnitBatch)], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP)) /
+                           kWave + 1;
+      if (done == min(kUnitBatch, nunits - b * kUnitBatch)) {
+        lds_wait_ge(&us.added, b, a.bar);
+        const int s0 = (b * kUnitBatch) % kUnitRing;
+        if (lane < NV) {
+          for (int m = 0; m < done; ++m) sysacc[lane * kSys + ring.sys[s0 + m]] += ring.v[s0 + m][lane];
+        }
+        us.count[b % (kUnitRing / kUnitBatch)] = 0;
+        __hip_atomic_store(&us.added, b + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+    }
+  }
+  __syncthreads();
+  if constexpr (NV > 0) {
+    for (int k = threadIdx.x; k < NV * kSys; k += kPB) {
+      const int kk = k / kSys, sy = k % kSys;
+      a.partials[((size_t)kk * G + blockIdx.x) * kSys + sy] = sysacc[k];
+    }
   }
 }
 
-// Row sums of the kPB rows of a tile, kPB / L rows at a time (one L-lane
-// group per row); each sum goes to callback g(row, acc) on the group's
-// first lane.
-template <int L, class G2>
-__device__ __forceinline__ void bd_tile_spmv(const BdArgs& a, const BdTile& tile, const double2* src, G2&& g) {
-  const int grp = threadIdx.x / L, lane = threadIdx.x & (L - 1);
-  const int end = tile.end;
-  const int base = tile.row0;
-  for (int sub = 0; sub < L; ++sub) {
-    const int row = base + sub * (kPB / L) + grp;
-    if (base + sub * (kPB / L) >= end) break;
-    double2 acc[1];
-    csr_rows<L, 1, double2>(row, end, a.rowptr, a.col, a.val, src, acc);
-    if (lane == 0 && row < end) g(row, acc[0]);
-  }
-}
-
-// Row-block variant: the tile's rows are cut into blocks of R consecutive
-// rows (R in {16, 32, 64}); wave w of the workgroup takes blocks w, w + kPW,
-// ... and streams each block's entries with all its lanes, CH entries per
-// lane per pass (csr_block_rows); each row's sum goes to callback g(row,
-// acc) in the lane that owns the row.  `stage` is the workgroup's staging
-// area (kPW slices of CH * 64 products).
-template <int R, int CH, class G2>
-__device__ __forceinline__ void bd_tile_spmv_rb(const BdArgs& a, const BdTile& tile, const double2* src,
-                                                double2* stage, G2&& g) {
-  const int end = tile.end;
+// The rows [r0, min(r0 + UR, tile end)) of one unit in one wave: an R-row
+// block (csr_block_rows, UR = R), or UR / (64 / L) passes of 64 / L rows with L
+// lanes each; g(row, sum) is called in the lane that holds the row's sum.
+template <int L, int R, int CH, class G2>
+__device__ __forceinline__ void bd_unit_spmv(const BdArgs& a, const BdTile& tile, int r0, const double2* src,
+                                             double2* stage, G2&& g) {
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  for (int r0 = tile.row0 + w * R; r0 < end; r0 += kPW * R) {  // uniform across the wave
-    const double2 acc = csr_block_rows<R, CH, double2, int>(r0, end, a.rowptr, a.col, a.val, src,
+  if constexpr (L == kRowBlockL) {
+    const double2 acc = csr_block_rows<R, CH, double2, int>(r0, tile.end, a.rowptr, a.col, a.val, src,
                                                             stage + w * CH * kWave);
-    if (l < R && r0 + l < end) g(r0 + l, acc);
+    if (l < R && r0 + l < tile.end) g(r0 + l, acc);
+  } else {
+    constexpr int UR = 16, RP = kWave / L;
+    for (int q = 0; q < UR; q += RP) {
+      const int row = r0 + q + l / L;
+      if (r0 + q >= tile.end) break;  // uniform across the wave
+      double2 acc[1];
+      csr_rows<L, 1, double2>(row, tile.end, a.rowptr, a.col, a.val, src, acc);
+      if ((l & (L - 1)) == 0 && row < tile.end) g(row, acc[0]);
+    }
   }
 }
 
-// Tile products: L in {4, 8, 16, 32} lane groups (R, CH unused), or
-// L == kRowBlockL row blocks of R rows, CH entries per lane per pass (CH = 8
-// needs more than the 128 VGPRs a 1024-thread workgroup allows).  Tiles are
-// a.tile_rows <= kPB rows (chosen at run time with the tile shape).
+// Tile products: L-lane groups per row (R, CH unused), or L == kRowBlockL
+// row blocks of R rows, CH entries per lane per pass (CH = 8 needs more than
+// the 128 VGPRs a 1024-thread workgroup allows).  Tiles are a.tile_rows <=
+// kPB rows (chosen at run time with the tile shape); the phases run them in
+// units (bd_units).
 template <int L, int R, int CH>
 __global__ __launch_bounds__(kPB) void k_blockdiag(BdArgs a) {
-  // [4 kPW] wave sums | [4 kSys] per-system sums | scratch shared by the
-  // barrier callbacks (4 kPW kSys doubles) and the row-block staging area,
-  // which are never live at the same time
+  // [4 kSys] per-system sums | scratch shared by the barrier callbacks
+  // (4 kPW kSys doubles) and the row-block staging area, which are never
+  // live at the same time
   constexpr int kFin = 4 * kPW * kSys;
   constexpr int kStage = L == kRowBlockL ? kPW * CH * kWave * 2 : 0;
-  __shared__ __align__(16) double lds[4 * kPW + 4 * kSys + (kFin > kStage ? kFin : kStage)];
+  __shared__ __align__(16) double lds[4 * kSys + (kFin > kStage ? kFin : kStage)];
   unsigned epoch = 0;
-  double* fin = lds + 4 * kPW + 4 * kSys;
+  double* fin = lds + 4 * kSys;
   double2* stage = reinterpret_cast<double2*>(fin);
   __shared__ BdShared sh;
+  __shared__ UnitSync us;
+  __shared__ BdRing ring;
   BatchState* st = a.st;
-  auto tile_spmv = [&](const BdTile& tile, const double2* src, auto&& g) {
-    if constexpr (L == kRowBlockL) bd_tile_spmv_rb<R, CH>(a, tile, src, stage, g);
-    else bd_tile_spmv<L>(a, tile, src, g);
+  // units: kWave rows (one per lane) in the element-wise phases, an R-row
+  // block (or 16 rows of L-lane groups) in the products
+  constexpr int kUR = L == kRowBlockL ? R : 16;
+  auto unit_spmv = [&](const BdTile& tile, int r0, const double2* src, auto&& g) {
+    bd_unit_spmv<L, R, CH>(a, tile, r0, src, stage, g);
   };
-  // the row of the calling thread in an element-wise phase (one per thread), or -1
-  auto my_row = [](const BdTile& tile) {
-    const int row = tile.row0 + (int)threadIdx.x;
+  // the row of the calling lane in an element-wise unit, or -1
+  auto my_row = [](const BdTile& tile, int r0) {
+    const int row = r0 + (int)(threadIdx.x & 63);
     return row < tile.end ? row : -1;
   };
 
@@ -1161,8 +1164,8 @@ __global__ __launch_bounds__(kPB) void k_blockdiag(BdArgs a) {
   };
 
   // ---- start: r = rhat = b, phat = D^-1 b, x = 0 (all tiles are active)
-  bd_phase<1>(a, lds, sh, [&](const BdTile& tile, double(&acc)[1]) {
-    const int row = my_row(tile);
+  bd_units<1, kWave>(a, lds, sh, us, ring, [&](const BdTile& tile, int r0, double(&acc)[1]) {
+    const int row = my_row(tile, r0);
     if (row >= 0) {
       const double2 b = a.B[row];
       a.R[row] = b; a.RH[row] = b; a.PH[row] = cmul(a.dinv[row], b); a.X[row] = make_double2(0, 0);
@@ -1188,8 +1191,8 @@ __global__ __launch_bounds__(kPB) void k_blockdiag(BdArgs a) {
   while (st->running > 0) {
     const long long it = st->iter;
     if (it > 1) {
-      bd_phase<1>(a, lds, sh, [&](const BdTile& tile, double(&)[1]) {
-        const int row = my_row(tile);
+      bd_units<0, kWave>(a, lds, sh, us, ring, [&](const BdTile& tile, int r0, double(&)[1]) {
+        const int row = my_row(tile, r0);
         if (row >= 0) {
           const double2 beta = sh.beta[tile.sys], bo = cmul(beta, sh.omega[tile.sys]);
           const double2 w = csub(a.R[row], cmul(bo, a.V[row]));
@@ -1199,8 +1202,8 @@ __global__ __launch_bounds__(kPB) void k_blockdiag(BdArgs a) {
       if (barrier_last(a.bar, epoch, [] {})) return;
     }
     // v = A phat ; sigma
-    bd_phase<2>(a, lds, sh, [&](const BdTile& tile, double(&acc)[2]) {
-      tile_spmv(tile, a.PH, [&](int row, double2 v) {
+    bd_units<2, kUR>(a, lds, sh, us, ring, [&](const BdTile& tile, int r0, double(&acc)[2]) {
+      unit_spmv(tile, r0, a.PH, [&](int row, double2 v) {
         a.V[row] = v;
         const double2 h = a.RH[row];
         acc[0] = fma(h.x, v.x, fma(h.y, v.y, acc[0]));
@@ -1214,8 +1217,8 @@ __global__ __launch_bounds__(kPB) void k_blockdiag(BdArgs a) {
         }))
       return;
     // s = r - alpha v ; shat ; ||s||^2
-    bd_phase<1>(a, lds, sh, [&](const BdTile& tile, double(&acc)[1]) {
-      const int row = my_row(tile);
+    bd_units<1, kWave>(a, lds, sh, us, ring, [&](const BdTile& tile, int r0, double(&acc)[1]) {
+      const int row = my_row(tile, r0);
       if (row >= 0 && sh.status[tile.sys] == B_RUN) {
         const double2 s = csub(a.R[row], cmul(sh.alpha[tile.sys], a.V[row]));
         a.SH[row] = cmul(a.dinv[row], s);
@@ -1229,9 +1232,9 @@ __global__ __launch_bounds__(kPB) void k_blockdiag(BdArgs a) {
         }))
       return;
     // t = A shat ; tau ; t^H s
-    bd_phase<3>(a, lds, sh, [&](const BdTile& tile, double(&acc)[3]) {
+    bd_units<3, kUR>(a, lds, sh, us, ring, [&](const BdTile& tile, int r0, double(&acc)[3]) {
       if (sh.status[tile.sys] != B_RUN) return;
-      tile_spmv(tile, a.SH, [&](int row, double2 t) {
+      unit_spmv(tile, r0, a.SH, [&](int row, double2 t) {
         a.T[row] = t;
         const double2 s = cmul(a.d[row], a.SH[row]);
         acc[0] = fma(t.x, t.x, fma(t.y, t.y, acc[0]));
@@ -1246,8 +1249,8 @@ __global__ __launch_bounds__(kPB) void k_blockdiag(BdArgs a) {
         }))
       return;
     // x, r updates ; ||r||^2 ; rhat^H r
-    bd_phase<3>(a, lds, sh, [&](const BdTile& tile, double(&acc)[3]) {
-      const int row = my_row(tile);
+    bd_units<3, kWave>(a, lds, sh, us, ring, [&](const BdTile& tile, int r0, double(&acc)[3]) {
+      const int row = my_row(tile, r0);
       if (row < 0) return;
       const int ss = sh.status[tile.sys];
       const double2 alpha = sh.alpha[tile.sys], omega = sh.omega[tile.sys];
@@ -1286,8 +1289,8 @@ __global__ __launch_bounds__(kPB) void k_blockdiag(BdArgs a) {
   }
   // true residual: all tiles
   if (barrier_last(a.bar, epoch, [&] { fill_active(true); })) return;
-  bd_phase<1>(a, lds, sh, [&](const BdTile& tile, double(&acc)[1]) {
-    tile_spmv(tile, a.X, [&](int row, double2 ax) {
+  bd_units<1, kUR>(a, lds, sh, us, ring, [&](const BdTile& tile, int r0, double(&acc)[1]) {
+    unit_spmv(tile, r0, a.X, [&](int row, double2 ax) {
       acc[0] += cabs2(csub(a.B[row], ax));
     });
   });

@@ -370,16 +370,20 @@ def sweep_solve(rowptr, col, K, M, kappa, B, tol=1e-8, max_iter=400000, shape=No
     return X, [i.as_dict() for i in infos]
 
 
-def blockdiag_solve(A: CSR, row_off, b, tol=1e-8, max_iter=400000, shape=None):
+def blockdiag_solve(A: CSR, row_off, b, tol=1e-8, max_iter=400000, shape=None, stamps=None):
     """Uneven batch: A block-diagonal with systems [row_off[k], row_off[k+1]).
     shape: a tile shape (lanes per row, rows per block, entries per lane,
-    tile rows) to use instead of the tuned one."""
+    tile rows) to use instead of the tuned one.  stamps: a float64 device
+    tensor of 8 (max_iter + 1) entries that receives the grid barriers' times
+    (as for sweep_solve)."""
     _cvec(b, name="b", n=A.n)
     nsys = len(row_off) - 1
     offs = (C.c_int64 * (nsys + 1))(*[int(v) for v in row_off])
     x = torch.zeros_like(b)
     infos = (SolveInfo * max(nsys, 1))()
     o = _opts(tol, max_iter, True, 0, False, None, shape=shape)
+    if stamps is not None:
+        o.d_history = _ptr(_cvec(stamps, torch.float64, name="stamps", n=8 * (int(max_iter) + 1)))
     _check(load().hk_blockdiag_solve(A.h, nsys, offs, _ptr(b), _ptr(x), C.byref(o), infos, _stream()),
            allow_positive=True)
     return x, [infos[k].as_dict() for k in range(nsys)]
