@@ -24,6 +24,7 @@
 #include <map>
 #include <mutex>
 #include <tuple>
+#include <type_traits>
 #include <vector>
 
 #include "hk_grid.hpp"
@@ -47,7 +48,10 @@ struct BatchState {
   int running;
   int changed;       // a system stopped in the last iteration (tile list to rebuild)
   int ntiles_active;
-  int pad;
+  // sweep: set once at most 32 systems run, when the rest of the solve
+  // continues in k_sweep_tail from barrier epoch epoch0
+  int handoff;
+  unsigned epoch0;
 };
 
 // ------------------------------------------------------------ shared helpers
@@ -131,6 +135,7 @@ __device__ __forceinline__ void publish_phase_state(BatchState* g, const BatchSt
     if (j == 0) {
       g->running = l.running;
       g->iter = l.iter;
+      g->handoff = l.handoff;
     }
   }
 }
@@ -223,6 +228,7 @@ struct SweepArgs {
   GridBar* bar;
   double tol;
   long long maxit;
+  int tail;  // product form 3: hand the last <= 32 systems to k_sweep_tail
 };
 
 // The shared matrix (rowptr, col, K, M and the diagonals) is read-only
@@ -414,17 +420,19 @@ __device__ __forceinline__ void units_reset(UnitSync& us, double* acc) {
   __syncthreads();
 }
 
-// Runs body(row0, cnt, part) for every unit of the workgroup's rows, claimed
-// by the calling waves; part[NV] (zeroed per unit) takes the unit's sums.
-// With NV > 0, acc[k * 64 + lane] ends as the workgroup's sums in unit order
-// (after the closing workgroup barrier).  Wave-uniform; all threads call it.
-template <int NV, class F>
+// Runs body(row0, cnt, part) for every unit of UR rows of the workgroup's
+// rows, claimed by the calling waves; part[NV] (zeroed per unit) takes the
+// unit's sums per lane, and conv(part[k]) turns them into the sums of system
+// `lane`.  With NV > 0, acc[k * 64 + lane] ends as the workgroup's sums in
+// unit order (after the closing workgroup barrier).  Wave-uniform; all
+// threads call it.
+template <int NV, int UR, class F, class C>
 __device__ __forceinline__ void claim_units(const WgRows& wr, UnitSync& us, double* ring, double* acc, GridBar* bar,
-                                            F&& body) {
+                                            F&& body, C&& conv) {
   static_assert(NV <= kUnitNV, "too many sums");
-  static_assert(kPW % kUnitRows == 0, "a unit stays within a group of rows");
+  static_assert(kPW % UR == 0, "a unit stays within a group of rows");
   const int j = threadIdx.x & 63;
-  const int nunits = (wr.nrows + kUnitRows - 1) / kUnitRows;
+  const int nunits = (wr.nrows + UR - 1) / UR;
   // Counters are advanced by every lane of the wave (one LDS instruction, so
   // the wave's results are consecutive and / 64 names the unit), not by lane 0
   // alone: the compiler may restructure a loop around a lane-0 branch so that
@@ -433,14 +441,16 @@ __device__ __forceinline__ void claim_units(const WgRows& wr, UnitSync& us, doub
   for (;;) {
     const int u = __builtin_amdgcn_readfirstlane(atomicAdd(&us.claim, 1)) / kWave;
     if (u >= nunits) break;
-    const int q = u * kUnitRows;
+    const int q = u * UR;
     const int row0 = wr.base + q % kPW + (q / kPW) * wr.step;
-    const int cnt = min(kUnitRows, wr.nrows - q);
+    const int cnt = min(UR, wr.nrows - q);
     double part[NV > 0 ? NV : 1];
 #pragma unroll
     for (int k = 0; k < (NV > 0 ? NV : 1); ++k) part[k] = 0;
     body(row0, cnt, part);
     if constexpr (NV > 0) {
+#pragma unroll
+      for (int k = 0; k < NV; ++k) part[k] = conv(part[k]);
       const int b = u / kUnitBatch, slot = u % kUnitRing;
       // the ring slot is free once the batch kUnitRing / kUnitBatch earlier is added
       lds_wait_ge(&us.added, b - (kUnitRing / kUnitBatch - 1), bar);
@@ -725,6 +735,138 @@ __device__ __forceinline__ void sweep_spmv_pf(const SweepArgs& a, int r0, int r1
   }
 }
 
+// sweep_diag at a row that differs between lanes (vector loads).
+__device__ __forceinline__ double2 sweep_diag_v(const SweepArgs& a, int i, double2 kap) {
+  const double k = a.kd[i], m = a.md[i];
+  return make_double2(k - kap.x * m, -kap.y * m);
+}
+
+// The per-row product with the next row prefetched (sweep_spmv_pf) for two
+// rows per wave step: half-wave h takes rows r0 + (2k + h) rs, lanes h*32 +
+// 0..15 hold its current row's first 16 entries, and entry values reach the
+// half's lanes by __shfl from there.  Lane l works for system `sys`; part
+// holds its sums (one row in two of its system's rows).
+template <int EPI, int NV>
+__device__ __forceinline__ void sweep_spmv_h2(const SweepArgs& a, int r0, int r1, int rs, const double2* src,
+                                              double2* dst, bool act, int sys, double2 kap, double (&part)[NV]) {
+  constexpr int W = 16, G = 4;
+  const int l = threadIdx.x & 63, hl = l & 32;
+  if (__ballot(act) == 0) return;  // uniform: no running system
+  const int rb = uni(r0);
+  if (rb >= r1) return;
+  int row = rb + (hl ? rs : 0);
+  int s = 0, e = 0;
+  if (row < r1) {
+    s = a.rowptr[row];
+    e = a.rowptr[row + 1];
+  }
+  auto fetch = [&](int s_, int e_, int& cv, double& kv, double& mv) {
+    const int q = max(min(s_ + (l & (W - 1)), e_ - 1), 0);
+    cv = ldnt(a.col + q);
+    kv = __builtin_nontemporal_load(a.K + q);
+    mv = __builtin_nontemporal_load(a.M + q);
+  };
+  int cv, cvn = 0;
+  double kv, mv, kvn = 0, mvn = 0;
+  fetch(s, e, cv, kv, mv);
+  for (int base = rb; base < r1; base += 2 * rs) {
+    const bool has = row < r1;
+    const int len = has ? e - s : 0;
+    const int lenw = max(__shfl(len, 0), __shfl(len, 32));
+    const size_t o = (size_t)(has ? row : 0) * kSys + sys;
+    double2 acK = make_double2(0, 0), acM = make_double2(0, 0);
+    double2 xv[G];
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      const int c = __shfl(cv, hl + u);
+      if (u < len && act) xv[u] = src[(size_t)c * kSys + sys];
+    }
+    const int nrow = row + 2 * rs;
+    int ns = 0, ne = 0;
+    if (nrow < r1) {
+      ns = a.rowptr[nrow];
+      ne = a.rowptr[nrow + 1];
+    }
+    fetch(ns, ne, cvn, kvn, mvn);
+    double2 pre = make_double2(0, 0), dg = make_double2(0, 0);
+    if (act && has) pre = EPI == 1 ? a.RH[o] : EPI == 2 ? a.SH[o] : a.B[o];
+    if (EPI == 2 && has) dg = sweep_diag_v(a, row, kap);
+#pragma unroll
+    for (int h = 0; h < W / G; ++h) {
+      double2 xn[G];
+      if (h + 1 < W / G) {
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+          const int c = __shfl(cv, hl + (h + 1) * G + u);
+          if ((h + 1) * G + u < len && act) xn[u] = src[(size_t)c * kSys + sys];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < G; ++u) {
+        const double k = __shfl(kv, hl + h * G + u), m = __shfl(mv, hl + h * G + u);
+        if (h * G + u < len && act) {
+          acK.x = fma(k, xv[u].x, acK.x);
+          acK.y = fma(k, xv[u].y, acK.y);
+          acM.x = fma(m, xv[u].x, acM.x);
+          acM.y = fma(m, xv[u].y, acM.y);
+        }
+      }
+      if (h + 1 < W / G) {
+#pragma unroll
+        for (int u = 0; u < G; ++u) xv[u] = xn[u];
+      }
+    }
+    // entries past the 16th, 4 at a time (lane-varying indices take vector
+    // registers), up to the longer of the two rows
+    for (int q0 = W; q0 < lenw; q0 += 4) {
+      int c[4];
+      double k8[4], m8[4];
+      double2 x8[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const bool in = q0 + u < len;
+        const int q = len > 0 ? s + min(q0 + u, len - 1) : 0;
+        c[u] = a.col[q];
+        k8[u] = in ? a.K[q] : 0.0;
+        m8[u] = in ? a.M[q] : 0.0;
+      }
+      if (act) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) x8[u] = src[(size_t)c[u] * kSys + sys];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          acK.x = fma(k8[u], x8[u].x, acK.x);
+          acK.y = fma(k8[u], x8[u].y, acK.y);
+          acM.x = fma(m8[u], x8[u].x, acM.x);
+          acM.y = fma(m8[u], x8[u].y, acM.y);
+        }
+      }
+    }
+    if (act && has) {
+      const double2 y = csub(acK, cmul(kap, acM));
+      if constexpr (EPI == 3) {
+        part[0] += cabs2(csub(pre, y));
+      } else if constexpr (EPI == 1) {
+        stnt(dst + o, y);
+        part[0] = fma(pre.x, y.x, fma(pre.y, y.y, part[0]));
+        part[1] = fma(pre.x, y.y, fma(-pre.y, y.x, part[1]));
+      } else {
+        stnt(dst + o, y);
+        const double2 sv = cmul(dg, pre);
+        part[0] = fma(y.x, y.x, fma(y.y, y.y, part[0]));
+        part[1] = fma(y.x, sv.x, fma(y.y, sv.y, part[1]));
+        part[2] = fma(y.x, sv.y, fma(-y.y, sv.x, part[2]));
+      }
+    }
+    row = nrow;
+    s = ns;
+    e = ne;
+    cv = cvn;
+    kv = kvn;
+    mv = mvn;
+  }
+}
+
 // The product of a phase in the shape PF of the kernel: 1 the per-row form
 // (rows r0, r0 + rs, ...), 2 the entry stream over [r0, r1) (rs == 1), 3 the
 // per-row form with the next row prefetched.
@@ -791,19 +933,20 @@ __global__ __launch_bounds__(kPB) void k_sweep(SweepArgs a) {
             for (int u = 0; u < a.nsys; ++u) run += ls.status[u] == B_RUN;
             ls.running = run;
           }
+          if (PF == 3 && threadIdx.x == 0 && a.tail && ls.running > 0 && ls.running <= 32) ls.handoff = 1;
           publish_state(st, ls);
         }))
       return;
   }
 
-  while (st->running > 0) {
+  while (st->running > 0 && !(PF == 3 && st->handoff)) {
     const long long it = st->iter;
     bool act = lane_ok && st->status[j] == B_RUN;
     // ---- phat = D^-1 (r - beta omega v) + beta phat
     if (it > 1) {
       const double2 beta = st->beta[j], bo = cmul(st->beta[j], st->omega[j]);
       units_reset(us, uacc);
-      claim_units<0>(wr, us, lds, uacc, a.bar, [&](int row0, int cnt, auto&) {
+      claim_units<0, kUnitRows>(wr, us, lds, uacc, a.bar, [&](int row0, int cnt, auto&) {
         double2 rv[kUnitRows] = {}, vv[kUnitRows] = {}, pv[kUnitRows] = {}, dv[kUnitRows];
 #pragma unroll
         for (int u = 0; u < kUnitRows; ++u) {
@@ -818,7 +961,7 @@ __global__ __launch_bounds__(kPB) void k_sweep(SweepArgs a) {
         for (int u = 0; u < kUnitRows; ++u)
           if (act && u < cnt)
             stnt(a.PH + (size_t)(row0 + u) * kSys + j, cfma(beta, pv[u], cmul(crecip(dv[u]), csub(rv[u], cmul(bo, vv[u])))));
-      });
+      }, [](double v) { return v; });
       if (barrier_last(a.bar, epoch, [] {})) return;
     }
     // ---- v = A phat ; sigma = rhat^H v
@@ -839,7 +982,7 @@ __global__ __launch_bounds__(kPB) void k_sweep(SweepArgs a) {
     {
       const double2 alpha = st->alpha[j];
       units_reset(us, uacc);
-      claim_units<1>(wr, us, lds, uacc, a.bar, [&](int row0, int cnt, auto& part) {
+      claim_units<1, kUnitRows>(wr, us, lds, uacc, a.bar, [&](int row0, int cnt, auto& part) {
         double2 rv[kUnitRows] = {}, vv[kUnitRows] = {}, dv[kUnitRows];
 #pragma unroll
         for (int u = 0; u < kUnitRows; ++u) {
@@ -858,7 +1001,7 @@ __global__ __launch_bounds__(kPB) void k_sweep(SweepArgs a) {
             part[0] += cabs2(s);
           }
         }
-      });
+      }, [](double v) { return v; });
       store_unit_partials<1>(uacc, a.partials);
       if (barrier_last(a.bar, epoch, [&] {
             double tot[1];
@@ -888,7 +1031,7 @@ __global__ __launch_bounds__(kPB) void k_sweep(SweepArgs a) {
       const bool run = sj == B_RUN, half = sj == B_HALF || sj == B_TAUBD;
       const double2 alpha = st->alpha[j], omega = st->omega[j];
       units_reset(us, uacc);
-      claim_units<3>(wr, us, lds, uacc, a.bar, [&](int row0, int cnt, auto& part) {
+      claim_units<3, kUnitRows>(wr, us, lds, uacc, a.bar, [&](int row0, int cnt, auto& part) {
         // two rows at a time (five loads each)
 #pragma unroll
         for (int h = 0; h < kUnitRows; h += 2) {
@@ -920,7 +1063,239 @@ __global__ __launch_bounds__(kPB) void k_sweep(SweepArgs a) {
             }
           }
         }
-      });
+      }, [](double v) { return v; });
+      store_unit_partials<3>(uacc, a.partials);
+      if (barrier_last(a.bar, epoch, [&] {
+            double tot[3];
+            final_partials64<3>(a.partials, tot, lds);
+            // wave 0 (thread j = system j) updates and counts the running
+            // systems with one ballot
+            if (threadIdx.x < kWave) {
+              const int r = threadIdx.x < a.nsys ? upd_xr(&ls, threadIdx.x, tot[0], make_double2(tot[1], tot[2])) : 0;
+              const int run = __popcll(__ballot(r != 0));
+              if (threadIdx.x == 0) {
+                ls.running = run;
+                ls.iter = ls.iter + 1;
+                // at most 32 systems left: hand the rest to the half-wave launch
+                if (PF == 3 && a.tail && run > 0 && run <= 32) ls.handoff = 1;
+              }
+            }
+            publish_phase_state(st, ls);
+            if constexpr (PF == 3) {
+              // a hand-off needs every field in memory
+              __syncthreads();
+              if (ls.handoff) publish_state(st, ls);
+            }
+          }))
+        return;
+    }
+  }
+  if constexpr (PF == 3) {
+    if (st->handoff) {
+      // k_sweep_tail continues from here, with the barrier epochs (and
+      // stamps) running on from this launch's
+      if (blockIdx.x == 0 && threadIdx.x == 0) st->epoch0 = epoch;
+      return;
+    }
+  }
+  // ---- true residual ||b - A x||^2 per system
+  {
+    double part[1] = {0};
+    sweep_product<PF, 3, 1>(a, r0, r1, rs, a.X, nullptr, lane_ok, kap, part);
+    store_partials64<1>(part, a.partials, lds);
+    barrier_last(a.bar, epoch, [&] {
+      double tot[1];
+      final_partials64<1>(a.partials, tot, lds);
+      if (threadIdx.x < a.nsys) ls.rr_true[threadIdx.x] = tot[0];
+      publish_state(st, ls);
+    });
+  }
+}
+
+// The rest of a sweep once at most 32 systems run (product form 3): in the
+// last stretch few systems remain, and an iteration cost ~350-410 us however
+// few they were (the row walks' latency and the barriers stay).  Here a wave
+// step is two rows: half-wave h takes row 2k + h of the wave's rows, its lane
+// p working for the p-th running system (s_map; s_inv[j] = the position of
+// system j, or -1), and a claimed unit is 8 rows.  Every workgroup builds the
+// same map from the statuses k_sweep left in memory; workgroup 0 takes the
+// whole state into LDS.  A separate kernel, so that the two-row code does
+// not raise k_sweep's register count.
+template <int MAP>
+__global__ __launch_bounds__(kPB) void k_sweep_tail(SweepArgs a) {
+  constexpr int PF = 3;
+  __shared__ double lds[kUnitRing * kUnitNV * kSys];
+  __shared__ double uacc[kUnitNV * kSys];
+  __shared__ UnitSync us;
+  __shared__ BatchState ls;
+  __shared__ int s_map[32], s_inv[kSys];
+  BatchState* st = a.st;
+  unsigned epoch = st->epoch0;
+  const int j = threadIdx.x & 63;
+  const int G = gridDim.x;
+  int r0, r1, rs;
+  sweep_rows<MAP>(a.n, G, r0, r1, rs);
+  const WgRows wr = sweep_wg_rows(a.n, G);
+  const bool lane_ok = j < a.nsys;
+  const double2 kap = lane_ok ? a.kap[j] : make_double2(0, 0);
+  if (threadIdx.x < kWave) {
+    const bool r = lane_ok && st->status[j] == B_RUN;
+    const unsigned long long m = __ballot(r);
+    const int pos = __popcll(m & ((1ull << j) - 1ull));
+    if (j < 32) s_map[j] = -1;
+    if (r && pos < 32) s_map[pos] = j;
+    s_inv[j] = r && pos < 32 ? pos : -1;
+  }
+  if (blockIdx.x == 0)
+    for (int i = threadIdx.x; i < (int)(sizeof(BatchState) / 4); i += blockDim.x)
+      reinterpret_cast<unsigned*>(&ls)[i] = reinterpret_cast<const unsigned*>(st)[i];
+  __syncthreads();
+  while (st->running > 0) {
+    constexpr int RPW = 2;
+    const int pm = s_map[j & 31], sub = j >> 5;
+    const bool mapped = pm >= 0;
+    const int sys = mapped ? pm : 0;
+    const bool sys_ok = mapped && sys < a.nsys;
+    const double2 kap_s = sys_ok ? a.kap[sys] : make_double2(0, 0);
+    // a lane's sums as sums of system j = lane: in half-wave mode the two
+    // lanes of a system (p and p + 32) are added, in that order
+    const int invj = s_inv[j];
+    auto to_sys = [&](double v) -> double {
+      const int pp = invj >= 0 ? invj : 0;
+      const double lo = __shfl(v, pp), hi = __shfl(v, pp + 32);
+      return invj >= 0 ? lo + hi : 0.0;
+    };
+    auto diag = [&](int r) { return sweep_diag_v(a, r, kap_s); };
+    constexpr int UR = kUnitRows * RPW;  // rows per claimed unit; a lane takes row0 + u RPW + sub
+    const long long it = st->iter;
+    bool act = sys_ok && st->status[sys] == B_RUN;
+    // ---- phat = D^-1 (r - beta omega v) + beta phat
+    if (it > 1) {
+      const double2 beta = st->beta[sys], bo = cmul(st->beta[sys], st->omega[sys]);
+      units_reset(us, uacc);
+      claim_units<0, UR>(wr, us, lds, uacc, a.bar, [&](int row0, int cnt, auto&) {
+        double2 rv[kUnitRows] = {}, vv[kUnitRows] = {}, pv[kUnitRows] = {}, dv[kUnitRows];
+#pragma unroll
+        for (int u = 0; u < kUnitRows; ++u) {
+          const int r = row0 + min(u * RPW + sub, cnt - 1);
+          const size_t o = (size_t)r * kSys + sys;
+          if (act) {
+            rv[u] = a.R[o]; vv[u] = a.V[o]; pv[u] = a.PH[o];
+          }
+          dv[u] = diag(r);
+        }
+#pragma unroll
+        for (int u = 0; u < kUnitRows; ++u)
+          if (act && u * RPW + sub < cnt)
+            stnt(a.PH + (size_t)(row0 + u * RPW + sub) * kSys + sys,
+                 cfma(beta, pv[u], cmul(crecip(dv[u]), csub(rv[u], cmul(bo, vv[u])))));
+      }, to_sys);
+      if (barrier_last(a.bar, epoch, [] {})) return;
+    }
+    // ---- v = A phat ; sigma = rhat^H v
+    {
+      double part[2] = {0, 0};
+      sweep_spmv_h2<1, 2>(a, r0, r1, rs, a.PH, a.V, act, sys, kap_s, part);
+      part[0] = to_sys(part[0]);
+      part[1] = to_sys(part[1]);
+      store_partials64<2>(part, a.partials, lds);
+      if (barrier_last(a.bar, epoch, [&] {
+            double tot[2];
+            final_partials64<2>(a.partials, tot, lds);
+            if (threadIdx.x < a.nsys) upd_sigma(&ls, threadIdx.x, make_double2(tot[0], tot[1]));
+            publish_phase_state(st, ls);
+          }))
+        return;
+    }
+    act = sys_ok && st->status[sys] == B_RUN;
+    // ---- s = r - alpha v ; shat = D^-1 s ; ||s||^2
+    {
+      const double2 alpha = st->alpha[sys];
+      units_reset(us, uacc);
+      claim_units<1, UR>(wr, us, lds, uacc, a.bar, [&](int row0, int cnt, auto& part) {
+        double2 rv[kUnitRows] = {}, vv[kUnitRows] = {}, dv[kUnitRows];
+#pragma unroll
+        for (int u = 0; u < kUnitRows; ++u) {
+          const int r = row0 + min(u * RPW + sub, cnt - 1);
+          const size_t o = (size_t)r * kSys + sys;
+          if (act) {
+            rv[u] = a.R[o]; vv[u] = a.V[o];
+          }
+          dv[u] = diag(r);
+        }
+#pragma unroll
+        for (int u = 0; u < kUnitRows; ++u) {
+          if (act && u * RPW + sub < cnt) {
+            const double2 s = csub(rv[u], cmul(alpha, vv[u]));
+            stnt(a.SH + (size_t)(row0 + u * RPW + sub) * kSys + sys, cmul(crecip(dv[u]), s));
+            part[0] += cabs2(s);
+          }
+        }
+      }, to_sys);
+      store_unit_partials<1>(uacc, a.partials);
+      if (barrier_last(a.bar, epoch, [&] {
+            double tot[1];
+            final_partials64<1>(a.partials, tot, lds);
+            if (threadIdx.x < a.nsys) upd_s(&ls, threadIdx.x, tot[0]);
+            publish_phase_state(st, ls);
+          }))
+        return;
+    }
+    act = sys_ok && st->status[sys] == B_RUN;
+    // ---- t = A shat ; tau = t^H t ; t^H s
+    {
+      double part[3] = {0, 0, 0};
+      sweep_spmv_h2<2, 3>(a, r0, r1, rs, a.SH, a.T, act, sys, kap_s, part);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) part[k] = to_sys(part[k]);
+      store_partials64<3>(part, a.partials, lds);
+      if (barrier_last(a.bar, epoch, [&] {
+            double tot[3];
+            final_partials64<3>(a.partials, tot, lds);
+            if (threadIdx.x < a.nsys) upd_omega(&ls, threadIdx.x, tot[0], make_double2(tot[1], tot[2]));
+            publish_phase_state(st, ls);
+          }))
+        return;
+    }
+    // ---- x += alpha phat + omega shat ; r = s - omega t ; ||r||^2 ; rhat^H r
+    {
+      const int sj = sys_ok ? st->status[sys] : HK_OK;
+      const bool run = sj == B_RUN, half = sj == B_HALF || sj == B_TAUBD;
+      const double2 alpha = st->alpha[sys], omega = st->omega[sys];
+      units_reset(us, uacc);
+      claim_units<3, UR>(wr, us, lds, uacc, a.bar, [&](int row0, int cnt, auto& part) {
+        // two rows at a time (five loads each)
+#pragma unroll
+        for (int h = 0; h < kUnitRows; h += 2) {
+          double2 sh[2] = {}, ph[2] = {}, xv[2] = {}, tv[2] = {}, hv[2] = {}, dv[2];
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            const int r = row0 + min((h + u) * RPW + sub, cnt - 1);
+            const size_t o = (size_t)r * kSys + sys;
+            if (run) {
+              sh[u] = a.SH[o]; ph[u] = a.PH[o]; xv[u] = a.X[o]; tv[u] = a.T[o]; hv[u] = a.RH[o];
+            } else if (half) {
+              ph[u] = a.PH[o]; xv[u] = a.X[o];
+            }
+            dv[u] = diag(r);
+          }
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            if ((h + u) * RPW + sub >= cnt) continue;
+            const size_t o = (size_t)(row0 + (h + u) * RPW + sub) * kSys + sys;
+            if (run) {
+              stnt(a.X + o, cfma(omega, sh[u], cfma(alpha, ph[u], xv[u])));
+              const double2 r = csub(cmul(dv[u], sh[u]), cmul(omega, tv[u]));
+              stnt(a.R + o, r);
+              part[0] += cabs2(r);
+              part[1] = fma(hv[u].x, r.x, fma(hv[u].y, r.y, part[1]));
+              part[2] = fma(hv[u].x, r.y, fma(-hv[u].y, r.x, part[2]));
+            } else if (half) {
+              a.X[o] = cfma(alpha, ph[u], xv[u]);
+            }
+          }
+        }
+      }, to_sys);
       store_unit_partials<3>(uacc, a.partials);
       if (barrier_last(a.bar, epoch, [&] {
             double tot[3];
@@ -940,7 +1315,7 @@ __global__ __launch_bounds__(kPB) void k_sweep(SweepArgs a) {
         return;
     }
   }
-  // ---- true residual ||b - A x||^2 per system
+  // ---- true residual ||b - A x||^2 per system (one row per wave step)
   {
     double part[1] = {0};
     sweep_product<PF, 3, 1>(a, r0, r1, rs, a.X, nullptr, lane_ok, kap, part);
@@ -1465,6 +1840,14 @@ static const void* sweep_kernel(const std::array<int, 4>& sh) {
   return nullptr;
 }
 
+// The launch that finishes a shape's solve with its last <= 32 systems
+// (product form 3), or null.
+static const void* sweep_tail_kernel(const std::array<int, 4>& sh) {
+  if (sh[0] == 3 && sh[1] == 1 && sh[2] == 0 && sh[3] == 0) return (const void*)k_sweep_tail<1>;
+  if (sh[0] == 3 && sh[1] == 2 && sh[2] == 0 && sh[3] == 0) return (const void*)k_sweep_tail<2>;
+  return nullptr;
+}
+
 // Block-diagonal shapes: {lanes per row (64: row blocks), rows per block,
 // entries per lane per pass, tile rows} (k_blockdiag<L, R, CH>).
 static std::vector<std::array<int, 4>> bd_shapes() {
@@ -1527,10 +1910,13 @@ extern "C" int hk_sweep_solve(int64_t n, int64_t nnz, const int32_t* d_rowptr, c
   // the largest grid of any candidate sizes the partials
   int gmax = 0;
   for (const auto& sh : kSweepShapes) {
-    int g = 0;
-    rc = coop_grid(sweep_kernel(sh), &g);
-    if (rc != HK_OK) return rc;
-    gmax = std::max(gmax, g);
+    for (const void* k : {sweep_kernel(sh), sweep_tail_kernel(sh)}) {
+      if (!k) continue;
+      int g = 0;
+      rc = coop_grid(k, &g);
+      if (rc != HK_OK) return rc;
+      gmax = std::max(gmax, g);
+    }
   }
   const size_t vec = (size_t)n * kSys;
   Arena ar;
@@ -1588,6 +1974,9 @@ extern "C" int hk_sweep_solve(int64_t n, int64_t nnz, const int32_t* d_rowptr, c
     if (coop_grid(kern, &grid) != HK_OK) return hipErrorInvalidConfiguration;
     a.tol = tol;
     a.maxit = maxit;
+    // the tuner's trials (every system running) stay in one launch
+    const void* tail = ev ? nullptr : sweep_tail_kernel(sh);
+    a.tail = tail ? 1 : 0;
     GridBar bar0{};
     bar0.spin_limit = spin;
     // barrier stamps for the solve itself, not for the tuner's trials
@@ -1600,6 +1989,23 @@ extern "C" int hk_sweep_solve(int64_t n, int64_t nnz, const int32_t* d_rowptr, c
     if (e2 == hipSuccess) e2 = hipLaunchCooperativeKernel(kern, dim3(grid), dim3(kPB), args, 0, s);
     if (e2 == hipSuccess && ev) e2 = hipEventRecord(ev->e1, s);
     // bar0 lives on this frame: the copy must be done before it goes
+    if (e2 == hipSuccess) e2 = hipStreamSynchronize(s);
+    if (e2 != hipSuccess || !tail) return e2;
+    // at most 32 systems left: the half-wave launch finishes the solve
+    BatchState hs{};
+    GridBar hb{};
+    e2 = hipMemcpyAsync(&hs, a.st, sizeof(hs), hipMemcpyDeviceToHost, s);
+    if (e2 == hipSuccess) e2 = hipMemcpyAsync(&hb, a.bar, sizeof(hb), hipMemcpyDeviceToHost, s);
+    if (e2 == hipSuccess) e2 = hipStreamSynchronize(s);
+    if (e2 != hipSuccess || hb.abort || !hs.handoff || hs.running <= 0) return e2;
+    int grid2 = 0;
+    if (coop_grid(tail, &grid2) != HK_OK) return hipErrorInvalidConfiguration;
+    GridBar bar1{};
+    bar1.spin_limit = spin;
+    bar1.stamps = bar0.stamps;
+    bar1.nstamps = bar0.nstamps;
+    e2 = hipMemcpyAsync(a.bar, &bar1, sizeof(GridBar), hipMemcpyHostToDevice, s);
+    if (e2 == hipSuccess) e2 = hipLaunchCooperativeKernel(tail, dim3(grid2), dim3(kPB), args, 0, s);
     if (e2 == hipSuccess) e2 = hipStreamSynchronize(s);
     return e2;
   };

@@ -77,7 +77,7 @@ def test_sweep_small_matches_oracle(hk, oracle, nc, nsys):
         # the dots (one 6^3 system: 100 here vs 135 in the oracle; the 16^3 cube:
         # numpy 1,960 vs oracle 2,410), so the count is bounded loosely and
         # the solution and true residual carry the parity
-        assert abs(infos[j]["iters"] - oi["iters"]) <= max(10, 0.4 * oi["iters"]), (j, infos[j], oi)
+        assert iters_plausible(oracle, p, val, B[:, j], infos[j]["iters"], oi["iters"], 1e-10), (j, infos[j], oi)
         r = oracle.residual(p.rowptr, p.col, val, B[:, j], Xh[:, j])
         assert abs(np.linalg.norm(r) / np.linalg.norm(B[:, j]) - infos[j]["relres_true"]) <= 1e-12
     assert np.all(Xh[:, nsys:] == 0)
@@ -95,6 +95,25 @@ def test_sweep_iteration_cap_and_zero_rhs(hk, oracle):
         val = H.helmholtz_values(p, kap[j])
         xo, _ = oracle.bicgstab(p.rowptr, p.col, val, B[:, j], tol=1e-14, maxit=4)
         assert np.linalg.norm(host(X)[:, j] - xo) <= 1e-12 * np.linalg.norm(xo)
+
+
+def iters_plausible(oracle, p, val, b, it, it_oracle, tol):
+    """The solver's iteration count against the oracle's: within 40% (or 10),
+    else within the oracle's own counts under rounding-size changes widened
+    by 20%.  On the highest-frequency systems of the 6^3 sweep the count at
+    1e-10 is chaotic in the rounding: the oracle's 118 iterations for one
+    system became 79-182 under eight random perturbations of b of relative
+    size 1e-13.  The envelope takes 24 such perturbations."""
+    if abs(it - it_oracle) <= max(10, 0.4 * it_oracle):
+        return True
+    rng = np.random.default_rng(13)
+    counts = []
+    for _ in range(24):
+        d = crandn(rng, p.n)
+        d[p.dirichlet] = 0
+        d *= 1e-13 * np.linalg.norm(b) / np.linalg.norm(d)
+        counts.append(oracle.bicgstab(p.rowptr, p.col, val, b + d, tol=tol)[1]["iters"])
+    return 0.8 * min(counts) <= it <= 1.2 * max(counts)
 
 
 def iterate_close(oracle, p, val, b, x, xo, maxit=4, base=1e-12):
@@ -332,6 +351,33 @@ def test_blockdiag_every_shape_uneven(hk, oracle):
     blockdiag_iterates_every_shape(hk, oracle, rowptr, np.concatenate(cols).astype(np.int32),
                                    np.concatenate(vals), np.concatenate(bs), np.array(offs, dtype=np.int64),
                                    "uneven32")
+
+
+def test_blockdiag_bitwise_repeatable_and_stamped(hk, oracle):
+    """The phases' rows are claimed by whichever wave is free, but each
+    unit's sums are added in unit order: two solves give the same bits and
+    iteration counts, with or without barrier stamps.  The stamps of a
+    solve of L iterations (every system still running) are 5L + 2 nonzero,
+    non-decreasing entries (start, 4 + 5 (L - 1) in the loop, 2 around the
+    true residual), the rest zero."""
+    sizes = [12, 7, 16, 9, 14, 5, 11, 15]
+    rowptr, col, val, b, offs = blockdiag_inputs(sizes, seed=4)
+    A = hk.CSR(dev(rowptr), dev(col), dev(val))
+    L = 12
+    say("blockdiag repeat", sizes)
+    x0, i0 = hk.blockdiag_solve(A, offs, dev(b), tol=1e-14, max_iter=L, shape=(64, 32, 4, 512))
+    st = torch.zeros(8 * (L + 1), dtype=torch.float64, device=DEV)
+    x1, i1 = hk.blockdiag_solve(A, offs, dev(b), tol=1e-14, max_iter=L, shape=(64, 32, 4, 512), stamps=st)
+    assert np.array_equal(host(x0), host(x1)) and [i["iters"] for i in i0] == [i["iters"] for i in i1]
+    assert all(i["iters"] == L for i in i0)
+    s_ = host(st)
+    nz = 5 * L + 2
+    assert np.all(s_[1:nz + 1] > 0) and np.all(np.diff(s_[1:nz + 1]) >= 0) and np.all(s_[nz + 1:] == 0)
+    say("blockdiag repeat, solve to 1e-10")
+    x2, i2 = hk.blockdiag_solve(A, offs, dev(b), tol=1e-10, max_iter=5000)
+    x3, i3 = hk.blockdiag_solve(A, offs, dev(b), tol=1e-10, max_iter=5000)
+    assert np.array_equal(host(x2), host(x3)) and [i["iters"] for i in i2] == [i["iters"] for i in i3]
+    assert all(i["status"] == 0 for i in i2)
 
 
 def test_blockdiag_rejects_coupled_systems(hk):
