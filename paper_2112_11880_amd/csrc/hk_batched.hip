@@ -48,8 +48,9 @@ struct BatchState {
   int running;
   int changed;       // a system stopped in the last iteration (tile list to rebuild)
   int ntiles_active;
-  // sweep: set once at most 32 systems run, when the rest of the solve
-  // continues in k_sweep_tail from barrier epoch epoch0
+  // sweep: the rows per wave step of the launch that continues the solve
+  // (k_sweep_tail<MAP, handoff>: 2 from 32 running systems, 4 from 16), 0
+  // while none; the next launch starts at barrier epoch epoch0
   int handoff;
   unsigned epoch0;
 };
@@ -741,20 +742,22 @@ __device__ __forceinline__ double2 sweep_diag_v(const SweepArgs& a, int i, doubl
   return make_double2(k - kap.x * m, -kap.y * m);
 }
 
-// The per-row product with the next row prefetched (sweep_spmv_pf) for two
-// rows per wave step: half-wave h takes rows r0 + (2k + h) rs, lanes h*32 +
-// 0..15 hold its current row's first 16 entries, and entry values reach the
-// half's lanes by __shfl from there.  Lane l works for system `sys`; part
-// holds its sums (one row in two of its system's rows).
-template <int EPI, int NV>
-__device__ __forceinline__ void sweep_spmv_h2(const SweepArgs& a, int r0, int r1, int rs, const double2* src,
+// The per-row product with the next row prefetched (sweep_spmv_pf) for RPW
+// (2 or 4) rows per wave step: lane group q of 64 / RPW lanes takes rows r0 +
+// (RPW k + q) rs, its lanes q*64/RPW + 0..15 hold its current row's first 16
+// entries, and entry values reach the group's lanes by __shfl from there.
+// Lane l works for system `sys`; part holds its sums (one row in RPW of its
+// system's rows).
+template <int EPI, int NV, int RPW>
+__device__ __forceinline__ void sweep_spmv_hr(const SweepArgs& a, int r0, int r1, int rs, const double2* src,
                                               double2* dst, bool act, int sys, double2 kap, double (&part)[NV]) {
-  constexpr int W = 16, G = 4;
-  const int l = threadIdx.x & 63, hl = l & 32;
+  constexpr int W = 16, G = 4, LPR = kWave / RPW;
+  static_assert(LPR >= W, "a lane group holds a row's first 16 entries");
+  const int l = threadIdx.x & 63, hl = l & ~(LPR - 1);
   if (__ballot(act) == 0) return;  // uniform: no running system
   const int rb = uni(r0);
   if (rb >= r1) return;
-  int row = rb + (hl ? rs : 0);
+  int row = rb + (l / LPR) * rs;
   int s = 0, e = 0;
   if (row < r1) {
     s = a.rowptr[row];
@@ -769,10 +772,12 @@ __device__ __forceinline__ void sweep_spmv_h2(const SweepArgs& a, int r0, int r1
   int cv, cvn = 0;
   double kv, mv, kvn = 0, mvn = 0;
   fetch(s, e, cv, kv, mv);
-  for (int base = rb; base < r1; base += 2 * rs) {
+  for (int base = rb; base < r1; base += RPW * rs) {
     const bool has = row < r1;
     const int len = has ? e - s : 0;
-    const int lenw = max(__shfl(len, 0), __shfl(len, 32));
+    int lenw = __shfl(len, 0);
+#pragma unroll
+    for (int q = 1; q < RPW; ++q) lenw = max(lenw, __shfl(len, q * LPR));
     const size_t o = (size_t)(has ? row : 0) * kSys + sys;
     double2 acK = make_double2(0, 0), acM = make_double2(0, 0);
     double2 xv[G];
@@ -781,7 +786,7 @@ __device__ __forceinline__ void sweep_spmv_h2(const SweepArgs& a, int r0, int r1
       const int c = __shfl(cv, hl + u);
       if (u < len && act) xv[u] = src[(size_t)c * kSys + sys];
     }
-    const int nrow = row + 2 * rs;
+    const int nrow = row + RPW * rs;
     int ns = 0, ne = 0;
     if (nrow < r1) {
       ns = a.rowptr[nrow];
@@ -933,7 +938,8 @@ __global__ __launch_bounds__(kPB) void k_sweep(SweepArgs a) {
             for (int u = 0; u < a.nsys; ++u) run += ls.status[u] == B_RUN;
             ls.running = run;
           }
-          if (PF == 3 && threadIdx.x == 0 && a.tail && ls.running > 0 && ls.running <= 32) ls.handoff = 1;
+          if (PF == 3 && threadIdx.x == 0 && a.tail && ls.running > 0 && ls.running <= 32)
+            ls.handoff = ls.running <= 16 ? 4 : 2;
           publish_state(st, ls);
         }))
       return;
@@ -1076,8 +1082,8 @@ __global__ __launch_bounds__(kPB) void k_sweep(SweepArgs a) {
               if (threadIdx.x == 0) {
                 ls.running = run;
                 ls.iter = ls.iter + 1;
-                // at most 32 systems left: hand the rest to the half-wave launch
-                if (PF == 3 && a.tail && run > 0 && run <= 32) ls.handoff = 1;
+                // at most 32 systems left: hand the rest to the multi-row launches
+                if (PF == 3 && a.tail && run > 0 && run <= 32) ls.handoff = run <= 16 ? 4 : 2;
               }
             }
             publish_phase_state(st, ls);
@@ -1112,23 +1118,24 @@ __global__ __launch_bounds__(kPB) void k_sweep(SweepArgs a) {
   }
 }
 
-// The rest of a sweep once at most 32 systems run (product form 3): in the
-// last stretch few systems remain, and an iteration cost ~350-410 us however
-// few they were (the row walks' latency and the barriers stay).  Here a wave
-// step is two rows: half-wave h takes row 2k + h of the wave's rows, its lane
-// p working for the p-th running system (s_map; s_inv[j] = the position of
-// system j, or -1), and a claimed unit is 8 rows.  Every workgroup builds the
-// same map from the statuses k_sweep left in memory; workgroup 0 takes the
-// whole state into LDS.  A separate kernel, so that the two-row code does
-// not raise k_sweep's register count.
-template <int MAP>
+// The rest of a sweep once at most 64 / RPW systems run (product form 3;
+// RPW = 2 from 32 systems, 4 from 16): in the last stretch few systems
+// remain, and an iteration cost ~350-410 us however few they were (the row
+// walks' latency and the barriers stay).  Here a wave step is RPW rows: lane
+// group q (64 / RPW lanes) takes row RPW k + q of the wave's rows, its lane p
+// working for the p-th running system (s_map; s_inv[j] = the position of
+// system j, or -1), and a claimed unit is 4 RPW rows.  Every workgroup builds
+// the same map from the statuses the previous launch left in memory;
+// workgroup 0 takes the whole state into LDS.  Separate kernels, so that the
+// multi-row code does not raise k_sweep's register count.
+template <int MAP, int RPW>
 __global__ __launch_bounds__(kPB) void k_sweep_tail(SweepArgs a) {
-  constexpr int PF = 3;
+  constexpr int PF = 3, LPR = kWave / RPW;
   __shared__ double lds[kUnitRing * kUnitNV * kSys];
   __shared__ double uacc[kUnitNV * kSys];
   __shared__ UnitSync us;
   __shared__ BatchState ls;
-  __shared__ int s_map[32], s_inv[kSys];
+  __shared__ int s_map[LPR], s_inv[kSys];
   BatchState* st = a.st;
   unsigned epoch = st->epoch0;
   const int j = threadIdx.x & 63;
@@ -1142,28 +1149,29 @@ __global__ __launch_bounds__(kPB) void k_sweep_tail(SweepArgs a) {
     const bool r = lane_ok && st->status[j] == B_RUN;
     const unsigned long long m = __ballot(r);
     const int pos = __popcll(m & ((1ull << j) - 1ull));
-    if (j < 32) s_map[j] = -1;
-    if (r && pos < 32) s_map[pos] = j;
-    s_inv[j] = r && pos < 32 ? pos : -1;
+    if (j < LPR) s_map[j] = -1;
+    if (r && pos < LPR) s_map[pos] = j;
+    s_inv[j] = r && pos < LPR ? pos : -1;
   }
   if (blockIdx.x == 0)
     for (int i = threadIdx.x; i < (int)(sizeof(BatchState) / 4); i += blockDim.x)
       reinterpret_cast<unsigned*>(&ls)[i] = reinterpret_cast<const unsigned*>(st)[i];
   __syncthreads();
-  while (st->running > 0) {
-    constexpr int RPW = 2;
-    const int pm = s_map[j & 31], sub = j >> 5;
+  while (st->running > 0 && !(RPW == 2 && st->handoff == 4)) {
+    const int pm = s_map[j & (LPR - 1)], sub = j / LPR;
     const bool mapped = pm >= 0;
     const int sys = mapped ? pm : 0;
     const bool sys_ok = mapped && sys < a.nsys;
     const double2 kap_s = sys_ok ? a.kap[sys] : make_double2(0, 0);
-    // a lane's sums as sums of system j = lane: in half-wave mode the two
-    // lanes of a system (p and p + 32) are added, in that order
+    // a lane's sums as sums of system j = lane: the RPW lanes of a system
+    // (p, p + LPR, ...) are added in that order
     const int invj = s_inv[j];
     auto to_sys = [&](double v) -> double {
       const int pp = invj >= 0 ? invj : 0;
-      const double lo = __shfl(v, pp), hi = __shfl(v, pp + 32);
-      return invj >= 0 ? lo + hi : 0.0;
+      double t = __shfl(v, pp);
+#pragma unroll
+      for (int q = 1; q < RPW; ++q) t += __shfl(v, pp + q * LPR);
+      return invj >= 0 ? t : 0.0;
     };
     auto diag = [&](int r) { return sweep_diag_v(a, r, kap_s); };
     constexpr int UR = kUnitRows * RPW;  // rows per claimed unit; a lane takes row0 + u RPW + sub
@@ -1195,7 +1203,7 @@ __global__ __launch_bounds__(kPB) void k_sweep_tail(SweepArgs a) {
     // ---- v = A phat ; sigma = rhat^H v
     {
       double part[2] = {0, 0};
-      sweep_spmv_h2<1, 2>(a, r0, r1, rs, a.PH, a.V, act, sys, kap_s, part);
+      sweep_spmv_hr<1, 2, RPW>(a, r0, r1, rs, a.PH, a.V, act, sys, kap_s, part);
       part[0] = to_sys(part[0]);
       part[1] = to_sys(part[1]);
       store_partials64<2>(part, a.partials, lds);
@@ -1245,7 +1253,7 @@ __global__ __launch_bounds__(kPB) void k_sweep_tail(SweepArgs a) {
     // ---- t = A shat ; tau = t^H t ; t^H s
     {
       double part[3] = {0, 0, 0};
-      sweep_spmv_h2<2, 3>(a, r0, r1, rs, a.SH, a.T, act, sys, kap_s, part);
+      sweep_spmv_hr<2, 3, RPW>(a, r0, r1, rs, a.SH, a.T, act, sys, kap_s, part);
 #pragma unroll
       for (int k = 0; k < 3; ++k) part[k] = to_sys(part[k]);
       store_partials64<3>(part, a.partials, lds);
@@ -1308,11 +1316,23 @@ __global__ __launch_bounds__(kPB) void k_sweep_tail(SweepArgs a) {
               if (threadIdx.x == 0) {
                 ls.running = run;
                 ls.iter = ls.iter + 1;
+                // at most 16 left: hand them to the four-row launch
+                if (RPW == 2 && run > 0 && run <= 16) ls.handoff = 4;
               }
             }
             publish_phase_state(st, ls);
+            if constexpr (RPW == 2) {
+              __syncthreads();
+              if (ls.handoff == 4) publish_state(st, ls);
+            }
           }))
         return;
+    }
+  }
+  if constexpr (RPW == 2) {
+    if (st->handoff == 4) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) st->epoch0 = epoch;
+      return;
     }
   }
   // ---- true residual ||b - A x||^2 per system (one row per wave step)
@@ -1840,11 +1860,12 @@ static const void* sweep_kernel(const std::array<int, 4>& sh) {
   return nullptr;
 }
 
-// The launch that finishes a shape's solve with its last <= 32 systems
+// The launch that continues a shape's solve with rpw rows per wave step
 // (product form 3), or null.
-static const void* sweep_tail_kernel(const std::array<int, 4>& sh) {
-  if (sh[0] == 3 && sh[1] == 1 && sh[2] == 0 && sh[3] == 0) return (const void*)k_sweep_tail<1>;
-  if (sh[0] == 3 && sh[1] == 2 && sh[2] == 0 && sh[3] == 0) return (const void*)k_sweep_tail<2>;
+static const void* sweep_tail_kernel(const std::array<int, 4>& sh, int rpw) {
+  if (sh[0] != 3 || sh[2] != 0 || sh[3] != 0) return nullptr;
+  if (sh[1] == 1) return rpw == 2 ? (const void*)k_sweep_tail<1, 2> : rpw == 4 ? (const void*)k_sweep_tail<1, 4> : nullptr;
+  if (sh[1] == 2) return rpw == 2 ? (const void*)k_sweep_tail<2, 2> : rpw == 4 ? (const void*)k_sweep_tail<2, 4> : nullptr;
   return nullptr;
 }
 
@@ -1910,7 +1931,7 @@ extern "C" int hk_sweep_solve(int64_t n, int64_t nnz, const int32_t* d_rowptr, c
   // the largest grid of any candidate sizes the partials
   int gmax = 0;
   for (const auto& sh : kSweepShapes) {
-    for (const void* k : {sweep_kernel(sh), sweep_tail_kernel(sh)}) {
+    for (const void* k : {sweep_kernel(sh), sweep_tail_kernel(sh, 2), sweep_tail_kernel(sh, 4)}) {
       if (!k) continue;
       int g = 0;
       rc = coop_grid(k, &g);
@@ -1975,8 +1996,7 @@ extern "C" int hk_sweep_solve(int64_t n, int64_t nnz, const int32_t* d_rowptr, c
     a.tol = tol;
     a.maxit = maxit;
     // the tuner's trials (every system running) stay in one launch
-    const void* tail = ev ? nullptr : sweep_tail_kernel(sh);
-    a.tail = tail ? 1 : 0;
+    a.tail = !ev && sweep_tail_kernel(sh, 2) ? 1 : 0;
     GridBar bar0{};
     bar0.spin_limit = spin;
     // barrier stamps for the solve itself, not for the tuner's trials
@@ -1990,23 +2010,26 @@ extern "C" int hk_sweep_solve(int64_t n, int64_t nnz, const int32_t* d_rowptr, c
     if (e2 == hipSuccess && ev) e2 = hipEventRecord(ev->e1, s);
     // bar0 lives on this frame: the copy must be done before it goes
     if (e2 == hipSuccess) e2 = hipStreamSynchronize(s);
-    if (e2 != hipSuccess || !tail) return e2;
-    // at most 32 systems left: the half-wave launch finishes the solve
-    BatchState hs{};
-    GridBar hb{};
-    e2 = hipMemcpyAsync(&hs, a.st, sizeof(hs), hipMemcpyDeviceToHost, s);
-    if (e2 == hipSuccess) e2 = hipMemcpyAsync(&hb, a.bar, sizeof(hb), hipMemcpyDeviceToHost, s);
-    if (e2 == hipSuccess) e2 = hipStreamSynchronize(s);
-    if (e2 != hipSuccess || hb.abort || !hs.handoff || hs.running <= 0) return e2;
-    int grid2 = 0;
-    if (coop_grid(tail, &grid2) != HK_OK) return hipErrorInvalidConfiguration;
-    GridBar bar1{};
-    bar1.spin_limit = spin;
-    bar1.stamps = bar0.stamps;
-    bar1.nstamps = bar0.nstamps;
-    e2 = hipMemcpyAsync(a.bar, &bar1, sizeof(GridBar), hipMemcpyHostToDevice, s);
-    if (e2 == hipSuccess) e2 = hipLaunchCooperativeKernel(tail, dim3(grid2), dim3(kPB), args, 0, s);
-    if (e2 == hipSuccess) e2 = hipStreamSynchronize(s);
+    // at most 32 (then 16) systems left: the multi-row launches continue
+    for (int stage = 1; e2 == hipSuccess && a.tail; ) {
+      BatchState hs{};
+      GridBar hb{};
+      e2 = hipMemcpyAsync(&hs, a.st, sizeof(hs), hipMemcpyDeviceToHost, s);
+      if (e2 == hipSuccess) e2 = hipMemcpyAsync(&hb, a.bar, sizeof(hb), hipMemcpyDeviceToHost, s);
+      if (e2 == hipSuccess) e2 = hipStreamSynchronize(s);
+      if (e2 != hipSuccess || hb.abort || hs.handoff <= stage || hs.running <= 0) break;
+      const void* tail = sweep_tail_kernel(sh, hs.handoff);
+      int grid2 = 0;
+      if (!tail || coop_grid(tail, &grid2) != HK_OK) return hipErrorInvalidConfiguration;
+      GridBar bar1{};
+      bar1.spin_limit = spin;
+      bar1.stamps = bar0.stamps;
+      bar1.nstamps = bar0.nstamps;
+      e2 = hipMemcpyAsync(a.bar, &bar1, sizeof(GridBar), hipMemcpyHostToDevice, s);
+      if (e2 == hipSuccess) e2 = hipLaunchCooperativeKernel(tail, dim3(grid2), dim3(kPB), args, 0, s);
+      if (e2 == hipSuccess) e2 = hipStreamSynchronize(s);
+      stage = hs.handoff;
+    }
     return e2;
   };
   auto aborted = [&](bool* ab) -> hipError_t {
