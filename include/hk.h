@@ -305,7 +305,11 @@ int hk_krylov_solve_mixed(hk_csr A, const void* d_b, void* d_x, double inner_tol
  * flight; row mapping 1 deals each XCD's eighth of the rows round-robin to
  * its waves, 2 deals all rows round-robin to all waves, 3 gives each wave a
  * contiguous range of its XCD's eighth (form 2 needs mapping 3).  The
- * candidates are {1,1}, {1,2}, {1,3}, {2,3}, {3,1} and {3,2}.  With
+ * candidates are {1,1}, {1,2}, {1,3}, {2,3}, {3,1} and {3,2}.  With form 3
+ * the solve continues in a second cooperative launch once at most 32
+ * systems run (two rows per wave step, one per half-wave, for the running
+ * systems only) and in a third once at most 16 run (four rows per step);
+ * the barrier stamps run on across the launches.  With
  * opts->shape all 0, the first call for a given (device, n, nnz, longest
  * row, nsys) runs every candidate for 4 iterations, timed with HIP events,
  * and keeps the fastest for this and later calls (the batch-plan analogue
