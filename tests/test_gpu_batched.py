@@ -176,6 +176,42 @@ def test_sweep_every_shape_small(hk, oracle):
     sweep_iterates_every_shape(hk, oracle, p, kap, B, "6^3")
 
 
+def test_sweep_multirow_launches_match_oracle(hk, oracle):
+    """With at most 32 (16) systems the per-row product form runs its
+    iterations two (four) rows per wave step from the start: the iterates
+    after 1, 2 and 4 iterations are the oracle's to 1e-12 (iterate_close), in
+    both row mappings, for 24 and 11 systems (one with b = 0); a full solve
+    to 1e-10 with 24 systems, which passes from two to four rows per step
+    when its 17th system converges, meets the oracle's solutions."""
+    for nsys in (24, 11):
+        p, kap, B = sweep_inputs(7, nsys, seed=5)
+        B[:, 3] = 0
+        args = (dev(p.rowptr), dev(p.col), dev(p.K), dev(p.M), kap, dev(B))
+        vals = [H.helmholtz_values(p, kap[j]) for j in range(nsys)]
+        for sh in ((3, 1, 0, 0), (3, 2, 0, 0)):
+            for mi in (1, 2, 4):
+                say("sweep multi-row", nsys, sh, mi)
+                X, infos = hk.sweep_solve(*args, tol=1e-14, max_iter=mi, shape=sh)
+                Xh = host(X)
+                for j in range(nsys):
+                    xo, oi = oracle.bicgstab(p.rowptr, p.col, vals[j], B[:, j], tol=1e-14, maxit=mi)
+                    assert infos[j]["iters"] == oi["iters"] and infos[j]["status"] == oi["status"], (nsys, sh, mi, j)
+                    assert iterate_close(oracle, p, vals[j], B[:, j], Xh[:, j], xo, maxit=mi), (nsys, sh, mi, j)
+                assert np.all(Xh[:, nsys:] == 0)
+    p, kap, B = sweep_inputs(7, 24, seed=6)
+    args = (dev(p.rowptr), dev(p.col), dev(p.K), dev(p.M), kap, dev(B))
+    say("sweep multi-row, full solve")
+    X, infos = hk.sweep_solve(*args, tol=1e-10, shape=(3, 1, 0, 0))
+    Xh = host(X)
+    for j in range(24):
+        val = H.helmholtz_values(p, kap[j])
+        xo, oi = oracle.bicgstab(p.rowptr, p.col, val, B[:, j], tol=1e-10)
+        assert infos[j]["status"] == 0, (j, infos[j])
+        assert np.linalg.norm(Xh[:, j] - xo) <= 1e-7 * np.linalg.norm(xo), j
+        r = oracle.residual(p.rowptr, p.col, val, B[:, j], Xh[:, j])
+        assert abs(np.linalg.norm(r) / np.linalg.norm(B[:, j]) - infos[j]["relres_true"]) <= 1e-12
+
+
 def test_sweep_every_shape_large(hk, oracle):
     """614,125 rows: more than 64 rows (and many 64-entry chunks) per wave in
     the entry-stream product; 7 systems (lanes 7..63 idle), one with b = 0."""
