@@ -120,6 +120,120 @@ __device__ __forceinline__ void final_partials64(const double* partials, double 
   __syncthreads();
 }
 
+// Grid barrier that also finishes an NV-sum reduction over the workgroups'
+// partials (partials[(k*G + b)*64 + j], k < NV <= 3).  Reading all G x 64 x
+// NV partials into workgroup 0 took 4.5-9.5 us per barrier (up to 393 KB
+// through one CU); here the kXcds groups of workgroups b = g, g + kXcds, ...
+// are first summed by workgroup g (group leader), each into
+// bar->gpart[(k*kXcds + g)*64 + j] (in member order, split over 16 thread
+// rows and then added in row order), and workgroup 0 adds the kXcds group
+// sums in group order and calls on_last(tot) in all its threads (tot[k]
+// valid in thread j < 64 for system j).  The order is fixed, so the sums
+// are bitwise reproducible.  Waits, fences and the abort path as in
+// barrier_last; lds needs 3 x 16 x 64 doubles.  Returns true if the kernel
+// must stop.  All threads of every workgroup call it.
+template <int NV, class F>
+__device__ __forceinline__ bool barrier_reduce(GridBar* bar, unsigned& epoch, const double* partials, double* lds,
+                                               F&& on_last) {
+  static_assert(NV >= 1 && NV <= 3, "one to three sums");
+  __shared__ int s_stop;
+  const unsigned e = ++epoch;
+  const int G = gridDim.x, b = blockIdx.x;
+  const int j = threadIdx.x & 63, q = threadIdx.x >> 6;  // q < 16
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // this workgroup's writes before its flag
+    st_relaxed_u32(&bar->arrive[b], e);
+  }
+  if (b < kXcds) {
+    // leader of group b: its members m_i = b + kXcds i, i < nm
+    const int nm = (G - b + kXcds - 1) / kXcds;
+    bool ok = true;
+    for (int i = threadIdx.x; i < nm; i += blockDim.x) ok = wait_epoch(&bar->arrive[b + kXcds * i], e, bar) && ok;
+    if (!ok) atomicExch(&bar->abort, 1);
+    __syncthreads();
+    if (threadIdx.x == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the members' partials
+    __syncthreads();
+    // thread row q sums members i = q, q + 16, ... in order (loads first)
+    double t[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) t[k] = 0;
+    for (int i0 = q; i0 < nm; i0 += 2 * kPW) {
+      double v[NV][2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int i = i0 + u * kPW < nm ? i0 + u * kPW : i0;
+#pragma unroll
+        for (int k = 0; k < NV; ++k) v[k][u] = partials[((size_t)k * G + b + kXcds * i) * kSys + j];
+      }
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+        if (i0 + u * kPW < nm) {
+#pragma unroll
+          for (int k = 0; k < NV; ++k) t[k] += v[k][u];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NV; ++k) lds[(k * kPW + q) * kSys + j] = t[k];
+    __syncthreads();
+    if (threadIdx.x < NV * kSys) {
+      const int k = threadIdx.x / kSys, jj = threadIdx.x % kSys;
+      double g = 0;
+      for (int r = 0; r < kPW; ++r) g += lds[(k * kPW + r) * kSys + jj];
+      bar->gpart[(k * kXcds + b) * kSys + jj] = g;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // the group's sums before its flag
+      st_relaxed_u32(&bar->garrive[b], e);
+    }
+  }
+  if (b == 0) {
+    bool ok = true;
+    if (threadIdx.x < kXcds) ok = wait_epoch(&bar->garrive[threadIdx.x], e, bar);
+    if (!ok) atomicExch(&bar->abort, 1);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      s_stop = ld_relaxed_i32(&bar->abort);
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // every group's sums
+      if (bar->stamps && e < bar->nstamps) bar->stamps[e] = (double)wall_clock64();
+    }
+    __syncthreads();
+    // the kXcds group sums: thread (k, j) adds them in group order, then
+    // threads j < 64 take all NV through LDS
+    if (threadIdx.x < NV * kSys) {
+      const int k = threadIdx.x / kSys;
+      double v[kXcds];
+#pragma unroll
+      for (int g = 0; g < kXcds; ++g) v[g] = bar->gpart[(k * kXcds + g) * kSys + j];
+      double tk = 0;
+#pragma unroll
+      for (int g = 0; g < kXcds; ++g) tk += v[g];
+      lds[threadIdx.x] = tk;
+    }
+    __syncthreads();
+    double tot[NV];
+    if (threadIdx.x < kSys) {
+#pragma unroll
+      for (int k = 0; k < NV; ++k) tot[k] = lds[k * kSys + j];
+    }
+    if (!s_stop) on_last(tot);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // the callback's writes before the epoch
+      st_relaxed_u32(&bar->release, e);
+    }
+  } else if (threadIdx.x == 0) {
+    (void)wait_epoch(&bar->release, e, bar);
+  }
+  if (threadIdx.x == 0) {
+    s_stop = ld_relaxed_i32(&bar->abort);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // workgroup 0's release, and through it every arrival
+  }
+  __syncthreads();
+  return s_stop != 0;
+}
+
 __device__ __forceinline__ double2 crecip(double2 d) { return cdiv(make_double2(1.0, 0.0), d); }
 
 // Copies of a workgroup's LDS copy of the state to memory, by wave 0 (the
@@ -1567,9 +1681,7 @@ __global__ __launch_bounds__(kPB) void k_blockdiag(BdArgs a) {
       acc[0] += cabs2(b);
     }
   });
-  if (barrier_last(a.bar, epoch, [&] {
-        double tot[1];
-        final_partials64<1>(a.partials, tot, fin);
+  if (barrier_reduce<1>(a.bar, epoch, a.partials, fin, [&](const double(&tot)[1]) {
         if (threadIdx.x < a.nsys) init_sys(st, threadIdx.x, tot[0], a.tol, a.maxit);
         if (threadIdx.x == 0) { st->iter = 1; st->maxit = a.maxit; }
         __syncthreads();
@@ -1605,9 +1717,7 @@ __global__ __launch_bounds__(kPB) void k_blockdiag(BdArgs a) {
         acc[1] = fma(h.x, v.y, fma(-h.y, v.x, acc[1]));
       });
     });
-    if (barrier_last(a.bar, epoch, [&] {
-          double tot[2];
-          final_partials64<2>(a.partials, tot, fin);
+    if (barrier_reduce<2>(a.bar, epoch, a.partials, fin, [&](const double(&tot)[2]) {
           if (threadIdx.x < a.nsys) upd_sigma(st, threadIdx.x, make_double2(tot[0], tot[1]));
         }))
       return;
@@ -1620,9 +1730,7 @@ __global__ __launch_bounds__(kPB) void k_blockdiag(BdArgs a) {
         acc[0] += cabs2(s);
       }
     });
-    if (barrier_last(a.bar, epoch, [&] {
-          double tot[1];
-          final_partials64<1>(a.partials, tot, fin);
+    if (barrier_reduce<1>(a.bar, epoch, a.partials, fin, [&](const double(&tot)[1]) {
           if (threadIdx.x < a.nsys) upd_s(st, threadIdx.x, tot[0]);
         }))
       return;
@@ -1637,9 +1745,7 @@ __global__ __launch_bounds__(kPB) void k_blockdiag(BdArgs a) {
         acc[2] = fma(t.x, s.y, fma(-t.y, s.x, acc[2]));
       });
     });
-    if (barrier_last(a.bar, epoch, [&] {
-          double tot[3];
-          final_partials64<3>(a.partials, tot, fin);
+    if (barrier_reduce<3>(a.bar, epoch, a.partials, fin, [&](const double(&tot)[3]) {
           if (threadIdx.x < a.nsys) upd_omega(st, threadIdx.x, tot[0], make_double2(tot[1], tot[2]));
         }))
       return;
@@ -1662,9 +1768,7 @@ __global__ __launch_bounds__(kPB) void k_blockdiag(BdArgs a) {
         a.X[row] = cfma(alpha, a.PH[row], a.X[row]);
       }
     });
-    if (barrier_last(a.bar, epoch, [&] {
-          double tot[3];
-          final_partials64<3>(a.partials, tot, fin);
+    if (barrier_reduce<3>(a.bar, epoch, a.partials, fin, [&](const double(&tot)[3]) {
           __shared__ int s_run[kSys];
           if (threadIdx.x < kSys)
             s_run[threadIdx.x] = threadIdx.x < a.nsys
@@ -1689,9 +1793,7 @@ __global__ __launch_bounds__(kPB) void k_blockdiag(BdArgs a) {
       acc[0] += cabs2(csub(a.B[row], ax));
     });
   });
-  barrier_last(a.bar, epoch, [&] {
-    double tot[1];
-    final_partials64<1>(a.partials, tot, fin);
+  barrier_reduce<1>(a.bar, epoch, a.partials, fin, [&](const double(&tot)[1]) {
     if (threadIdx.x < a.nsys) st->rr_true[threadIdx.x] = tot[0];
   });
 }
@@ -2125,7 +2227,8 @@ extern "C" int hk_blockdiag_solve(hk_csr A, int32_t nsys, const int64_t* row_off
   Arena ar;
   const size_t bytes = 8 * a256(16 * (size_t)n) + 3 * a256(4 * (size_t)nt_max) +
                        a256(4 * (size_t)n) + 4 * a256(4 * (kSys + 1)) + a256(8 * 4 * (size_t)gmax * kSys) +
-                       a256(sizeof(BatchState)) + a256(sizeof(GridBar)) + a256(64);
+                       a256(sizeof(BatchState)) + a256(sizeof(GridBar)) + a256(8 * 4 * (size_t)kXcds * kSys) +
+                       a256(64);
   if (hipMalloc((void**)&ar.base, bytes) != hipSuccess) HK_FAIL(HK_ENOMEM, "hk_blockdiag_solve: hipMalloc(%zu)", bytes);
   BdArgs a{};
   a.n = (int)n; a.nsys = nsys; a.rowptr = A->rowptr; a.col = A->col;
@@ -2145,6 +2248,7 @@ extern "C" int hk_blockdiag_solve(hk_csr A, int32_t nsys, const int64_t* row_off
   a.partials = ar.take<double>(4 * (size_t)gmax * kSys);
   a.st = ar.take<BatchState>(1);
   a.bar = ar.take<GridBar>(1);
+  double* gpart = ar.take<double>(4 * (size_t)kXcds * kSys);
   int* flag = ar.take<int>(16);
   if (ar.off > bytes) {
     (void)hipFree(ar.base);
@@ -2200,6 +2304,7 @@ extern "C" int hk_blockdiag_solve(hk_csr A, int32_t nsys, const int64_t* row_off
     init.ntiles_active = nt;
     GridBar bar0{};
     bar0.spin_limit = spin;
+    bar0.gpart = gpart;
     // barrier stamps for the solve itself, not for the tuner's trials
     bar0.stamps = ev ? nullptr : opts->d_history;
     bar0.nstamps = bar0.stamps ? 8ull * ((unsigned long long)maxit + 1) : 0;

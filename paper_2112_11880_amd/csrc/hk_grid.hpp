@@ -42,8 +42,11 @@ struct GridBar {
   // arrived at barrier e, for e < nstamps (null: none)
   double* stamps;
   unsigned long long nstamps;
-  unsigned pad[56];      // keep release/abort on their own 256-byte line
+  // per-XCD-group sums of barrier_reduce: kXcds x 4 x 64 doubles (null if unused)
+  double* gpart;
+  unsigned pad[54];      // keep release/abort on their own 256-byte line
   unsigned arrive[kBarMaxBlocks];  // last epoch each workgroup arrived at
+  unsigned garrive[kXcds];         // last epoch each group's sums were published at
 };
 
 // 100 MHz constant clock: 4e8 ticks = 4 s.
