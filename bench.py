@@ -136,20 +136,22 @@ def _blas1_once(hk, torch, dev, h, reps, sets, seed=7):
     return res
 
 
-def bench_blas1(hk, torch, dev, stream, log, h=14_000_000, reps=21, sets=3):
+def bench_blas1(hk, torch, dev, stream, log, h=14_000_000, reps=21, sets=3, paper_sizes=True):
     """BLAS-1 kernels at the paper's vector sizes, achieved algorithmic GB/s
     (zdotc 32 B/element, dznrm2 16, zaxpy 48, zscal 32, zaxmy 48) and GFLOP/s
     in the paper's flop convention.  Each entry point call (its kernels and,
     for the reductions, the finalize) is timed; the calls rotate over
     independent vector pairs, enough of them (at least 512 MB in all) that
-    the operands do not stay in the 256 MB last-level cache between calls."""
+    the operands do not stay in the 256 MB last-level cache between calls.
+    paper_sizes=False keeps to h (the profiling run)."""
     res = _blas1_once(hk, torch, dev, h, reps, sets)
     log("blas1", res)
     paper = {}
-    for hp in (648_849, 2_000_000, 9_000_000):
+    for hp in (648_849, 2_000_000, 9_000_000) if paper_sizes else ():
         ns = max(2, -(-512 * 2**20 // (32 * hp)))
         paper[str(hp)] = {"rotating_sets": ns, "ops": _blas1_once(hk, torch, dev, hp, max(reps, ns + 1), ns)}
-    log("blas1 at the paper's other sizes", {k: {o: v["us"] for o, v in d["ops"].items()} for k, d in paper.items()})
+    if paper:
+        log("blas1 at the paper's other sizes", {k: {o: v["us"] for o, v in d["ops"].items()} for k, d in paper.items()})
     return {"blas1": {"h": h, "rotating_sets": sets, "ops": res, "paper_sizes": paper}}
 
 
@@ -528,11 +530,12 @@ def main():
                     help="force the batched solvers' launch shape 'a,b,c,d' (counter runs)")
     ap.add_argument("--solve-max-iter", type=int, default=0,
                     help="counter runs: cap the plain solve at this many iterations and skip the other solves")
-    ap.add_argument("--only", choices=["hex", "sweep", "uneven", "adjoint", "tfqmr", "bicgstab_l", "mixed"],
+    ap.add_argument("--only", choices=["hex", "sweep", "uneven", "adjoint", "tfqmr", "bicgstab_l", "mixed", "blas1"],
                     default="",
                     help="profiling runs: this leg alone (batched legs without their plain references; "
-                         "tfqmr, bicgstab_l and mixed on the 192x96x96 system), capped at --solve-max-iter "
-                         "iterations (cycles, inner iterations) when given; its record printed as one JSON line")
+                         "tfqmr, bicgstab_l and mixed on the 192x96x96 system; blas1 at h = 14M only), capped "
+                         "at --solve-max-iter iterations (cycles, inner iterations) when given; its record "
+                         "printed as one JSON line")
     ap.add_argument("--no-batched", dest="batched", action="store_false",
                     help="skip the batched sweep / uneven-batch extras")
     args = ap.parse_args()
@@ -561,6 +564,8 @@ def main():
                             plan=ints(args.plan), solver_plan=ints(args.solver_plan))
         elif args.only == "adjoint":
             rec = bench_adjoint(hk, torch, np, dev, log)
+        elif args.only == "blas1":
+            rec = bench_blas1(hk, torch, dev, torch.cuda.current_stream(), log, paper_sizes=False)
         elif args.only in ("sweep", "uneven"):
             rec = bench_batched(hk, torch, np, dev, log, legs=(args.only,), plain=False, max_iter=cap,
                                 shape=ints(args.batch_shape))
