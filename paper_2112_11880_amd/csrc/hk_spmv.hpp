@@ -142,7 +142,13 @@ __device__ __forceinline__ V csr_block_rows(int r0, int n, const int* __restrict
   else rend = __shfl(rs, R, kWave);
   const int nxt = __shfl(rs, (l + 1) & (kWave - 1), kWave);
   const int re = l < kWave - 1 ? nxt : rend;
-  const int s0 = __shfl(rs, 0, kWave);
+  // passes start at a 128-byte line of values (up to AL - 1 entries before
+  // the block's first, loaded and never summed), so each 64-entry value load
+  // covers whole lines; from the block's first entry a complex128 load
+  // straddled 9 lines, and under non-temporal streaming a line two loads
+  // share can be fetched twice
+  constexpr int AL = 128 / (int)sizeof(V);
+  const int s0 = __shfl(rs, 0, kWave) & ~(AL - 1);
   // entry range of the row this lane sums (row r0 + l / S)
   constexpr int S = kWave / R;
   const int rsum = S > 1 ? __shfl(rs, l / S, kWave) : (l < R ? rs : 0);
@@ -157,6 +163,8 @@ __device__ __forceinline__ V csr_block_rows(int r0, int n, const int* __restrict
       const int e = c0 + l + kWave * k;
       const int p = e < cend ? e : cend - 1;
       c[k] = col_at(col, p, base);
+      // an entry before the block decodes a 16-bit offset with this block's base
+      if constexpr (sizeof(CI) == 2) c[k] = min(max(c[k], 0), n - 1);
       a[k] = ldnt(val + p);
     }
     V xv[CH];
