@@ -54,7 +54,9 @@ __global__ __launch_bounds__(kRbThreads) void k_spmv_rb(int n, int ntiles, const
   V* buf = lds + (threadIdx.x / kWave) * CH * kWave;
   const int l = threadIdx.x & (kWave - 1);
   for (int tb = blockIdx.x; tb < ntiles; tb += gridDim.x) {
-    const int t = R == 32 ? tile_of<kSpmvTileChunk>(tb, ntiles) : tile_of(tb, ntiles);
+    const int t = R == 32   ? tile_of<kSpmvTileChunk>(tb, ntiles)
+                  : R == 16 ? tile_of<kSpmvTileChunk16>(tb, ntiles)
+                            : tile_of(tb, ntiles);
     const int r0 = t * (kRbWaves * R) + (threadIdx.x / kWave) * R;
     const V acc = csr_block_rows<R, CH, V, CI>(r0, n, rowptr, col, val, x, buf);
     const int r = r0 + l;

@@ -261,9 +261,13 @@ __device__ __forceinline__ V csr_block_rows_pairs(int r0, int n, const int* __re
 // 32 or 128 on the 1.8M-row system; the plain product with 32 rows per wave
 // and 16-bit columns measured 94.4 us with chunks of 512 tiles against 95.9
 // us with 8 (and 95.1-96.4 us with 128, 256, 1024 or 2048), so it uses 512;
-// with 64 rows per wave 512 was no better, and the other shapes keep 8.
+// with 64 rows per wave 512 was no better.  With 16 rows per wave (the Q1
+// hexahedral product, 27-entry rows) chunks of 32 tiles measured 60.9-61.1
+// us against 61.8 (8), 61.5 (16) and 61.2 (64), and 66.5 -> 68.7 us with
+// 512; the other shapes keep 8.
 constexpr int kTileChunk = 8;
 constexpr int kSpmvTileChunk = 512;
+constexpr int kSpmvTileChunk16 = 32;
 template <int CHUNK = kTileChunk>
 __device__ __forceinline__ int tile_of(int b, int ntiles) {
   constexpr int S = kXcds * CHUNK;
