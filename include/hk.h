@@ -279,7 +279,9 @@ int hk_krylov_solve_mixed(hk_csr A, const void* d_b, void* d_x, double inner_tol
  * With opts->d_history non-null (device, 8 (max_iter + 1) doubles, caller
  * owned) the solve records barrier times in it: entry e (e >= 1, the e-th
  * barrier of the launch) = the device's 100 MHz wall clock when the last
- * workgroup arrived; entries of barriers that did not happen are left
+ * workgroup arrived (at a barrier that also sums per-system dot products:
+ * once the last group of workgroups has summed its part); entries of
+ * barriers that did not happen are left
  * untouched.  The barriers of both solves are: 1 after the start phase;
  * then per iteration (4 in the first, which has no p update) after the p
  * update, the v product, the s update, the t product and the x/r update;

@@ -76,46 +76,42 @@ __device__ __forceinline__ void store_partials64(const double (&v)[NV], double* 
   }
 }
 
-// Second stage: out[k] (valid in threads 0..63, thread j = system j) = sum
-// over workgroups in a fixed order.  Thread (g, j) sums workgroups g, g +
-// kPW, g + 2 kPW, ... in that order; the loads of kFinBatch of them (for all
-// NV sums; twice as many for one sum) are issued before any is added, since
-// the partials come from memory after the barrier's acquire and a load-add
-// chain would wait out every load in turn.
-constexpr int kFinBatch = 8;
+// Group leader b's part of barrier_reduce: the NV sums of its members
+// m_i = b + kXcds i (i < nm), thread row q adding members q, q + 16, ... in
+// order, then the 16 rows in row order, into gpart[(k*kXcds + b)*64 + j].
+// Out of line, so that its loops do not raise the register allocation of
+// the persistent kernels that call the barrier at every phase.  All threads
+// of the workgroup call it.
 template <int NV>
-__device__ __forceinline__ void final_partials64(const double* partials, double (&out)[NV], double* lds) {
-  const int j = threadIdx.x & 63, g = threadIdx.x >> 6, G = gridDim.x;
-  // one sum: twice the loads in flight in the same registers
-  constexpr int FB = NV == 1 ? 2 * kFinBatch : kFinBatch;
-  double s[NV];
+__device__ __noinline__ void group_partials(const double* partials, int G, int b, double* lds, double* gpart) {
+  const int j = threadIdx.x & 63, q = threadIdx.x >> 6;  // q < 16
+  const int nm = (G - b + kXcds - 1) / kXcds;
+  double t[NV];
 #pragma unroll
-  for (int k = 0; k < NV; ++k) s[k] = 0;
-  for (int b0 = g; b0 < G; b0 += FB * kPW) {
-    double v[NV][FB];
+  for (int k = 0; k < NV; ++k) t[k] = 0;
+  for (int i0 = q; i0 < nm; i0 += 2 * kPW) {
+    double v[NV][2];
 #pragma unroll
-    for (int u = 0; u < FB; ++u) {
-      const int b = b0 + u * kPW < G ? b0 + u * kPW : b0;
+    for (int u = 0; u < 2; ++u) {
+      const int i = i0 + u * kPW < nm ? i0 + u * kPW : i0;
 #pragma unroll
-      for (int k = 0; k < NV; ++k) v[k][u] = partials[((size_t)k * G + b) * kSys + j];
+      for (int k = 0; k < NV; ++k) v[k][u] = partials[((size_t)k * G + b + kXcds * i) * kSys + j];
     }
 #pragma unroll
-    for (int u = 0; u < FB; ++u)
-      if (b0 + u * kPW < G) {
+    for (int u = 0; u < 2; ++u)
+      if (i0 + u * kPW < nm) {
 #pragma unroll
-        for (int k = 0; k < NV; ++k) s[k] += v[k][u];
+        for (int k = 0; k < NV; ++k) t[k] += v[k][u];
       }
   }
 #pragma unroll
-  for (int k = 0; k < NV; ++k) lds[(k * kPW + g) * kSys + j] = s[k];
+  for (int k = 0; k < NV; ++k) lds[(k * kPW + q) * kSys + j] = t[k];
   __syncthreads();
-  if (threadIdx.x < kSys) {
-#pragma unroll
-    for (int k = 0; k < NV; ++k) {
-      double s = 0;
-      for (int u = 0; u < kPW; ++u) s += lds[(k * kPW + u) * kSys + j];
-      out[k] = s;
-    }
+  if (threadIdx.x < NV * kSys) {
+    const int k = threadIdx.x / kSys, jj = threadIdx.x % kSys;
+    double g = 0;
+    for (int r = 0; r < kPW; ++r) g += lds[(k * kPW + r) * kSys + jj];
+    gpart[(k * kXcds + b) * kSys + jj] = g;
   }
   __syncthreads();
 }
@@ -123,13 +119,13 @@ __device__ __forceinline__ void final_partials64(const double* partials, double 
 // Grid barrier that also finishes an NV-sum reduction over the workgroups'
 // partials (partials[(k*G + b)*64 + j], k < NV <= 3).  Reading all G x 64 x
 // NV partials into workgroup 0 took 4.5-9.5 us per barrier (up to 393 KB
-// through one CU); here the kXcds groups of workgroups b = g, g + kXcds, ...
-// are first summed by workgroup g (group leader), each into
-// bar->gpart[(k*kXcds + g)*64 + j] (in member order, split over 16 thread
-// rows and then added in row order), and workgroup 0 adds the kXcds group
-// sums in group order and calls on_last(tot) in all its threads (tot[k]
-// valid in thread j < 64 for system j).  The order is fixed, so the sums
-// are bitwise reproducible.  Waits, fences and the abort path as in
+// through one CU, while the other workgroups waited); here the kXcds groups
+// of workgroups b = g, g + kXcds, ... are first summed by workgroup g (group
+// leader), each into bar->gpart[(k*kXcds + g)*64 + j] (in member order,
+// split over 16 thread rows and then added in row order; group_partials),
+// and workgroup 0 adds the kXcds group sums in group order and calls
+// on_last(tot) in all its threads (tot[k] valid in thread j < 64 for system
+// j).  The order is fixed, so the sums are bitwise reproducible.  Waits, fences and the abort path as in
 // barrier_last; lds needs 3 x 16 x 64 doubles.  Returns true if the kernel
 // must stop.  All threads of every workgroup call it.
 template <int NV, class F>
@@ -139,7 +135,7 @@ __device__ __forceinline__ bool barrier_reduce(GridBar* bar, unsigned& epoch, co
   __shared__ int s_stop;
   const unsigned e = ++epoch;
   const int G = gridDim.x, b = blockIdx.x;
-  const int j = threadIdx.x & 63, q = threadIdx.x >> 6;  // q < 16
+  const int j = threadIdx.x & 63;
   __syncthreads();
   if (threadIdx.x == 0) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // this workgroup's writes before its flag
@@ -154,35 +150,7 @@ __device__ __forceinline__ bool barrier_reduce(GridBar* bar, unsigned& epoch, co
     __syncthreads();
     if (threadIdx.x == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the members' partials
     __syncthreads();
-    // thread row q sums members i = q, q + 16, ... in order (loads first)
-    double t[NV];
-#pragma unroll
-    for (int k = 0; k < NV; ++k) t[k] = 0;
-    for (int i0 = q; i0 < nm; i0 += 2 * kPW) {
-      double v[NV][2];
-#pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const int i = i0 + u * kPW < nm ? i0 + u * kPW : i0;
-#pragma unroll
-        for (int k = 0; k < NV; ++k) v[k][u] = partials[((size_t)k * G + b + kXcds * i) * kSys + j];
-      }
-#pragma unroll
-      for (int u = 0; u < 2; ++u)
-        if (i0 + u * kPW < nm) {
-#pragma unroll
-          for (int k = 0; k < NV; ++k) t[k] += v[k][u];
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < NV; ++k) lds[(k * kPW + q) * kSys + j] = t[k];
-    __syncthreads();
-    if (threadIdx.x < NV * kSys) {
-      const int k = threadIdx.x / kSys, jj = threadIdx.x % kSys;
-      double g = 0;
-      for (int r = 0; r < kPW; ++r) g += lds[(k * kPW + r) * kSys + jj];
-      bar->gpart[(k * kXcds + b) * kSys + jj] = g;
-    }
-    __syncthreads();
+    group_partials<NV>(partials, G, b, lds, bar->gpart);
     if (threadIdx.x == 0) {
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // the group's sums before its flag
       st_relaxed_u32(&bar->garrive[b], e);
@@ -1035,9 +1003,7 @@ __global__ __launch_bounds__(kPB) void k_sweep(SweepArgs a) {
       part[0] += cabs2(b);
     }
     store_partials64<1>(part, a.partials, lds);
-    if (barrier_last(a.bar, epoch, [&] {
-          double tot[1];
-          final_partials64<1>(a.partials, tot, lds);
+    if (barrier_reduce<1>(a.bar, epoch, a.partials, lds, [&](const double(&tot)[1]) {
           for (int i = threadIdx.x; i < (int)(sizeof(BatchState) / 4); i += blockDim.x)
             reinterpret_cast<unsigned*>(&ls)[i] = 0;
           __syncthreads();
@@ -1089,9 +1055,7 @@ __global__ __launch_bounds__(kPB) void k_sweep(SweepArgs a) {
       double part[2] = {0, 0};
       sweep_product<PF, 1, 2>(a, r0, r1, rs, a.PH, a.V, act, kap, part);
       store_partials64<2>(part, a.partials, lds);
-      if (barrier_last(a.bar, epoch, [&] {
-            double tot[2];
-            final_partials64<2>(a.partials, tot, lds);
+      if (barrier_reduce<2>(a.bar, epoch, a.partials, lds, [&](const double(&tot)[2]) {
             if (threadIdx.x < a.nsys) upd_sigma(&ls, threadIdx.x, make_double2(tot[0], tot[1]));
             publish_phase_state(st, ls);
           }))
@@ -1123,9 +1087,7 @@ __global__ __launch_bounds__(kPB) void k_sweep(SweepArgs a) {
         }
       }, [](double v) { return v; });
       store_unit_partials<1>(uacc, a.partials);
-      if (barrier_last(a.bar, epoch, [&] {
-            double tot[1];
-            final_partials64<1>(a.partials, tot, lds);
+      if (barrier_reduce<1>(a.bar, epoch, a.partials, lds, [&](const double(&tot)[1]) {
             if (threadIdx.x < a.nsys) upd_s(&ls, threadIdx.x, tot[0]);
             publish_phase_state(st, ls);
           }))
@@ -1137,9 +1099,7 @@ __global__ __launch_bounds__(kPB) void k_sweep(SweepArgs a) {
       double part[3] = {0, 0, 0};
       sweep_product<PF, 2, 3>(a, r0, r1, rs, a.SH, a.T, act, kap, part);
       store_partials64<3>(part, a.partials, lds);
-      if (barrier_last(a.bar, epoch, [&] {
-            double tot[3];
-            final_partials64<3>(a.partials, tot, lds);
+      if (barrier_reduce<3>(a.bar, epoch, a.partials, lds, [&](const double(&tot)[3]) {
             if (threadIdx.x < a.nsys) upd_omega(&ls, threadIdx.x, tot[0], make_double2(tot[1], tot[2]));
             publish_phase_state(st, ls);
           }))
@@ -1185,9 +1145,7 @@ __global__ __launch_bounds__(kPB) void k_sweep(SweepArgs a) {
         }
       }, [](double v) { return v; });
       store_unit_partials<3>(uacc, a.partials);
-      if (barrier_last(a.bar, epoch, [&] {
-            double tot[3];
-            final_partials64<3>(a.partials, tot, lds);
+      if (barrier_reduce<3>(a.bar, epoch, a.partials, lds, [&](const double(&tot)[3]) {
             // wave 0 (thread j = system j) updates and counts the running
             // systems with one ballot
             if (threadIdx.x < kWave) {
@@ -1223,9 +1181,7 @@ __global__ __launch_bounds__(kPB) void k_sweep(SweepArgs a) {
     double part[1] = {0};
     sweep_product<PF, 3, 1>(a, r0, r1, rs, a.X, nullptr, lane_ok, kap, part);
     store_partials64<1>(part, a.partials, lds);
-    barrier_last(a.bar, epoch, [&] {
-      double tot[1];
-      final_partials64<1>(a.partials, tot, lds);
+    barrier_reduce<1>(a.bar, epoch, a.partials, lds, [&](const double(&tot)[1]) {
       if (threadIdx.x < a.nsys) ls.rr_true[threadIdx.x] = tot[0];
       publish_state(st, ls);
     });
@@ -1321,9 +1277,7 @@ __global__ __launch_bounds__(kPB) void k_sweep_tail(SweepArgs a) {
       part[0] = to_sys(part[0]);
       part[1] = to_sys(part[1]);
       store_partials64<2>(part, a.partials, lds);
-      if (barrier_last(a.bar, epoch, [&] {
-            double tot[2];
-            final_partials64<2>(a.partials, tot, lds);
+      if (barrier_reduce<2>(a.bar, epoch, a.partials, lds, [&](const double(&tot)[2]) {
             if (threadIdx.x < a.nsys) upd_sigma(&ls, threadIdx.x, make_double2(tot[0], tot[1]));
             publish_phase_state(st, ls);
           }))
@@ -1355,9 +1309,7 @@ __global__ __launch_bounds__(kPB) void k_sweep_tail(SweepArgs a) {
         }
       }, to_sys);
       store_unit_partials<1>(uacc, a.partials);
-      if (barrier_last(a.bar, epoch, [&] {
-            double tot[1];
-            final_partials64<1>(a.partials, tot, lds);
+      if (barrier_reduce<1>(a.bar, epoch, a.partials, lds, [&](const double(&tot)[1]) {
             if (threadIdx.x < a.nsys) upd_s(&ls, threadIdx.x, tot[0]);
             publish_phase_state(st, ls);
           }))
@@ -1371,9 +1323,7 @@ __global__ __launch_bounds__(kPB) void k_sweep_tail(SweepArgs a) {
 #pragma unroll
       for (int k = 0; k < 3; ++k) part[k] = to_sys(part[k]);
       store_partials64<3>(part, a.partials, lds);
-      if (barrier_last(a.bar, epoch, [&] {
-            double tot[3];
-            final_partials64<3>(a.partials, tot, lds);
+      if (barrier_reduce<3>(a.bar, epoch, a.partials, lds, [&](const double(&tot)[3]) {
             if (threadIdx.x < a.nsys) upd_omega(&ls, threadIdx.x, tot[0], make_double2(tot[1], tot[2]));
             publish_phase_state(st, ls);
           }))
@@ -1419,9 +1369,7 @@ __global__ __launch_bounds__(kPB) void k_sweep_tail(SweepArgs a) {
         }
       }, to_sys);
       store_unit_partials<3>(uacc, a.partials);
-      if (barrier_last(a.bar, epoch, [&] {
-            double tot[3];
-            final_partials64<3>(a.partials, tot, lds);
+      if (barrier_reduce<3>(a.bar, epoch, a.partials, lds, [&](const double(&tot)[3]) {
             // wave 0 (thread j = system j) updates and counts the running
             // systems with one ballot
             if (threadIdx.x < kWave) {
@@ -1454,9 +1402,7 @@ __global__ __launch_bounds__(kPB) void k_sweep_tail(SweepArgs a) {
     double part[1] = {0};
     sweep_product<PF, 3, 1>(a, r0, r1, rs, a.X, nullptr, lane_ok, kap, part);
     store_partials64<1>(part, a.partials, lds);
-    barrier_last(a.bar, epoch, [&] {
-      double tot[1];
-      final_partials64<1>(a.partials, tot, lds);
+    barrier_reduce<1>(a.bar, epoch, a.partials, lds, [&](const double(&tot)[1]) {
       if (threadIdx.x < a.nsys) ls.rr_true[threadIdx.x] = tot[0];
       publish_state(st, ls);
     });
@@ -2045,7 +1991,7 @@ extern "C" int hk_sweep_solve(int64_t n, int64_t nnz, const int32_t* d_rowptr, c
   Arena ar;
   const size_t bytes = 6 * a256(16 * vec) + 2 * a256(8 * n) + a256(16 * kSys) +
                        a256(8 * 4 * (size_t)gmax * kSys) + a256(sizeof(BatchState)) + a256(sizeof(GridBar)) +
-                       a256(64);
+                       a256(8 * 4 * (size_t)kXcds * kSys) + a256(64);
   if (hipMalloc((void**)&ar.base, bytes) != hipSuccess) HK_FAIL(HK_ENOMEM, "hk_sweep_solve: hipMalloc(%zu)", bytes);
   SweepArgs a{};
   a.n = (int)n; a.nsys = nsys; a.rowptr = d_rowptr; a.col = d_col; a.K = d_K; a.M = d_M;
@@ -2057,6 +2003,8 @@ extern "C" int hk_sweep_solve(int64_t n, int64_t nnz, const int32_t* d_rowptr, c
   a.partials = ar.take<double>(4 * (size_t)gmax * kSys);
   a.st = ar.take<BatchState>(1);
   a.bar = ar.take<GridBar>(1);
+  // per-XCD-group sums of the reducing barriers
+  double* gpart = ar.take<double>(4 * (size_t)kXcds * kSys);
   int* flag = ar.take<int>(16);
   if (ar.off > bytes) {
     (void)hipFree(ar.base);
@@ -2101,6 +2049,7 @@ extern "C" int hk_sweep_solve(int64_t n, int64_t nnz, const int32_t* d_rowptr, c
     a.tail = !ev && sweep_tail_kernel(sh, 2) ? 1 : 0;
     GridBar bar0{};
     bar0.spin_limit = spin;
+    bar0.gpart = gpart;
     // barrier stamps for the solve itself, not for the tuner's trials
     bar0.stamps = ev ? nullptr : opts->d_history;
     bar0.nstamps = bar0.stamps ? 8ull * ((unsigned long long)maxit + 1) : 0;
@@ -2125,6 +2074,7 @@ extern "C" int hk_sweep_solve(int64_t n, int64_t nnz, const int32_t* d_rowptr, c
       if (!tail || coop_grid(tail, &grid2) != HK_OK) return hipErrorInvalidConfiguration;
       GridBar bar1{};
       bar1.spin_limit = spin;
+      bar1.gpart = gpart;
       bar1.stamps = bar0.stamps;
       bar1.nstamps = bar0.nstamps;
       e2 = hipMemcpyAsync(a.bar, &bar1, sizeof(GridBar), hipMemcpyHostToDevice, s);
