@@ -125,9 +125,10 @@ __device__ __noinline__ void group_partials(const double* partials, int G, int b
 // split over 16 thread rows and then added in row order; group_partials),
 // and workgroup 0 adds the kXcds group sums in group order and calls
 // on_last(tot) in all its threads (tot[k] valid in thread j < 64 for system
-// j).  The order is fixed, so the sums are bitwise reproducible.  Waits, fences and the abort path as in
-// barrier_last; lds needs 3 x 16 x 64 doubles.  Returns true if the kernel
-// must stop.  All threads of every workgroup call it.
+// j).  The order is fixed, so the sums are bitwise reproducible.  Waits,
+// fences and the abort path as in barrier_last; lds needs 3 x 16 x 64
+// doubles.  Returns true if the kernel must stop.  All threads of every
+// workgroup call it.
 template <int NV, class F>
 __device__ __forceinline__ bool barrier_reduce(GridBar* bar, unsigned& epoch, const double* partials, double* lds,
                                                F&& on_last) {

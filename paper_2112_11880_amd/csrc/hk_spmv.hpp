@@ -116,15 +116,18 @@ __device__ __forceinline__ V block_row_total(V acc) {
 }
 
 // Row-block CSR: one wave per R consecutive rows r0 .. r0+R-1 (R in
-// {16, 32, 64}, r0 a multiple of R); col is either column stream (col_at).  The wave streams the rows' entries with all 64 lanes --
-// entry e of the block goes to lane e % 64, CH entries per lane per pass,
-// every column and value load issued before any gather -- parks the
-// products in its LDS slice buf[CH*64], then the 64/R lanes of each row
-// sum interleaved parts of its products and combine them by a butterfly
-// (block_row_sums, block_row_total).  On the 86^3 Q1 system (27 entries per
-// row, 16-row blocks) this cut the product from 68.3 to 65.6 us against one
-// lane summing each row in entry order.  Rows of any length are handled by passes
-// over the block's entry range (the pass count is uniform across the wave).
+// {16, 32, 64}, r0 a multiple of R); col is either column stream (col_at).
+// The wave streams the rows' entries with all 64 lanes -- entry e of a pass
+// goes to lane e % 64, CH entries per lane per pass, every column and value
+// load issued before any gather -- parks the products in its LDS slice
+// buf[CH*64], then the 64/R lanes of each row sum interleaved parts of its
+// products and combine them by a butterfly (block_row_sums,
+// block_row_total).  On the 86^3 Q1 system (27 entries per row, 16-row
+// blocks) this cut the product from 68.3 to 65.6 us against one lane
+// summing each row in entry order.  Rows of any length are handled by
+// passes over the block's entry range, the first starting at the 128-byte
+// line of values that holds the block's first entry (the pass count is
+// uniform across the wave).
 // Returns the sum of row r0 + lane for lanes < R with r0 + lane < n, zero
 // otherwise.  All 64 lanes must call it.
 template <int R, int CH, class V, class CI>
